@@ -1,0 +1,208 @@
+/*
+ * rpchol: bistochastic kernel eigendecomposition by randomly pivoted partial
+ * Cholesky, for AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Vales & Giannakis, "Accelerated decomposition of
+ * bistochastic kernel matrices by low rank approximation":
+ *   - rpchol_factor   : Algorithm 2 (accelerated randomly pivoted Cholesky,
+ *                       ARPC) with Algorithm 3 (its accept/reject check), on
+ *                       the Gaussian kernel K_ij = exp(-|x_i - x_j|^2 / eps)
+ *                       of the Application section (eq. data-kernel), which
+ *                       is never formed;
+ *   - bistoch_degrees : the normalisation vectors d~ = diag(F F^T 1) and
+ *                       q~ = diag(F F^T D~^{-1} 1) of Algorithm 1 and the
+ *                       section "Bistochastic normalization";
+ *   - bistoch_eig     : the rest of Algorithm 1 (QR of D~^{-1} F, EVD of the
+ *                       small inner matrix R C R^T with C = F^T Q~^{-1} F,
+ *                       eigenvectors U = Q V), top nev eigenpairs;
+ *   - nystrom_extend  : the Nystrom extension of the section "Nystrom method
+ *                       connection", applied to P~, at new points.
+ *
+ * Conventions shared by every entry point:
+ *   - Every data pointer is a DEVICE pointer owned by the caller.  The
+ *     library allocates nothing on these paths; scratch memory comes from
+ *     a caller-provided workspace whose size the *_workspace_size call
+ *     returns.  Workspaces may not be shared by calls that overlap in time.
+ *   - Every call is stream-ordered and asynchronous on `stream` (0 = the
+ *     null stream).  The return value reports host-side argument checks and
+ *     launch errors only.
+ *   - Failures found on the device (a degree <= 0, a Cholesky breakdown,
+ *     non-finite input) are written to the device int32 *dev_status, which
+ *     the caller clears to 0 before the call and reads after a sync
+ *     (rpc_status_sync does both the sync and the read).  The first error
+ *     written wins.
+ *   - The accepted pivot count k lives in device memory (int32) so that no
+ *     call needs a host synchronisation; columns of F at index >= k are 0.
+ *   - Layouts: X is row-major N x d (float32, leading dimension ldx >= d).
+ *     F is column-major N x r with leading dimension ldf >= N, ldf a
+ *     multiple of 8.  U is column-major N x nev (leading dimension ldu >= N,
+ *     a multiple of 8).  Phi is column-major M x nev (ldphi >= M).
+ *   - Nothing throws across the ABI.  Calls on distinct buffers and
+ *     workspaces may run concurrently on different streams.
+ */
+#ifndef RPCHOL_H_
+#define RPCHOL_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* rpc_stream_t; /* a hipStream_t */
+
+typedef enum {
+  RPC_OK = 0,
+  RPC_EINVAL = -1,      /* bad argument: r > N, b < 1, greedy with b != 1, eps <= 0, nev > r, NULL, dtype */
+  RPC_EWORKSPACE = -2,  /* workspace smaller than *_workspace_size reported */
+  RPC_EHIP = -3,        /* HIP launch or runtime error */
+  RPC_EDEGREE = -4,     /* device: an entry of d~ = diag(F F^T 1) is not > 0 (Algorithm 1 assert) */
+  RPC_EQDEGREE = -5,    /* device: an entry of q~ = diag(F F^T D~^{-1} 1) is not > 0 (Algorithm 1 assert) */
+  RPC_EBREAKDOWN = -6,  /* device: Cholesky of a Gram or a replayed pivot block not positive definite */
+  RPC_ENONFINITE = -7,  /* device: non-finite value in the input points */
+  RPC_ENOCONV = -8      /* device: the small eigensolver hit its iteration limit */
+} rpc_status;
+
+typedef enum { RPC_F64 = 0, RPC_F32 = 1, RPC_BF16 = 2 } rpc_dtype;
+
+typedef enum {
+  RPC_SAMPLED = 0, /* Algorithm 2: b iid proposals per round from rho / sum(rho) */
+  RPC_GREEDY = 1,  /* deterministic pivoting: argmax rho (lowest index on ties); needs b = 1 */
+  RPC_REPLAY = 2   /* the ordered pivots in `replay` are taken, all accepted */
+} rpc_mode;
+
+/* Points: N rows of dimension d, row-major float32, and the bandwidth eps of
+ * k(x, y) = exp(-|x - y|^2 / eps). */
+typedef struct {
+  int64_t N;
+  int64_t d;
+  int64_t ldx;
+  const float* X; /* device */
+  double eps;
+} rpc_points;
+
+/* Options of rpchol_factor (Algorithm 2).
+ *  r, b         rank budget and block size; t = ceil(r / b) rounds, the last
+ *               proposes r - (t - 1) b pivots.
+ *  gemm_dtype   arithmetic of the kernel-column distance products:
+ *               F64 (points upcast exactly), F32, or BF16 (points rounded to
+ *               bf16; squared norms of the rounded points in fp32; the result
+ *               is the exact Gaussian kernel of the rounded points up to fp32
+ *               accumulation).  The pivot block H uses the same points.
+ *  factor_dtype F64 or F32: storage of F and arithmetic of the Schur update.
+ *               Pivot selection, the pivot-block Cholesky, the triangular
+ *               solve and the residual diagonal are float64 in every mode.
+ *  tau          a proposal whose updated pivot H(i, i) <= tau is rejected.
+ *  uniforms     device doubles in [0, 1), multiples of 2^-53; round i uses
+ *               uniforms[2 b i + j] for proposal j and uniforms[2 b i + b + j]
+ *               for its accept test; n_uniforms >= 2 b ceil(r / b)
+ *               (SAMPLED only).
+ *  replay       device int64 ordered pivots (REPLAY only), n_replay <= r.
+ *  round_accepted  optional device int32 array of ceil(r / b) entries (or
+ *               ceil(n_replay / b) in replay mode) receiving the number of
+ *               pivots accepted in each round; may be NULL. */
+typedef struct {
+  int32_t r;
+  int32_t b;
+  int32_t mode;         /* rpc_mode */
+  int32_t gemm_dtype;   /* rpc_dtype */
+  int32_t factor_dtype; /* RPC_F64 or RPC_F32 */
+  int32_t pad_;
+  double tau;
+  const double* uniforms;
+  int64_t n_uniforms;
+  const int64_t* replay;
+  int64_t n_replay;
+  int32_t* round_accepted;
+} rpc_factor_opts;
+
+/* Options of bistoch_eig (Algorithm 1 after the factorisation).
+ *  nev        number of leading eigenpairs returned (1 <= nev <= r).
+ *  gamma      regulariser added to the entries (i, i), i < k, of D~^{-1} F
+ *             before the QR (the paper's stabilised QR); default 0.
+ *  fix_const  if nonzero, U(:, 0) is set to 1/sqrt(N) and U re-orthonormalised
+ *             by a QR with positive diag(R) (Algorithm 1, optional lines).
+ *  gram_dtype F64 or F32: arithmetic of the two N-long Gram products
+ *             (float64 accumulation across row chunks in both cases).
+ *  u_dtype    F64 or F32 storage of U. */
+typedef struct {
+  int32_t nev;
+  int32_t fix_const;
+  int32_t gram_dtype;
+  int32_t u_dtype;
+  double gamma;
+} rpc_eig_opts;
+
+/* ---- Algorithm 2 (ARPC) with Algorithm 3 ------------------------------
+ * Outputs: F (N x r, column-major, dtype factor_dtype; columns >= k are 0),
+ * pivots (r int64 in acceptance order, entries >= k set to -1), rho (N
+ * doubles: the final residual diagonal diag(K - F F^T), clamped >= 0, zero at
+ * pivots), k_out (device int32: accepted pivot count).  The relative trace
+ * error of the approximation is sum(rho) / N. */
+int rpchol_factor_workspace_size(const rpc_points* X, const rpc_factor_opts* opts, size_t* bytes);
+int rpchol_factor(const rpc_points* X, const rpc_factor_opts* opts, void* F, int64_t ldf,
+                  int64_t* pivots, double* rho, int32_t* k_out, void* workspace,
+                  size_t workspace_bytes, int32_t* dev_status, rpc_stream_t stream);
+
+/* ---- Algorithm 1: normalisation vectors -------------------------------
+ * c = F^T 1 (r doubles), d~ = F c (N doubles, asserted > 0, RPC_EDEGREE),
+ * w = F^T (1/d~), q~ = F w (N doubles, asserted > 0, RPC_EQDEGREE).  Only the
+ * first *k columns of F are read. */
+int bistoch_degrees_workspace_size(int64_t N, int32_t r, size_t* bytes);
+int bistoch_degrees(const void* F, int32_t f_dtype, int64_t N, int64_t ldf, int32_t r,
+                    const int32_t* k, double* c, double* d_tilde, double* q_tilde,
+                    void* workspace, size_t workspace_bytes, int32_t* dev_status,
+                    rpc_stream_t stream);
+
+/* ---- Algorithm 1: factored EVD ----------------------------------------
+ * With B = D~^{-1} F (+ gamma on its leading diagonal) and C = F^T Q~^{-1} F:
+ * G_B = B^T B = R^T R (Cholesky QR, R upper triangular with positive
+ * diagonal, so Q = B R^{-1} is never formed), M = R C R^T, M = V Lambda V^T,
+ * U = B R^{-1} V(:, :nev).  Outputs: U (N x nev, column-major, u_dtype;
+ * each column signed so its largest-magnitude entry, lowest index on ties,
+ * is positive), lambda (nev doubles, decreasing), ext_E (r x nev doubles,
+ * column-major: E = C R^T V Lambda^{-1} with rows >= k zero), which
+ * nystrom_extend consumes. */
+int bistoch_eig_workspace_size(int64_t N, int32_t r, const rpc_eig_opts* opts, size_t* bytes);
+int bistoch_eig(const void* F, int32_t f_dtype, int64_t N, int64_t ldf, int32_t r,
+                const int32_t* k, const double* c, const double* d_tilde, const double* q_tilde,
+                const rpc_eig_opts* opts, void* U, int64_t ldu, double* lambda, double* ext_E,
+                void* workspace, size_t workspace_bytes, int32_t* dev_status, rpc_stream_t stream);
+
+/* ---- Nystrom extension to new points ----------------------------------
+ * For each row y of Y (M x d float32, row-major, same d and eps as X):
+ * f(y) = F(S, :)^{-1} k(X_S, y) with S the accepted pivots (F(S, :) is lower
+ * triangular in pivot order), d~(y) = c^T f(y), and
+ * Phi(y, :) = f(y)^T E / d~(y).  At a training point this reproduces the row
+ * of U.  Phi is column-major M x nev float64. */
+int nystrom_extend_workspace_size(int64_t M, int64_t d, int32_t r, int32_t nev, size_t* bytes);
+int nystrom_extend(const rpc_points* Y, const rpc_points* X, const int64_t* pivots,
+                   const int32_t* k, const void* F, int32_t f_dtype, int64_t ldf, int32_t r,
+                   const double* c, const double* ext_E, int32_t nev, double* Phi, int64_t ldphi,
+                   void* workspace, size_t workspace_bytes, int32_t* dev_status,
+                   rpc_stream_t stream);
+
+/* ---- Per-kernel timing (diagnostics for benchmarking) ------------------
+ * When enabled, the library brackets each launch of its main kernel classes
+ * with HIP events on the launching stream.  rpc_profile_read synchronises on
+ * the recorded events and returns, for one class, the summed duration in ms
+ * and the number of launches since the last reset.  Classes: 0 kernel
+ * columns, 1 Schur update, 2 triangular solve + downdate, 3 pivot draw,
+ * 4 pivot block + accept/reject, 5 degrees, 6 Gram products, 7 r x r work,
+ * 8 eigenvector formation, 9 Nystrom extension.  Process-global state, not
+ * thread-safe; returns RPC_EWORKSPACE if the event pool overflowed. */
+int rpc_profile_enable(int on);
+int rpc_profile_reset(void);
+int rpc_profile_read(int32_t kind, double* total_ms, int64_t* launches);
+
+/* Synchronise `stream` and return the device status word (or RPC_EHIP). */
+int rpc_status_sync(const int32_t* dev_status, rpc_stream_t stream);
+
+/* Library version string. */
+const char* rpc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RPCHOL_H_ */

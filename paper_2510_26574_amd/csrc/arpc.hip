@@ -1,0 +1,785 @@
+// rpchol_factor: accelerated randomly pivoted partial Cholesky (the paper's
+// Algorithm 2, with the accept/reject check of Algorithm 3) on the Gaussian
+// kernel k(x, y) = exp(-|x - y|^2 / eps), for gfx950.
+//
+// One round i, all on the device and without host synchronisation:
+//   pivot draw      b proposals from rho / sum(rho) through an integer CDF
+//                   (rho_q = floor(rho 2^40), exact and summation-order free),
+//                   or argmax rho in greedy mode, or the replay list;
+//   gather          proposal rows of the points and of F;
+//   pivot block     H = K(S', S') - F(S', :) F(S', :)^T in float64;
+//   accept/reject   Algorithm 3 on H in one workgroup (H resident in LDS),
+//                   giving the accepted set T, L = chol block and L^{-1};
+//   kernel columns  W = K(:, S_i): MFMA distance product
+//                   |x|^2 + |s|^2 - 2 <x, s> with an exp epilogue;
+//   Schur update    W -= F(:, :k) F(S_i, :k)^T (MFMA);
+//   solve+downdate  G = W L^{-T} (float64 MFMA), F(:, k:k+|T|) = G,
+//                   rho = max(rho - rownorms(G)^2, 0);
+//   round end       rho(S_i) = 0, k += |T|.
+#include <math.h>
+
+#include <type_traits>
+
+#include "common.hpp"
+#include "profile.hpp"
+#include "tile_gemm.hpp"
+
+namespace {
+
+constexpr int CHUNK = 4096;  // rho entries per partial sum (pivot draw)
+constexpr int MAXB = 128;    // largest supported block size
+constexpr double QSCALE = 1099511627776.0;  // 2^40
+
+__device__ inline unsigned long long quant_rho(double r) {
+  return r > 0.0 ? (unsigned long long)floor(r * QSCALE) : 0ull;
+}
+
+struct RoundState {
+  int32_t* k;      // accepted pivots so far (the caller's k_out)
+  int32_t* nT;     // accepted in this round
+  int32_t* stop;   // nonzero once the residual is exhausted
+};
+
+// ------------------------------------------------------------ preparation
+// Xp[n][:] = points converted to the product type, zero-padded to dp columns;
+// xn[n] = squared norm of the converted row (computed in float64, stored in
+// the epilogue type).  Also initialises rho = 1 (diag of the Gaussian kernel),
+// pivots = -1 and the counters.
+template <typename T, typename TN>
+__global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, int64_t N, int64_t d,
+                                              int64_t ldx, int64_t dp, T* __restrict__ Xp,
+                                              TN* __restrict__ xn, double* __restrict__ rho,
+                                              int32_t* status) {
+  const int lane = threadIdx.x & 63;
+  const int64_t n = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (n >= N) return;
+  double s = 0.0;
+  bool bad = false;
+  for (int64_t j = lane; j < dp; j += 64) {
+    float v = j < d ? X[n * ldx + j] : 0.0f;
+    if (!isfinite(v)) bad = true;
+    T c = cvt<T>(v);
+    Xp[n * dp + j] = c;
+    double cd = to_d(c);
+    s += cd * cd;
+  }
+  s = wave_sum(s);
+  if (__any(bad) && lane == 0) set_status(status, RPC_ENONFINITE);
+  if (lane == 0) {
+    xn[n] = (TN)s;
+    rho[n] = 1.0;
+  }
+}
+
+__global__ void k_init_small(int64_t* pivots, int r, int32_t* k, int32_t* nT, int32_t* stop) {
+  for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < r; i += blockDim.x * gridDim.x) pivots[i] = -1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *k = 0;
+    *nT = 0;
+    *stop = 0;
+  }
+}
+
+// ------------------------------------------------------------ pivot draw
+__global__ __launch_bounds__(256) void k_rho_partial(const double* __restrict__ rho, int64_t N,
+                                                     unsigned long long* __restrict__ part,
+                                                     const int32_t* stop) {
+  if (*stop) return;
+  __shared__ unsigned long long ws[4];
+  const int64_t base = (int64_t)blockIdx.x * CHUNK;
+  unsigned long long s = 0;
+  for (int e = threadIdx.x; e < CHUNK; e += 256) {
+    int64_t i = base + e;
+    if (i < N) s += quant_rho(rho[i]);
+  }
+  s = wave_sum_u64(s);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// One workgroup: inclusive scan of the partial sums, then one wave per
+// proposal resolves  s = min{ j : C_j > floor(m T / 2^53) }.
+__global__ __launch_bounds__(1024) void k_draw(const double* __restrict__ rho, int64_t N,
+                                               unsigned long long* __restrict__ part, int nb,
+                                               const double* __restrict__ u, int bi,
+                                               int64_t* __restrict__ prop, int32_t* stop) {
+  if (*stop) return;
+  __shared__ unsigned long long tsum[1024];
+  __shared__ unsigned long long total;
+  const int tid = threadIdx.x;
+  // each thread owns a contiguous run of partial sums
+  const int per = (nb + 1023) / 1024;
+  const int b0 = tid * per;
+  unsigned long long loc = 0;
+  for (int j = 0; j < per; ++j)
+    if (b0 + j < nb) loc += part[b0 + j];
+  tsum[tid] = loc;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    unsigned long long v = tid >= off ? tsum[tid - off] : 0ull;
+    __syncthreads();
+    tsum[tid] += v;
+    __syncthreads();
+  }
+  // write inclusive prefix of the partial sums back in place
+  unsigned long long run = tid > 0 ? tsum[tid - 1] : 0ull;
+  for (int j = 0; j < per; ++j)
+    if (b0 + j < nb) {
+      run += part[b0 + j];
+      part[b0 + j] = run;
+    }
+  if (tid == 1023) total = tsum[1023];
+  __syncthreads();
+  const unsigned long long T = total;
+  if (T == 0ull) {
+    if (tid == 0) *stop = 1;
+    return;
+  }
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int j = wave; j < bi; j += 16) {
+    const unsigned long long m = (unsigned long long)(u[j] * 9007199254740992.0);  // u * 2^53
+    const unsigned long long hi = __umul64hi(m, T), lo = m * T;
+    const unsigned long long target = (hi << 11) | (lo >> 53);
+    // first block whose inclusive prefix exceeds the target
+    int lo_b = 0, hi_b = nb - 1;
+    while (lo_b < hi_b) {
+      int mid = (lo_b + hi_b) >> 1;
+      if (part[mid] > target) hi_b = mid; else lo_b = mid + 1;
+    }
+    const int blk = lo_b;
+    unsigned long long carry = blk > 0 ? part[blk - 1] : 0ull;
+    int64_t found = -1;
+    for (int c = 0; c < CHUNK / 64 && found < 0; ++c) {
+      const int64_t i = (int64_t)blk * CHUNK + c * 64 + lane;
+      unsigned long long q = i < N ? quant_rho(rho[i]) : 0ull;
+      // inclusive wave scan
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        unsigned long long t = __shfl_up(q, o, 64);
+        if (lane >= o) q += t;
+      }
+      const unsigned long long incl = carry + q;
+      const unsigned long long mask = __ballot(incl > target);
+      if (mask) {
+        found = (int64_t)blk * CHUNK + c * 64 + __ffsll((long long)mask) - 1;
+      } else {
+        carry = __shfl(incl, 63, 64);
+      }
+    }
+    if (lane == 0) prop[j] = found;
+  }
+}
+
+// Greedy: argmax rho, lowest index on ties.
+__global__ __launch_bounds__(256) void k_argmax_partial(const double* __restrict__ rho, int64_t N,
+                                                        double* __restrict__ pv,
+                                                        int64_t* __restrict__ pi,
+                                                        const int32_t* stop) {
+  if (*stop) return;
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  const int64_t base = (int64_t)blockIdx.x * CHUNK;
+  double bv = -1.0;
+  int64_t bix = -1;
+  for (int e = threadIdx.x; e < CHUNK; e += 256) {
+    int64_t i = base + e;
+    if (i < N) {
+      double v = rho[i];
+      if (v > bv) { bv = v; bix = i; }
+    }
+  }
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bix;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      double v2 = sv[threadIdx.x + off];
+      int64_t i2 = si[threadIdx.x + off];
+      double v1 = sv[threadIdx.x];
+      int64_t i1 = si[threadIdx.x];
+      if (v2 > v1 || (v2 == v1 && i2 >= 0 && (i1 < 0 || i2 < i1))) {
+        sv[threadIdx.x] = v2;
+        si[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    pv[blockIdx.x] = sv[0];
+    pi[blockIdx.x] = si[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_argmax_final(const double* __restrict__ pv,
+                                                      const int64_t* __restrict__ pi, int nb,
+                                                      int64_t* __restrict__ prop, int32_t* stop) {
+  if (*stop) return;
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  double bv = -1.0;
+  int64_t bix = -1;
+  for (int e = threadIdx.x; e < nb; e += 256) {
+    double v = pv[e];
+    int64_t i = pi[e];
+    if (i >= 0 && (v > bv || (v == bv && (bix < 0 || i < bix)))) { bv = v; bix = i; }
+  }
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bix;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      double v2 = sv[threadIdx.x + off];
+      int64_t i2 = si[threadIdx.x + off];
+      double v1 = sv[threadIdx.x];
+      int64_t i1 = si[threadIdx.x];
+      if (i2 >= 0 && (i1 < 0 || v2 > v1 || (v2 == v1 && i2 < i1))) {
+        sv[threadIdx.x] = v2;
+        si[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (!(sv[0] > 0.0) || si[0] < 0) {
+      *stop = 1;
+    } else {
+      prop[0] = si[0];
+    }
+  }
+}
+
+__global__ void k_replay_props(const int64_t* __restrict__ replay, int64_t off, int bi, int64_t N,
+                               int64_t* __restrict__ prop, int32_t* status, int32_t* stop) {
+  int j = threadIdx.x;
+  if (j < bi) {
+    int64_t s = replay[off + j];
+    if (s < 0 || s >= N) {
+      set_status(status, RPC_EINVAL);
+      *stop = 1;
+      s = 0;
+    }
+    prop[j] = s;
+  }
+}
+
+// ------------------------------------------------------------ gather
+// XS[j][:] = Xp[prop[j]][:], ns[j] = xn[prop[j]], FS[j][l] = F[prop[j] + l ldf] (l < k).
+template <typename T, typename TN, typename TF>
+__global__ __launch_bounds__(256) void k_gather(const T* __restrict__ Xp, const TN* __restrict__ xn,
+                                                int64_t dp, const TF* __restrict__ F, int64_t ldf,
+                                                int r, const int64_t* __restrict__ prop, int bi,
+                                                const int32_t* kptr, const int32_t* stop,
+                                                T* __restrict__ XS, TN* __restrict__ ns,
+                                                TF* __restrict__ FS, int64_t N, int32_t* status) {
+  if (*stop) return;
+  const int j = blockIdx.x;
+  if (j >= bi) return;
+  int64_t s = prop[j];
+  if (s < 0 || s >= N) {  // cannot happen with a consistent CDF; keep accesses in bounds
+    if (threadIdx.x == 0) set_status(status, RPC_EHIP);
+    s = 0;
+  }
+  const int k = *kptr;
+  for (int64_t c = threadIdx.x; c < dp; c += 256) XS[j * dp + c] = Xp[s * dp + c];
+  for (int l = threadIdx.x; l < k; l += 256) FS[(int64_t)j * r + l] = F[s + (int64_t)l * ldf];
+  if (threadIdx.x == 0) ns[j] = xn[s];
+}
+
+// H[i][j] = exp(-sum_l (x_i - x_j)^2 / eps) - sum_l FS[i][l] FS[j][l], float64.
+// Grid (ceil(bi/16), ceil(bi/16)); thread (ty, tx) owns pair (i0 + ty, j0 + tx).
+template <typename T, typename TF>
+__global__ __launch_bounds__(256) void k_pivot_block(const T* __restrict__ XS, int64_t dp,
+                                                     const TF* __restrict__ FS, int r, int bi,
+                                                     const int32_t* kptr, const int32_t* stop,
+                                                     double eps, int ldh, double* __restrict__ H) {
+  if (*stop) return;
+  __shared__ double si_[16][65];
+  __shared__ double sj_[16][65];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+  const int i = i0 + ty, j = j0 + tx;
+  const int k = *kptr;
+  double d2 = 0.0, ff = 0.0;
+  for (int64_t c0 = 0; c0 < dp; c0 += 64) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      int rr = e / 64, cc = e % 64;
+      int64_t c = c0 + cc;
+      si_[rr][cc] = (i0 + rr < bi && c < dp) ? to_d(XS[(int64_t)(i0 + rr) * dp + c]) : 0.0;
+      sj_[rr][cc] = (j0 + rr < bi && c < dp) ? to_d(XS[(int64_t)(j0 + rr) * dp + c]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int cc = 0; cc < 64; ++cc) {
+      double t = si_[ty][cc] - sj_[tx][cc];
+      d2 += t * t;
+    }
+    __syncthreads();
+  }
+  for (int l0 = 0; l0 < k; l0 += 64) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      int rr = e / 64, cc = e % 64;
+      int l = l0 + cc;
+      si_[rr][cc] = (i0 + rr < bi && l < k) ? to_d(FS[(int64_t)(i0 + rr) * r + l]) : 0.0;
+      sj_[rr][cc] = (j0 + rr < bi && l < k) ? to_d(FS[(int64_t)(j0 + rr) * r + l]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int cc = 0; cc < 64; ++cc) ff += si_[ty][cc] * sj_[tx][cc];
+    __syncthreads();
+  }
+  if (i < bi && j < bi) H[i * ldh + j] = exp(-d2 / eps) - ff;
+}
+
+// ------------------------------------------------------------ Algorithm 3
+// One workgroup of 1024 threads; H (bi x bi, stride MAXB) lives in LDS.
+// Outputs the accepted positions, the accepted pivots (appended to `pivots`),
+// L^{-1} of the accepted block (row-major MAXB x MAXB, zero-padded), and the
+// accepted rows XSa / nsa / FSa that the column kernels consume.
+template <typename T, typename TN, typename TF>
+__global__ __launch_bounds__(1024) void k_accept_reject(
+    const double* __restrict__ Hg, int bi, const int64_t* __restrict__ prop,
+    const double* __restrict__ z, double tau, int mode, const T* __restrict__ XS, int64_t dp,
+    const TN* __restrict__ ns, const TF* __restrict__ FS, int r, int32_t* kptr, int32_t* nTptr,
+    const int32_t* stop, int64_t* __restrict__ pivots, double* __restrict__ Linv,
+    int64_t* __restrict__ Si, T* __restrict__ XSa, TN* __restrict__ nsa, TF* __restrict__ FSa,
+    int32_t* status) {
+  __shared__ double H[MAXB * MAXB];
+  __shared__ int accl[MAXB];
+  __shared__ double rho_loc[MAXB];
+  __shared__ int nacc;
+  __shared__ int decide;
+  const int tid = threadIdx.x;
+  if (*stop) {
+    if (tid == 0) *nTptr = 0;
+    return;
+  }
+  const int k = *kptr;
+  for (int e = tid; e < bi * bi; e += 1024) {
+    int a = e / bi, c = e % bi;
+    H[a * MAXB + c] = Hg[a * MAXB + c];
+  }
+  if (tid == 0) nacc = 0;
+  __syncthreads();
+  if (tid < bi) rho_loc[tid] = H[tid * MAXB + tid];
+  __syncthreads();
+  for (int i = 0; i < bi; ++i) {
+    if (tid < 64) {
+      // reject a repeat of an accepted proposal of this block
+      const int64_t pi = prop[i];
+      bool dup = false;
+      for (int a = tid; a < nacc; a += 64) dup |= (prop[accl[a]] == pi);
+      dup = __any(dup);
+      if (tid == 0) {
+        const double hii = H[i * MAXB + i];
+        bool ok;
+        if (mode == RPC_REPLAY) {
+          ok = hii > tau && !dup;
+          if (!ok) set_status(status, RPC_EBREAKDOWN);
+        } else if (mode == RPC_GREEDY) {
+          ok = hii > tau;  // b = 1: z * H(0,0) < H(0,0) holds for every z in [0, 1)
+        } else {
+          ok = !dup && hii > tau && z[i] * rho_loc[i] < hii;
+        }
+        decide = ok ? 1 : 0;
+        if (ok) accl[nacc++] = i;
+      }
+    }
+    __syncthreads();
+    if (decide) {
+      const double hii = H[i * MAXB + i];
+      const int m = bi - i - 1;
+      for (int e = tid; e < m * m; e += 1024) {
+        const int a = i + 1 + e / m, c = i + 1 + e % m;
+        H[a * MAXB + c] -= H[a * MAXB + i] * H[c * MAXB + i] / hii;
+      }
+      __syncthreads();
+      const double piv = sqrt(hii);
+      for (int a = i + tid; a < bi; a += 1024) H[a * MAXB + i] /= piv;
+    }
+    __syncthreads();
+  }
+  const int nt = nacc;
+  // L(T, T)^{-1}, one thread per column (forward substitution)
+  if (tid < nt) {
+    const int c = tid;
+    // column c of L^{-1}: x_c = 1 / L_cc; x_j = -(sum_{l=c}^{j-1} L_jl x_l) / L_jj
+    for (int j = 0; j < MAXB; ++j) Linv[j * MAXB + c] = 0.0;
+    const int ac = accl[c];
+    double xc = 1.0 / H[ac * MAXB + ac];
+    Linv[c * MAXB + c] = xc;
+    for (int j = c + 1; j < nt; ++j) {
+      const int aj = accl[j];
+      double s = 0.0;
+      for (int l = c; l < j; ++l) s += H[aj * MAXB + accl[l]] * Linv[l * MAXB + c];
+      Linv[j * MAXB + c] = -s / H[aj * MAXB + aj];
+    }
+  } else if (tid < MAXB) {
+    for (int j = 0; j < MAXB; ++j) Linv[j * MAXB + tid] = 0.0;
+  }
+  // accepted rows for the column kernels
+  for (int e = tid; e < nt * dp; e += 1024) {
+    int a = e / dp;
+    int64_t c = e % dp;
+    XSa[a * dp + c] = XS[(int64_t)accl[a] * dp + c];
+  }
+  for (int e = tid; e < nt * k; e += 1024) {
+    int a = e / k, l = e % k;
+    FSa[(int64_t)a * r + l] = FS[(int64_t)accl[a] * r + l];
+  }
+  if (tid < nt) {
+    nsa[tid] = ns[accl[tid]];
+    Si[tid] = prop[accl[tid]];
+    pivots[k + tid] = prop[accl[tid]];
+  }
+  if (tid == 0) *nTptr = nt;
+}
+
+// ------------------------------------------------------------ kernel columns
+// W[n][j] = exp(-max(0, xn[n] + nsa[j] - 2 <Xp[n], XSa[j]>) / eps), j < nT.
+template <typename T, typename TN, typename TW, class Cfg>
+__global__ __launch_bounds__(Cfg::NT) void k_kernel_cols(const T* __restrict__ Xp,
+                                                         const TN* __restrict__ xn, int64_t N,
+                                                         int64_t dp, const T* __restrict__ XSa,
+                                                         const TN* __restrict__ nsa,
+                                                         const int32_t* nTptr, double eps,
+                                                         TW* __restrict__ W, int64_t ldw) {
+  const int nt = *nTptr;
+  const int64_t n0 = (int64_t)blockIdx.y * Cfg::BN;
+  if (n0 >= nt) return;
+  extern __shared__ char smem_raw[];
+  typename Cfg::T* smem = reinterpret_cast<typename Cfg::T*>(smem_raw);
+  const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM;
+  GOperand<T, true> A{Xp, dp, N, dp, nullptr, true};
+  GOperand<T, true> B{XSa, dp, nt, dp, nullptr, true};
+  TileAcc<Cfg> acc;
+  acc.zero();
+  tile_mainloop<Cfg>(acc, A, B, m0, n0, 0, dp, smem);
+  typedef typename Cfg::MM::acc_t AT;
+  const AT ie = (AT)(1.0 / eps);
+  for_each_acc<Cfg>(acc, [&](int row, int col, AT v) {
+    const int64_t m = m0 + row, n = n0 + col;
+    if (m < N && n < nt) {
+      AT d2 = (AT)xn[m] + (AT)nsa[n] - (AT)2 * v;
+      d2 = d2 > (AT)0 ? d2 : (AT)0;
+      W[m + n * ldw] = (TW)exp(-d2 * ie);
+    }
+  });
+}
+
+// ------------------------------------------------------------ Schur update
+// W[:, j] -= F(:, :k) FSa[j][:k]^T, j < nT.
+template <typename TF, class Cfg>
+__global__ __launch_bounds__(Cfg::NT) void k_schur(const TF* __restrict__ F, int64_t ldf,
+                                                   int64_t N, const TF* __restrict__ FSa, int r,
+                                                   const int32_t* kptr, const int32_t* nTptr,
+                                                   TF* __restrict__ W, int64_t ldw) {
+  const int nt = *nTptr;
+  const int k = *kptr;
+  const int64_t n0 = (int64_t)blockIdx.y * Cfg::BN;
+  if (n0 >= nt || k == 0) return;
+  extern __shared__ char smem_raw[];
+  typename Cfg::T* smem = reinterpret_cast<typename Cfg::T*>(smem_raw);
+  const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM;
+  GOperand<TF, false> A{F, ldf, N, k, nullptr, true};
+  GOperand<TF, true> B{FSa, r, nt, k, nullptr, (r % (16 / (int)sizeof(TF))) == 0};
+  TileAcc<Cfg> acc;
+  acc.zero();
+  tile_mainloop<Cfg>(acc, A, B, m0, n0, 0, k, smem);
+  for_each_acc<Cfg>(acc, [&](int row, int col, typename Cfg::MM::acc_t v) {
+    const int64_t m = m0 + row, n = n0 + col;
+    if (m < N && n < nt) W[m + n * ldw] -= (TF)v;
+  });
+}
+
+// ------------------------------------------------------------ solve + downdate
+// G = W L^{-T} in float64 (four waves stacked along rows, each holding full
+// rows), F(:, k + j) = G(:, j), rho = max(rho - sum_j G^2, 0).
+template <typename TF>
+__global__ __launch_bounds__(256) void k_solve_downdate(const TF* __restrict__ W, int64_t ldw,
+                                                        int64_t N, const double* __restrict__ Linv,
+                                                        const int32_t* kptr, const int32_t* nTptr,
+                                                        TF* __restrict__ F, int64_t ldf,
+                                                        double* __restrict__ rho) {
+  typedef TileCfg<double, 128, 128, 16, 4, 1> Cfg;
+  const int nt = *nTptr;
+  if (nt == 0) return;
+  const int k = *kptr;
+  extern __shared__ char smem_raw[];
+  double* smem = reinterpret_cast<double*>(smem_raw);
+  const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM;
+  GOperand<TF, false> A{W, ldw, N, nt, nullptr, true};
+  GOperand<double, true> B{Linv, MAXB, nt, nt, nullptr, true};
+  TileAcc<Cfg> acc;
+  acc.zero();
+  tile_mainloop<Cfg>(acc, A, B, m0, 0, 0, nt, smem);
+  // each lane holds 4 rows x (NI columns); sum squares over its columns, then
+  // across the 16 lanes that share those rows (fixed order: deterministic)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < Cfg::NI; ++j)
+#pragma unroll
+    for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = wave * Cfg::WTM + i * 16 + Cfg::MM::row(lane, e);
+        const int col = j * 16 + (lane & 15);
+        const int64_t m = m0 + row;
+        const double g = acc.a[i][j][e];
+        if (m < N && col < nt) F[m + (int64_t)(k + col) * ldf] = (TF)g;
+      }
+  // row sums: MI x 4 rows per lane
+#pragma unroll
+  for (int i = 0; i < Cfg::MI; ++i) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < Cfg::NI; ++j) {
+        const int col = j * 16 + (lane & 15);
+        const double g = col < nt ? acc.a[i][j][e] : 0.0;
+        s += g * g;
+      }
+      // reduce over the 16 lanes with the same (lane >> 4)
+      s += __shfl_xor(s, 1, 64);
+      s += __shfl_xor(s, 2, 64);
+      s += __shfl_xor(s, 4, 64);
+      s += __shfl_xor(s, 8, 64);
+      const int row = wave * Cfg::WTM + i * 16 + Cfg::MM::row(lane, e);
+      const int64_t m = m0 + row;
+      if ((lane & 15) == 0 && m < N) {
+        double v = rho[m] - s;
+        rho[m] = v > 0.0 ? v : 0.0;
+      }
+    }
+  }
+}
+
+__global__ void k_round_end(const int64_t* __restrict__ Si, int32_t* kptr, const int32_t* nTptr,
+                            double* __restrict__ rho, int32_t* round_acc, int round) {
+  const int nt = *nTptr;
+  for (int j = threadIdx.x; j < nt; j += blockDim.x) rho[Si[j]] = 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *kptr += nt;
+    if (round_acc) round_acc[round] = nt;
+  }
+}
+
+// Zero F columns k .. r-1 (unused budget).
+template <typename TF>
+__global__ __launch_bounds__(256) void k_zero_tail(TF* __restrict__ F, int64_t ldf, int64_t N, int r,
+                                                   const int32_t* kptr) {
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  const int k = *kptr;
+  for (int c = k; c < r; ++c) F[n + (int64_t)c * ldf] = (TF)0;
+}
+
+// ------------------------------------------------------------ host driver
+struct FactorWs {
+  void* Xp;
+  void* xn;
+  void* W;
+  unsigned long long* part;
+  double* pv;
+  int64_t* pi;
+  int64_t* prop;
+  void* XS;
+  void* ns;
+  void* FS;
+  double* H;
+  double* Linv;
+  int64_t* Si;
+  void* XSa;
+  void* nsa;
+  void* FSa;
+  int32_t* nT;
+  int32_t* stop;
+  int64_t ldw;
+  int64_t dp;
+};
+
+template <typename T, typename TN, typename TF>
+static size_t carve(WsCursor& c, FactorWs& w, int64_t N, int64_t d, int r) {
+  w.dp = (int64_t)align_up((size_t)d, 32);
+  w.ldw = (int64_t)align_up((size_t)N, 8);
+  const int nb = (int)((N + CHUNK - 1) / CHUNK);
+  w.Xp = c.take<T>((size_t)N * w.dp);
+  w.xn = c.take<TN>((size_t)N);
+  w.W = c.take<TF>((size_t)w.ldw * MAXB);
+  w.part = c.take<unsigned long long>((size_t)nb);
+  w.pv = c.take<double>((size_t)nb);
+  w.pi = c.take<int64_t>((size_t)nb);
+  w.prop = c.take<int64_t>(MAXB);
+  w.XS = c.take<T>((size_t)MAXB * w.dp);
+  w.ns = c.take<TN>(MAXB);
+  w.FS = c.take<TF>((size_t)MAXB * r);
+  w.H = c.take<double>((size_t)MAXB * MAXB);
+  w.Linv = c.take<double>((size_t)MAXB * MAXB);
+  w.Si = c.take<int64_t>(MAXB);
+  w.XSa = c.take<T>((size_t)MAXB * w.dp);
+  w.nsa = c.take<TN>(MAXB);
+  w.FSa = c.take<TF>((size_t)MAXB * r);
+  w.nT = c.take<int32_t>(1);
+  w.stop = c.take<int32_t>(1);
+  return c.used;
+}
+
+template <typename T, typename TN, typename TF>
+static int run_factor(const rpc_points* X, const rpc_factor_opts* o, TF* F, int64_t ldf,
+                      int64_t* pivots, double* rho, int32_t* k_out, void* ws, size_t ws_bytes,
+                      int32_t* status, hipStream_t st) {
+  WsCursor cur{(char*)ws, 0, ws_bytes, true};
+  FactorWs w;
+  carve<T, TN, TF>(cur, w, X->N, X->d, o->r);
+  if (!cur.ok) return RPC_EWORKSPACE;
+  const int64_t N = X->N;
+  const int r = o->r, b = o->b;
+  const int nb = (int)((N + CHUNK - 1) / CHUNK);
+  const int64_t dp = w.dp;
+
+  hipLaunchKernelGGL((k_prep<T, TN>), dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, X->X, N,
+                     X->d, X->ldx, dp, (T*)w.Xp, (TN*)w.xn, rho, status);
+  RPC_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_init_small, dim3(1), dim3(256), 0, st, pivots, r, k_out, w.nT, w.stop);
+  RPC_LAUNCH_CHECK();
+
+  typedef TileCfg<T, 128, 128, (sizeof(T) == 2 ? 64 : 16), 2, 2> CfgK;
+  typedef TileCfg<TF, 128, 128, 16, 2, 2> CfgS;
+  typedef TileCfg<double, 128, 128, 16, 4, 1> CfgD;
+  const unsigned gm = (unsigned)((N + 127) / 128);
+
+  int t;
+  if (o->mode == RPC_REPLAY)
+    t = (int)((o->n_replay + b - 1) / b);
+  else
+    t = (r + b - 1) / b;
+  for (int i = 0; i < t; ++i) {
+    int bi;
+    if (o->mode == RPC_REPLAY)
+      bi = (int)(o->n_replay - (int64_t)i * b < b ? o->n_replay - (int64_t)i * b : b);
+    else
+      bi = r - i * b < b ? r - i * b : b;
+    const double* z = nullptr;
+    prof::begin(prof::PIVOT, st);
+    if (o->mode == RPC_SAMPLED) {
+      hipLaunchKernelGGL(k_rho_partial, dim3(nb), dim3(256), 0, st, rho, N, w.part, w.stop);
+      hipLaunchKernelGGL(k_draw, dim3(1), dim3(1024), 0, st, rho, N, w.part, nb,
+                         o->uniforms + (int64_t)2 * b * i, bi, w.prop, w.stop);
+      z = o->uniforms + (int64_t)2 * b * i + b;
+    } else if (o->mode == RPC_GREEDY) {
+      hipLaunchKernelGGL(k_argmax_partial, dim3(nb), dim3(256), 0, st, rho, N, w.pv, w.pi, w.stop);
+      hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(256), 0, st, w.pv, w.pi, nb, w.prop, w.stop);
+      z = nullptr;
+    } else {
+      hipLaunchKernelGGL(k_replay_props, dim3(1), dim3(MAXB), 0, st, o->replay, (int64_t)i * b, bi,
+                         N, w.prop, status, w.stop);
+    }
+    prof::end(prof::PIVOT, st);
+    RPC_LAUNCH_CHECK();
+    prof::begin(prof::ACCEPT, st);
+    hipLaunchKernelGGL((k_gather<T, TN, TF>), dim3(bi), dim3(256), 0, st, (const T*)w.Xp,
+                       (const TN*)w.xn, dp, (const TF*)F, ldf, r, w.prop, bi, k_out, w.stop,
+                       (T*)w.XS, (TN*)w.ns, (TF*)w.FS, N, status);
+    const unsigned hb = (unsigned)((bi + 15) / 16);
+    hipLaunchKernelGGL((k_pivot_block<T, TF>), dim3(hb, hb), dim3(256), 0, st, (const T*)w.XS, dp,
+                       (const TF*)w.FS, r, bi, k_out, w.stop, X->eps, MAXB, w.H);
+    RPC_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_accept_reject<T, TN, TF>), dim3(1), dim3(1024), 0, st, w.H, bi, w.prop,
+                       z, o->tau, o->mode, (const T*)w.XS, dp, (const TN*)w.ns,
+                       (const TF*)w.FS, r, k_out, w.nT, w.stop, pivots, w.Linv, w.Si, (T*)w.XSa,
+                       (TN*)w.nsa, (TF*)w.FSa, status);
+    prof::end(prof::ACCEPT, st);
+    RPC_LAUNCH_CHECK();
+    prof::begin(prof::KERNEL_COLS, st);
+    hipLaunchKernelGGL((k_kernel_cols<T, TN, TF, CfgK>), dim3(gm, 1), dim3(CfgK::NT),
+                       CfgK::smem_bytes, st, (const T*)w.Xp, (const TN*)w.xn, N, dp,
+                       (const T*)w.XSa, (const TN*)w.nsa, w.nT, X->eps, (TF*)w.W, w.ldw);
+    prof::end(prof::KERNEL_COLS, st);
+    RPC_LAUNCH_CHECK();
+    prof::begin(prof::SCHUR, st);
+    hipLaunchKernelGGL((k_schur<TF, CfgS>), dim3(gm, 1), dim3(CfgS::NT), CfgS::smem_bytes, st,
+                       (const TF*)F, ldf, N, (const TF*)w.FSa, r, k_out, w.nT, (TF*)w.W, w.ldw);
+    prof::end(prof::SCHUR, st);
+    RPC_LAUNCH_CHECK();
+    prof::begin(prof::SOLVE, st);
+    hipLaunchKernelGGL((k_solve_downdate<TF>), dim3(gm), dim3(256), CfgD::smem_bytes, st,
+                       (const TF*)w.W, w.ldw, N, w.Linv, k_out, w.nT, F, ldf, rho);
+    RPC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(MAXB), 0, st, w.Si, k_out, w.nT, rho,
+                       o->round_accepted, i);
+    prof::end(prof::SOLVE, st);
+    RPC_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL((k_zero_tail<TF>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, F, ldf,
+                     N, r, k_out);
+  RPC_LAUNCH_CHECK();
+  return RPC_OK;
+}
+
+static int check_factor_args(const rpc_points* X, const rpc_factor_opts* o) {
+  if (!X || !o || !X->X) return RPC_EINVAL;
+  if (X->N < 1 || X->d < 1 || X->ldx < X->d || !(X->eps > 0.0)) return RPC_EINVAL;
+  if (o->r < 1 || o->r > X->N || o->b < 1 || o->b > MAXB) return RPC_EINVAL;
+  if (o->mode == RPC_GREEDY && o->b != 1) return RPC_EINVAL;
+  if (o->mode != RPC_SAMPLED && o->mode != RPC_GREEDY && o->mode != RPC_REPLAY) return RPC_EINVAL;
+  if (o->gemm_dtype != RPC_F64 && o->gemm_dtype != RPC_F32 && o->gemm_dtype != RPC_BF16)
+    return RPC_EINVAL;
+  if (o->factor_dtype != RPC_F64 && o->factor_dtype != RPC_F32) return RPC_EINVAL;
+  if (o->gemm_dtype == RPC_F64 && o->factor_dtype != RPC_F64) return RPC_EINVAL;
+  if (o->mode == RPC_SAMPLED) {
+    const int64_t t = (o->r + o->b - 1) / o->b;
+    if (!o->uniforms || o->n_uniforms < 2 * (int64_t)o->b * t) return RPC_EINVAL;
+  }
+  if (o->mode == RPC_REPLAY) {
+    if (!o->replay || o->n_replay < 1 || o->n_replay > o->r) return RPC_EINVAL;
+  }
+  if (!(o->tau >= 0.0)) return RPC_EINVAL;
+  if (X->N > (int64_t)1 << 23) return RPC_EINVAL;  // keeps sum(rho_q) < 2^63
+  return RPC_OK;
+}
+
+template <typename Fn>
+static int dispatch(const rpc_factor_opts* o, Fn&& fn) {
+  if (o->gemm_dtype == RPC_F64) return fn((double*)0, (double*)0, (double*)0);
+  if (o->gemm_dtype == RPC_F32) {
+    if (o->factor_dtype == RPC_F32) return fn((float*)0, (float*)0, (float*)0);
+    return fn((float*)0, (float*)0, (double*)0);
+  }
+  if (o->factor_dtype == RPC_F32) return fn((__bf16*)0, (float*)0, (float*)0);
+  return fn((__bf16*)0, (float*)0, (double*)0);
+}
+
+}  // namespace
+
+extern "C" int rpchol_factor_workspace_size(const rpc_points* X, const rpc_factor_opts* o,
+                                            size_t* bytes) {
+  int rc = check_factor_args(X, o);
+  if (rc) return rc;
+  if (!bytes) return RPC_EINVAL;
+  return dispatch(o, [&](auto* t, auto* tn, auto* tf) {
+    typedef typename std::remove_pointer<decltype(t)>::type T;
+    typedef typename std::remove_pointer<decltype(tn)>::type TN;
+    typedef typename std::remove_pointer<decltype(tf)>::type TF;
+    WsCursor c{nullptr, 0, 0, true};
+    FactorWs w;
+    *bytes = carve<T, TN, TF>(c, w, X->N, X->d, o->r);
+    return (int)RPC_OK;
+  });
+}
+
+extern "C" int rpchol_factor(const rpc_points* X, const rpc_factor_opts* o, void* F, int64_t ldf,
+                             int64_t* pivots, double* rho, int32_t* k_out, void* ws,
+                             size_t ws_bytes, int32_t* status, rpc_stream_t stream) {
+  int rc = check_factor_args(X, o);
+  if (rc) return rc;
+  if (!F || !pivots || !rho || !k_out || !status || ldf < X->N || ldf % 8 != 0) return RPC_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  return dispatch(o, [&](auto* t, auto* tn, auto* tf) {
+    typedef typename std::remove_pointer<decltype(t)>::type T;
+    typedef typename std::remove_pointer<decltype(tn)>::type TN;
+    typedef typename std::remove_pointer<decltype(tf)>::type TF;
+    return run_factor<T, TN, TF>(X, o, (TF*)F, ldf, pivots, rho, k_out, ws, ws_bytes, status, st);
+  });
+}

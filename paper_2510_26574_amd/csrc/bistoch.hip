@@ -1,0 +1,691 @@
+// bistoch_degrees and bistoch_eig: Algorithm 1 of the paper after the
+// factorisation, on gfx950.
+//
+// With K~ = F F^T (F: N x r, column-major, columns >= k zero):
+//   c  = F^T 1,  d~ = F c           (diag(D~) = K~ 1, asserted > 0)
+//   w  = F^T (1/d~),  q~ = F w      (diag(Q~) = K~ D~^{-1} 1, asserted > 0)
+//   B  = D~^{-1} F,  C = F^T Q~^{-1} F     (factored P~ = B C B^T)
+//   G_B = B^T B = R^T R              (Cholesky QR: Q = B R^{-1} is never formed)
+//   M  = R C R^T = V Lambda V^T      (top nev eigenpairs)
+//   U  = B R^{-1} V                  (N x nev)
+// The two N-long Gram products dominate; they run as MFMA tiles over row
+// chunks with float64 accumulation across chunks.  Everything of size r x r
+// is float64.  Unused budget columns (index >= k) are handled by padding the
+// Gram with the identity there, so every launch has a static shape and no
+// host synchronisation is needed.
+#include <math.h>
+
+#include <type_traits>
+
+#include "common.hpp"
+#include "dense.hpp"
+#include "profile.hpp"
+#include "tile_gemm.hpp"
+
+namespace {
+
+constexpr int COLCHUNK = 8192;  // rows per partial column sum
+
+// part[chunk][col] = sum_{n in chunk} F[n, col] * wgt[n]   (col < k; 0 beyond)
+template <typename TF>
+__global__ __launch_bounds__(1024) void k_coldot_partial(const TF* __restrict__ F, int64_t ldf,
+                                                         int64_t N, int r, const int32_t* kptr,
+                                                         const double* __restrict__ wgt,
+                                                         double* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = blockIdx.y * 16 + wave;
+  if (col >= r) return;
+  const int k = *kptr;
+  const int64_t r0 = (int64_t)blockIdx.x * COLCHUNK;
+  double s = 0.0;
+  if (col < k) {
+    const TF* f = F + (int64_t)col * ldf;
+    for (int64_t i = r0 + lane; i < r0 + COLCHUNK && i < N; i += 64) {
+      const double v = to_d(f[i]);
+      s += wgt ? v * wgt[i] : v;
+    }
+  }
+  s = wave_sum(s);
+  if (lane == 0) part[(int64_t)blockIdx.x * r + col] = s;
+}
+
+__global__ void k_reduce_cols(const double* __restrict__ part, int nch, int r, double* __restrict__ out) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= r) return;
+  double s = 0.0;
+  for (int c = 0; c < nch; ++c) s += part[(int64_t)c * r + col];
+  out[col] = s;
+}
+
+// out[n] = sum_{l<k} F[n, l] v[l]; assert out > 0 (else `code`); inv[n] = 1/out[n].
+template <typename TF>
+__global__ __launch_bounds__(256) void k_rowdot(const TF* __restrict__ F, int64_t ldf, int64_t N,
+                                                int r, const int32_t* kptr,
+                                                const double* __restrict__ v,
+                                                double* __restrict__ out, double* __restrict__ inv,
+                                                int32_t code, int32_t* status) {
+  extern __shared__ double vs[];
+  const int k = *kptr;
+  for (int l = threadIdx.x; l < k; l += 256) vs[l] = v[l];
+  __syncthreads();
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  double s0 = 0.0, s1 = 0.0;
+  int l = 0;
+  for (; l + 1 < k; l += 2) {
+    s0 += to_d(F[n + (int64_t)l * ldf]) * vs[l];
+    s1 += to_d(F[n + (int64_t)(l + 1) * ldf]) * vs[l + 1];
+  }
+  if (l < k) s0 += to_d(F[n + (int64_t)l * ldf]) * vs[l];
+  const double s = s0 + s1;
+  if (!(s > 0.0)) set_status(status, code);
+  if (out) out[n] = s;
+  if (inv) inv[n] = 1.0 / s;
+}
+
+// ------------------------------------------------------------ Gram products
+// part[chunk][i + j r] (i <= j tiles only) = sum_{n in chunk} F[n,i] sa[n] F[n,j] sb[n]
+// in the MFMA type T; float32 tiles are flushed into float64 every 256 rows.
+template <typename T, typename TF>
+__global__ __launch_bounds__(256) void k_gram_partial(const TF* __restrict__ F, int64_t ldf,
+                                                      int64_t N, int r,
+                                                      const double* __restrict__ sa,
+                                                      const double* __restrict__ sb,
+                                                      int64_t chunk, double* __restrict__ part) {
+  typedef TileCfg<T, 128, 128, 16, 2, 2> Cfg;
+  const int nt = (r + 127) / 128;
+  const int ti = blockIdx.x % nt, tj = blockIdx.x / nt;
+  if (ti > tj) return;
+  extern __shared__ char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  const int64_t c0 = (int64_t)blockIdx.y * chunk;
+  int64_t c1 = c0 + chunk;
+  if (c1 > N) c1 = N;
+  const bool vec = (ldf % (16 / (int)sizeof(TF))) == 0;
+  GOperand<TF, true> A{F, ldf, r, N, sa, vec};
+  GOperand<TF, true> B{F, ldf, r, N, sb, vec};
+  const int64_t m0 = (int64_t)ti * 128, n0 = (int64_t)tj * 128;
+  double acc64[Cfg::MI][Cfg::NI][4];
+#pragma unroll
+  for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+    for (int j = 0; j < Cfg::NI; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc64[i][j][e] = 0.0;
+  const int64_t slice = sizeof(T) == 8 ? chunk : 256;
+  for (int64_t kb = c0; kb < c1; kb += slice) {
+    const int64_t ke = kb + slice < c1 ? kb + slice : c1;
+    TileAcc<Cfg> acc;
+    acc.zero();
+    tile_mainloop<Cfg>(acc, A, B, m0, n0, kb, ke, smem);
+#pragma unroll
+    for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+      for (int j = 0; j < Cfg::NI; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc64[i][j][e] += (double)acc.a[i][j][e];
+  }
+  double* out = part + (int64_t)blockIdx.y * r * r;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % Cfg::WAVES_M, wn = wave / Cfg::WAVES_M;
+#pragma unroll
+  for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+    for (int j = 0; j < Cfg::NI; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = m0 + wm * Cfg::WTM + i * 16 + Cfg::MM::row(lane, e);
+        const int64_t col = n0 + wn * Cfg::WTN + j * 16 + (lane & 15);
+        if (row < r && col < r) out[row + col * r] = acc64[i][j][e];
+      }
+}
+
+// Sum the chunk partials (fixed order) for i <= j tiles and mirror.
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part, int nch, int r,
+                                                     double* __restrict__ G) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * r) return;
+  const int i = (int)(e % r), j = (int)(e / r);
+  const int ti = i / 128, tj = j / 128;
+  const int a = ti <= tj ? i : j, b = ti <= tj ? j : i;  // read from the computed (upper) tile
+  double s = 0.0;
+  for (int c = 0; c < nch; ++c) s += part[(int64_t)c * r * r + a + (int64_t)b * r];
+  G[i + (int64_t)j * r] = s;
+}
+
+// Finalise G_B and C:
+//   G_B += gamma (B[0:k,:] + B[0:k,:]^T) + gamma^2 I_k  (B = D~^{-1} F);
+//   unused indices (>= k): G_B = I, C = 0;
+//   equilibrate: s_i = 1/sqrt(G_B[i,i]); Gs = S G_B S; Cs = S^{-1} C S^{-1}.
+template <typename TF>
+__global__ __launch_bounds__(256) void k_gram_finish(double* __restrict__ GB, double* __restrict__ C,
+                                                     double* __restrict__ Gs,
+                                                     double* __restrict__ Cs,
+                                                     double* __restrict__ s, int r,
+                                                     const int32_t* kptr, const TF* __restrict__ F,
+                                                     int64_t ldf, int64_t N,
+                                                     const double* __restrict__ dinv, double gamma,
+                                                     int phase) {
+  const int k = *kptr;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * r) return;
+  const int i = (int)(e % r), j = (int)(e / r);
+  if (phase == 0) {
+    double g = GB[e], c = C[e];
+    if (i >= k || j >= k) {
+      g = (i == j) ? 1.0 : 0.0;
+      c = 0.0;
+    } else if (gamma != 0.0) {
+      const double bij = i < N ? to_d(F[i + (int64_t)j * ldf]) * dinv[i] : 0.0;
+      const double bji = j < N ? to_d(F[j + (int64_t)i * ldf]) * dinv[j] : 0.0;
+      g += gamma * (bij + bji) + (i == j ? gamma * gamma : 0.0);
+    }
+    GB[e] = g;
+    C[e] = c;
+  } else {
+    const double si = 1.0 / sqrt(GB[i + (int64_t)i * r]);
+    const double sj = 1.0 / sqrt(GB[j + (int64_t)j * r]);
+    Gs[e] = GB[e] * si * sj;
+    Cs[e] = C[e] / (si * sj);
+    if (i == j) s[i] = si;
+  }
+}
+
+// Deterministic start block for the subspace iteration (hash-based uniform in [-1, 1]).
+__global__ void k_fill_start(double* Q, int r, int p) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * p) return;
+  unsigned long long z = (unsigned long long)e * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  Q[e] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// conv = 1 if every Ritz pair i < nev has |Y_i - theta_i Q_i| <= tol |theta_0|.
+__global__ __launch_bounds__(1024) void k_ritz_check(const double* __restrict__ Y,
+                                                     const double* __restrict__ Q,
+                                                     const double* __restrict__ theta, int r,
+                                                     int nev, double tol, int32_t* conv) {
+  if (*conv) return;
+  __shared__ int ok;
+  if (threadIdx.x == 0) ok = 1;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < nev; i += 16) {
+    double s = 0.0;
+    for (int l = lane; l < r; l += 64) {
+      const double d = Y[l + (int64_t)i * r] - theta[i] * Q[l + (int64_t)i * r];
+      s += d * d;
+    }
+    s = wave_sum(s);
+    if (lane == 0 && !(sqrt(s) <= tol * fabs(theta[0]))) atomicAnd(&ok, 0);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && ok) *conv = 1;
+}
+
+__global__ void k_copy_cols(const double* __restrict__ src, int64_t lds, double* __restrict__ dst,
+                            int64_t ldd, int rows, int cols, const int32_t* skip) {
+  if (skip && *skip) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)rows * cols) return;
+  const int i = (int)(e % rows), j = (int)(e / rows);
+  dst[i + j * ldd] = src[i + j * lds];
+}
+
+// rows scaled: X[i, j] *= s[i]  (or /= s[i] when divide)
+__global__ void k_scale_rows(double* X, int64_t ldx, int rows, int cols, const double* s,
+                             int divide) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)rows * cols) return;
+  const int i = (int)(e % rows), j = (int)(e / rows);
+  X[i + j * ldx] = divide ? X[i + j * ldx] / s[i] : X[i + j * ldx] * s[i];
+}
+
+__global__ void k_recip(const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = 1.0 / x[i];
+}
+
+__global__ void k_set_int(int32_t* p, int32_t v) { *p = v; }
+
+__global__ void k_flag_noconv(const int32_t* conv, int32_t* status) {
+  if (!*conv) set_status(status, RPC_ENOCONV);
+}
+
+// U = diag(dinv) F Z   (F: N x r, Z: r x nev column-major; dinv may be null)
+template <typename T, typename TF, typename TU>
+__global__ __launch_bounds__(256) void k_form_u(const TF* __restrict__ F, int64_t ldf, int64_t N,
+                                                int r, const double* __restrict__ Z, int nev,
+                                                const double* __restrict__ dinv,
+                                                TU* __restrict__ U, int64_t ldu) {
+  typedef TileCfg<T, 128, 64, 16, 2, 2> Cfg;
+  extern __shared__ char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM, n0 = (int64_t)blockIdx.y * Cfg::BN;
+  GOperand<TF, false> A{F, ldf, N, r, nullptr, true};
+  GOperand<double, true> B{Z, r, nev, r, nullptr, (r % 2) == 0};
+  TileAcc<Cfg> acc;
+  acc.zero();
+  tile_mainloop<Cfg>(acc, A, B, m0, n0, 0, r, smem);
+  for_each_acc<Cfg>(acc, [&](int row, int col, typename Cfg::MM::acc_t v) {
+    const int64_t m = m0 + row, n = n0 + col;
+    if (m < N && n < nev) U[m + n * ldu] = (TU)(dinv ? (double)v * dinv[m] : (double)v);
+  });
+}
+
+// Column sign: find the largest |U[:, j]| (lowest index on ties).
+template <typename TU>
+__global__ __launch_bounds__(256) void k_colmax_partial(const TU* __restrict__ U, int64_t ldu,
+                                                        int64_t N, int nev, double* __restrict__ pv,
+                                                        int64_t* __restrict__ pi, int nb) {
+  const int j = blockIdx.y;
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  const int64_t base = (int64_t)blockIdx.x * 4096;
+  double bv = -1.0, bs = 0.0;
+  int64_t bix = -1;
+  for (int e = threadIdx.x; e < 4096; e += 256) {
+    const int64_t i = base + e;
+    if (i < N) {
+      const double v = to_d(U[i + j * ldu]);
+      if (fabs(v) > bv) { bv = fabs(v); bix = i; bs = v; }
+    }
+  }
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bix;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      const double v2 = sv[threadIdx.x + off], v1 = sv[threadIdx.x];
+      const int64_t i2 = si[threadIdx.x + off], i1 = si[threadIdx.x];
+      if (i2 >= 0 && (i1 < 0 || v2 > v1 || (v2 == v1 && i2 < i1))) {
+        sv[threadIdx.x] = v2;
+        si[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  (void)bs;
+  if (threadIdx.x == 0) {
+    pv[(int64_t)j * nb + blockIdx.x] = sv[0];
+    pi[(int64_t)j * nb + blockIdx.x] = si[0];
+  }
+}
+
+template <typename TU>
+__global__ __launch_bounds__(256) void k_colsign(const TU* __restrict__ U, int64_t ldu,
+                                                 const double* __restrict__ pv,
+                                                 const int64_t* __restrict__ pi, int nb,
+                                                 double* __restrict__ sgn) {
+  const int j = blockIdx.x;
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  double bv = -1.0;
+  int64_t bix = -1;
+  for (int e = threadIdx.x; e < nb; e += 256) {
+    const double v = pv[(int64_t)j * nb + e];
+    const int64_t i = pi[(int64_t)j * nb + e];
+    if (i >= 0 && (v > bv || (v == bv && (bix < 0 || i < bix)))) { bv = v; bix = i; }
+  }
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bix;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      const double v2 = sv[threadIdx.x + off], v1 = sv[threadIdx.x];
+      const int64_t i2 = si[threadIdx.x + off], i1 = si[threadIdx.x];
+      if (i2 >= 0 && (i1 < 0 || v2 > v1 || (v2 == v1 && i2 < i1))) {
+        sv[threadIdx.x] = v2;
+        si[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sgn[j] = (si[0] >= 0 && to_d(U[si[0] + j * ldu]) < 0.0) ? -1.0 : 1.0;
+}
+
+template <typename TU>
+__global__ __launch_bounds__(256) void k_apply_sign(TU* __restrict__ U, int64_t ldu, int64_t N,
+                                                    int nev, const double* __restrict__ sgn) {
+  const int j = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < N && sgn[j] < 0.0) U[i + j * ldu] = -U[i + j * ldu];
+}
+
+template <typename TU>
+__global__ void k_const_col(TU* U, int64_t N, double v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < N) U[i] = (TU)v;
+}
+
+// E[:, j] = T[:, j] * sgn[j] / lambda[j]
+__global__ void k_scale_E(double* E, int r, int nev, const double* sgn, const double* lam) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * nev) return;
+  const int j = (int)(e / r);
+  E[e] = E[e] * sgn[j] / lam[j];
+}
+
+struct EigWs {
+  double *sd, *sq, *part, *GB, *C, *Gs, *Cs, *s, *T1, *M;
+  double *Q, *Y, *H, *Wm, *theta, *Gp, *Rinv, *Qt;
+  double *V, *Z, *T2, *sgn, *pv;
+  int64_t* pi;
+  double* Ut;
+  int32_t* conv;
+  int nch;
+  int64_t chunk;
+  int p;
+};
+
+static void gram_plan(int64_t N, int& nch, int64_t& chunk) {
+  int64_t want = (N + 255) / 256;
+  nch = (int)(want < 32 ? want : 32);
+  if (nch < 1) nch = 1;
+  chunk = (int64_t)align_up((size_t)((N + nch - 1) / nch), 256);
+  nch = (int)((N + chunk - 1) / chunk);
+}
+
+static size_t carve_eig(WsCursor& c, EigWs& w, int64_t N, int r, int nev, bool fix_const) {
+  gram_plan(N, w.nch, w.chunk);
+  w.p = r <= dense::JMAX ? r : dense::JMAX;
+  const int p = w.p;
+  const int nbu = (int)((N + 4095) / 4096);
+  w.sd = c.take<double>(N);
+  w.sq = c.take<double>(N);
+  w.part = c.take<double>((size_t)w.nch * r * r);
+  w.GB = c.take<double>((size_t)r * r);
+  w.C = c.take<double>((size_t)r * r);
+  w.Gs = c.take<double>((size_t)r * r);
+  w.Cs = c.take<double>((size_t)r * r);
+  w.s = c.take<double>(r);
+  w.T1 = c.take<double>((size_t)r * r);
+  w.M = c.take<double>((size_t)r * r);
+  w.Q = c.take<double>((size_t)r * p);
+  w.Y = c.take<double>((size_t)r * p);
+  w.H = c.take<double>((size_t)p * p);
+  w.Wm = c.take<double>((size_t)p * p);
+  w.theta = c.take<double>(p);
+  w.Gp = c.take<double>((size_t)p * p);
+  w.Rinv = c.take<double>((size_t)p * p);
+  w.Qt = c.take<double>((size_t)r * p);
+  w.V = c.take<double>((size_t)r * nev);
+  w.Z = c.take<double>((size_t)r * nev);
+  w.T2 = c.take<double>((size_t)r * nev);
+  w.sgn = c.take<double>(nev);
+  w.pv = c.take<double>((size_t)nbu * nev);
+  w.pi = c.take<int64_t>((size_t)nbu * nev);
+  w.Ut = fix_const ? c.take<double>((size_t)align_up((size_t)N, 8) * nev) : nullptr;
+  w.conv = c.take<int32_t>(1);
+  return c.used;
+}
+
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// Orthonormalise the r x p block Y into Q by Cholesky QR (Gram, one-workgroup
+// Cholesky + inverse, product).
+static void chol_qr(hipStream_t st, const double* Y, double* Q, int r, int p, EigWs& w,
+                    int32_t* status, const int32_t* skip) {
+  dense::gemm64<true, true>(st, p, p, r, Y, r, Y, r, w.Gp, p, 1.0, 0.0, skip);
+  hipLaunchKernelGGL(dense::k_chol_inv_small, dim3(1), dim3(1024), 0, st, w.Gp, (int64_t)p, p,
+                     w.Rinv, (int64_t)p, status, skip);
+  dense::gemm64<false, true>(st, r, p, p, Y, r, w.Rinv, p, Q, r, 1.0, 0.0, skip);
+}
+
+
+template <typename TG, typename TF, typename TU>
+static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
+                   const double* dt, const double* qt, const rpc_eig_opts* o, TU* U, int64_t ldu,
+                   double* lambda, double* ext_E, void* ws, size_t ws_bytes, int32_t* status,
+                   hipStream_t st) {
+  const int nev = o->nev;
+  WsCursor cur{(char*)ws, 0, ws_bytes, true};
+  EigWs w;
+  carve_eig(cur, w, N, r, nev, o->fix_const != 0);
+  if (!cur.ok) return RPC_EWORKSPACE;
+  const int p = w.p;
+  prof::begin(prof::GRAM, st);
+  hipLaunchKernelGGL(k_recip, dim3(nblk(N)), dim3(256), 0, st, dt, w.sd, N);
+  hipLaunchKernelGGL(k_recip, dim3(nblk(N)), dim3(256), 0, st, qt, w.sq, N);
+
+  // ---- the two N-long Grams: G_B = F^T D~^{-2} F and C = F^T Q~^{-1} F
+  typedef TileCfg<TG, 128, 128, 16, 2, 2> CfgG;
+  const int ntile = (r + 127) / 128;
+  const dim3 gg((unsigned)(ntile * ntile), (unsigned)w.nch);
+  const unsigned grr = nblk((int64_t)r * r);
+  hipLaunchKernelGGL((k_gram_partial<TG, TF>), gg, dim3(256), CfgG::smem_bytes, st, F, ldf, N, r,
+                     (const double*)w.sd, (const double*)w.sd, w.chunk, w.part);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(grr), dim3(256), 0, st, (const double*)w.part, w.nch, r, w.GB);
+  hipLaunchKernelGGL((k_gram_partial<TG, TF>), gg, dim3(256), CfgG::smem_bytes, st, F, ldf, N, r,
+                     (const double*)w.sq, (const double*)nullptr, w.chunk, w.part);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(grr), dim3(256), 0, st, (const double*)w.part, w.nch, r, w.C);
+  prof::end(prof::GRAM, st);
+  prof::begin(prof::SMALL, st);
+  hipLaunchKernelGGL((k_gram_finish<TF>), dim3(grr), dim3(256), 0, st, w.GB, w.C, w.Gs, w.Cs, w.s,
+                     r, k, F, ldf, N, (const double*)w.sd, o->gamma, 0);
+  hipLaunchKernelGGL((k_gram_finish<TF>), dim3(grr), dim3(256), 0, st, w.GB, w.C, w.Gs, w.Cs, w.s,
+                     r, k, F, ldf, N, (const double*)w.sd, o->gamma, 1);
+  RPC_LAUNCH_CHECK();
+
+  // ---- Cholesky QR in Gram space: S G_B S = L' L'^T, R = L'^T S^{-1}
+  dense::cholesky(st, w.Gs, r, r, status);
+  // M = R C R^T = L'^T (S^{-1} C S^{-1}) L'
+  dense::gemm64<false, true>(st, r, r, r, w.Cs, r, w.Gs, r, w.T1, r, 1.0, 0.0);
+  dense::gemm64<true, true>(st, r, r, r, w.Gs, r, w.T1, r, w.M, r, 1.0, 0.0);
+  RPC_LAUNCH_CHECK();
+
+  // ---- top-nev eigenpairs of M
+  const double jtol = 1e-15;
+  if (r <= dense::JMAX) {
+    hipLaunchKernelGGL(dense::k_jacobi, dim3(1), dim3(1024), 0, st, (const double*)w.M, (int64_t)r,
+                       r, w.theta, w.Wm, (int64_t)r, 40, jtol, status, (const int32_t*)nullptr);
+    hipLaunchKernelGGL(k_copy_cols, dim3(nblk((int64_t)r * nev)), dim3(256), 0, st,
+                       (const double*)w.Wm, (int64_t)r, w.V, (int64_t)r, r, nev,
+                       (const int32_t*)nullptr);
+  } else {
+    // subspace iteration with Rayleigh-Ritz on a p-dimensional block
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, w.conv, 0);
+    hipLaunchKernelGGL(k_fill_start, dim3(nblk((int64_t)r * p)), dim3(256), 0, st, w.Y, r, p);
+    chol_qr(st, w.Y, w.Q, r, p, w, status, nullptr);
+    chol_qr(st, w.Q, w.Y, r, p, w, status, nullptr);
+    hipLaunchKernelGGL(k_copy_cols, dim3(nblk((int64_t)r * p)), dim3(256), 0, st,
+                       (const double*)w.Y, (int64_t)r, w.Q, (int64_t)r, r, p,
+                       (const int32_t*)nullptr);
+    const int max_outer = 40;
+    for (int it = 0; it < max_outer; ++it) {
+      for (int in = 0; in < 3; ++in) {
+        dense::gemm64<false, true>(st, r, p, r, w.M, r, w.Q, r, w.Y, r, 1.0, 0.0, w.conv);
+        chol_qr(st, w.Y, w.Q, r, p, w, status, w.conv);
+      }
+      dense::gemm64<false, true>(st, r, p, r, w.M, r, w.Q, r, w.Y, r, 1.0, 0.0, w.conv);
+      dense::gemm64<true, true>(st, p, p, r, w.Q, r, w.Y, r, w.H, p, 1.0, 0.0, w.conv);
+      hipLaunchKernelGGL(dense::k_jacobi, dim3(1), dim3(1024), 0, st, (const double*)w.H,
+                         (int64_t)p, p, w.theta, w.Wm, (int64_t)p, 40, jtol, status,
+                         (const int32_t*)w.conv);
+      dense::gemm64<false, true>(st, r, p, p, w.Q, r, w.Wm, p, w.Qt, r, 1.0, 0.0, w.conv);
+      dense::gemm64<false, true>(st, r, p, p, w.Y, r, w.Wm, p, w.T1, r, 1.0, 0.0, w.conv);
+      hipLaunchKernelGGL(k_copy_cols, dim3(nblk((int64_t)r * p)), dim3(256), 0, st,
+                         (const double*)w.Qt, (int64_t)r, w.Q, (int64_t)r, r, p,
+                         (const int32_t*)w.conv);
+      hipLaunchKernelGGL(k_ritz_check, dim3(1), dim3(1024), 0, st, (const double*)w.T1,
+                         (const double*)w.Q, (const double*)w.theta, r, nev, 1e-10, w.conv);
+    }
+    hipLaunchKernelGGL(k_flag_noconv, dim3(1), dim3(1), 0, st, (const int32_t*)w.conv, status);
+    hipLaunchKernelGGL(k_copy_cols, dim3(nblk((int64_t)r * nev)), dim3(256), 0, st,
+                       (const double*)w.Q, (int64_t)r, w.V, (int64_t)r, r, nev,
+                       (const int32_t*)nullptr);
+  }
+  hipLaunchKernelGGL(k_copy_cols, dim3(nblk(nev)), dim3(256), 0, st, (const double*)w.theta,
+                     (int64_t)nev, lambda, (int64_t)nev, nev, 1, (const int32_t*)nullptr);
+  RPC_LAUNCH_CHECK();
+
+  prof::end(prof::SMALL, st);
+  prof::begin(prof::FORM_U, st);
+  // ---- Z = R^{-1} V = S L'^{-T} V ;  U = D~^{-1} F Z
+  hipLaunchKernelGGL(k_copy_cols, dim3(nblk((int64_t)r * nev)), dim3(256), 0, st,
+                     (const double*)w.V, (int64_t)r, w.Z, (int64_t)r, r, nev, (const int32_t*)nullptr);
+  dense::trsm_lt(st, w.Gs, r, r, w.Z, r, nev);
+  hipLaunchKernelGGL(k_scale_rows, dim3(nblk((int64_t)r * nev)), dim3(256), 0, st, w.Z, (int64_t)r,
+                     r, nev, (const double*)w.s, 0);
+  typedef TileCfg<TG, 128, 64, 16, 2, 2> CfgU;
+  const dim3 gu((unsigned)((N + 127) / 128), (unsigned)((nev + 63) / 64));
+  hipLaunchKernelGGL((k_form_u<TG, TF, TU>), gu, dim3(256), CfgU::smem_bytes, st, F, ldf, N, r,
+                     (const double*)w.Z, nev, (const double*)w.sd, U, ldu);
+  RPC_LAUNCH_CHECK();
+
+  if (o->fix_const) {
+    // U(:, 0) = 1/sqrt(N), then Cholesky QR with positive diag(R)
+    hipLaunchKernelGGL((k_const_col<TU>), dim3(nblk(N)), dim3(256), 0, st, U, N, 1.0 / sqrt((double)N));
+    int nchu;
+    int64_t chu;
+    gram_plan(N, nchu, chu);
+    const int ntu = (nev + 127) / 128;
+    typedef TileCfg<double, 128, 128, 16, 2, 2> CfgD;
+    hipLaunchKernelGGL((k_gram_partial<double, double>), dim3((unsigned)(ntu * ntu), (unsigned)nchu),
+                       dim3(256), CfgD::smem_bytes, st, (const double*)U, ldu, N, nev,
+                       (const double*)nullptr, (const double*)nullptr, chu, w.part);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(nblk((int64_t)nev * nev)), dim3(256), 0, st,
+                       (const double*)w.part, nchu, nev, w.Gp);
+    hipLaunchKernelGGL(dense::k_chol_inv_small, dim3(1), dim3(1024), 0, st, (const double*)w.Gp,
+                       (int64_t)nev, nev, w.Rinv, (int64_t)nev, status, (const int32_t*)nullptr);
+    const int64_t ldut = (int64_t)align_up((size_t)N, 8);
+    hipLaunchKernelGGL(k_copy_cols, dim3(nblk(N * nev)), dim3(256), 0, st, (const double*)U, ldu,
+                       w.Ut, ldut, (int)N, nev, (const int32_t*)nullptr);
+    typedef TileCfg<double, 128, 64, 16, 2, 2> CfgU2;
+    hipLaunchKernelGGL((k_form_u<double, double, TU>), gu, dim3(256), CfgU2::smem_bytes, st,
+                       (const double*)w.Ut, ldut, N, nev, (const double*)w.Rinv, nev,
+                       (const double*)nullptr, U, ldu);
+    RPC_LAUNCH_CHECK();
+  }
+
+  // ---- column signs: largest-magnitude entry positive
+  const int nbu = (int)((N + 4095) / 4096);
+  hipLaunchKernelGGL((k_colmax_partial<TU>), dim3((unsigned)nbu, (unsigned)nev), dim3(256), 0, st,
+                     (const TU*)U, ldu, N, nev, w.pv, w.pi, nbu);
+  hipLaunchKernelGGL((k_colsign<TU>), dim3((unsigned)nev), dim3(256), 0, st, (const TU*)U, ldu,
+                     (const double*)w.pv, (const int64_t*)w.pi, nbu, w.sgn);
+  hipLaunchKernelGGL((k_apply_sign<TU>), dim3(nblk(N), (unsigned)nev), dim3(256), 0, st, U, ldu, N,
+                     nev, (const double*)w.sgn);
+  prof::end(prof::FORM_U, st);
+  RPC_LAUNCH_CHECK();
+
+  // ---- extension matrix E = C R^T V Lambda^{-1} (signed like U); R^T = S^{-1} L'
+  dense::gemm64<false, true>(st, r, nev, r, w.Gs, r, w.V, r, w.T2, r, 1.0, 0.0);
+  hipLaunchKernelGGL(k_scale_rows, dim3(nblk((int64_t)r * nev)), dim3(256), 0, st, w.T2, (int64_t)r,
+                     r, nev, (const double*)w.s, 1);
+  dense::gemm64<false, true>(st, r, nev, r, w.C, r, w.T2, r, ext_E, r, 1.0, 0.0);
+  hipLaunchKernelGGL(k_scale_E, dim3(nblk((int64_t)r * nev)), dim3(256), 0, st, ext_E, r, nev,
+                     (const double*)w.sgn, (const double*)lambda);
+  RPC_LAUNCH_CHECK();
+  return RPC_OK;
+}
+
+template <typename TF>
+static int run_degrees(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k, double* c,
+                       double* dt, double* qt, void* ws, size_t ws_bytes, int32_t* status,
+                       hipStream_t st) {
+  WsCursor cur{(char*)ws, 0, ws_bytes, true};
+  const int nch = (int)((N + COLCHUNK - 1) / COLCHUNK);
+  double* part = cur.take<double>((size_t)nch * r);
+  double* inv = cur.take<double>((size_t)N);
+  double* wv = cur.take<double>((size_t)r);
+  if (!cur.ok) return RPC_EWORKSPACE;
+  const dim3 gc((unsigned)nch, (unsigned)((r + 15) / 16));
+  const size_t sh = (size_t)r * sizeof(double);
+  prof::begin(prof::DEGREES, st);
+  hipLaunchKernelGGL((k_coldot_partial<TF>), gc, dim3(1024), 0, st, F, ldf, N, r, k,
+                     (const double*)nullptr, part);
+  hipLaunchKernelGGL(k_reduce_cols, dim3((r + 255) / 256), dim3(256), 0, st, (const double*)part, nch,
+                     r, c);
+  hipLaunchKernelGGL((k_rowdot<TF>), dim3(nblk(N)), dim3(256), sh, st, F, ldf, N, r, k,
+                     (const double*)c, dt, inv, (int32_t)RPC_EDEGREE, status);
+  hipLaunchKernelGGL((k_coldot_partial<TF>), gc, dim3(1024), 0, st, F, ldf, N, r, k,
+                     (const double*)inv, part);
+  hipLaunchKernelGGL(k_reduce_cols, dim3((r + 255) / 256), dim3(256), 0, st, (const double*)part, nch,
+                     r, wv);
+  hipLaunchKernelGGL((k_rowdot<TF>), dim3(nblk(N)), dim3(256), sh, st, F, ldf, N, r, k,
+                     (const double*)wv, qt, (double*)nullptr, (int32_t)RPC_EQDEGREE, status);
+  prof::end(prof::DEGREES, st);
+  RPC_LAUNCH_CHECK();
+  return RPC_OK;
+}
+
+static size_t degrees_ws(int64_t N, int r) {
+  WsCursor c{nullptr, 0, 0, true};
+  const int nch = (int)((N + COLCHUNK - 1) / COLCHUNK);
+  c.take<double>((size_t)nch * r);
+  c.take<double>((size_t)N);
+  c.take<double>((size_t)r);
+  return c.used;
+}
+
+static int check_eig_opts(int64_t N, int r, const rpc_eig_opts* o) {
+  if (!o || N < 1 || r < 1 || r > N || r > 8192) return RPC_EINVAL;
+  if (o->nev < 1 || o->nev > r) return RPC_EINVAL;
+  if (r > dense::JMAX && o->nev > 64) return RPC_EINVAL;
+  if (o->gram_dtype != RPC_F64 && o->gram_dtype != RPC_F32) return RPC_EINVAL;
+  if (o->u_dtype != RPC_F64 && o->u_dtype != RPC_F32) return RPC_EINVAL;
+  if (o->fix_const && o->u_dtype != RPC_F64) return RPC_EINVAL;
+  if (!(o->gamma >= 0.0)) return RPC_EINVAL;
+  return RPC_OK;
+}
+
+}  // namespace
+
+extern "C" int bistoch_degrees_workspace_size(int64_t N, int32_t r, size_t* bytes) {
+  if (N < 1 || r < 1 || !bytes) return RPC_EINVAL;
+  *bytes = degrees_ws(N, r);
+  return RPC_OK;
+}
+
+extern "C" int bistoch_degrees(const void* F, int32_t fdt, int64_t N, int64_t ldf, int32_t r,
+                               const int32_t* k, double* c, double* dt, double* qt, void* ws,
+                               size_t ws_bytes, int32_t* status, rpc_stream_t stream) {
+  if (!F || !k || !c || !dt || !qt || !status || N < 1 || r < 1 || r > N || ldf < N) return RPC_EINVAL;
+  if (r > 8192) return RPC_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (fdt == RPC_F64)
+    return run_degrees<double>((const double*)F, N, ldf, r, k, c, dt, qt, ws, ws_bytes, status, st);
+  if (fdt == RPC_F32)
+    return run_degrees<float>((const float*)F, N, ldf, r, k, c, dt, qt, ws, ws_bytes, status, st);
+  return RPC_EINVAL;
+}
+
+extern "C" int bistoch_eig_workspace_size(int64_t N, int32_t r, const rpc_eig_opts* o, size_t* bytes) {
+  int rc = check_eig_opts(N, r, o);
+  if (rc) return rc;
+  if (!bytes) return RPC_EINVAL;
+  WsCursor c{nullptr, 0, 0, true};
+  EigWs w;
+  *bytes = carve_eig(c, w, N, r, o->nev, o->fix_const != 0);
+  return RPC_OK;
+}
+
+extern "C" int bistoch_eig(const void* F, int32_t fdt, int64_t N, int64_t ldf, int32_t r,
+                           const int32_t* k, const double* c, const double* dt, const double* qt,
+                           const rpc_eig_opts* o, void* U, int64_t ldu, double* lambda,
+                           double* ext_E, void* ws, size_t ws_bytes, int32_t* status,
+                           rpc_stream_t stream) {
+  int rc = check_eig_opts(N, r, o);
+  if (rc) return rc;
+  (void)c;
+  if (!F || !k || !dt || !qt || !U || !lambda || !ext_E || !status) return RPC_EINVAL;
+  if (ldf < N || ldf % 8 != 0 || ldu < N || ldu % 8 != 0) return RPC_EINVAL;
+  if (fdt != RPC_F64 && fdt != RPC_F32) return RPC_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const bool g64 = o->gram_dtype == RPC_F64;
+  const bool u64 = o->u_dtype == RPC_F64;
+#define RPC_EIG_CALL(TG, TF, TU)                                                                  \
+  return run_eig<TG, TF, TU>((const TF*)F, N, ldf, r, k, dt, qt, o, (TU*)U, ldu, lambda, ext_E, ws, \
+                             ws_bytes, status, st)
+  if (fdt == RPC_F64) {
+    if (g64) { if (u64) RPC_EIG_CALL(double, double, double); else RPC_EIG_CALL(double, double, float); }
+    if (u64) RPC_EIG_CALL(float, double, double); else RPC_EIG_CALL(float, double, float);
+  } else {
+    if (g64) { if (u64) RPC_EIG_CALL(double, float, double); else RPC_EIG_CALL(double, float, float); }
+    if (u64) RPC_EIG_CALL(float, float, double); else RPC_EIG_CALL(float, float, float);
+  }
+#undef RPC_EIG_CALL
+}

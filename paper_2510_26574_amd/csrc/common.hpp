@@ -1,0 +1,147 @@
+// Shared device helpers for the gfx950 kernels: vector types, MFMA wrappers
+// with their lane layouts, wave reductions, and the error plumbing of the
+// C-ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rpchol.h"
+
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+
+#define RPC_WAVE 64
+
+// ---------------------------------------------------------------- MFMA
+// Layouts measured on gfx950 (16 x 16 output tile, 64 lanes):
+//   A[m][k] operand: lane l holds m = l % 16 and the k-slot l / 16 (one
+//     element for f32/f64, eight consecutive k for bf16);
+//   B[k][n] operand: lane l holds n = l % 16 and the same k-slot;
+//   f32 / bf16 accumulators: element i of lane l is D[4 (l/16) + i][l % 16];
+//   f64 accumulators:        element i of lane l is D[(l/16) + 4 i][l % 16].
+// Only the pairing of A and B k-slots matters for the product, so loaders
+// may permute k freely as long as A and B agree.
+template <typename T>
+struct Mma;
+
+template <>
+struct Mma<double> {
+  typedef double frag;
+  typedef v4d acc;
+  typedef double acc_t;
+  static constexpr int KS = 4;   // k per instruction
+  static constexpr int EPL = 1;  // k elements per lane per instruction
+  __device__ static inline acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int i) { return (lane >> 4) + 4 * i; }
+};
+
+template <>
+struct Mma<float> {
+  typedef float frag;
+  typedef v4f acc;
+  typedef float acc_t;
+  static constexpr int KS = 4;
+  static constexpr int EPL = 1;
+  __device__ static inline acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+
+template <>
+struct Mma<__bf16> {
+  typedef v8bf frag;
+  typedef v4f acc;
+  typedef float acc_t;
+  static constexpr int KS = 32;
+  static constexpr int EPL = 8;
+  __device__ static inline acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+
+// --------------------------------------------------------- conversions
+template <typename T>
+__device__ inline T cvt(float x);
+template <>
+__device__ inline float cvt<float>(float x) { return x; }
+template <>
+__device__ inline double cvt<double>(float x) { return (double)x; }
+template <>
+__device__ inline __bf16 cvt<__bf16>(float x) { return (__bf16)x; }
+
+template <typename T>
+__device__ inline T cvtd(double x);
+template <>
+__device__ inline float cvtd<float>(double x) { return (float)x; }
+template <>
+__device__ inline double cvtd<double>(double x) { return x; }
+template <>
+__device__ inline __bf16 cvtd<__bf16>(double x) { return (__bf16)(float)x; }
+
+template <typename T>
+__device__ inline double to_d(T x) { return (double)x; }
+template <>
+__device__ inline double to_d<__bf16>(__bf16 x) { return (double)(float)x; }
+
+// ------------------------------------------------------ wave reductions
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, RPC_WAVE);
+  return v;
+}
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, RPC_WAVE);
+  return v;
+}
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, RPC_WAVE);
+  return v;
+}
+
+// Status words written from the device (first error wins).
+__device__ inline void set_status(int32_t* st, int32_t code) {
+  if (st) atomicCAS(st, 0, code);
+}
+
+static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Host-side bump allocator over a caller-provided workspace.
+struct WsCursor {
+  char* base;
+  size_t used;
+  size_t cap;
+  bool ok;
+  template <typename T>
+  T* take(size_t count) {
+    size_t off = align_up(used, 256);
+    size_t need = off + align_up(count * sizeof(T), 256);
+    if (base == nullptr || need > cap) {
+      ok = false;
+      used = need;
+      return nullptr;
+    }
+    used = need;
+    return reinterpret_cast<T*>(base + off);
+  }
+};
+
+#define RPC_HIP_CHECK(expr)                    \
+  do {                                         \
+    hipError_t _e = (expr);                    \
+    if (_e != hipSuccess) return RPC_EHIP;     \
+  } while (0)
+
+#define RPC_LAUNCH_CHECK()                           \
+  do {                                               \
+    hipError_t _e = hipGetLastError();               \
+    if (_e != hipSuccess) return RPC_EHIP;           \
+  } while (0)

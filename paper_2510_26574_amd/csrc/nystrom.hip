@@ -1,0 +1,213 @@
+// nystrom_extend: out-of-sample values of the eigenvectors of P~ (the
+// extension formula of the paper's "Nystrom method connection" section,
+// applied to the bistochastic approximation), on gfx950.
+//
+// For a new point y:  f(y) = F(S, :)^{-1} k(X_S, y),  d~(y) = c^T f(y),
+// phi(y) = f(y)^T E / d~(y),  E = C R^T V Lambda^{-1} (from bistoch_eig).
+// F(S, :) is lower triangular in pivot order, so the two triangular solves
+// are folded once into E' = F(S, :)^{-T} [c | E]; each block of new points
+// then costs one MFMA distance product with an exp epilogue and one product
+// with E'.  Everything is float64.
+#include <math.h>
+
+#include "common.hpp"
+#include "dense.hpp"
+#include "profile.hpp"
+#include "tile_gemm.hpp"
+
+namespace {
+
+constexpr int64_t MCH = 65536;  // new points per block
+
+// XS[i][:] = X[piv[i]][:] (i < k; zero rows beyond), xsn[i] = |XS[i]|^2;
+// FS (r x r column-major) = F(S, :) on the leading k x k block, identity beyond.
+template <typename TF>
+__global__ __launch_bounds__(256) void k_gather_pivots(const float* __restrict__ X, int64_t ldx,
+                                                       int64_t d, int64_t dp,
+                                                       const int64_t* __restrict__ piv,
+                                                       const int32_t* kptr,
+                                                       const TF* __restrict__ F, int64_t ldf,
+                                                       int r, double* __restrict__ XS,
+                                                       double* __restrict__ xsn,
+                                                       double* __restrict__ FS) {
+  const int i = blockIdx.x;
+  const int k = *kptr;
+  __shared__ double red[4];
+  double s = 0.0;
+  const int64_t p = i < k ? piv[i] : -1;
+  for (int64_t c = threadIdx.x; c < dp; c += 256) {
+    const double v = (p >= 0 && c < d) ? (double)X[p * ldx + c] : 0.0;
+    XS[(int64_t)i * dp + c] = v;
+    s += v * v;
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) xsn[i] = red[0] + red[1] + red[2] + red[3];
+  for (int j = threadIdx.x; j < r; j += 256) {
+    double v;
+    if (i < k && j < k)
+      v = to_d(F[p + (int64_t)j * ldf]);
+    else
+      v = (i == j) ? 1.0 : 0.0;
+    FS[i + (int64_t)j * r] = v;
+  }
+}
+
+// rhs = [c | E] (r x (nev+1), column-major), rows >= k zero.
+__global__ void k_rhs(const double* __restrict__ c, const double* __restrict__ E, int r, int nev,
+                      const int32_t* kptr, double* __restrict__ B0) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * (nev + 1)) return;
+  const int i = (int)(e % r), j = (int)(e / r);
+  const int k = *kptr;
+  double v = 0.0;
+  if (i < k) v = j == 0 ? c[i] : E[i + (int64_t)(j - 1) * r];
+  B0[e] = v;
+}
+
+__global__ __launch_bounds__(256) void k_prep_rows64(const float* __restrict__ Y, int64_t ldy,
+                                                     int64_t m, int64_t d, int64_t dp,
+                                                     double* __restrict__ Yp,
+                                                     double* __restrict__ yn, int32_t* status) {
+  const int lane = threadIdx.x & 63;
+  const int64_t n = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (n >= m) return;
+  double s = 0.0;
+  bool bad = false;
+  for (int64_t j = lane; j < dp; j += 64) {
+    const float v = j < d ? Y[n * ldy + j] : 0.0f;
+    if (!isfinite(v)) bad = true;
+    Yp[n * dp + j] = (double)v;
+    s += (double)v * (double)v;
+  }
+  s = wave_sum(s);
+  if (__any(bad) && lane == 0) set_status(status, RPC_ENONFINITE);
+  if (lane == 0) yn[n] = s;
+}
+
+// Kys[m][i] = exp(-max(0, yn + xsn - 2 <y, x_i>) / eps), column-major m x r.
+__global__ __launch_bounds__(256) void k_cross_kernel(const double* __restrict__ Yp,
+                                                      const double* __restrict__ yn, int64_t m,
+                                                      int64_t dp, const double* __restrict__ XS,
+                                                      const double* __restrict__ xsn, int r,
+                                                      double eps, double* __restrict__ K,
+                                                      int64_t ldk) {
+  typedef TileCfg<double, 64, 64, 16, 2, 2> Cfg;
+  __shared__ double smem[(Cfg::BM + Cfg::BN) * Cfg::LDK];
+  const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM, n0 = (int64_t)blockIdx.y * Cfg::BN;
+  GOperand<double, true> A{Yp, dp, m, dp, nullptr, true};
+  GOperand<double, true> B{XS, dp, r, dp, nullptr, true};
+  TileAcc<Cfg> acc;
+  acc.zero();
+  tile_mainloop<Cfg>(acc, A, B, m0, n0, 0, dp, smem);
+  for_each_acc<Cfg>(acc, [&](int row, int col, double v) {
+    const int64_t i = m0 + row, j = n0 + col;
+    if (i < m && j < r) {
+      double d2 = yn[i] + xsn[j] - 2.0 * v;
+      d2 = d2 > 0.0 ? d2 : 0.0;
+      K[i + j * ldk] = exp(-d2 / eps);
+    }
+  });
+}
+
+__global__ void k_divide(const double* __restrict__ P, int64_t ldp, int64_t m, int nev,
+                         double* __restrict__ Phi, int64_t ldphi) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= m * nev) return;
+  const int64_t i = e % m;
+  const int j = (int)(e / m);
+  Phi[i + j * ldphi] = P[i + (int64_t)(j + 1) * ldp] / P[i];
+}
+
+struct NysWs {
+  double *XS, *xsn, *FS, *B0, *Yp, *yn, *K, *P;
+  int64_t dp, mch;
+};
+
+static size_t carve_nys(WsCursor& c, NysWs& w, int64_t M, int64_t d, int r, int nev) {
+  w.dp = (int64_t)align_up((size_t)d, 16);
+  w.mch = M < MCH ? M : MCH;
+  w.XS = c.take<double>((size_t)r * w.dp);
+  w.xsn = c.take<double>(r);
+  w.FS = c.take<double>((size_t)r * r);
+  w.B0 = c.take<double>((size_t)r * (nev + 1));
+  w.Yp = c.take<double>((size_t)w.mch * w.dp);
+  w.yn = c.take<double>(w.mch);
+  w.K = c.take<double>((size_t)w.mch * r);
+  w.P = c.take<double>((size_t)w.mch * (nev + 1));
+  return c.used;
+}
+
+template <typename TF>
+static int run_nys(const rpc_points* Y, const rpc_points* X, const int64_t* piv, const int32_t* k,
+                   const TF* F, int64_t ldf, int r, const double* c, const double* E, int nev,
+                   double* Phi, int64_t ldphi, void* ws, size_t ws_bytes, int32_t* status,
+                   hipStream_t st) {
+  WsCursor cur{(char*)ws, 0, ws_bytes, true};
+  NysWs w;
+  carve_nys(cur, w, Y->N, Y->d, r, nev);
+  if (!cur.ok) return RPC_EWORKSPACE;
+  prof::begin(prof::NYSTROM, st);
+  hipLaunchKernelGGL((k_gather_pivots<TF>), dim3(r), dim3(256), 0, st, X->X, X->ldx, X->d, w.dp, piv,
+                     k, F, ldf, r, w.XS, w.xsn, w.FS);
+  hipLaunchKernelGGL(k_rhs, dim3((unsigned)(((int64_t)r * (nev + 1) + 255) / 256)), dim3(256), 0, st,
+                     c, E, r, nev, k, w.B0);
+  dense::trsm_lt(st, w.FS, r, r, w.B0, r, nev + 1);
+  RPC_LAUNCH_CHECK();
+  for (int64_t m0 = 0; m0 < Y->N; m0 += w.mch) {
+    const int64_t m = Y->N - m0 < w.mch ? Y->N - m0 : w.mch;
+    hipLaunchKernelGGL(k_prep_rows64, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st,
+                       Y->X + m0 * Y->ldx, Y->ldx, m, Y->d, w.dp, w.Yp, w.yn, status);
+    hipLaunchKernelGGL(k_cross_kernel, dim3((unsigned)((m + 63) / 64), (unsigned)((r + 63) / 64)),
+                       dim3(256), 0, st, (const double*)w.Yp, (const double*)w.yn, m, w.dp,
+                       (const double*)w.XS, (const double*)w.xsn, r, X->eps, w.K, m);
+    dense::gemm64<false, true>(st, m, nev + 1, r, w.K, m, w.B0, r, w.P, m, 1.0, 0.0);
+    hipLaunchKernelGGL(k_divide, dim3((unsigned)((m * nev + 255) / 256)), dim3(256), 0, st,
+                       (const double*)w.P, m, m, nev, Phi + m0, ldphi);
+    RPC_LAUNCH_CHECK();
+  }
+  prof::end(prof::NYSTROM, st);
+  return RPC_OK;
+}
+
+}  // namespace
+
+extern "C" int nystrom_extend_workspace_size(int64_t M, int64_t d, int32_t r, int32_t nev,
+                                             size_t* bytes) {
+  if (M < 1 || d < 1 || r < 1 || nev < 1 || nev > r || !bytes) return RPC_EINVAL;
+  WsCursor c{nullptr, 0, 0, true};
+  NysWs w;
+  *bytes = carve_nys(c, w, M, d, r, nev);
+  return RPC_OK;
+}
+
+extern "C" int nystrom_extend(const rpc_points* Y, const rpc_points* X, const int64_t* pivots,
+                              const int32_t* k, const void* F, int32_t fdt, int64_t ldf, int32_t r,
+                              const double* c, const double* E, int32_t nev, double* Phi,
+                              int64_t ldphi, void* ws, size_t ws_bytes, int32_t* status,
+                              rpc_stream_t stream) {
+  if (!Y || !X || !Y->X || !X->X || !pivots || !k || !F || !c || !E || !Phi || !status)
+    return RPC_EINVAL;
+  if (Y->N < 1 || Y->d != X->d || Y->ldx < Y->d || X->ldx < X->d || !(X->eps > 0.0)) return RPC_EINVAL;
+  if (r < 1 || r > X->N || nev < 1 || nev > r || ldf < X->N || ldphi < Y->N) return RPC_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (fdt == RPC_F64)
+    return run_nys<double>(Y, X, pivots, k, (const double*)F, ldf, r, c, E, nev, Phi, ldphi, ws,
+                           ws_bytes, status, st);
+  if (fdt == RPC_F32)
+    return run_nys<float>(Y, X, pivots, k, (const float*)F, ldf, r, c, E, nev, Phi, ldphi, ws,
+                          ws_bytes, status, st);
+  return RPC_EINVAL;
+}
+
+extern "C" int rpc_status_sync(const int32_t* dev_status, rpc_stream_t stream) {
+  if (!dev_status) return RPC_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (hipStreamSynchronize(st) != hipSuccess) return RPC_EHIP;
+  int32_t v = 0;
+  if (hipMemcpy(&v, dev_status, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return RPC_EHIP;
+  return v;
+}
+
+extern "C" const char* rpc_version(void) { return "rpchol 0.1 (gfx950)"; }

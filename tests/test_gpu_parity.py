@@ -1,0 +1,272 @@
+"""GPU parity: the HIP path (through the C-ABI) against the float64 CPU oracle.
+
+Bars (the contract of the method's precision forms):
+  * pivots identical (greedy and sampled mode share the integer CDF, so any
+    difference is a defect; cross-precision runs use replay);
+  * F within 1e-12 (FP64) of the oracle relative to max |F|; in FP32 within
+    5e-5: kernel entries carry a relative error of about u32 (|x|^2+|s|^2)/eps
+    ~ 2e-7 from the norm expansion, which the pivot-block solves L^{-T}
+    amplify by up to ~1e2 at r = 64; in BF16 products within 1e-2 on
+    delay-embedded (d = 512) points, whose rounding errors average over
+    the coordinates;
+  * eigenvalues within 1e-6 relative at FP64/FP32 (1e-10 is asked at FP64)
+    and 1e-3 at BF16; principal angles of the leading eigenvector subspace
+    within 1e-4 rad (FP64/FP32) and 1e-2 (BF16).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import median_sq_distance, torus_points, uniform_stream
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_26574_amd as rp
+
+    rp.load_library()
+    return torch, rp
+
+
+def _angle(U, V):
+    Qu, _ = np.linalg.qr(U)
+    Qv, _ = np.linalg.qr(V)
+    s = np.linalg.norm(Qv - Qu @ (Qu.T @ Qv), 2)
+    return float(np.arcsin(min(s, 1.0)))
+
+
+def _gap_index(lam, nev, rel=1e-3):
+    """Largest m <= nev with a relative gap between lam[m-1] and lam[m]."""
+    for m in range(nev, 0, -1):
+        if m < len(lam) and lam[m - 1] / lam[m] - 1 > rel:
+            return m
+    return nev
+
+
+def _torus_case(n=2000, seed=0):
+    X = torus_points(n, seed=seed)
+    return X, median_sq_distance(X, seed=seed)
+
+
+def _run_factor(gpu, X, eps, r, b, mode, u=None, replay=None, gdt="f64", fdt="f64", tau=0.0):
+    torch, rp = gpu
+    Xd = torch.from_numpy(X).cuda()
+    kw = {}
+    if u is not None:
+        kw["uniforms"] = torch.from_numpy(u).cuda()
+    if replay is not None:
+        kw["replay"] = torch.as_tensor(np.asarray(replay, dtype=np.int64)).cuda()
+    out = rp.rpchol_factor(Xd, eps, r, b, mode=mode, gemm_dtype=gdt, factor_dtype=fdt, tau=tau, **kw)
+    st = rp.status_sync(out["status"])
+    assert st == 0, rp.STATUS_NAMES.get(st, st)
+    k = int(out["k"].item())
+    F = out["F"].double().cpu().numpy()
+    return out, k, F, out["pivots"].cpu().numpy(), out["rho"].cpu().numpy()
+
+
+def test_library_loads(gpu):
+    torch, rp = gpu
+    assert "gfx950" in rp.version()
+
+
+def test_greedy_c1_pivots_and_factor(gpu):
+    X, eps = _torus_case()
+    ref = oracle.arpc(X, eps, r=64, b=1, mode="greedy")
+    out, k, F, piv, rho = _run_factor(gpu, X, eps, 64, 1, "greedy")
+    assert k == ref["k"] == 64
+    assert list(piv[:k]) == list(ref["S"])
+    scale = np.abs(ref["F"]).max()
+    assert np.abs(F[:, :k] - ref["F"]).max() / scale < 1e-12
+    assert np.all(F[:, k:] == 0)
+    assert np.abs(rho - ref["rho"]).max() < 1e-12
+
+
+@pytest.mark.parametrize("b", [1, 8, 16])
+def test_sampled_c1_pivots_and_factor(gpu, b):
+    X, eps = _torus_case(seed=b)
+    r = 64
+    u = uniform_stream(2 * b * (-(-r // b)), seed=100 + b)
+    ref = oracle.arpc(X, eps, r=r, b=b, mode="sampled", uniforms=u)
+    out, k, F, piv, rho = _run_factor(gpu, X, eps, r, b, "sampled", u=u)
+    assert k == ref["k"]
+    assert list(piv[:k]) == list(ref["S"])
+    assert np.all(piv[k:] == -1)
+    scale = np.abs(ref["F"]).max()
+    assert np.abs(F[:, :k] - ref["F"]).max() / scale < 1e-12
+    assert np.abs(rho - ref["rho"]).max() < 1e-12
+    assert np.all(rho[ref["S"]] == 0)
+
+
+def test_sampled_ragged_shapes(gpu):
+    """N not a multiple of the tiles, d not a multiple of the k-step, r not a
+    multiple of b (last round proposes r - (t-1) b)."""
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((1337, 37)).astype(np.float32)
+    eps = median_sq_distance(X, seed=5)
+    r, b = 100, 16
+    u = uniform_stream(2 * b * 7, seed=77)
+    ref = oracle.arpc(X, eps, r=r, b=b, mode="sampled", uniforms=u)
+    out, k, F, piv, rho = _run_factor(gpu, X, eps, r, b, "sampled", u=u)
+    assert k == ref["k"] and list(piv[:k]) == list(ref["S"])
+    assert np.abs(F[:, :k] - ref["F"]).max() / np.abs(ref["F"]).max() < 1e-12
+
+
+def test_degenerate_all_equal_points(gpu):
+    X = np.ones((300, 4), dtype=np.float32)
+    u = uniform_stream(2 * 4 * 4, seed=1)
+    out, k, F, piv, rho = _run_factor(gpu, X, 1.0, 16, 4, "sampled", u=u)
+    assert k == 1 and np.allclose(F[:, 0], 1.0) and np.all(F[:, 1:] == 0) and np.all(rho == 0)
+
+
+def test_replay_f64_matches_oracle(gpu):
+    X, eps = _torus_case(seed=3)
+    u = uniform_stream(2 * 16 * 4, seed=3)
+    ref = oracle.arpc(X, eps, r=64, b=16, mode="sampled", uniforms=u)
+    out, k, F, piv, rho = _run_factor(gpu, X, eps, 64, 16, "replay", replay=ref["S"])
+    assert k == ref["k"] and list(piv[:k]) == list(ref["S"])
+    assert np.abs(F[:, :k] - ref["F"]).max() / np.abs(ref["F"]).max() < 1e-12
+
+
+def _ks_case(n=2000, seed=0, q=8):
+    from synth import ks_points
+
+    X = ks_points(n, q=q, seed=seed)
+    return X, median_sq_distance(X, seed=seed)
+
+
+@pytest.mark.parametrize("gdt,fdt,ftol", [("f32", "f32", 5e-5), ("bf16", "f32", 1e-2)])
+def test_replay_reduced_precision(gpu, gdt, fdt, ftol):
+    X, eps = _torus_case(seed=4) if gdt == "f32" else _ks_case(seed=4)
+    u = uniform_stream(2 * 16 * 4, seed=4)
+    ref = oracle.arpc(X, eps, r=64, b=16, mode="sampled", uniforms=u)
+    out, k, F, piv, rho = _run_factor(gpu, X, eps, 64, 16, "replay", replay=ref["S"], gdt=gdt, fdt=fdt)
+    assert k == ref["k"]
+    assert np.abs(F[:, :k] - ref["F"]).max() / np.abs(ref["F"]).max() < ftol
+
+
+def _eig_case(gpu, X, eps, r, b, nev, seed, gdt="f64", fdt="f64", gram="f64", fix_const=False):
+    torch, rp = gpu
+    u = uniform_stream(2 * b * (-(-r // b)), seed=seed)
+    ref = oracle.arpc(X, eps, r=r, b=b, mode="sampled", uniforms=u)
+    mode, kw = ("sampled", {"u": u}) if gdt == "f64" else ("replay", {"replay": ref["S"]})
+    out, k, F, piv, rho = _run_factor(gpu, X, eps, r, b, mode, gdt=gdt, fdt=fdt, **kw)
+    deg = rp.bistoch_degrees(out["F"], out["k"])
+    eig = rp.bistoch_eig(out["F"], out["k"], deg["d"], deg["q"], nev, gram_dtype=gram, fix_const=fix_const)
+    assert rp.status_sync(eig["status"]) == 0
+    assert rp.status_sync(deg["status"]) == 0
+    res = oracle.bistoch_eig(ref["F"], nev, fix_const=fix_const)
+    return ref, out, deg, eig, res
+
+
+def test_degrees_and_eig_c1_f64(gpu):
+    X, eps = _torus_case()
+    nev = 16
+    ref, out, deg, eig, res = _eig_case(gpu, X, eps, 64, 8, nev, seed=21)
+    c, d, q = (deg[x].cpu().numpy() for x in ("c", "d", "q"))
+    k = ref["k"]
+    assert np.abs(c[:k] - res["c"]).max() / np.abs(res["c"]).max() < 1e-12
+    assert np.all(c[k:] == 0)
+    assert np.abs(d / res["d"] - 1).max() < 1e-12
+    assert np.abs(q / res["q"] - 1).max() < 1e-12
+    lam = eig["lam"].cpu().numpy()
+    assert np.abs(lam / res["lam"] - 1).max() < 1e-10
+    U = eig["U"].cpu().numpy()
+    m = _gap_index(res["lam_all"], nev)
+    assert _angle(U[:, :m], res["U"][:, :m]) < 1e-8
+    # sign convention: largest-magnitude entry positive
+    for j in range(nev):
+        i = int(np.argmax(np.abs(U[:, j])))
+        assert U[i, j] > 0
+    # P~ 1 = 1 means the constant vector is an eigenvector with eigenvalue 1
+    assert np.min(np.abs(lam - 1.0)) < 1e-10
+
+
+def test_eig_fix_const(gpu):
+    X, eps = _torus_case(seed=2)
+    ref, out, deg, eig, res = _eig_case(gpu, X, eps, 64, 8, 8, seed=22, fix_const=True)
+    U = eig["U"].cpu().numpy()
+    assert np.abs(U[:, 0] - 1 / math.sqrt(U.shape[0])).max() < 1e-12
+    assert np.abs(U.T @ U - np.eye(8)).max() < 1e-12
+    assert _angle(U, res["U"]) < 1e-8
+
+
+@pytest.mark.parametrize("gdt,fdt,gram,ltol,atol", [
+    ("f32", "f32", "f32", 1e-6, 1e-4),
+    ("bf16", "f32", "f32", 1e-3, 1e-2),
+])
+def test_eig_reduced_precision(gpu, gdt, fdt, gram, ltol, atol):
+    X, eps = _torus_case(seed=6) if gdt == "f32" else _ks_case(seed=6)
+    nev = 16
+    ref, out, deg, eig, res = _eig_case(gpu, X, eps, 64, 16, nev, seed=23, gdt=gdt, fdt=fdt, gram=gram)
+    lam = eig["lam"].cpu().numpy()
+    assert np.abs(lam / res["lam"] - 1).max() < ltol
+    m = _gap_index(res["lam_all"], nev)
+    assert _angle(eig["U"].cpu().numpy()[:, :m], res["U"][:, :m]) < atol
+
+
+def test_subspace_iteration_path(gpu):
+    """r > 96 takes the subspace-iteration eigensolver."""
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((3000, 6)).astype(np.float32)
+    eps = median_sq_distance(X, seed=8)
+    nev = 24
+    ref, out, deg, eig, res = _eig_case(gpu, X, eps, 160, 32, nev, seed=24)
+    lam = eig["lam"].cpu().numpy()
+    assert np.abs(lam / res["lam"] - 1).max() < 1e-10
+    m = _gap_index(res["lam_all"], nev)
+    assert _angle(eig["U"].cpu().numpy()[:, :m], res["U"][:, :m]) < 1e-8
+
+
+def test_nystrom_extension(gpu):
+    torch, rp = gpu
+    X, eps = _torus_case(seed=7)
+    nev = 10
+    ref, out, deg, eig, res = _eig_case(gpu, X, eps, 64, 8, nev, seed=25)
+    Y = torus_points(500, seed=99)
+    ph = rp.nystrom_extend(torch.from_numpy(Y).cuda(), torch.from_numpy(X).cuda(), eps, out["pivots"],
+                           out["k"], out["F"], deg["c"], eig["E"])
+    assert rp.status_sync(ph["status"]) == 0
+    Phi = ph["Phi"].cpu().numpy()
+    phi_ref = oracle.nystrom_extend(Y, X, ref["S"], ref["F"], res["c"], res["E"], eps)
+    assert np.abs(Phi - phi_ref).max() / np.abs(phi_ref).max() < 1e-9
+    # at training points the extension reproduces U
+    rows = np.array([0, 5, 999, 1999])
+    ph2 = rp.nystrom_extend(torch.from_numpy(X[rows]).cuda(), torch.from_numpy(X).cuda(), eps,
+                            out["pivots"], out["k"], out["F"], deg["c"], eig["E"])
+    U = eig["U"].cpu().numpy()
+    assert np.abs(ph2["Phi"].cpu().numpy() - U[rows]).max() < 1e-9
+
+
+def test_invalid_arguments_rejected(gpu):
+    torch, rp = gpu
+    X = torch.zeros((10, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(rp.RpcError):
+        rp.rpchol_factor(X, 1.0, 11, 1, mode="greedy")  # r > N
+    with pytest.raises(rp.RpcError):
+        rp.rpchol_factor(X, 1.0, 4, 2, mode="greedy")  # greedy needs b = 1
+    with pytest.raises(rp.RpcError):
+        rp.rpchol_factor(X, -1.0, 4, 1, mode="greedy")  # eps <= 0
+
+
+def test_nonfinite_input_flagged(gpu):
+    torch, rp = gpu
+    X = np.ones((64, 3), dtype=np.float32)
+    X[5, 1] = np.nan
+    out = rp.rpchol_factor(torch.from_numpy(X).cuda(), 1.0, 4, 1, mode="greedy")
+    assert rp.status_sync(out["status"]) == rp.RPC_ENONFINITE
+
+
+def test_repeat_runs_bitwise_identical(gpu):
+    X, eps = _torus_case(seed=9)
+    u = uniform_stream(2 * 16 * 4, seed=9)
+    _, k1, F1, p1, r1 = _run_factor(gpu, X, eps, 64, 16, "sampled", u=u)
+    _, k2, F2, p2, r2 = _run_factor(gpu, X, eps, 64, 16, "sampled", u=u)
+    assert k1 == k2 and np.array_equal(p1, p2) and np.array_equal(F1, F2) and np.array_equal(r1, r2)
