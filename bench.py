@@ -229,6 +229,7 @@ def main():
     log(f"[bench] mixed {t_mixed * 1e3:.2f} ms/step")
     roof, per_kernel = roofline(w, X.shape[1], res_m, prof, args.steps, mixed)
     t_plain = None
+    prof_p = None
     if not args.no_plain:
         log("[bench] plain FP64 path")
         t_plain, res_p, prof_p = timed(rp, torch, Xd, eps, ud, w, plain, args.steps, args.warmup, profile=True)
@@ -256,6 +257,8 @@ def main():
         "cpu_baseline": cpu,
         "kernels_mixed": per_kernel,
         "kernels_plain_fp64": per_kernel_p if t_plain else None,
+        "phases_ms_mixed": {k: v[0] / args.steps for k, v in prof.items() if v[1]},
+        "phases_ms_plain_fp64": {k: v[0] / args.steps for k, v in prof_p.items() if v[1]} if t_plain else None,
         "parity_vs_fp64_replay": par,
     }
     print(json.dumps(line), flush=True)

@@ -190,7 +190,9 @@ int nystrom_extend(const rpc_points* Y, const rpc_points* X, const int64_t* pivo
  * and the number of launches since the last reset.  Classes: 0 kernel
  * columns, 1 Schur update, 2 triangular solve + downdate, 3 pivot draw,
  * 4 pivot block + accept/reject, 5 degrees, 6 Gram products, 7 r x r work,
- * 8 eigenvector formation, 9 Nystrom extension.  Process-global state, not
+ * 8 eigenvector formation, 9 Nystrom extension, 10 inner eigensolver
+ * (class 7 then covers the Gram finish, Cholesky and inner product).
+ * Process-global state, not
  * thread-safe; returns RPC_EWORKSPACE if the event pool overflowed. */
 int rpc_profile_enable(int on);
 int rpc_profile_reset(void);

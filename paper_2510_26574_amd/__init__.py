@@ -260,7 +260,7 @@ def version():
 
 
 PROFILE_KINDS = ["kernel_cols", "schur", "solve_downdate", "pivot", "accept_reject", "degrees", "gram",
-                 "small", "form_u", "nystrom"]
+                 "small", "form_u", "nystrom", "eig"]
 
 
 def profile_enable(on=True):

@@ -501,7 +501,7 @@ __global__ __launch_bounds__(256) void k_solve_downdate(const TF* __restrict__ W
                                                         const int32_t* kptr, const int32_t* nTptr,
                                                         TF* __restrict__ F, int64_t ldf,
                                                         double* __restrict__ rho) {
-  typedef TileCfg<double, 128, 128, 16, 4, 1> Cfg;
+  typedef TileCfg<double, 64, 128, 16, 4, 1> Cfg;
   const int nt = *nTptr;
   if (nt == 0) return;
   const int k = *kptr;
@@ -645,9 +645,12 @@ static int run_factor(const rpc_points* X, const rpc_factor_opts* o, TF* F, int6
   hipLaunchKernelGGL(k_init_small, dim3(1), dim3(256), 0, st, pivots, r, k_out, w.nT, w.stop);
   RPC_LAUNCH_CHECK();
 
-  typedef TileCfg<T, 128, 128, (sizeof(T) == 2 ? 64 : 16), 2, 2> CfgK;
-  typedef TileCfg<TF, 128, 128, 16, 2, 2> CfgS;
-  typedef TileCfg<double, 128, 128, 16, 4, 1> CfgD;
+  typedef TileCfg<T, 128, 128, (sizeof(T) == 2 ? 64 : (sizeof(T) == 4 ? 32 : 16)), 2, 2> CfgK;
+  typedef TileCfg<TF, 128, 128, (sizeof(TF) == 4 ? 32 : 16), 2, 2> CfgS;
+  typedef TileCfg<double, 64, 128, 16, 4, 1> CfgD;
+  const size_t smK = TileSmem<CfgK, true, true>::bytes;
+  const size_t smS = TileSmem<CfgS, false, true>::bytes;
+  const size_t smD = TileSmem<CfgD, false, true>::bytes;
   const unsigned gm = (unsigned)((N + 127) / 128);
 
   int t;
@@ -693,18 +696,17 @@ static int run_factor(const rpc_points* X, const rpc_factor_opts* o, TF* F, int6
     prof::end(prof::ACCEPT, st);
     RPC_LAUNCH_CHECK();
     prof::begin(prof::KERNEL_COLS, st);
-    hipLaunchKernelGGL((k_kernel_cols<T, TN, TF, CfgK>), dim3(gm, 1), dim3(CfgK::NT),
-                       CfgK::smem_bytes, st, (const T*)w.Xp, (const TN*)w.xn, N, dp,
+    hipLaunchKernelGGL((k_kernel_cols<T, TN, TF, CfgK>), dim3(gm, 1), dim3(CfgK::NT), smK, st, (const T*)w.Xp, (const TN*)w.xn, N, dp,
                        (const T*)w.XSa, (const TN*)w.nsa, w.nT, X->eps, (TF*)w.W, w.ldw);
     prof::end(prof::KERNEL_COLS, st);
     RPC_LAUNCH_CHECK();
     prof::begin(prof::SCHUR, st);
-    hipLaunchKernelGGL((k_schur<TF, CfgS>), dim3(gm, 1), dim3(CfgS::NT), CfgS::smem_bytes, st,
+    hipLaunchKernelGGL((k_schur<TF, CfgS>), dim3(gm, 1), dim3(CfgS::NT), smS, st,
                        (const TF*)F, ldf, N, (const TF*)w.FSa, r, k_out, w.nT, (TF*)w.W, w.ldw);
     prof::end(prof::SCHUR, st);
     RPC_LAUNCH_CHECK();
     prof::begin(prof::SOLVE, st);
-    hipLaunchKernelGGL((k_solve_downdate<TF>), dim3(gm), dim3(256), CfgD::smem_bytes, st,
+    hipLaunchKernelGGL((k_solve_downdate<TF>), dim3((unsigned)((N + 63) / 64)), dim3(256), smD, st,
                        (const TF*)w.W, w.ldw, N, w.Linv, k_out, w.nT, F, ldf, rho);
     RPC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_round_end, dim3(1), dim3(MAXB), 0, st, w.Si, k_out, w.nT, rho,

@@ -20,6 +20,7 @@
 #include "common.hpp"
 #include "dense.hpp"
 #include "profile.hpp"
+#include "syrk.hpp"
 #include "tile_gemm.hpp"
 
 namespace {
@@ -81,76 +82,6 @@ __global__ __launch_bounds__(256) void k_rowdot(const TF* __restrict__ F, int64_
   if (!(s > 0.0)) set_status(status, code);
   if (out) out[n] = s;
   if (inv) inv[n] = 1.0 / s;
-}
-
-// ------------------------------------------------------------ Gram products
-// part[chunk][i + j r] (i <= j tiles only) = sum_{n in chunk} F[n,i] sa[n] F[n,j] sb[n]
-// in the MFMA type T; float32 tiles are flushed into float64 every 256 rows.
-template <typename T, typename TF>
-__global__ __launch_bounds__(256) void k_gram_partial(const TF* __restrict__ F, int64_t ldf,
-                                                      int64_t N, int r,
-                                                      const double* __restrict__ sa,
-                                                      const double* __restrict__ sb,
-                                                      int64_t chunk, double* __restrict__ part) {
-  typedef TileCfg<T, 128, 128, 16, 2, 2> Cfg;
-  const int nt = (r + 127) / 128;
-  const int ti = blockIdx.x % nt, tj = blockIdx.x / nt;
-  if (ti > tj) return;
-  extern __shared__ char smem_raw[];
-  T* smem = reinterpret_cast<T*>(smem_raw);
-  const int64_t c0 = (int64_t)blockIdx.y * chunk;
-  int64_t c1 = c0 + chunk;
-  if (c1 > N) c1 = N;
-  const bool vec = (ldf % (16 / (int)sizeof(TF))) == 0;
-  GOperand<TF, true> A{F, ldf, r, N, sa, vec};
-  GOperand<TF, true> B{F, ldf, r, N, sb, vec};
-  const int64_t m0 = (int64_t)ti * 128, n0 = (int64_t)tj * 128;
-  double acc64[Cfg::MI][Cfg::NI][4];
-#pragma unroll
-  for (int i = 0; i < Cfg::MI; ++i)
-#pragma unroll
-    for (int j = 0; j < Cfg::NI; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) acc64[i][j][e] = 0.0;
-  const int64_t slice = sizeof(T) == 8 ? chunk : 256;
-  for (int64_t kb = c0; kb < c1; kb += slice) {
-    const int64_t ke = kb + slice < c1 ? kb + slice : c1;
-    TileAcc<Cfg> acc;
-    acc.zero();
-    tile_mainloop<Cfg>(acc, A, B, m0, n0, kb, ke, smem);
-#pragma unroll
-    for (int i = 0; i < Cfg::MI; ++i)
-#pragma unroll
-      for (int j = 0; j < Cfg::NI; ++j)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc64[i][j][e] += (double)acc.a[i][j][e];
-  }
-  double* out = part + (int64_t)blockIdx.y * r * r;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave % Cfg::WAVES_M, wn = wave / Cfg::WAVES_M;
-#pragma unroll
-  for (int i = 0; i < Cfg::MI; ++i)
-#pragma unroll
-    for (int j = 0; j < Cfg::NI; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t row = m0 + wm * Cfg::WTM + i * 16 + Cfg::MM::row(lane, e);
-        const int64_t col = n0 + wn * Cfg::WTN + j * 16 + (lane & 15);
-        if (row < r && col < r) out[row + col * r] = acc64[i][j][e];
-      }
-}
-
-// Sum the chunk partials (fixed order) for i <= j tiles and mirror.
-__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part, int nch, int r,
-                                                     double* __restrict__ G) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)r * r) return;
-  const int i = (int)(e % r), j = (int)(e / r);
-  const int ti = i / 128, tj = j / 128;
-  const int a = ti <= tj ? i : j, b = ti <= tj ? j : i;  // read from the computed (upper) tile
-  double s = 0.0;
-  for (int c = 0; c < nch; ++c) s += part[(int64_t)c * r * r + a + (int64_t)b * r];
-  G[i + (int64_t)j * r] = s;
 }
 
 // Finalise G_B and C:
@@ -246,6 +177,17 @@ __global__ void k_scale_rows(double* X, int64_t ldx, int rows, int cols, const d
 __global__ void k_recip(const double* __restrict__ x, double* __restrict__ y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) y[i] = 1.0 / x[i];
+}
+
+// Row scales of the two Grams in the product type: 1/d~ and 1/sqrt(q~).
+template <typename T>
+__global__ void k_gram_scales(const double* __restrict__ dt, const double* __restrict__ qt,
+                              T* __restrict__ sd, T* __restrict__ sq, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    sd[i] = (T)(1.0 / dt[i]);
+    sq[i] = (T)(1.0 / sqrt(qt[i]));
+  }
 }
 
 __global__ void k_set_int(int32_t* p, int32_t v) { *p = v; }
@@ -369,33 +311,28 @@ __global__ void k_scale_E(double* E, int r, int nev, const double* sgn, const do
 }
 
 struct EigWs {
-  double *sd, *sq, *part, *GB, *C, *Gs, *Cs, *s, *T1, *M;
+  double *sd, *sq, *part, *part1, *GB, *C, *Gs, *Cs, *s, *T1, *M;
+  void *ssd, *ssq;
   double *Q, *Y, *H, *Wm, *theta, *Gp, *Rinv, *Qt;
   double *V, *Z, *T2, *sgn, *pv;
   int64_t* pi;
   double* Ut;
   int32_t* conv;
-  int nch;
-  int64_t chunk;
+  size_t part_cap;
   int p;
 };
 
-static void gram_plan(int64_t N, int& nch, int64_t& chunk) {
-  int64_t want = (N + 255) / 256;
-  nch = (int)(want < 32 ? want : 32);
-  if (nch < 1) nch = 1;
-  chunk = (int64_t)align_up((size_t)((N + nch - 1) / nch), 256);
-  nch = (int)((N + chunk - 1) / chunk);
-}
-
 static size_t carve_eig(WsCursor& c, EigWs& w, int64_t N, int r, int nev, bool fix_const) {
-  gram_plan(N, w.nch, w.chunk);
   w.p = r <= dense::JMAX ? r : dense::JMAX;
   const int p = w.p;
   const int nbu = (int)((N + 4095) / 4096);
   w.sd = c.take<double>(N);
   w.sq = c.take<double>(N);
-  w.part = c.take<double>((size_t)w.nch * r * r);
+  w.ssd = c.take<double>(N);
+  w.ssq = c.take<double>(N);
+  w.part_cap = syrk::part_elems_any(N, r);
+  w.part = c.take<double>(w.part_cap);
+  w.part1 = c.take<double>(w.part_cap);
   w.GB = c.take<double>((size_t)r * r);
   w.C = c.take<double>((size_t)r * r);
   w.Gs = c.take<double>((size_t)r * r);
@@ -450,17 +387,14 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   hipLaunchKernelGGL(k_recip, dim3(nblk(N)), dim3(256), 0, st, dt, w.sd, N);
   hipLaunchKernelGGL(k_recip, dim3(nblk(N)), dim3(256), 0, st, qt, w.sq, N);
 
-  // ---- the two N-long Grams: G_B = F^T D~^{-2} F and C = F^T Q~^{-1} F
-  typedef TileCfg<TG, 128, 128, 16, 2, 2> CfgG;
-  const int ntile = (r + 127) / 128;
-  const dim3 gg((unsigned)(ntile * ntile), (unsigned)w.nch);
+  // ---- the two N-long Grams: G_B = (D~^{-1} F)^T (D~^{-1} F), C = (Q~^{-1/2} F)^T (Q~^{-1/2} F)
+  hipLaunchKernelGGL((k_gram_scales<TG>), dim3(nblk(N)), dim3(256), 0, st, dt, qt, (TG*)w.ssd,
+                     (TG*)w.ssq, N);
+  if (!syrk::gram2<TG, TF>(st, F, ldf, N, r, 2, (const TG*)w.ssd, (const TG*)w.ssq, w.part, w.part1,
+                           w.part_cap, w.GB, w.C))
+    return RPC_EWORKSPACE;
   const unsigned grr = nblk((int64_t)r * r);
-  hipLaunchKernelGGL((k_gram_partial<TG, TF>), gg, dim3(256), CfgG::smem_bytes, st, F, ldf, N, r,
-                     (const double*)w.sd, (const double*)w.sd, w.chunk, w.part);
-  hipLaunchKernelGGL(k_gram_reduce, dim3(grr), dim3(256), 0, st, (const double*)w.part, w.nch, r, w.GB);
-  hipLaunchKernelGGL((k_gram_partial<TG, TF>), gg, dim3(256), CfgG::smem_bytes, st, F, ldf, N, r,
-                     (const double*)w.sq, (const double*)nullptr, w.chunk, w.part);
-  hipLaunchKernelGGL(k_gram_reduce, dim3(grr), dim3(256), 0, st, (const double*)w.part, w.nch, r, w.C);
+  RPC_LAUNCH_CHECK();
   prof::end(prof::GRAM, st);
   prof::begin(prof::SMALL, st);
   hipLaunchKernelGGL((k_gram_finish<TF>), dim3(grr), dim3(256), 0, st, w.GB, w.C, w.Gs, w.Cs, w.s,
@@ -477,6 +411,8 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   RPC_LAUNCH_CHECK();
 
   // ---- top-nev eigenpairs of M
+  prof::end(prof::SMALL, st);
+  prof::begin(prof::EIG, st);
   const double jtol = 1e-15;
   if (r <= dense::JMAX) {
     hipLaunchKernelGGL(dense::k_jacobi, dim3(1), dim3(1024), 0, st, (const double*)w.M, (int64_t)r,
@@ -521,7 +457,7 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
                      (int64_t)nev, lambda, (int64_t)nev, nev, 1, (const int32_t*)nullptr);
   RPC_LAUNCH_CHECK();
 
-  prof::end(prof::SMALL, st);
+  prof::end(prof::EIG, st);
   prof::begin(prof::FORM_U, st);
   // ---- Z = R^{-1} V = S L'^{-T} V ;  U = D~^{-1} F Z
   hipLaunchKernelGGL(k_copy_cols, dim3(nblk((int64_t)r * nev)), dim3(256), 0, st,
@@ -531,30 +467,25 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
                      r, nev, (const double*)w.s, 0);
   typedef TileCfg<TG, 128, 64, 16, 2, 2> CfgU;
   const dim3 gu((unsigned)((N + 127) / 128), (unsigned)((nev + 63) / 64));
-  hipLaunchKernelGGL((k_form_u<TG, TF, TU>), gu, dim3(256), CfgU::smem_bytes, st, F, ldf, N, r,
+  const size_t smU = TileSmem<CfgU, false, true>::bytes;
+  hipLaunchKernelGGL((k_form_u<TG, TF, TU>), gu, dim3(256), smU, st, F, ldf, N, r,
                      (const double*)w.Z, nev, (const double*)w.sd, U, ldu);
   RPC_LAUNCH_CHECK();
 
   if (o->fix_const) {
     // U(:, 0) = 1/sqrt(N), then Cholesky QR with positive diag(R)
     hipLaunchKernelGGL((k_const_col<TU>), dim3(nblk(N)), dim3(256), 0, st, U, N, 1.0 / sqrt((double)N));
-    int nchu;
-    int64_t chu;
-    gram_plan(N, nchu, chu);
-    const int ntu = (nev + 127) / 128;
-    typedef TileCfg<double, 128, 128, 16, 2, 2> CfgD;
-    hipLaunchKernelGGL((k_gram_partial<double, double>), dim3((unsigned)(ntu * ntu), (unsigned)nchu),
-                       dim3(256), CfgD::smem_bytes, st, (const double*)U, ldu, N, nev,
-                       (const double*)nullptr, (const double*)nullptr, chu, w.part);
-    hipLaunchKernelGGL(k_gram_reduce, dim3(nblk((int64_t)nev * nev)), dim3(256), 0, st,
-                       (const double*)w.part, nchu, nev, w.Gp);
+    if (!syrk::gram2<double, TU>(st, (const TU*)U, ldu, N, nev, 1, (const double*)nullptr,
+                                 (const double*)nullptr, w.part, w.part1, w.part_cap, w.Gp, nullptr))
+      return RPC_EWORKSPACE;
     hipLaunchKernelGGL(dense::k_chol_inv_small, dim3(1), dim3(1024), 0, st, (const double*)w.Gp,
                        (int64_t)nev, nev, w.Rinv, (int64_t)nev, status, (const int32_t*)nullptr);
     const int64_t ldut = (int64_t)align_up((size_t)N, 8);
     hipLaunchKernelGGL(k_copy_cols, dim3(nblk(N * nev)), dim3(256), 0, st, (const double*)U, ldu,
                        w.Ut, ldut, (int)N, nev, (const int32_t*)nullptr);
     typedef TileCfg<double, 128, 64, 16, 2, 2> CfgU2;
-    hipLaunchKernelGGL((k_form_u<double, double, TU>), gu, dim3(256), CfgU2::smem_bytes, st,
+    const size_t smU2 = TileSmem<CfgU2, false, true>::bytes;
+    hipLaunchKernelGGL((k_form_u<double, double, TU>), gu, dim3(256), smU2, st,
                        (const double*)w.Ut, ldut, N, nev, (const double*)w.Rinv, nev,
                        (const double*)nullptr, U, ldu);
     RPC_LAUNCH_CHECK();

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void k_gemm64(int64_t M, int64_t N, int64_t K,
                                                 double beta, const int32_t* skip) {
   if (skip && *skip) return;
   typedef TileCfg<double, 64, 64, 16, 2, 2> Cfg;
-  __shared__ double smem[(Cfg::BM + Cfg::BN) * Cfg::LDK];
+  __shared__ double smem[TileSmem<Cfg, KCA, KCB>::bytes / sizeof(double)];
   const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM, n0 = (int64_t)blockIdx.y * Cfg::BN;
   GOperand<double, KCA> a{A, lda, M, K, nullptr, (lda % 2) == 0};
   GOperand<double, KCB> b{B, ldb, N, K, nullptr, (ldb % 2) == 0};

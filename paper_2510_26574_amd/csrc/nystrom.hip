@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_cross_kernel(const double* __restrict__
                                                       double eps, double* __restrict__ K,
                                                       int64_t ldk) {
   typedef TileCfg<double, 64, 64, 16, 2, 2> Cfg;
-  __shared__ double smem[(Cfg::BM + Cfg::BN) * Cfg::LDK];
+  __shared__ double smem[TileSmem<Cfg, true, true>::bytes / sizeof(double)];
   const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM, n0 = (int64_t)blockIdx.y * Cfg::BN;
   GOperand<double, true> A{Yp, dp, m, dp, nullptr, true};
   GOperand<double, true> B{XS, dp, r, dp, nullptr, true};

@@ -18,7 +18,8 @@ enum Kind {
   SMALL = 7,        // r x r work: Cholesky, inner product, eigensolver
   FORM_U = 8,       // U = D~^{-1} F R^{-1} V and signs
   NYSTROM = 9,
-  NKIND = 10
+  EIG = 10,         // top-nev eigenpairs of the r x r inner matrix
+  NKIND = 11
 };
 bool enabled();
 void begin(int kind, hipStream_t st);

@@ -32,13 +32,29 @@ struct TileCfg {
   static constexpr int NT = 64 * WAVES_M * WAVES_N;
   static constexpr int WTM = BM / WAVES_M, WTN = BN / WAVES_N;
   static constexpr int MI = WTM / 16, NI = WTN / 16;
-  // LDS row padding: keeps 16-byte alignment for bf16 fragments and spreads
-  // the 16 rows of a fragment over distinct banks.
-  static constexpr int PAD = (sizeof(T_) == 2) ? 8 : 1;
-  static constexpr int LDK = BK + PAD;
-  static constexpr size_t smem_bytes = (size_t)(BM + BN) * LDK * sizeof(T_);
   static_assert(BM % (16 * WAVES_M) == 0 && BN % (16 * WAVES_N) == 0, "tile");
   static_assert(BK % MM::KS == 0, "BK must be a multiple of the MFMA k");
+};
+
+// LDS layout of one staged operand slice (ROWS x BK):
+//   k-contiguous operand   -> s[row * LDK + k],  LDK = BK + 16 bytes of pad
+//   row-contiguous operand -> s[k * LDR + row],  LDR = ROWS + 16 elements of pad
+// Both keep 16-byte aligned vector stores (the staged vectors run along the
+// contiguous index) and spread a fragment's 16 rows over distinct banks.
+template <typename T, int ROWS, int BK, bool KC>
+struct SliceLayout {
+  static constexpr int LDK = BK + 16 / (int)sizeof(T);
+  static constexpr int LDR = ROWS + 16;
+  static constexpr int ELEMS = KC ? ROWS * LDK : BK * LDR;
+  __device__ static inline int at(int row, int k) { return KC ? row * LDK + k : k * LDR + row; }
+};
+
+template <class Cfg, bool KCA, bool KCB>
+struct TileSmem {
+  typedef SliceLayout<typename Cfg::T, Cfg::BM, Cfg::BK, KCA> LA;
+  typedef SliceLayout<typename Cfg::T, Cfg::BN, Cfg::BK, KCB> LB;
+  static constexpr int STAGE = LA::ELEMS + LB::ELEMS;  // one buffer (A then B)
+  static constexpr size_t bytes = 2 * (size_t)STAGE * sizeof(typename Cfg::T);  // double buffered
 };
 
 template <typename T, typename TG>
@@ -51,59 +67,81 @@ __device__ inline T scale_cvt(TG v, const double* ks, int64_t k) {
   }
 }
 
-// Stage a ROWS x BK slice (rows r0.., k k0..) of operand `op` into s[row][k].
-template <typename T, int ROWS, int BK, int LDK, int NT, typename TG, bool KC>
-__device__ inline void stage_tile(T* __restrict__ s, const GOperand<TG, KC>& op, int64_t r0,
-                                  int64_t k0, int tid) {
-  constexpr int V = 16 / sizeof(TG);
-  if constexpr (KC) {
-    constexpr int VPR = BK / V;  // vectors per row
-    static_assert(BK % V == 0, "BK");
-    constexpr int NV = ROWS * VPR;
-    for (int vid = tid; vid < NV; vid += NT) {
-      const int row = vid / VPR;
-      const int kv = (vid % VPR) * V;
-      const int64_t gr = r0 + row, gk = k0 + kv;
-      T* dst = s + row * LDK + kv;
-      if (gr < op.rows && gk + V <= op.K && op.vec) {
-        typedef TG vt __attribute__((ext_vector_type(V)));
-        vt v = *reinterpret_cast<const vt*>(op.p + gr * op.ld + gk);
-#pragma unroll
-        for (int j = 0; j < V; ++j) dst[j] = scale_cvt<T>(v[j], op.kscale, gk + j);
-      } else {
-#pragma unroll
-        for (int j = 0; j < V; ++j) {
-          const int64_t kk = gk + j;
-          dst[j] = (gr < op.rows && kk < op.K) ? scale_cvt<T>(op.p[gr * op.ld + kk], op.kscale, kk)
-                                               : cvtd<T>(0.0);
-        }
-      }
+// Register-staged copy of a ROWS x BK slice (rows r0.., k k0..) of operand
+// `op`: load() issues the global reads (zero-filled out of range), store()
+// converts and writes them to LDS in the operand's SliceLayout.  Splitting
+// the two lets the main loop fetch the next slice while the MFMAs consume
+// the current one.
+template <typename T, int ROWS, int BK, int NT, typename TG, bool KC>
+struct TileStage {
+  typedef SliceLayout<T, ROWS, BK, KC> L;
+  static constexpr int V = 16 / sizeof(TG);
+  static constexpr int NV = KC ? ROWS * (BK / V) : BK * (ROWS / V);
+  static constexpr int PER = (NV + NT - 1) / NT;
+  static_assert(KC ? (BK % V == 0) : (ROWS % V == 0), "tile shape vs vector width");
+  typedef TG vt __attribute__((ext_vector_type(V)));
+  typedef T st __attribute__((ext_vector_type(V)));
+  vt buf[PER];
+
+  __device__ inline void coords(int vid, int& row, int& kk) const {
+    if constexpr (KC) {
+      row = vid / (BK / V);
+      kk = (vid % (BK / V)) * V;
+    } else {
+      kk = vid / (ROWS / V);
+      row = (vid % (ROWS / V)) * V;
     }
-  } else {
-    constexpr int VPC = ROWS / V;  // vectors per k-column
-    static_assert(ROWS % V == 0, "ROWS");
-    constexpr int NV = BK * VPC;
-    for (int vid = tid; vid < NV; vid += NT) {
-      const int kc = vid / VPC;
-      const int rv = (vid % VPC) * V;
-      const int64_t gr = r0 + rv, gk = k0 + kc;
-      if (gk < op.K && gr + V <= op.rows && op.vec) {
-        typedef TG vt __attribute__((ext_vector_type(V)));
-        vt v = *reinterpret_cast<const vt*>(op.p + gr + gk * op.ld);
+  }
+
+  __device__ inline void load(const GOperand<TG, KC>& op, int64_t r0, int64_t k0, int tid) {
 #pragma unroll
-        for (int j = 0; j < V; ++j) s[(rv + j) * LDK + kc] = scale_cvt<T>(v[j], op.kscale, gk);
+    for (int p = 0; p < PER; ++p) {
+      const int vid = tid + p * NT;
+      if (NV % NT != 0 && vid >= NV) break;
+      int row, kk;
+      coords(vid, row, kk);
+      const int64_t gr = r0 + row, gk = k0 + kk;
+      if constexpr (KC) {
+        if (gr < op.rows && gk + V <= op.K && op.vec) {
+          buf[p] = *reinterpret_cast<const vt*>(op.p + gr * op.ld + gk);
+        } else {
+#pragma unroll
+          for (int j = 0; j < V; ++j)
+            buf[p][j] = (gr < op.rows && gk + j < op.K) ? op.p[gr * op.ld + gk + j] : (TG)0;
+        }
       } else {
+        if (gk < op.K && gr + V <= op.rows && op.vec) {
+          buf[p] = *reinterpret_cast<const vt*>(op.p + gr + gk * op.ld);
+        } else {
 #pragma unroll
-        for (int j = 0; j < V; ++j) {
-          const int64_t rr = gr + j;
-          s[(rv + j) * LDK + kc] = (rr < op.rows && gk < op.K)
-                                       ? scale_cvt<T>(op.p[rr + gk * op.ld], op.kscale, gk)
-                                       : cvtd<T>(0.0);
+          for (int j = 0; j < V; ++j)
+            buf[p][j] = (gr + j < op.rows && gk < op.K) ? op.p[gr + j + gk * op.ld] : (TG)0;
         }
       }
     }
   }
-}
+
+  __device__ inline void store(T* __restrict__ s, const GOperand<TG, KC>& op, int64_t k0,
+                               int tid) const {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int vid = tid + p * NT;
+      if (NV % NT != 0 && vid >= NV) break;
+      int row, kk;
+      coords(vid, row, kk);
+      T* dst = s + L::at(row, kk);  // the V elements run along the contiguous index
+      if (op.kscale == nullptr && sizeof(T) == sizeof(TG)) {
+        st v;
+#pragma unroll
+        for (int j = 0; j < V; ++j) v[j] = (T)buf[p][j];
+        *reinterpret_cast<st*>(dst) = v;
+      } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) dst[j] = scale_cvt<T>(buf[p][j], op.kscale, k0 + (KC ? kk + j : kk));
+      }
+    }
+  }
+};
 
 template <class Cfg>
 struct TileAcc {
@@ -118,54 +156,74 @@ struct TileAcc {
   }
 };
 
-template <class Cfg>
+template <class Cfg, int ROWS, bool KC>
 __device__ inline typename Cfg::MM::frag load_frag(const typename Cfg::T* s, int row, int kk,
                                                    int lane) {
   typedef typename Cfg::MM MM;
-  const typename Cfg::T* p = s + row * Cfg::LDK + kk + (lane >> 4) * MM::EPL;
+  typedef SliceLayout<typename Cfg::T, ROWS, Cfg::BK, KC> L;
   if constexpr (MM::EPL == 1) {
-    return *p;
+    return s[L::at(row, kk + (lane >> 4))];
   } else {
-    return *reinterpret_cast<const typename MM::frag*>(p);
+    static_assert(KC, "multi-element fragments need a k-contiguous slice");
+    return *reinterpret_cast<const typename MM::frag*>(s + L::at(row, kk + (lane >> 4) * MM::EPL));
   }
 }
 
 // acc += A(m0.., kb..ke) * B(n0.., kb..ke)^T over the k range [kb, ke).
+// smem must hold TileSmem<Cfg, KCA, KCB>::bytes.
 template <class Cfg, typename TGA, bool KCA, typename TGB, bool KCB>
 __device__ inline void tile_mainloop(TileAcc<Cfg>& acc, const GOperand<TGA, KCA>& A,
                                      const GOperand<TGB, KCB>& B, int64_t m0, int64_t n0,
                                      int64_t kb, int64_t ke, typename Cfg::T* smem) {
   typedef typename Cfg::T T;
   typedef typename Cfg::MM MM;
-  T* As = smem;
-  T* Bs = smem + Cfg::BM * Cfg::LDK;
+  typedef TileSmem<Cfg, KCA, KCB> SM;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave % Cfg::WAVES_M, wn = wave / Cfg::WAVES_M;
+  GOperand<TGA, KCA> a = A;
+  GOperand<TGB, KCB> b = B;
+  a.K = ke < A.K ? ke : A.K;
+  b.K = ke < B.K ? ke : B.K;
+  TileStage<T, Cfg::BM, Cfg::BK, Cfg::NT, TGA, KCA> sa;
+  TileStage<T, Cfg::BN, Cfg::BK, Cfg::NT, TGB, KCB> sb;
+  if (kb >= ke) return;
+  sa.load(a, m0, kb, tid);
+  sb.load(b, n0, kb, tid);
+  sa.store(smem, a, kb, tid);
+  sb.store(smem + SM::LA::ELEMS, b, kb, tid);
+  __syncthreads();
+  int buf = 0;
   for (int64_t k0 = kb; k0 < ke; k0 += Cfg::BK) {
-    GOperand<TGA, KCA> a = A;
-    GOperand<TGB, KCB> b = B;
-    a.K = ke < A.K ? ke : A.K;
-    b.K = ke < B.K ? ke : B.K;
-    stage_tile<T, Cfg::BM, Cfg::BK, Cfg::LDK, Cfg::NT>(As, a, m0, k0, tid);
-    stage_tile<T, Cfg::BN, Cfg::BK, Cfg::LDK, Cfg::NT>(Bs, b, n0, k0, tid);
-    __syncthreads();
+    const bool more = k0 + Cfg::BK < ke;
+    if (more) {
+      sa.load(a, m0, k0 + Cfg::BK, tid);
+      sb.load(b, n0, k0 + Cfg::BK, tid);
+    }
+    const T* As = smem + buf * SM::STAGE;
+    const T* Bs = As + SM::LA::ELEMS;
 #pragma unroll
     for (int kk = 0; kk < Cfg::BK; kk += MM::KS) {
       typename MM::frag fa[Cfg::MI], fb[Cfg::NI];
 #pragma unroll
       for (int i = 0; i < Cfg::MI; ++i)
-        fa[i] = load_frag<Cfg>(As, wm * Cfg::WTM + i * 16 + (lane & 15), kk, lane);
+        fa[i] = load_frag<Cfg, Cfg::BM, KCA>(As, wm * Cfg::WTM + i * 16 + (lane & 15), kk, lane);
 #pragma unroll
       for (int j = 0; j < Cfg::NI; ++j)
-        fb[j] = load_frag<Cfg>(Bs, wn * Cfg::WTN + j * 16 + (lane & 15), kk, lane);
+        fb[j] = load_frag<Cfg, Cfg::BN, KCB>(Bs, wn * Cfg::WTN + j * 16 + (lane & 15), kk, lane);
 #pragma unroll
       for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
         for (int j = 0; j < Cfg::NI; ++j) acc.a[i][j] = MM::mma(fa[i], fb[j], acc.a[i][j]);
     }
+    if (more) {
+      T* nA = smem + (buf ^ 1) * SM::STAGE;
+      sa.store(nA, a, k0 + Cfg::BK, tid);
+      sb.store(nA + SM::LA::ELEMS, b, k0 + Cfg::BK, tid);
+    }
     __syncthreads();
+    buf ^= 1;
   }
 }
 
