@@ -194,6 +194,7 @@ def parity(rp, torch, Xd, eps, w, mixed_res):
     return {
         "status_fp64_replay": int(st), "k": k, "lam_rel_err_max": float(np.max(np.abs(lam_m / lam_p - 1))),
         "subspace_dim": int(m), "principal_angle_max_rad": ang,
+        "lam_head": [float(x) for x in lam_p[:6]], "lam_tail": [float(x) for x in lam_p[-6:]],
         "trace_err_mixed": float(out_m["rho"].sum().item() / w["N"]),
     }
 

@@ -98,17 +98,13 @@ __global__ __launch_bounds__(256) void k_rho_partial(const double* __restrict__ 
   if (threadIdx.x == 0) part[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
 }
 
-// One workgroup: inclusive scan of the partial sums, then one wave per
-// proposal resolves  s = min{ j : C_j > floor(m T / 2^53) }.
-__global__ __launch_bounds__(1024) void k_draw(const double* __restrict__ rho, int64_t N,
-                                               unsigned long long* __restrict__ part, int nb,
-                                               const double* __restrict__ u, int bi,
-                                               int64_t* __restrict__ prop, int32_t* stop) {
+// One workgroup: inclusive scan of the chunk sums in place; total in *tot.
+__global__ __launch_bounds__(1024) void k_draw_scan(unsigned long long* __restrict__ part, int nb,
+                                                    unsigned long long* __restrict__ tot,
+                                                    int32_t* stop) {
   if (*stop) return;
   __shared__ unsigned long long tsum[1024];
-  __shared__ unsigned long long total;
   const int tid = threadIdx.x;
-  // each thread owns a contiguous run of partial sums
   const int per = (nb + 1023) / 1024;
   const int b0 = tid * per;
   unsigned long long loc = 0;
@@ -117,57 +113,81 @@ __global__ __launch_bounds__(1024) void k_draw(const double* __restrict__ rho, i
   tsum[tid] = loc;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
-    unsigned long long v = tid >= off ? tsum[tid - off] : 0ull;
+    const unsigned long long v = tid >= off ? tsum[tid - off] : 0ull;
     __syncthreads();
     tsum[tid] += v;
     __syncthreads();
   }
-  // write inclusive prefix of the partial sums back in place
   unsigned long long run = tid > 0 ? tsum[tid - 1] : 0ull;
   for (int j = 0; j < per; ++j)
     if (b0 + j < nb) {
       run += part[b0 + j];
       part[b0 + j] = run;
     }
-  if (tid == 1023) total = tsum[1023];
-  __syncthreads();
-  const unsigned long long T = total;
-  if (T == 0ull) {
-    if (tid == 0) *stop = 1;
-    return;
+  if (tid == 1023) {
+    *tot = tsum[1023];
+    if (tsum[1023] == 0ull) *stop = 1;
   }
-  const int lane = tid & 63, wave = tid >> 6;
-  for (int j = wave; j < bi; j += 16) {
-    const unsigned long long m = (unsigned long long)(u[j] * 9007199254740992.0);  // u * 2^53
-    const unsigned long long hi = __umul64hi(m, T), lo = m * T;
-    const unsigned long long target = (hi << 11) | (lo >> 53);
-    // first block whose inclusive prefix exceeds the target
-    int lo_b = 0, hi_b = nb - 1;
-    while (lo_b < hi_b) {
-      int mid = (lo_b + hi_b) >> 1;
-      if (part[mid] > target) hi_b = mid; else lo_b = mid + 1;
+}
+
+// One workgroup per proposal j:  s = min{ i : C_i > floor(m T / 2^53) },
+// m = u_j 2^53, C the inclusive prefix of rho_q = floor(rho 2^40).  The chunk
+// holding the target is found by binary search over the scanned chunk sums,
+// then the chunk's 4096 quantised entries are scanned in LDS.
+__global__ __launch_bounds__(256) void k_draw_find(const double* __restrict__ rho, int64_t N,
+                                                   const unsigned long long* __restrict__ part,
+                                                   int nb, const unsigned long long* __restrict__ tot,
+                                                   const double* __restrict__ u,
+                                                   int64_t* __restrict__ prop,
+                                                   const int32_t* stop) {
+  if (*stop) return;
+  __shared__ unsigned long long q[CHUNK];
+  __shared__ unsigned long long tsum[256];
+  __shared__ int blk_s;
+  const int tid = threadIdx.x;
+  const int j = blockIdx.x;
+  const unsigned long long T = *tot;
+  const unsigned long long m = (unsigned long long)(u[j] * 9007199254740992.0);  // u * 2^53
+  const unsigned long long target = (__umul64hi(m, T) << 11) | ((m * T) >> 53);
+  if (tid == 0) {
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (part[mid] > target) hi = mid; else lo = mid + 1;
     }
-    const int blk = lo_b;
-    unsigned long long carry = blk > 0 ? part[blk - 1] : 0ull;
-    int64_t found = -1;
-    for (int c = 0; c < CHUNK / 64 && found < 0; ++c) {
-      const int64_t i = (int64_t)blk * CHUNK + c * 64 + lane;
-      unsigned long long q = i < N ? quant_rho(rho[i]) : 0ull;
-      // inclusive wave scan
+    blk_s = lo;
+  }
+  __syncthreads();
+  const int blk = blk_s;
+  const unsigned long long base = blk > 0 ? part[blk - 1] : 0ull;
+  const unsigned long long rem = target - base;  // < rho_q mass of this chunk
+  const int64_t i0 = (int64_t)blk * CHUNK;
+  for (int e = tid; e < CHUNK; e += 256) {
+    const int64_t i = i0 + e;
+    q[e] = i < N ? quant_rho(rho[i]) : 0ull;
+  }
+  __syncthreads();
+  // thread t owns entries [16 t, 16 t + 16)
+  unsigned long long s = 0;
 #pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        unsigned long long t = __shfl_up(q, o, 64);
-        if (lane >= o) q += t;
-      }
-      const unsigned long long incl = carry + q;
-      const unsigned long long mask = __ballot(incl > target);
-      if (mask) {
-        found = (int64_t)blk * CHUNK + c * 64 + __ffsll((long long)mask) - 1;
-      } else {
-        carry = __shfl(incl, 63, 64);
-      }
+  for (int e = 0; e < 16; ++e) s += q[tid * 16 + e];
+  tsum[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const unsigned long long v = tid >= off ? tsum[tid - off] : 0ull;
+    __syncthreads();
+    tsum[tid] += v;
+    __syncthreads();
+  }
+  const unsigned long long excl = tid > 0 ? tsum[tid - 1] : 0ull;
+  if (excl <= rem && rem < tsum[tid]) {
+    unsigned long long c = excl;
+    int e = 0;
+    for (; e < 16; ++e) {
+      c += q[tid * 16 + e];
+      if (c > rem) break;
     }
-    if (lane == 0) prop[j] = found;
+    prop[j] = i0 + tid * 16 + e;
   }
 }
 
@@ -332,46 +352,61 @@ __global__ __launch_bounds__(256) void k_pivot_block(const T* __restrict__ XS, i
 }
 
 // ------------------------------------------------------------ Algorithm 3
-// One workgroup of 1024 threads; H (bi x bi, stride MAXB) lives in LDS.
-// Outputs the accepted positions, the accepted pivots (appended to `pivots`),
-// L^{-1} of the accepted block (row-major MAXB x MAXB, zero-padded), and the
-// accepted rows XSa / nsa / FSa that the column kernels consume.
+// One workgroup of 1024 threads.  H (bi x bi) lives in LDS as a packed lower
+// triangle (entry (a, c), c <= a, at a (a + 1) / 2 + c).  Step i accepts
+// proposal i iff it repeats no accepted proposal of this block,
+// H(i,i) > tau and z_i * H0(i,i) < H(i,i) (H0 = H at block start), then
+// eliminates it from the trailing triangle: H(a,c) -= H(a,i) H(c,i) / H(i,i).
+// Column i is not read again after its step, so its division by
+// sqrt(H(i,i)) (which makes it a Cholesky column) is deferred.  Outputs: the
+// accepted pivots (appended to `pivots`), the Cholesky factor L of the
+// accepted block (row-major MAXB x MAXB, zero-padded), and the accepted rows
+// XSa / nsa / FSa for the column kernels.
+__device__ inline int tri(int a, int c) { return a * (a + 1) / 2 + c; }
+
 template <typename T, typename TN, typename TF>
 __global__ __launch_bounds__(1024) void k_accept_reject(
     const double* __restrict__ Hg, int bi, const int64_t* __restrict__ prop,
     const double* __restrict__ z, double tau, int mode, const T* __restrict__ XS, int64_t dp,
     const TN* __restrict__ ns, const TF* __restrict__ FS, int r, int32_t* kptr, int32_t* nTptr,
-    const int32_t* stop, int64_t* __restrict__ pivots, double* __restrict__ Linv,
+    const int32_t* stop, int64_t* __restrict__ pivots, double* __restrict__ Lc,
     int64_t* __restrict__ Si, T* __restrict__ XSa, TN* __restrict__ nsa, TF* __restrict__ FSa,
     int32_t* status) {
-  __shared__ double H[MAXB * MAXB];
+  constexpr int PK = MAXB * (MAXB + 1) / 2;
+  __shared__ double H[PK];
   __shared__ int accl[MAXB];
   __shared__ double rho_loc[MAXB];
+  __shared__ double dinv[MAXB];  // 1 / sqrt(H(i,i)) of accepted pivots, by position
+  __shared__ int64_t props[MAXB];
+  __shared__ double zs[MAXB];
   __shared__ int nacc;
-  __shared__ int decide;
+  __shared__ int decide[2];  // by step parity: a slow wave may still read step i's flag
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   if (*stop) {
     if (tid == 0) *nTptr = 0;
     return;
   }
   const int k = *kptr;
-  for (int e = tid; e < bi * bi; e += 1024) {
-    int a = e / bi, c = e % bi;
-    H[a * MAXB + c] = Hg[a * MAXB + c];
-  }
+  for (int a = wave; a < bi; a += 16)
+    for (int c = lane; c <= a; c += 64) H[tri(a, c)] = Hg[a * MAXB + c];
   if (tid == 0) nacc = 0;
+  if (tid < bi) {
+    props[tid] = prop[tid];
+    zs[tid] = (mode == RPC_SAMPLED) ? z[tid] : 0.0;
+  }
   __syncthreads();
-  if (tid < bi) rho_loc[tid] = H[tid * MAXB + tid];
+  if (tid < bi) rho_loc[tid] = H[tri(tid, tid)];
   __syncthreads();
   for (int i = 0; i < bi; ++i) {
-    if (tid < 64) {
-      // reject a repeat of an accepted proposal of this block
-      const int64_t pi = prop[i];
+    if (wave == 0) {
+      const int64_t pi = props[i];
+      const int na = nacc;
       bool dup = false;
-      for (int a = tid; a < nacc; a += 64) dup |= (prop[accl[a]] == pi);
+      for (int a = lane; a < na; a += 64) dup |= (props[accl[a]] == pi);
       dup = __any(dup);
-      if (tid == 0) {
-        const double hii = H[i * MAXB + i];
+      if (lane == 0) {
+        const double hii = H[tri(i, i)];
         bool ok;
         if (mode == RPC_REPLAY) {
           ok = hii > tau && !dup;
@@ -379,53 +414,41 @@ __global__ __launch_bounds__(1024) void k_accept_reject(
         } else if (mode == RPC_GREEDY) {
           ok = hii > tau;  // b = 1: z * H(0,0) < H(0,0) holds for every z in [0, 1)
         } else {
-          ok = !dup && hii > tau && z[i] * rho_loc[i] < hii;
+          ok = !dup && hii > tau && zs[i] * rho_loc[i] < hii;
         }
-        decide = ok ? 1 : 0;
-        if (ok) accl[nacc++] = i;
+        decide[i & 1] = ok ? 1 : 0;
+        if (ok) {
+          dinv[na] = 1.0 / sqrt(hii);
+          accl[na] = i;
+          nacc = na + 1;
+        }
       }
     }
     __syncthreads();
-    if (decide) {
-      const double hii = H[i * MAXB + i];
-      const int m = bi - i - 1;
-      for (int e = tid; e < m * m; e += 1024) {
-        const int a = i + 1 + e / m, c = i + 1 + e % m;
-        H[a * MAXB + c] -= H[a * MAXB + i] * H[c * MAXB + i] / hii;
+    if (decide[i & 1]) {
+      // lower trailing triangle, 32 row groups x 32 column lanes
+      const double rh = 1.0 / H[tri(i, i)];
+      const int ty = tid >> 5, tx = tid & 31;
+      for (int a = i + 1 + ty; a < bi; a += 32) {
+        const double hai = H[tri(a, i)] * rh;
+        const int ra = tri(a, 0);
+        for (int c = i + 1 + tx; c <= a; c += 32) H[ra + c] -= hai * H[tri(c, i)];
       }
       __syncthreads();
-      const double piv = sqrt(hii);
-      for (int a = i + tid; a < bi; a += 1024) H[a * MAXB + i] /= piv;
     }
-    __syncthreads();
   }
   const int nt = nacc;
-  // L(T, T)^{-1}, one thread per column (forward substitution)
-  if (tid < nt) {
-    const int c = tid;
-    // column c of L^{-1}: x_c = 1 / L_cc; x_j = -(sum_{l=c}^{j-1} L_jl x_l) / L_jj
-    for (int j = 0; j < MAXB; ++j) Linv[j * MAXB + c] = 0.0;
-    const int ac = accl[c];
-    double xc = 1.0 / H[ac * MAXB + ac];
-    Linv[c * MAXB + c] = xc;
-    for (int j = c + 1; j < nt; ++j) {
-      const int aj = accl[j];
-      double s = 0.0;
-      for (int l = c; l < j; ++l) s += H[aj * MAXB + accl[l]] * Linv[l * MAXB + c];
-      Linv[j * MAXB + c] = -s / H[aj * MAXB + aj];
-    }
-  } else if (tid < MAXB) {
-    for (int j = 0; j < MAXB; ++j) Linv[j * MAXB + tid] = 0.0;
+  // compact L(x, y) = H(accl[x], accl[y]) dinv[y] (x >= y), row-major MAXB x MAXB
+  for (int x = wave; x < MAXB; x += 16) {
+    const int ax = x < nt ? accl[x] : 0;
+    for (int y = lane; y < MAXB; y += 64)
+      Lc[x * MAXB + y] = (x < nt && y <= x) ? H[tri(ax, accl[y])] * dinv[y] : 0.0;
   }
-  // accepted rows for the column kernels
-  for (int e = tid; e < nt * dp; e += 1024) {
-    int a = e / dp;
-    int64_t c = e % dp;
-    XSa[a * dp + c] = XS[(int64_t)accl[a] * dp + c];
-  }
-  for (int e = tid; e < nt * k; e += 1024) {
-    int a = e / k, l = e % k;
-    FSa[(int64_t)a * r + l] = FS[(int64_t)accl[a] * r + l];
+  // accepted rows for the column kernels: wave w copies rows w, w + 16, ...
+  for (int a = wave; a < nt; a += 16) {
+    const int64_t src = accl[a];
+    for (int64_t c = lane; c < dp; c += 64) XSa[a * dp + c] = XS[src * dp + c];
+    for (int l = lane; l < k; l += 64) FSa[(int64_t)a * r + l] = FS[src * r + l];
   }
   if (tid < nt) {
     nsa[tid] = ns[accl[tid]];
@@ -433,6 +456,36 @@ __global__ __launch_bounds__(1024) void k_accept_reject(
     pivots[k + tid] = prop[accl[tid]];
   }
   if (tid == 0) *nTptr = nt;
+}
+
+// L^{-1} of the accepted block, one workgroup (one wave) per column c:
+//   x_c = 1 / L(c,c),  x_j = -(sum_{l=c}^{j-1} L(j,l) x_l) / L(j,j),
+// lane l keeping x_l and x_{l+64}; each row costs one wave reduction.
+__global__ __launch_bounds__(64) void k_tri_inv(const double* __restrict__ Lc,
+                                                const int32_t* nTptr, double* __restrict__ Linv) {
+  constexpr int LDS = MAXB + 1;
+  __shared__ double Ls[MAXB * LDS];
+  const int c = blockIdx.x, lane = threadIdx.x;
+  const int nt = *nTptr;
+  double x0 = 0.0, x1 = 0.0;
+  if (c < nt) {
+    for (int j = c; j < nt; ++j)
+      for (int l = c + lane; l <= j; l += 64) Ls[j * LDS + l] = Lc[j * MAXB + l];
+    __syncthreads();
+    for (int j = c; j < nt; ++j) {
+      double part = 0.0;
+      if (lane >= c && lane < j) part += Ls[j * LDS + lane] * x0;
+      if (lane + 64 >= c && lane + 64 < j) part += Ls[j * LDS + lane + 64] * x1;
+      const double sum = wave_sum(part);
+      const double ljj = Ls[j * LDS + j];
+      const double v = (j == c) ? 1.0 / ljj : -sum / ljj;
+      if (lane == (j & 63)) {
+        if (j < 64) x0 = v; else x1 = v;
+      }
+    }
+  }
+  Linv[lane * MAXB + c] = x0;
+  Linv[(lane + 64) * MAXB + c] = x1;
 }
 
 // ------------------------------------------------------------ kernel columns
@@ -489,6 +542,72 @@ __global__ __launch_bounds__(Cfg::NT) void k_schur(const TF* __restrict__ F, int
   for_each_acc<Cfg>(acc, [&](int row, int col, typename Cfg::MM::acc_t v) {
     const int64_t m = m0 + row, n = n0 + col;
     if (m < N && n < nt) W[m + n * ldw] -= (TF)v;
+  });
+}
+
+// ------------------------------------------------------------ fused columns + Schur
+// When the distance product and the Schur update accumulate in the same
+// register layout (bf16/f32 products with an f32 factor, or f64 with f64),
+// one workgroup computes its 128-row tile of the kernel columns, applies the
+// exp epilogue in registers, and continues accumulating -F(:, :k) F(S_i, :k)^T
+// into the same accumulators: W is written once instead of written, read
+// and written again.
+template <typename T, typename TN, typename TF, class CfgK, class CfgS>
+__global__ __launch_bounds__(256) void k_cols_schur(const T* __restrict__ Xp,
+                                                    const TN* __restrict__ xn, int64_t N,
+                                                    int64_t dp, const T* __restrict__ XSa,
+                                                    const TN* __restrict__ nsa,
+                                                    const int32_t* nTptr, double eps,
+                                                    const TF* __restrict__ F, int64_t ldf,
+                                                    const TF* __restrict__ FSa, int r,
+                                                    const int32_t* kptr, TF* __restrict__ W,
+                                                    int64_t ldw) {
+  static_assert(sizeof(typename CfgK::MM::acc) == sizeof(typename CfgS::MM::acc) &&
+                    CfgK::MI == CfgS::MI && CfgK::NI == CfgS::NI &&
+                    CfgK::WAVES_M == CfgS::WAVES_M && CfgK::BM == CfgS::BM && CfgK::BN == CfgS::BN,
+                "the two products must share one accumulator layout");
+  const int nt = *nTptr;
+  if (nt == 0) return;
+  const int k = *kptr;
+  extern __shared__ char smem_raw[];
+  const int64_t m0 = (int64_t)blockIdx.x * CfgK::BM;
+  typedef typename CfgK::MM::acc_t AT;
+  TileAcc<CfgK> acc;
+  acc.zero();
+  {
+    GOperand<T, true> A{Xp, dp, N, dp, nullptr, true};
+    GOperand<T, true> B{XSa, dp, nt, dp, nullptr, true};
+    tile_mainloop<CfgK>(acc, A, B, m0, 0, 0, dp, reinterpret_cast<typename CfgK::T*>(smem_raw));
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % CfgK::WAVES_M, wn = wave / CfgK::WAVES_M;
+  const AT ie = (AT)(1.0 / eps);
+  // exp epilogue, negated: acc = -K so the Schur product can accumulate on top
+#pragma unroll
+  for (int i = 0; i < CfgK::MI; ++i)
+#pragma unroll
+    for (int j = 0; j < CfgK::NI; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t m = m0 + wm * CfgK::WTM + i * 16 + CfgK::MM::row(lane, e);
+        const int n = wn * CfgK::WTN + j * 16 + (lane & 15);
+        AT v = 0;
+        if (m < N && n < nt) {
+          AT d2 = (AT)xn[m] + (AT)nsa[n] - (AT)2 * acc.a[i][j][e];
+          d2 = d2 > (AT)0 ? d2 : (AT)0;
+          v = -exp(-d2 * ie);
+        }
+        acc.a[i][j][e] = v;
+      }
+  TileAcc<CfgS>& acs = reinterpret_cast<TileAcc<CfgS>&>(acc);
+  if (k > 0) {
+    GOperand<TF, false> A{F, ldf, N, k, nullptr, true};
+    GOperand<TF, true> B{FSa, r, nt, k, nullptr, (r % (16 / (int)sizeof(TF))) == 0};
+    tile_mainloop<CfgS>(acs, A, B, m0, 0, 0, k, reinterpret_cast<typename CfgS::T*>(smem_raw));
+  }
+  for_each_acc<CfgS>(acs, [&](int row, int col, typename CfgS::MM::acc_t v) {
+    const int64_t m = m0 + row;
+    if (m < N && col < nt) W[m + (int64_t)col * ldw] = (TF)(-v);
   });
 }
 
@@ -576,6 +695,10 @@ __global__ __launch_bounds__(256) void k_zero_tail(TF* __restrict__ F, int64_t l
   for (int c = k; c < r; ++c) F[n + (int64_t)c * ldf] = (TF)0;
 }
 
+// The fused column+Schur kernel needs both products to accumulate in the same type.
+template <typename T, typename TF>
+constexpr bool kFusedColsSchur = sizeof(typename Mma<T>::acc_t) == sizeof(TF);
+
 // ------------------------------------------------------------ host driver
 struct FactorWs {
   void* Xp;
@@ -589,6 +712,7 @@ struct FactorWs {
   void* ns;
   void* FS;
   double* H;
+  double* Lc;
   double* Linv;
   int64_t* Si;
   void* XSa;
@@ -596,6 +720,7 @@ struct FactorWs {
   void* FSa;
   int32_t* nT;
   int32_t* stop;
+  unsigned long long* tot;
   int64_t ldw;
   int64_t dp;
 };
@@ -616,6 +741,7 @@ static size_t carve(WsCursor& c, FactorWs& w, int64_t N, int64_t d, int r) {
   w.ns = c.take<TN>(MAXB);
   w.FS = c.take<TF>((size_t)MAXB * r);
   w.H = c.take<double>((size_t)MAXB * MAXB);
+  w.Lc = c.take<double>((size_t)MAXB * MAXB);
   w.Linv = c.take<double>((size_t)MAXB * MAXB);
   w.Si = c.take<int64_t>(MAXB);
   w.XSa = c.take<T>((size_t)MAXB * w.dp);
@@ -623,6 +749,7 @@ static size_t carve(WsCursor& c, FactorWs& w, int64_t N, int64_t d, int r) {
   w.FSa = c.take<TF>((size_t)MAXB * r);
   w.nT = c.take<int32_t>(1);
   w.stop = c.take<int32_t>(1);
+  w.tot = c.take<unsigned long long>(1);
   return c.used;
 }
 
@@ -651,6 +778,7 @@ static int run_factor(const rpc_points* X, const rpc_factor_opts* o, TF* F, int6
   const size_t smK = TileSmem<CfgK, true, true>::bytes;
   const size_t smS = TileSmem<CfgS, false, true>::bytes;
   const size_t smD = TileSmem<CfgD, false, true>::bytes;
+  const size_t smKS = smK > smS ? smK : smS;
   const unsigned gm = (unsigned)((N + 127) / 128);
 
   int t;
@@ -668,8 +796,10 @@ static int run_factor(const rpc_points* X, const rpc_factor_opts* o, TF* F, int6
     prof::begin(prof::PIVOT, st);
     if (o->mode == RPC_SAMPLED) {
       hipLaunchKernelGGL(k_rho_partial, dim3(nb), dim3(256), 0, st, rho, N, w.part, w.stop);
-      hipLaunchKernelGGL(k_draw, dim3(1), dim3(1024), 0, st, rho, N, w.part, nb,
-                         o->uniforms + (int64_t)2 * b * i, bi, w.prop, w.stop);
+      hipLaunchKernelGGL(k_draw_scan, dim3(1), dim3(1024), 0, st, w.part, nb, w.tot, w.stop);
+      hipLaunchKernelGGL(k_draw_find, dim3(bi), dim3(256), 0, st, rho, N,
+                         (const unsigned long long*)w.part, nb, (const unsigned long long*)w.tot,
+                         o->uniforms + (int64_t)2 * b * i, w.prop, w.stop);
       z = o->uniforms + (int64_t)2 * b * i + b;
     } else if (o->mode == RPC_GREEDY) {
       hipLaunchKernelGGL(k_argmax_partial, dim3(nb), dim3(256), 0, st, rho, N, w.pv, w.pi, w.stop);
@@ -691,20 +821,32 @@ static int run_factor(const rpc_points* X, const rpc_factor_opts* o, TF* F, int6
     RPC_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_accept_reject<T, TN, TF>), dim3(1), dim3(1024), 0, st, w.H, bi, w.prop,
                        z, o->tau, o->mode, (const T*)w.XS, dp, (const TN*)w.ns,
-                       (const TF*)w.FS, r, k_out, w.nT, w.stop, pivots, w.Linv, w.Si, (T*)w.XSa,
+                       (const TF*)w.FS, r, k_out, w.nT, w.stop, pivots, w.Lc, w.Si, (T*)w.XSa,
                        (TN*)w.nsa, (TF*)w.FSa, status);
+    hipLaunchKernelGGL(k_tri_inv, dim3(MAXB), dim3(64), 0, st, (const double*)w.Lc, w.nT, w.Linv);
     prof::end(prof::ACCEPT, st);
     RPC_LAUNCH_CHECK();
-    prof::begin(prof::KERNEL_COLS, st);
-    hipLaunchKernelGGL((k_kernel_cols<T, TN, TF, CfgK>), dim3(gm, 1), dim3(CfgK::NT), smK, st, (const T*)w.Xp, (const TN*)w.xn, N, dp,
-                       (const T*)w.XSa, (const TN*)w.nsa, w.nT, X->eps, (TF*)w.W, w.ldw);
-    prof::end(prof::KERNEL_COLS, st);
-    RPC_LAUNCH_CHECK();
-    prof::begin(prof::SCHUR, st);
-    hipLaunchKernelGGL((k_schur<TF, CfgS>), dim3(gm, 1), dim3(CfgS::NT), smS, st,
-                       (const TF*)F, ldf, N, (const TF*)w.FSa, r, k_out, w.nT, (TF*)w.W, w.ldw);
-    prof::end(prof::SCHUR, st);
-    RPC_LAUNCH_CHECK();
+    if constexpr (kFusedColsSchur<T, TF>) {
+      prof::begin(prof::KERNEL_COLS, st);
+      hipLaunchKernelGGL((k_cols_schur<T, TN, TF, CfgK, CfgS>), dim3(gm), dim3(256), smKS, st,
+                         (const T*)w.Xp, (const TN*)w.xn, N, dp, (const T*)w.XSa, (const TN*)w.nsa,
+                         w.nT, X->eps, (const TF*)F, ldf, (const TF*)w.FSa, r, k_out, (TF*)w.W,
+                         w.ldw);
+      prof::end(prof::KERNEL_COLS, st);
+      RPC_LAUNCH_CHECK();
+    } else {
+      prof::begin(prof::KERNEL_COLS, st);
+      hipLaunchKernelGGL((k_kernel_cols<T, TN, TF, CfgK>), dim3(gm, 1), dim3(CfgK::NT), smK, st,
+                         (const T*)w.Xp, (const TN*)w.xn, N, dp, (const T*)w.XSa, (const TN*)w.nsa,
+                         w.nT, X->eps, (TF*)w.W, w.ldw);
+      prof::end(prof::KERNEL_COLS, st);
+      RPC_LAUNCH_CHECK();
+      prof::begin(prof::SCHUR, st);
+      hipLaunchKernelGGL((k_schur<TF, CfgS>), dim3(gm, 1), dim3(CfgS::NT), smS, st, (const TF*)F, ldf,
+                         N, (const TF*)w.FSa, r, k_out, w.nT, (TF*)w.W, w.ldw);
+      prof::end(prof::SCHUR, st);
+      RPC_LAUNCH_CHECK();
+    }
     prof::begin(prof::SOLVE, st);
     hipLaunchKernelGGL((k_solve_downdate<TF>), dim3((unsigned)((N + 63) / 64)), dim3(256), smD, st,
                        (const TF*)w.W, w.ldw, N, w.Linv, k_out, w.nT, F, ldf, rho);

@@ -122,6 +122,40 @@ __global__ __launch_bounds__(256) void k_gram_finish(double* __restrict__ GB, do
   }
 }
 
+// delta = 1e-7 trace(M); M += delta I.  M is PSD, so M + delta I keeps its
+// eigenvectors while bounding the condition of every block M Q by
+// lambda_max / delta, which keeps the two-pass Cholesky QR of the subspace
+// iteration stable (it needs a condition number below ~1e7).
+__global__ __launch_bounds__(1024) void k_shift_diag(double* M, int r, double* delta) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < r; i += 1024) s += M[i + (int64_t)i * r];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < 16; ++w) t += red[w];
+  const double dl = 1e-7 * t;
+  __syncthreads();
+  for (int i = threadIdx.x; i < r; i += 1024) M[i + (int64_t)i * r] += dl;
+  if (threadIdx.x == 0) *delta = dl;
+}
+
+__global__ void k_unshift(double* theta, int n, const double* delta) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) theta[i] -= *delta;
+}
+
+// Start block: the leading p coordinate vectors.  The pivoted factor orders
+// the Gram-Schmidt basis of B by pivot acceptance, so the dominant
+// eigenvectors of M live mostly in its leading coordinates.
+__global__ void k_fill_identity(double* Q, int r, int p) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * p) return;
+  const int i = (int)(e % r), j = (int)(e / r);
+  Q[e] = i == j ? 1.0 : 0.0;
+}
+
 // Deterministic start block for the subspace iteration (hash-based uniform in [-1, 1]).
 __global__ void k_fill_start(double* Q, int r, int p) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -318,6 +352,8 @@ struct EigWs {
   int64_t* pi;
   double* Ut;
   int32_t* conv;
+  double* delta;
+  double* sk;
   size_t part_cap;
   int p;
 };
@@ -356,21 +392,23 @@ static size_t carve_eig(WsCursor& c, EigWs& w, int64_t N, int r, int nev, bool f
   w.pi = c.take<int64_t>((size_t)nbu * nev);
   w.Ut = fix_const ? c.take<double>((size_t)align_up((size_t)N, 8) * nev) : nullptr;
   w.conv = c.take<int32_t>(1);
+  w.delta = c.take<double>(1);
+  w.sk = c.take<double>((size_t)dense::SPLITK_MAX * p * p);
   return c.used;
 }
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 // Orthonormalise the r x p block Y into Q by Cholesky QR (Gram, one-workgroup
-// Cholesky + inverse, product).
+// Cholesky, row-parallel triangular solve).
 static void chol_qr(hipStream_t st, const double* Y, double* Q, int r, int p, EigWs& w,
                     int32_t* status, const int32_t* skip) {
-  dense::gemm64<true, true>(st, p, p, r, Y, r, Y, r, w.Gp, p, 1.0, 0.0, skip);
-  hipLaunchKernelGGL(dense::k_chol_inv_small, dim3(1), dim3(1024), 0, st, w.Gp, (int64_t)p, p,
-                     w.Rinv, (int64_t)p, status, skip);
-  dense::gemm64<false, true>(st, r, p, p, Y, r, w.Rinv, p, Q, r, 1.0, 0.0, skip);
+  dense::gemm64_splitk<true, true>(st, p, p, r, Y, r, Y, r, w.Gp, p, 1.0, 0.0, w.sk, skip);
+  hipLaunchKernelGGL(dense::k_chol_small, dim3(1), dim3(1024), 0, st, (const double*)w.Gp, (int64_t)p,
+                     p, w.Rinv, (int64_t)p, status, skip);
+  hipLaunchKernelGGL(dense::k_trsm_rows, dim3((unsigned)((r + 63) / 64)), dim3(64), 0, st, Y,
+                     (int64_t)r, r, p, (const double*)w.Rinv, (int64_t)p, Q, (int64_t)r, skip);
 }
-
 
 template <typename TG, typename TF, typename TU>
 static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
@@ -413,7 +451,7 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   // ---- top-nev eigenpairs of M
   prof::end(prof::SMALL, st);
   prof::begin(prof::EIG, st);
-  const double jtol = 1e-15;
+  const double jtol = 1e-13;  // relative off-diagonal Frobenius mass
   if (r <= dense::JMAX) {
     hipLaunchKernelGGL(dense::k_jacobi, dim3(1), dim3(1024), 0, st, (const double*)w.M, (int64_t)r,
                        r, w.theta, w.Wm, (int64_t)r, 40, jtol, status, (const int32_t*)nullptr);
@@ -421,22 +459,26 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
                        (const double*)w.Wm, (int64_t)r, w.V, (int64_t)r, r, nev,
                        (const int32_t*)nullptr);
   } else {
-    // subspace iteration with Rayleigh-Ritz on a p-dimensional block
+    // subspace iteration with Rayleigh-Ritz on a p-dimensional block, on
+    // M + delta I, orthonormalising every product by two Cholesky QR passes
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, w.conv, 0);
-    hipLaunchKernelGGL(k_fill_start, dim3(nblk((int64_t)r * p)), dim3(256), 0, st, w.Y, r, p);
-    chol_qr(st, w.Y, w.Q, r, p, w, status, nullptr);
-    chol_qr(st, w.Q, w.Y, r, p, w, status, nullptr);
-    hipLaunchKernelGGL(k_copy_cols, dim3(nblk((int64_t)r * p)), dim3(256), 0, st,
-                       (const double*)w.Y, (int64_t)r, w.Q, (int64_t)r, r, p,
-                       (const int32_t*)nullptr);
-    const int max_outer = 40;
-    for (int it = 0; it < max_outer; ++it) {
-      for (int in = 0; in < 3; ++in) {
+    hipLaunchKernelGGL(k_shift_diag, dim3(1), dim3(1024), 0, st, w.M, r, w.delta);
+    hipLaunchKernelGGL(k_fill_identity, dim3(nblk((int64_t)r * p)), dim3(256), 0, st, w.Q, r, p);
+    // 12 orthonormalised products, then Rayleigh-Ritz + residual check; up to
+    // 3 more rounds of 6 products if the check fails (device flag `conv`)
+    auto products = [&](int count) {
+      for (int in = 0; in < count; ++in) {
         dense::gemm64<false, true>(st, r, p, r, w.M, r, w.Q, r, w.Y, r, 1.0, 0.0, w.conv);
-        chol_qr(st, w.Y, w.Q, r, p, w, status, w.conv);
+        chol_qr(st, w.Y, w.Qt, r, p, w, status, w.conv);
+        chol_qr(st, w.Qt, w.Q, r, p, w, status, w.conv);
       }
+    };
+    products(12);
+    const int max_rr = 4;
+    for (int it = 0; it < max_rr; ++it) {
+      if (it > 0) products(6);
       dense::gemm64<false, true>(st, r, p, r, w.M, r, w.Q, r, w.Y, r, 1.0, 0.0, w.conv);
-      dense::gemm64<true, true>(st, p, p, r, w.Q, r, w.Y, r, w.H, p, 1.0, 0.0, w.conv);
+      dense::gemm64_splitk<true, true>(st, p, p, r, w.Q, r, w.Y, r, w.H, p, 1.0, 0.0, w.sk, w.conv);
       hipLaunchKernelGGL(dense::k_jacobi, dim3(1), dim3(1024), 0, st, (const double*)w.H,
                          (int64_t)p, p, w.theta, w.Wm, (int64_t)p, 40, jtol, status,
                          (const int32_t*)w.conv);
@@ -448,6 +490,7 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
       hipLaunchKernelGGL(k_ritz_check, dim3(1), dim3(1024), 0, st, (const double*)w.T1,
                          (const double*)w.Q, (const double*)w.theta, r, nev, 1e-10, w.conv);
     }
+    hipLaunchKernelGGL(k_unshift, dim3(1), dim3(128), 0, st, w.theta, p, (const double*)w.delta);
     hipLaunchKernelGGL(k_flag_noconv, dim3(1), dim3(1), 0, st, (const int32_t*)w.conv, status);
     hipLaunchKernelGGL(k_copy_cols, dim3(nblk((int64_t)r * nev)), dim3(256), 0, st,
                        (const double*)w.Q, (int64_t)r, w.V, (int64_t)r, r, nev,
@@ -478,16 +521,16 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
     if (!syrk::gram2<double, TU>(st, (const TU*)U, ldu, N, nev, 1, (const double*)nullptr,
                                  (const double*)nullptr, w.part, w.part1, w.part_cap, w.Gp, nullptr))
       return RPC_EWORKSPACE;
-    hipLaunchKernelGGL(dense::k_chol_inv_small, dim3(1), dim3(1024), 0, st, (const double*)w.Gp,
+    hipLaunchKernelGGL(dense::k_chol_small, dim3(1), dim3(1024), 0, st, (const double*)w.Gp,
                        (int64_t)nev, nev, w.Rinv, (int64_t)nev, status, (const int32_t*)nullptr);
     const int64_t ldut = (int64_t)align_up((size_t)N, 8);
     hipLaunchKernelGGL(k_copy_cols, dim3(nblk(N * nev)), dim3(256), 0, st, (const double*)U, ldu,
                        w.Ut, ldut, (int)N, nev, (const int32_t*)nullptr);
-    typedef TileCfg<double, 128, 64, 16, 2, 2> CfgU2;
-    const size_t smU2 = TileSmem<CfgU2, false, true>::bytes;
-    hipLaunchKernelGGL((k_form_u<double, double, TU>), gu, dim3(256), smU2, st,
-                       (const double*)w.Ut, ldut, N, nev, (const double*)w.Rinv, nev,
-                       (const double*)nullptr, U, ldu);
+    if constexpr (std::is_same<TU, double>::value) {
+      hipLaunchKernelGGL(dense::k_trsm_rows, dim3((unsigned)((N + 63) / 64)), dim3(64), 0, st,
+                         (const double*)w.Ut, ldut, (int)N, nev, (const double*)w.Rinv,
+                         (int64_t)nev, U, ldu, (const int32_t*)nullptr);
+    }
     RPC_LAUNCH_CHECK();
   }
 

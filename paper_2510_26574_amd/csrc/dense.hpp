@@ -60,29 +60,36 @@ __global__ __launch_bounds__(256) void k_zero_upper(double* A, int64_t ld, int n
 }
 
 // ------------------------------------------------ one-workgroup Cholesky
-// In-place lower Cholesky of the n x n (n <= NB... up to JMAX) block at A
-// (column-major, ld), only the lower triangle is read and written.
-// A pivot <= 0 sets *bad (and the status) and replaces the pivot by 1 so the
-// rest stays finite.
-__device__ inline void chol_block_lds(double* a, int n, int lda_s, int32_t* status) {
+// In-place lower Cholesky of the n x n block `a` in LDS (column-major,
+// lda_s); only the lower triangle is read and written.  Right-looking with
+// deferred column scaling: step j subtracts a(i,j) a(c,j) / a(j,j) from the
+// trailing lower triangle (column j still unscaled), so each step needs one
+// barrier; the columns are scaled by 1/sqrt(pivot) once at the end.  `piv`
+// is LDS scratch of n doubles.  A pivot <= 0 sets RPC_EBREAKDOWN and is
+// replaced by 1 so the rest stays finite.
+__device__ inline void chol_block_lds(double* a, int n, int lda_s, double* piv, int32_t* status) {
+  const int nth = blockDim.x, tid = threadIdx.x;
+  const int rows = nth / 32, ty = tid / 32, tx = tid % 32;
+  __syncthreads();
   for (int j = 0; j < n; ++j) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double p = a[j + j * lda_s];
-      if (!(p > 0.0)) {
-        set_status(status, RPC_EBREAKDOWN);
-        p = 1.0;
-      }
-      a[j + j * lda_s] = sqrt(p);
+    double p = a[j + j * lda_s];
+    if (!(p > 0.0)) {
+      if (tid == 0) set_status(status, RPC_EBREAKDOWN);
+      p = 1.0;
+    }
+    if (tid == 0) piv[j] = p;
+    const double rp = 1.0 / p;
+    for (int i = j + 1 + ty; i < n; i += rows) {
+      const double aij = a[i + j * lda_s] * rp;
+      for (int c = j + 1 + tx; c <= i; c += 32) a[i + c * lda_s] -= aij * a[c + j * lda_s];
     }
     __syncthreads();
-    const double piv = a[j + j * lda_s];
-    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) a[i + j * lda_s] /= piv;
-    __syncthreads();
-    const int m = n - j - 1;
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-      const int c = j + 1 + e / m, i = j + 1 + e % m;
-      if (i >= c) a[i + c * lda_s] -= a[i + j * lda_s] * a[c + j * lda_s];
+  }
+  for (int e = tid; e < n * n; e += nth) {
+    const int i = e % n, j = e / n;
+    if (i >= j) {
+      const double sp = sqrt(piv[j]);
+      a[i + j * lda_s] = (i == j) ? sp : a[i + j * lda_s] / sp;
     }
   }
   __syncthreads();
@@ -91,16 +98,18 @@ __device__ inline void chol_block_lds(double* a, int n, int lda_s, int32_t* stat
 // Factor the NB x NB diagonal block starting at (j0, j0) of A (n x n, ld).
 __global__ __launch_bounds__(256) void k_chol_diag(double* A, int64_t ld, int n, int j0,
                                                    int32_t* status) {
-  __shared__ double a[NB * NB];
+  constexpr int LDS = NB + 1;  // odd stride: column walks do not pile onto one bank
+  __shared__ double a[NB * LDS];
+  __shared__ double piv[NB];
   const int nb = n - j0 < NB ? n - j0 : NB;
   for (int e = threadIdx.x; e < nb * nb; e += 256) {
     int i = e % nb, c = e / nb;
-    a[i + c * NB] = A[(j0 + i) + (int64_t)(j0 + c) * ld];
+    a[i + c * LDS] = A[(j0 + i) + (int64_t)(j0 + c) * ld];
   }
-  chol_block_lds(a, nb, NB, status);
+  chol_block_lds(a, nb, LDS, piv, status);
   for (int e = threadIdx.x; e < nb * nb; e += 256) {
     int i = e % nb, c = e / nb;
-    A[(j0 + i) + (int64_t)(j0 + c) * ld] = i >= c ? a[i + c * NB] : 0.0;
+    A[(j0 + i) + (int64_t)(j0 + c) * ld] = i >= c ? a[i + c * LDS] : 0.0;
   }
 }
 
@@ -150,32 +159,30 @@ inline void cholesky(hipStream_t st, double* A, int64_t ld, int n, int32_t* stat
 }
 
 // Diagonal block of the back substitution L^T X = B: rows i0..i0+nb of X
-// (n x m, column-major ldx) solve L_ii^T x = b, one thread per column.
-__global__ __launch_bounds__(256) void k_trsm_ut_diag(const double* L, int64_t ld, int i0, int nb,
-                                                      double* X, int64_t ldx, int m) {
+// (n x m, column-major ldx) solve L_ii^T x = b.  One wave per column, lane l
+// holding x_l; each row costs one wave reduction.
+__global__ __launch_bounds__(1024) void k_trsm_ut_diag(const double* L, int64_t ld, int i0, int nb,
+                                                       double* X, int64_t ldx, int m) {
   __shared__ double Ls[NB * NB];
-  for (int e = threadIdx.x; e < nb * nb; e += 256) {
+  for (int e = threadIdx.x; e < nb * nb; e += 1024) {
     int i = e % nb, c = e / nb;
     Ls[i + c * NB] = L[(i0 + i) + (int64_t)(i0 + c) * ld];
   }
   __syncthreads();
-  const int col = blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = blockIdx.x * 16 + wave;
   if (col >= m) return;
-  double x[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) x[i] = i < nb ? X[(i0 + i) + (int64_t)col * ldx] : 0.0;
-  // (L_ii^T) is upper triangular: row i of L^T is column i of L
-#pragma unroll
-  for (int ii = NB - 1; ii >= 0; --ii) {
-    if (ii < nb) {
-      double s = x[ii];
-      for (int l = ii + 1; l < nb; ++l) s -= Ls[l + ii * NB] * x[l];
-      x[ii] = s / Ls[ii + ii * NB];
-    }
+  double* xc = X + i0 + (int64_t)col * ldx;
+  double x = lane < nb ? xc[lane] : 0.0;
+  double sol = 0.0;
+  for (int ii = nb - 1; ii >= 0; --ii) {
+    // (L^T)(ii, l) = L(l, ii), l > ii already solved
+    const double part = (lane > ii && lane < nb) ? Ls[lane + ii * NB] * sol : 0.0;
+    const double s = wave_sum(part);
+    const double v = (__shfl(x, ii, 64) - s) / Ls[ii + ii * NB];
+    if (lane == ii) sol = v;
   }
-#pragma unroll
-  for (int i = 0; i < NB; ++i)
-    if (i < nb) X[(i0 + i) + (int64_t)col * ldx] = x[i];
+  if (lane < nb) xc[lane] = sol;
 }
 
 // Solve L^T X = B in place (L lower n x n column-major; X n x m column-major).
@@ -192,7 +199,7 @@ inline void trsm_lt(hipStream_t st, const double* L, int64_t ld, int n, double* 
       gemm64<true, true>(st, nb, m, below, L + (i0 + nb) + (int64_t)i0 * ld, ld, X + (i0 + nb), ldx,
                          X + i0, ldx, -1.0, 1.0);
     }
-    hipLaunchKernelGGL(k_trsm_ut_diag, dim3((m + 255) / 256), dim3(256), 0, st, L, ld, i0, nb, X,
+    hipLaunchKernelGGL(k_trsm_ut_diag, dim3((m + 15) / 16), dim3(1024), 0, st, L, ld, i0, nb, X,
                        ldx, m);
   }
 }
@@ -331,38 +338,119 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ A, i
   }
 }
 
-// One-workgroup Cholesky G = R^T R (R upper) of a p x p SPD matrix and the
-// inverse R^{-1} (upper), p <= JMAX.  On breakdown the status is set.
-__global__ __launch_bounds__(1024) void k_chol_inv_small(const double* __restrict__ G, int64_t ldg,
-                                                         int p, double* __restrict__ Rinv,
-                                                         int64_t ldr, int32_t* status,
-                                                         const int32_t* skip) {
+// One-workgroup Cholesky G = R^T R of a p x p SPD matrix (p <= JMAX); writes
+// R (upper, column-major, ldr; zero below the diagonal).  On breakdown the
+// status is set.
+__global__ __launch_bounds__(1024) void k_chol_small(const double* __restrict__ G, int64_t ldg,
+                                                     int p, double* __restrict__ R, int64_t ldr,
+                                                     int32_t* status, const int32_t* skip) {
   if (skip && *skip) return;
-  __shared__ double a[JMAX * JMAX];
-  __shared__ double x[JMAX * JMAX];
+  constexpr int LDS = JMAX + 1;
+  __shared__ double a[JMAX * LDS];
+  __shared__ double piv[JMAX];
   const int tid = threadIdx.x;
   for (int e = tid; e < p * p; e += 1024) {
-    int i = e % p, c = e / p;
-    a[i + c * p] = G[i + c * ldg];
+    const int i = e % p, c = e / p;
+    a[i + c * LDS] = G[i + c * ldg];
   }
-  chol_block_lds(a, p, p, status);  // lower L, R = L^T
-  // X = L^{-1} (lower), column c by forward substitution, one thread per column
-  if (tid < p) {
-    const int c = tid;
-    for (int i = 0; i < c; ++i) x[i + c * p] = 0.0;
-    x[c + c * p] = 1.0 / a[c + c * p];
-    for (int i = c + 1; i < p; ++i) {
-      double s = 0.0;
-      for (int l = c; l < i; ++l) s += a[i + l * p] * x[l + c * p];
-      x[i + c * p] = -s / a[i + i * p];
-    }
-  }
-  __syncthreads();
-  // R^{-1} = (L^{-1})^T
+  chol_block_lds(a, p, LDS, piv, status);  // lower L, R = L^T
   for (int e = tid; e < p * p; e += 1024) {
-    int i = e % p, c = e / p;
-    Rinv[i + c * ldr] = x[c + i * p];
+    const int i = e % p, c = e / p;
+    R[i + c * ldr] = (i <= c) ? a[c + i * LDS] : 0.0;
   }
+}
+
+// Q = Y R^{-1} (R upper p x p, Y r x p, both column-major): each thread
+// solves one row q R = y by forward substitution, its row staged in LDS
+// (odd stride) and R broadcast from LDS.  64 rows per workgroup.
+__global__ __launch_bounds__(64) void k_trsm_rows(const double* __restrict__ Y, int64_t ldy,
+                                                  int rows, int p, const double* __restrict__ R,
+                                                  int64_t ldr, double* __restrict__ Q,
+                                                  int64_t ldq, const int32_t* skip) {
+  if (skip && *skip) return;
+  constexpr int LDS = JMAX + 1;
+  __shared__ double Rs[JMAX * JMAX];
+  __shared__ double q[64 * LDS];
+  const int t = threadIdx.x;
+  for (int e = t; e < p * p; e += 64) {
+    const int i = e % p, c = e / p;
+    Rs[i + c * p] = R[i + c * ldr];
+  }
+  const int row = blockIdx.x * 64 + t;
+  for (int j = 0; j < p; ++j) q[t * LDS + j] = row < rows ? Y[row + (int64_t)j * ldy] : 0.0;
+  __syncthreads();
+  for (int j = 0; j < p; ++j) {
+    double sacc = q[t * LDS + j];
+    for (int l = 0; l < j; ++l) sacc -= q[t * LDS + l] * Rs[l + j * p];
+    q[t * LDS + j] = sacc / Rs[j + j * p];
+  }
+  if (row < rows)
+    for (int j = 0; j < p; ++j) Q[row + (int64_t)j * ldq] = q[t * LDS + j];
+}
+
+// ------------------------------------------------ split-K product
+// Same product as k_gemm64 for short-and-wide shapes (few output tiles, long
+// K): grid.z slices K, each slice writes its float64 partial tile, and
+// k_splitk_reduce adds them in a fixed order.
+template <bool KCA, bool KCB>
+__global__ __launch_bounds__(256) void k_gemm64_part(int64_t M, int64_t N, int64_t K, int64_t kc,
+                                                     const double* __restrict__ A, int64_t lda,
+                                                     const double* __restrict__ B, int64_t ldb,
+                                                     double* __restrict__ part,
+                                                     const int32_t* skip) {
+  if (skip && *skip) return;
+  typedef TileCfg<double, 64, 64, 16, 2, 2> Cfg;
+  __shared__ double smem[TileSmem<Cfg, KCA, KCB>::bytes / sizeof(double)];
+  const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM, n0 = (int64_t)blockIdx.y * Cfg::BN;
+  const int64_t kb = (int64_t)blockIdx.z * kc;
+  const int64_t ke = kb + kc < K ? kb + kc : K;
+  GOperand<double, KCA> a{A, lda, M, K, nullptr, (lda % 2) == 0};
+  GOperand<double, KCB> b{B, ldb, N, K, nullptr, (ldb % 2) == 0};
+  TileAcc<Cfg> acc;
+  acc.zero();
+  tile_mainloop<Cfg>(acc, a, b, m0, n0, kb, ke, smem);
+  double* out = part + (int64_t)blockIdx.z * M * N;
+  for_each_acc<Cfg>(acc, [&](int row, int col, double v) {
+    const int64_t m = m0 + row, n = n0 + col;
+    if (m < M && n < N) out[m + n * M] = v;
+  });
+}
+
+__global__ __launch_bounds__(256) void k_splitk_reduce(const double* __restrict__ part, int splits,
+                                                       int64_t M, int64_t N, double* __restrict__ C,
+                                                       int64_t ldc, double alpha, double beta,
+                                                       const int32_t* skip) {
+  if (skip && *skip) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= M * N) return;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + e];
+  const int64_t m = e % M, n = e / M;
+  double* c = C + m + n * ldc;
+  *c = beta == 0.0 ? alpha * s : alpha * s + beta * *c;
+}
+
+constexpr int SPLITK_MAX = 16;
+
+// C = alpha A B^T + beta C with K sliced into up to SPLITK_MAX pieces of at
+// least 64; `part` holds SPLITK_MAX * M * N doubles.
+template <bool KCA, bool KCB>
+inline void gemm64_splitk(hipStream_t st, int64_t M, int64_t N, int64_t K, const double* A,
+                          int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
+                          double alpha, double beta, double* part, const int32_t* skip = nullptr) {
+  if (M <= 0 || N <= 0) return;
+  int splits = (int)((K + 63) / 64);
+  if (splits > SPLITK_MAX) splits = SPLITK_MAX;
+  if (splits < 2) {
+    gemm64<KCA, KCB>(st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, skip);
+    return;
+  }
+  const int64_t kc = (K + splits - 1) / splits;
+  dim3 g((unsigned)((M + 63) / 64), (unsigned)((N + 63) / 64), (unsigned)splits);
+  hipLaunchKernelGGL((k_gemm64_part<KCA, KCB>), g, dim3(256), 0, st, M, N, K, kc, A, lda, B, ldb, part,
+                     skip);
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((M * N + 255) / 256)), dim3(256), 0, st,
+                     (const double*)part, splits, M, N, C, ldc, alpha, beta, skip);
 }
 
 }  // namespace
