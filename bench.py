@@ -114,7 +114,8 @@ def roofline(w, d, res, prof, steps, prec):
         "kernel_cols": (2.0 * N * dp * k, rounds * N * dp * xs + N * k * fs, prec[0]),
         "schur": (float(np.sum(2.0 * N * kb * nT)), float(np.sum(N * kb * fs + 2 * N * nT * fs)), prec[1]),
         "solve_downdate": (float(np.sum(1.0 * N * nT * nT)), float(np.sum(2 * N * nT * fs + 16 * N)), "f64"),
-        "gram": (2.0 * N * r * (r + 1), 2.0 * N * r * fs, prec[2]),
+        # both Grams over the k nonzero columns (symmetric: k (k + 1) / 2 dot products each)
+        "gram": (2.0 * N * k * (k + 1), 2.0 * N * k * fs, prec[2]),
     }
     out = {}
     for name, (fl, by, dt) in work.items():
@@ -208,6 +209,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=8192)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the method's data-parallel path is built and timed on a "
@@ -223,6 +226,12 @@ def main():
     X, eps, u = make_inputs(w)
     Xd = torch.from_numpy(X).cuda()
     ud = torch.from_numpy(u).cuda()
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     mixed = ("bf16", "f32", "f32")
     plain = ("f64", "f64", "f64")
     log("[bench] mixed path")

@@ -235,16 +235,18 @@ template <typename T, typename TF, typename TU>
 __global__ __launch_bounds__(256) void k_form_u(const TF* __restrict__ F, int64_t ldf, int64_t N,
                                                 int r, const double* __restrict__ Z, int nev,
                                                 const double* __restrict__ dinv,
-                                                TU* __restrict__ U, int64_t ldu) {
+                                                TU* __restrict__ U, int64_t ldu,
+                                                const int32_t* kptr) {
   typedef TileCfg<T, 128, 64, 16, 2, 2> Cfg;
   extern __shared__ char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM, n0 = (int64_t)blockIdx.y * Cfg::BN;
-  GOperand<TF, false> A{F, ldf, N, r, nullptr, true};
-  GOperand<double, true> B{Z, r, nev, r, nullptr, (r % 2) == 0};
+  const int kk = kptr ? *kptr : r;  // columns >= k of F are zero
+  GOperand<TF, false> A{F, ldf, N, kk, nullptr, true};
+  GOperand<double, true> B{Z, r, nev, kk, nullptr, (r % 2) == 0};
   TileAcc<Cfg> acc;
   acc.zero();
-  tile_mainloop<Cfg>(acc, A, B, m0, n0, 0, r, smem);
+  tile_mainloop<Cfg>(acc, A, B, m0, n0, 0, kk, smem);
   for_each_acc<Cfg>(acc, [&](int row, int col, typename Cfg::MM::acc_t v) {
     const int64_t m = m0 + row, n = n0 + col;
     if (m < N && n < nev) U[m + n * ldu] = (TU)(dinv ? (double)v * dinv[m] : (double)v);
@@ -429,7 +431,7 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   hipLaunchKernelGGL((k_gram_scales<TG>), dim3(nblk(N)), dim3(256), 0, st, dt, qt, (TG*)w.ssd,
                      (TG*)w.ssq, N);
   if (!syrk::gram2<TG, TF>(st, F, ldf, N, r, 2, (const TG*)w.ssd, (const TG*)w.ssq, w.part, w.part1,
-                           w.part_cap, w.GB, w.C))
+                           w.part_cap, w.GB, w.C, k))
     return RPC_EWORKSPACE;
   const unsigned grr = nblk((int64_t)r * r);
   RPC_LAUNCH_CHECK();
@@ -512,7 +514,7 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   const dim3 gu((unsigned)((N + 127) / 128), (unsigned)((nev + 63) / 64));
   const size_t smU = TileSmem<CfgU, false, true>::bytes;
   hipLaunchKernelGGL((k_form_u<TG, TF, TU>), gu, dim3(256), smU, st, F, ldf, N, r,
-                     (const double*)w.Z, nev, (const double*)w.sd, U, ldu);
+                     (const double*)w.Z, nev, (const double*)w.sd, U, ldu, k);
   RPC_LAUNCH_CHECK();
 
   if (o->fix_const) {

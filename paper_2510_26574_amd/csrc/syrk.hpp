@@ -131,7 +131,8 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_partial(const TF* __restrict__ 
                                                          const T* __restrict__ s1, int nz,
                                                          int64_t chunk, int nch,
                                                          double* __restrict__ part0,
-                                                         double* __restrict__ part1) {
+                                                         double* __restrict__ part1,
+                                                         const int32_t* kptr) {
   typedef Mma<T> MM;
   constexpr int BK = SyrkTraits<T>::BK;
   constexpr int LDK = BK + SyrkTraits<T>::PAD;
@@ -149,6 +150,10 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_partial(const TF* __restrict__ 
   const int z = g / nch, ch = g % nch;
   int ti, tj;
   upper_decode(tile, nt, ti, tj);
+  // columns >= k are zero: tiles entirely beyond k are skipped (the reduce
+  // writes zeros there)
+  const int kk = kptr ? *kptr : r;
+  if (tj * TILE >= kk) return;
   const bool diag = ti == tj;
   const T* s = z ? s1 : s0;
   double* out = (z ? part1 : part0) + ((int64_t)ch * nu + tile) * TILE * TILE;
@@ -242,10 +247,15 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_partial(const TF* __restrict__ 
 
 // G[i + j r] = sum over chunks of the partial tile holding (i, j) (or (j, i)).
 __global__ __launch_bounds__(256) void k_syrk_reduce(const double* __restrict__ part, int nch, int r,
-                                                     double* __restrict__ G) {
+                                                     double* __restrict__ G, const int32_t* kptr) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)r * r) return;
   const int i = (int)(e % r), j = (int)(e / r);
+  const int kk = kptr ? *kptr : r;
+  if (i >= kk || j >= kk) {
+    G[e] = 0.0;
+    return;
+  }
   const int nt = n_tiles(r), nu = n_upper(nt);
   int a = i, b = j;
   if (i / TILE > j / TILE) {
@@ -290,7 +300,7 @@ inline size_t part_elems_any(int64_t N, int r) {
 template <typename T, typename TF>
 inline bool gram2(hipStream_t st, const TF* A, int64_t lda, int64_t N, int r, int nz, const T* s0,
                   const T* s1, double* part0, double* part1, size_t part_cap, double* G0,
-                  double* G1) {
+                  double* G1, const int32_t* kptr = nullptr) {
   int nch;
   int64_t chunk;
   plan(N, nch, chunk, sizeof(T) == 4);
@@ -299,10 +309,11 @@ inline bool gram2(hipStream_t st, const TF* A, int64_t lda, int64_t N, int r, in
   const int groups = nz * nch;
   const unsigned blocks = (unsigned)(8 * ((groups + 7) / 8) * nu);
   hipLaunchKernelGGL((k_syrk_partial<T, TF>), dim3(blocks), dim3(NTH), 0, st, A, lda, N, r, s0, s1, nz,
-                     chunk, nch, part0, part1);
+                     chunk, nch, part0, part1, kptr);
   const unsigned gr = (unsigned)(((int64_t)r * r + 255) / 256);
-  hipLaunchKernelGGL(k_syrk_reduce, dim3(gr), dim3(256), 0, st, (const double*)part0, nch, r, G0);
-  if (nz == 2) hipLaunchKernelGGL(k_syrk_reduce, dim3(gr), dim3(256), 0, st, (const double*)part1, nch, r, G1);
+  hipLaunchKernelGGL(k_syrk_reduce, dim3(gr), dim3(256), 0, st, (const double*)part0, nch, r, G0, kptr);
+  if (nz == 2)
+    hipLaunchKernelGGL(k_syrk_reduce, dim3(gr), dim3(256), 0, st, (const double*)part1, nch, r, G1, kptr);
   return true;
 }
 
