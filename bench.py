@@ -141,8 +141,43 @@ def roofline(w, d, res, prof, steps, prec):
     else:
         ach, peak, unit = o["gbs"], PEAK["hbm"], "GB/s"
     line = {"bound": o["bound"], "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
-            "traffic": None, "kernel": dom, "avg_launch_ms": o["ms_per_step"] / nl}
+            "traffic": pmc_traffic(KERNEL_NAMES.get(dom)), "kernel": dom,
+            "avg_launch_ms": o["ms_per_step"] / nl}
     return line, out
+
+
+# profile class -> kernel the class brackets (mixed form) as named by rocprofv3
+KERNEL_NAMES = {"gram": "k_syrk_partial<float, float>"}
+
+
+def pmc_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summaries (FETCH_SIZE and WRITE_SIZE runs, scaled by a 1 GiB copy), or None
+    when no summary covers it or its sources changed since the counters were
+    taken (the summary records a hash of them)."""
+    import hashlib
+    import re
+
+    if kernel is None:
+        return None
+    root = os.path.dirname(os.path.abspath(__file__))
+    pdir = os.path.join(root, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    pat = re.compile(r'^PMC_TRAFFIC kernel="([^"]+)" bytes_per_launch=(\d+) src_sha256=(\w+) srcs=(\S+)')
+    for fn in sorted(os.listdir(pdir)):
+        with open(os.path.join(pdir, fn)) as fh:
+            for ln in fh:
+                m = pat.match(ln.strip())
+                if not m or m.group(1) != kernel:
+                    continue
+                h = hashlib.sha256()
+                for src in m.group(4).split(","):
+                    with open(os.path.join(root, src), "rb") as sf:
+                        h.update(sf.read())
+                if h.hexdigest()[:len(m.group(3))] == m.group(3):
+                    return int(m.group(2))
+    return None
 
 
 def cpu_baseline(X, eps, w, n_sample):

@@ -423,20 +423,25 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   carve_eig(cur, w, N, r, nev, o->fix_const != 0);
   if (!cur.ok) return RPC_EWORKSPACE;
   const int p = w.p;
-  prof::begin(prof::GRAM, st);
+  if (!syrk::gram2_fits<TG>(N, r, w.part_cap) ||
+      (o->fix_const && !syrk::gram2_fits<double>(N, nev, w.part_cap)))
+    return RPC_EWORKSPACE;
+  prof::begin(prof::SMALL, st);
   hipLaunchKernelGGL(k_recip, dim3(nblk(N)), dim3(256), 0, st, dt, w.sd, N);
   hipLaunchKernelGGL(k_recip, dim3(nblk(N)), dim3(256), 0, st, qt, w.sq, N);
-
-  // ---- the two N-long Grams: G_B = (D~^{-1} F)^T (D~^{-1} F), C = (Q~^{-1/2} F)^T (Q~^{-1/2} F)
   hipLaunchKernelGGL((k_gram_scales<TG>), dim3(nblk(N)), dim3(256), 0, st, dt, qt, (TG*)w.ssd,
                      (TG*)w.ssq, N);
-  if (!syrk::gram2<TG, TF>(st, F, ldf, N, r, 2, (const TG*)w.ssd, (const TG*)w.ssq, w.part, w.part1,
-                           w.part_cap, w.GB, w.C, k))
-    return RPC_EWORKSPACE;
+  prof::end(prof::SMALL, st);
+
+  // ---- the two N-long Grams: G_B = (D~^{-1} F)^T (D~^{-1} F), C = (Q~^{-1/2} F)^T (Q~^{-1/2} F)
+  prof::begin(prof::GRAM, st);
+  syrk::gram2_partial<TG, TF>(st, F, ldf, N, r, 2, (const TG*)w.ssd, (const TG*)w.ssq, w.part,
+                              w.part1, k);
+  prof::end(prof::GRAM, st);
   const unsigned grr = nblk((int64_t)r * r);
   RPC_LAUNCH_CHECK();
-  prof::end(prof::GRAM, st);
   prof::begin(prof::SMALL, st);
+  syrk::gram2_reduce<TG>(st, N, r, 2, w.part, w.part1, w.GB, w.C, k);
   hipLaunchKernelGGL((k_gram_finish<TF>), dim3(grr), dim3(256), 0, st, w.GB, w.C, w.Gs, w.Cs, w.s,
                      r, k, F, ldf, N, (const double*)w.sd, o->gamma, 0);
   hipLaunchKernelGGL((k_gram_finish<TF>), dim3(grr), dim3(256), 0, st, w.GB, w.C, w.Gs, w.Cs, w.s,
@@ -520,9 +525,9 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   if (o->fix_const) {
     // U(:, 0) = 1/sqrt(N), then Cholesky QR with positive diag(R)
     hipLaunchKernelGGL((k_const_col<TU>), dim3(nblk(N)), dim3(256), 0, st, U, N, 1.0 / sqrt((double)N));
-    if (!syrk::gram2<double, TU>(st, (const TU*)U, ldu, N, nev, 1, (const double*)nullptr,
-                                 (const double*)nullptr, w.part, w.part1, w.part_cap, w.Gp, nullptr))
-      return RPC_EWORKSPACE;
+    syrk::gram2_partial<double, TU>(st, (const TU*)U, ldu, N, nev, 1, (const double*)nullptr,
+                                    (const double*)nullptr, w.part, w.part1);
+    syrk::gram2_reduce<double>(st, N, nev, 1, w.part, w.part1, w.Gp, nullptr);
     hipLaunchKernelGGL(dense::k_chol_small, dim3(1), dim3(1024), 0, st, (const double*)w.Gp,
                        (int64_t)nev, nev, w.Rinv, (int64_t)nev, status, (const int32_t*)nullptr);
     const int64_t ldut = (int64_t)align_up((size_t)N, 8);

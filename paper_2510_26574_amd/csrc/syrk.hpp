@@ -293,28 +293,43 @@ inline size_t part_elems_any(int64_t N, int r) {
   return a > b ? a : b;
 }
 
-// Launch: part0/part1 each hold at least part_elems(N, r, sizeof(T) == 4)
-// doubles (`part_cap`); G0/G1 are r x r.  Returns false (and launches
-// nothing) if the partial buffers are too small.
+// part0/part1 each hold part_cap doubles, enough when gram2_fits holds
+// (part_elems(N, r, sizeof(T) == 4)); G0/G1 are r x r.
 // nz = 1: only G0 (s0 may be null = no scaling); nz = 2: G0 and G1.
+template <typename T>
+inline bool gram2_fits(int64_t N, int r, size_t part_cap) {
+  int nch;
+  int64_t chunk;
+  plan(N, nch, chunk, sizeof(T) == 4);
+  return (size_t)nch * n_upper(n_tiles(r)) * TILE * TILE <= part_cap;
+}
+
+// Chunked partial products of nz (1 or 2) Grams; the caller checked
+// gram2_fits.  gram2_reduce then sums the chunks into the r x r results.
 template <typename T, typename TF>
-inline bool gram2(hipStream_t st, const TF* A, int64_t lda, int64_t N, int r, int nz, const T* s0,
-                  const T* s1, double* part0, double* part1, size_t part_cap, double* G0,
-                  double* G1, const int32_t* kptr = nullptr) {
+inline void gram2_partial(hipStream_t st, const TF* A, int64_t lda, int64_t N, int r, int nz,
+                          const T* s0, const T* s1, double* part0, double* part1,
+                          const int32_t* kptr = nullptr) {
   int nch;
   int64_t chunk;
   plan(N, nch, chunk, sizeof(T) == 4);
   const int nu = n_upper(n_tiles(r));
-  if ((size_t)nch * nu * TILE * TILE > part_cap) return false;
   const int groups = nz * nch;
   const unsigned blocks = (unsigned)(8 * ((groups + 7) / 8) * nu);
   hipLaunchKernelGGL((k_syrk_partial<T, TF>), dim3(blocks), dim3(NTH), 0, st, A, lda, N, r, s0, s1, nz,
                      chunk, nch, part0, part1, kptr);
+}
+
+template <typename T>
+inline void gram2_reduce(hipStream_t st, int64_t N, int r, int nz, const double* part0,
+                         const double* part1, double* G0, double* G1,
+                         const int32_t* kptr = nullptr) {
+  int nch;
+  int64_t chunk;
+  plan(N, nch, chunk, sizeof(T) == 4);
   const unsigned gr = (unsigned)(((int64_t)r * r + 255) / 256);
-  hipLaunchKernelGGL(k_syrk_reduce, dim3(gr), dim3(256), 0, st, (const double*)part0, nch, r, G0, kptr);
-  if (nz == 2)
-    hipLaunchKernelGGL(k_syrk_reduce, dim3(gr), dim3(256), 0, st, (const double*)part1, nch, r, G1, kptr);
-  return true;
+  hipLaunchKernelGGL(k_syrk_reduce, dim3(gr), dim3(256), 0, st, part0, nch, r, G0, kptr);
+  if (nz == 2) hipLaunchKernelGGL(k_syrk_reduce, dim3(gr), dim3(256), 0, st, part1, nch, r, G1, kptr);
 }
 
 }  // namespace
