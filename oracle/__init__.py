@@ -8,6 +8,9 @@ Each function cites the part of the paper it follows (Vales & Giannakis,
 "Accelerated decomposition of bistochastic kernel matrices by low rank
 approximation").  Where the paper leaves a detail open, the reading taken is
 stated next to the code that implements it.
+
+`oracle.surrogate` holds the float64 reference of the learned surrogate of
+the Nystrom extension (multilayer perceptron, its gradients and AdamW).
 """
 from .kernel import gaussian_kernel, sq_distances
 from .arpc import (
@@ -18,6 +21,7 @@ from .arpc import (
     arpc,
     QSCALE,
 )
+from . import surrogate
 from .bistoch import (
     bistoch_degrees,
     bistoch_eig,
@@ -44,4 +48,5 @@ __all__ = [
     "dense_bistochastic",
     "dense_symmetric",
     "symmetric_eig",
+    "surrogate",
 ]
