@@ -183,15 +183,128 @@ int nystrom_extend(const rpc_points* Y, const rpc_points* X, const int64_t* pivo
                    void* workspace, size_t workspace_bytes, int32_t* dev_status,
                    rpc_stream_t stream);
 
+/* ---- Learned surrogate of the Nystrom extension -------------------------
+ * The Nystrom extension above maps a new state y to the values of the
+ * approximate eigenvectors at y.  The surrogate is a multilayer perceptron
+ * trained to reproduce sqrt(N) U (eigenfunction values of order one) at the
+ * training states:
+ *     z1 = W1 x + b1, a1 = gelu(z1), z2 = W2 a1 + b2, a2 = gelu(z2),
+ *     y  = W3 a2 + b3 (n_out outputs),  res = wr . a2 + br,
+ * with x the state standardised per feature, gelu(t) = t Phi(t) (exact erf
+ * form, Hendrycks & Gimpel 2016), and res a predicted log10 of the RMS error
+ * of y against the exact extension, used to fall back to nystrom_extend per
+ * point.  Products run on bf16 MFMA with fp32 accumulation: the standardised
+ * input, the weights, the hidden activations and the back-propagated errors
+ * are rounded to bf16; biases, pre-activations, the loss and the optimiser
+ * state stay fp32.  Training: mean squared error over batch and outputs,
+ * AdamW (Loshchilov & Hutter 2019; decoupled decay on every trained entry,
+ * bias-corrected moments).  Phase 0 trains W1..b3 against the targets;
+ * phase 1 trains only the residual head (wr, br) against log10 RMS errors.
+ *
+ * Parameter vector (float32, caller-owned, sur_layout offsets, each a
+ * multiple of 64 elements): W1 h x d row-major, b1 (h), W2 h x h, b2 (h),
+ * W3 n3 x h with n3 = n_out + 1 rounded up to 16 (rows 0..n_out-1: output
+ * layer; row n_out: wr; the rest zero), b3 (n3; entry n_out is br).  The
+ * AdamW moments m and v use the same layout; `wbf16` holds the bf16 copy of
+ * the parameter vector (same offsets) that the products read. */
+typedef struct {
+  int32_t d;     /* input width, 8 <= d <= 4096, multiple of 8 */
+  int32_t h;     /* hidden width, 64 <= h <= 4096, multiple of 64 */
+  int32_t n_out; /* outputs, 1 <= n_out <= 255 */
+} sur_shape;
+
+typedef struct {
+  int64_t W1, b1, W2, b2, W3, b3; /* element offsets into the parameter vector */
+  int64_t total;                  /* elements of the vector (and of m, v, wbf16) */
+  int32_t n3;                     /* rows of W3 (output layer + residual head + zero pad) */
+} sur_layout;
+
+typedef struct {
+  double lr, beta1, beta2, eps, weight_decay; /* AdamW hyper-parameters */
+  int64_t step;   /* AdamW step number t >= 1, counted per phase */
+  int32_t phase;  /* 0: W1..b3 on the targets; 1: residual head only */
+  int32_t splits; /* batch splits of the weight-gradient sums, 1..64 (0 = 8) */
+} sur_train_opts;
+
+/* Host only.  RPC_EINVAL for a shape outside the limits above. */
+int surrogate_layout(const sur_shape* shape, sur_layout* out);
+
+/* Prepare a freshly initialised parameter vector: zero the pad entries of
+ * `params`, zero both AdamW moments, write the bf16 copy. */
+int surrogate_init(const sur_shape* shape, float* params, float* adam_m, float* adam_v,
+                   uint16_t* wbf16, rpc_stream_t stream);
+
+/* Per-feature mean and 1/(population standard deviation) of the N x d
+ * float32 rows X (row-major, ldx >= d), in float64 (two passes); a constant
+ * feature gets scale 1. */
+int surrogate_standardize_workspace_size(int64_t N, int64_t d, size_t* bytes);
+int surrogate_standardize(const float* X, int64_t N, int64_t d, int64_t ldx, double* mean,
+                          double* rstd, void* workspace, size_t workspace_bytes,
+                          rpc_stream_t stream);
+
+/* One AdamW step on the batch rows idx[0..batch) (device int64, each in
+ * [0, N) of X; out-of-range indices set RPC_EINVAL in *dev_status and leave
+ * the step's outputs undefined).  Targets: phase 0, target(b, j) =
+ * tscale * T[idx[b] + j ldt] for j < n_out (column-major, t_dtype F32 or
+ * F64, e.g. U of bistoch_eig with tscale = sqrt(N)); phase 1, target(b) =
+ * T[idx[b]] (per-point log10 RMS error).  Updates params, adam_m, adam_v and
+ * wbf16 in place.  Optional outputs (NULL to skip): grad (float32, parameter
+ * layout: the summed gradient of the step, zero for entries the phase does
+ * not train) and loss (one device double: the batch loss before the step).
+ * 1 <= batch <= 65536. */
+int surrogate_train_workspace_size(const sur_shape* shape, int64_t batch, int32_t splits,
+                                   size_t* bytes);
+int surrogate_train_step(const sur_shape* shape, const sur_train_opts* opts, const float* X,
+                         int64_t ldx, int64_t N, const double* mean, const double* rstd,
+                         const int64_t* idx, int64_t batch, const void* T, int32_t t_dtype,
+                         int64_t ldt, double tscale, float* params, float* adam_m,
+                         float* adam_v, uint16_t* wbf16, float* grad, double* loss,
+                         void* workspace, size_t workspace_bytes, int32_t* dev_status,
+                         rpc_stream_t stream);
+
+/* Forward pass over the M rows of Y (float32 row-major, ldy >= d): Phi (M x
+ * n_out float32, column-major, ldphi >= M) and, if non-NULL, res (M float32,
+ * the residual head).  Rows are processed in chunks of at most 65536. */
+int surrogate_infer_workspace_size(const sur_shape* shape, int64_t M, size_t* bytes);
+int surrogate_infer(const sur_shape* shape, const float* params, const uint16_t* wbf16,
+                    const float* Y, int64_t ldy, int64_t M, const double* mean,
+                    const double* rstd, float* Phi, int64_t ldphi, float* res, void* workspace,
+                    size_t workspace_bytes, int32_t* dev_status, rpc_stream_t stream);
+
+/* Residual-head targets for phase 1: out[m] = log10 of the RMS over j <
+ * n_out of Phi_s(m, j) - scale * Phi_n(m, j) (Phi_s float32 and Phi_n
+ * float64, both column-major); out is float64.  A zero difference gives
+ * log10 of the smallest normal double, -307.65. */
+int surrogate_residual_target(const float* Phi_s, int64_t lds, const double* Phi_n,
+                              int64_t ldn, double scale, int64_t M, int32_t n_out, double* out,
+                              rpc_stream_t stream);
+
+/* Hybrid extension: the surrogate everywhere, then the exact Nystrom
+ * extension (scaled by `scale`, normally sqrt(N)) at the points whose
+ * residual head predicts res > log10_threshold.  The surrogate's n_out must
+ * not exceed nev.  Synchronises `stream` once (to size the fallback set);
+ * *n_fallback (host) receives its size.  The workspace covers both parts. */
+int surrogate_extend_workspace_size(const sur_shape* shape, int64_t M, int64_t d, int32_t r,
+                                    int32_t nev, size_t* bytes);
+int surrogate_extend(const sur_shape* shape, const float* params, const uint16_t* wbf16,
+                     const double* mean, const double* rstd, double log10_threshold,
+                     const rpc_points* Y, const rpc_points* X, const int64_t* pivots,
+                     const int32_t* k, const void* F, int32_t f_dtype, int64_t ldf, int32_t r,
+                     const double* c, const double* ext_E, int32_t nev, double scale,
+                     float* Phi, int64_t ldphi, float* res, int64_t* n_fallback,
+                     void* workspace, size_t workspace_bytes, int32_t* dev_status,
+                     rpc_stream_t stream);
+
 /* ---- Per-kernel timing (diagnostics for benchmarking) ------------------
  * When enabled, the library brackets each launch of its main kernel classes
  * with HIP events on the launching stream.  rpc_profile_read synchronises on
  * the recorded events and returns, for one class, the summed duration in ms
  * and the number of launches since the last reset.  Classes: 0 kernel
  * columns, 1 Schur update, 2 triangular solve + downdate, 3 pivot draw,
- * 4 pivot block + accept/reject, 5 degrees, 6 Gram products, 7 r x r work,
- * 8 eigenvector formation, 9 Nystrom extension, 10 inner eigensolver
- * (class 7 then covers the Gram finish, Cholesky and inner product).
+ * 4 pivot block + accept/reject, 5 degrees, 6 Gram partial products,
+ * 7 r x r work (Gram row scales, chunk reduction and finish, Cholesky, inner
+ * product), 8 eigenvector formation, 9 Nystrom extension, 10 inner
+ * eigensolver, 11 surrogate training step, 12 surrogate inference.
  * Process-global state, not
  * thread-safe; returns RPC_EWORKSPACE if the event pool overflowed. */
 int rpc_profile_enable(int on);

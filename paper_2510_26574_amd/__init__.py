@@ -9,7 +9,10 @@ The names follow the C-ABI in include/rpchol.h:
                    with the accept/reject check of Algorithm 3);
   bistoch_degrees  d~ = diag(F F^T 1), q~ = diag(F F^T D~^{-1} 1) (Algorithm 1);
   bistoch_eig      top eigenpairs of P~ = B C B^T (Algorithm 1);
-  nystrom_extend   extension of the eigenvectors to new points.
+  nystrom_extend   extension of the eigenvectors to new points;
+  surrogate_*      the learned surrogate of the extension (a perceptron
+                   trained on the eigenvectors, with a per-point fallback to
+                   nystrom_extend).
 """
 import ctypes
 import os
@@ -66,6 +69,21 @@ _SIGS = {
     "nystrom_extend_workspace_size": [_I64, _I64, _I32, _I32, _VP],
     "nystrom_extend": [_VP, _VP, _VP, _VP, _VP, _I32, _I64, _I32, _VP, _VP, _I32, _VP, _I64, _VP,
                        _SZ, _VP, _VP],
+    "surrogate_layout": [_VP, _VP],
+    "surrogate_init": [_VP, _VP, _VP, _VP, _VP, _VP],
+    "surrogate_standardize_workspace_size": [_I64, _I64, _VP],
+    "surrogate_standardize": [_VP, _I64, _I64, _I64, _VP, _VP, _VP, _SZ, _VP],
+    "surrogate_train_workspace_size": [_VP, _I64, _I32, _VP],
+    "surrogate_train_step": [_VP, _VP, _VP, _I64, _I64, _VP, _VP, _VP, _I64, _VP, _I32, _I64,
+                             ctypes.c_double, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP, _VP],
+    "surrogate_infer_workspace_size": [_VP, _I64, _VP],
+    "surrogate_infer": [_VP, _VP, _VP, _VP, _I64, _I64, _VP, _VP, _VP, _I64, _VP, _VP, _SZ, _VP,
+                        _VP],
+    "surrogate_residual_target": [_VP, _I64, _VP, _I64, ctypes.c_double, _I64, _I32, _VP, _VP],
+    "surrogate_extend_workspace_size": [_VP, _I64, _I64, _I32, _I32, _VP],
+    "surrogate_extend": [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP, _VP, _VP, _VP, _I32,
+                         _I64, _I32, _VP, _VP, _I32, ctypes.c_double, _VP, _I64, _VP, _VP, _VP,
+                         _SZ, _VP, _VP],
     "rpc_status_sync": [_VP, _VP],
     "rpc_version": [],
     "rpc_profile_enable": [ctypes.c_int],
@@ -227,7 +245,7 @@ def bistoch_eig(F, k, d, q, nev, gamma=0.0, fix_const=False, gram_dtype="f64", u
     _check(lib.bistoch_eig_workspace_size(N, r, ctypes.byref(opts), ctypes.byref(nb)),
            "bistoch_eig_workspace_size")
     ws = _workspace(torch, nb.value, dev)
-    _check(lib.bistoch_eig(_ptr(F), code, N, ldf, r, _ptr(k), _ptr(d), _ptr(d), _ptr(q),
+    _check(lib.bistoch_eig(_ptr(F), code, N, ldf, r, _ptr(k), _ptr(None), _ptr(d), _ptr(q),
                            ctypes.byref(opts), _ptr(Ubuf), ldu, _ptr(lam), _ptr(E), _ptr(ws), nb.value,
                            _ptr(st), _stream(torch, stream)), "bistoch_eig")
     return {"U": Ubuf[:, :N].t(), "lam": lam, "E": E.t(), "status": st, "workspace": ws}
@@ -255,12 +273,181 @@ def nystrom_extend(Y, X, eps, pivots, k, F, c, E, status=None, stream=None):
     return {"Phi": Phib.t(), "status": st}
 
 
+class sur_shape(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("h", ctypes.c_int32), ("n_out", ctypes.c_int32)]
+
+
+class sur_layout(ctypes.Structure):
+    _fields_ = [("W1", ctypes.c_int64), ("b1", ctypes.c_int64), ("W2", ctypes.c_int64),
+                ("b2", ctypes.c_int64), ("W3", ctypes.c_int64), ("b3", ctypes.c_int64),
+                ("total", ctypes.c_int64), ("n3", ctypes.c_int32)]
+
+
+class sur_train_opts(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double), ("weight_decay", ctypes.c_double),
+                ("step", ctypes.c_int64), ("phase", ctypes.c_int32), ("splits", ctypes.c_int32)]
+
+
+def surrogate_layout(d, h, n_out):
+    """Offsets of W1, b1, W2, b2, W3, b3 in the parameter vector, its length
+    `total`, and n3 (rows of W3: outputs, residual head, zero pad)."""
+    lib = load_library()
+    lay = sur_layout()
+    sh = sur_shape(int(d), int(h), int(n_out))
+    _check(lib.surrogate_layout(ctypes.byref(sh), ctypes.byref(lay)), "surrogate_layout")
+    return {f: getattr(lay, f) for f, _ in sur_layout._fields_}
+
+
+class Surrogate:
+    """Parameter vector, AdamW moments and bf16 copy of one surrogate, in
+    device memory (float32 / bfloat16 torch tensors owned here)."""
+
+    def __init__(self, d, h, n_out, init, device="cuda", stream=None):
+        torch = _torch()
+        lib = load_library()
+        self.shape = sur_shape(int(d), int(h), int(n_out))
+        self.layout = surrogate_layout(d, h, n_out)
+        tot = self.layout["total"]
+        init = torch.as_tensor(init, dtype=torch.float32)
+        assert init.numel() == tot, f"initial parameter vector must have {tot} entries"
+        self.params = init.to(device).contiguous()
+        self.m = torch.empty(tot, dtype=torch.float32, device=device)
+        self.v = torch.empty(tot, dtype=torch.float32, device=device)
+        self.wbf16 = torch.empty(tot, dtype=torch.bfloat16, device=device)
+        self.step = 0
+        _check(lib.surrogate_init(ctypes.byref(self.shape), _ptr(self.params), _ptr(self.m),
+                                  _ptr(self.v), _ptr(self.wbf16), _stream(torch, stream)),
+               "surrogate_init")
+        self._ws = {}
+
+    def _wsbuf(self, key, nbytes, device):
+        torch = _torch()
+        buf = self._ws.get(key)
+        if buf is None or buf.numel() < nbytes:
+            buf = _workspace(torch, nbytes, device)
+            self._ws[key] = buf
+        return buf
+
+    def train_step(self, X, mean, rstd, idx, T, tscale=1.0, phase=0, step=None, lr=1e-3,
+                   betas=(0.9, 0.999), eps=1e-8, weight_decay=0.01, splits=0, grad=None,
+                   loss=None, status=None, stream=None):
+        """One AdamW step on rows idx of X against T (see surrogate_train_step)."""
+        torch = _torch()
+        lib = load_library()
+        if step is None:
+            self.step += 1
+            step = self.step
+        B = idx.numel()
+        assert idx.dtype == torch.int64 and X.dtype == torch.float32 and X.stride(1) == 1
+        if phase == 0:
+            assert T.dim() == 2 and T.stride(0) == 1, "phase-0 targets must be column-major N x n_out"
+            ldt = T.stride(1) if T.shape[1] > 1 else T.shape[0]
+        else:
+            assert T.dim() == 1
+            ldt = T.shape[0]
+        tcode = DTYPES["f64"] if T.dtype == torch.float64 else DTYPES["f32"]
+        opts = sur_train_opts(float(lr), float(betas[0]), float(betas[1]), float(eps),
+                              float(weight_decay), int(step), int(phase), int(splits))
+        nb = ctypes.c_size_t(0)
+        _check(lib.surrogate_train_workspace_size(ctypes.byref(self.shape), B, int(splits),
+                                                  ctypes.byref(nb)), "surrogate_train_workspace_size")
+        ws = self._wsbuf("train", nb.value, X.device)
+        st = status if status is not None else torch.zeros(1, dtype=torch.int32, device=X.device)
+        _check(lib.surrogate_train_step(ctypes.byref(self.shape), ctypes.byref(opts), _ptr(X),
+                                        X.stride(0), X.shape[0], _ptr(mean), _ptr(rstd), _ptr(idx), B,
+                                        _ptr(T), tcode, ldt, float(tscale), _ptr(self.params),
+                                        _ptr(self.m), _ptr(self.v), _ptr(self.wbf16), _ptr(grad),
+                                        _ptr(loss), _ptr(ws), nb.value, _ptr(st),
+                                        _stream(torch, stream)), "surrogate_train_step")
+        return st
+
+    def infer(self, Y, mean, rstd, with_res=True, status=None, stream=None):
+        """Phi (M x n_out float32 view of column-major storage) and the residual head."""
+        torch = _torch()
+        lib = load_library()
+        M = Y.shape[0]
+        n_out = self.shape.n_out
+        Phib = torch.empty((n_out, max(M, 1)), dtype=torch.float32, device=Y.device)
+        res = torch.empty(max(M, 1), dtype=torch.float32, device=Y.device) if with_res else None
+        nb = ctypes.c_size_t(0)
+        _check(lib.surrogate_infer_workspace_size(ctypes.byref(self.shape), M, ctypes.byref(nb)),
+               "surrogate_infer_workspace_size")
+        ws = self._wsbuf("infer", nb.value, Y.device)
+        st = status if status is not None else torch.zeros(1, dtype=torch.int32, device=Y.device)
+        _check(lib.surrogate_infer(ctypes.byref(self.shape), _ptr(self.params), _ptr(self.wbf16),
+                                   _ptr(Y), Y.stride(0), M, _ptr(mean), _ptr(rstd), _ptr(Phib),
+                                   max(M, 1), _ptr(res), _ptr(ws), nb.value, _ptr(st),
+                                   _stream(torch, stream)), "surrogate_infer")
+        return {"Phi": Phib[:, :M].t(), "res": res[:M] if res is not None else None, "status": st}
+
+    def extend(self, Y, X, eps, pivots, k, F, c, E, mean, rstd, scale, log10_threshold=-2.0,
+               status=None, stream=None):
+        """Hybrid extension: surrogate everywhere, exact Nystrom (times scale)
+        where the residual head exceeds the threshold.  Synchronises once."""
+        torch = _torch()
+        lib = load_library()
+        code, N, ldf, r = _factor_args(F)
+        nev = E.shape[1]
+        assert E.stride(0) == 1 and E.stride(1) == r, "E must be r x nev column-major"
+        M = Y.shape[0]
+        n_out = self.shape.n_out
+        Phib = torch.empty((n_out, max(M, 1)), dtype=torch.float32, device=Y.device)
+        res = torch.empty(max(M, 1), dtype=torch.float32, device=Y.device)
+        py, px = _points(Y, eps), _points(X, eps)
+        nb = ctypes.c_size_t(0)
+        _check(lib.surrogate_extend_workspace_size(ctypes.byref(self.shape), M, Y.shape[1], r, nev,
+                                                   ctypes.byref(nb)), "surrogate_extend_workspace_size")
+        ws = self._wsbuf("extend", nb.value, Y.device)
+        st = status if status is not None else torch.zeros(1, dtype=torch.int32, device=Y.device)
+        nf = ctypes.c_int64(0)
+        _check(lib.surrogate_extend(ctypes.byref(self.shape), _ptr(self.params), _ptr(self.wbf16),
+                                    _ptr(mean), _ptr(rstd), float(log10_threshold), ctypes.byref(py),
+                                    ctypes.byref(px), _ptr(pivots), _ptr(k), _ptr(F), code, ldf, r,
+                                    _ptr(c), _ptr(E), nev, float(scale), _ptr(Phib), max(M, 1),
+                                    _ptr(res), ctypes.byref(nf), _ptr(ws), nb.value, _ptr(st),
+                                    _stream(torch, stream)), "surrogate_extend")
+        return {"Phi": Phib[:, :M].t(), "res": res[:M], "n_fallback": nf.value, "status": st}
+
+
+def surrogate_standardize(X, stream=None):
+    """Per-feature mean and 1/std (float64) of the rows of X (N x d float32)."""
+    torch = _torch()
+    lib = load_library()
+    N, d = X.shape
+    assert X.dtype == torch.float32 and X.stride(1) == 1
+    mean = torch.empty(d, dtype=torch.float64, device=X.device)
+    rstd = torch.empty(d, dtype=torch.float64, device=X.device)
+    nb = ctypes.c_size_t(0)
+    _check(lib.surrogate_standardize_workspace_size(N, d, ctypes.byref(nb)),
+           "surrogate_standardize_workspace_size")
+    ws = _workspace(torch, nb.value, X.device)
+    _check(lib.surrogate_standardize(_ptr(X), N, d, X.stride(0), _ptr(mean), _ptr(rstd), _ptr(ws),
+                                     nb.value, _stream(torch, stream)), "surrogate_standardize")
+    return mean, rstd
+
+
+def surrogate_residual_target(Phi_s, Phi_n, scale, stream=None):
+    """log10 RMS over outputs of Phi_s - scale Phi_n (both M x n column-major views)."""
+    torch = _torch()
+    lib = load_library()
+    M, n = Phi_s.shape
+    assert Phi_s.stride(0) == 1 and Phi_n.stride(0) == 1 and Phi_n.shape[0] == M
+    assert Phi_s.dtype == torch.float32 and Phi_n.dtype == torch.float64
+    out = torch.empty(max(M, 1), dtype=torch.float64, device=Phi_s.device)
+    lds = Phi_s.stride(1) if n > 1 else max(M, 1)
+    ldn = Phi_n.stride(1) if Phi_n.shape[1] > 1 else max(M, 1)
+    _check(lib.surrogate_residual_target(_ptr(Phi_s), lds, _ptr(Phi_n), ldn, float(scale), M, n,
+                                         _ptr(out), _stream(torch, stream)), "surrogate_residual_target")
+    return out[:M]
+
+
 def version():
     return load_library().rpc_version().decode()
 
 
 PROFILE_KINDS = ["kernel_cols", "schur", "solve_downdate", "pivot", "accept_reject", "degrees", "gram",
-                 "small", "form_u", "nystrom", "eig"]
+                 "small", "form_u", "nystrom", "eig", "sur_train", "sur_infer"]
 
 
 def profile_enable(on=True):

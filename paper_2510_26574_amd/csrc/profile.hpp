@@ -14,12 +14,14 @@ enum Kind {
   PIVOT = 3,        // residual quantisation, CDF draw / argmax
   ACCEPT = 4,       // pivot block H and Algorithm 3
   DEGREES = 5,      // c, d~, w, q~
-  GRAM = 6,         // the two N-long Gram products
-  SMALL = 7,        // r x r work: Cholesky, inner product, eigensolver
+  GRAM = 6,         // the N-long Gram partial products
+  SMALL = 7,        // r x r work: Gram reduction and finish, Cholesky, inner product
   FORM_U = 8,       // U = D~^{-1} F R^{-1} V and signs
   NYSTROM = 9,
   EIG = 10,         // top-nev eigenpairs of the r x r inner matrix
-  NKIND = 11
+  SUR_TRAIN = 11,   // one surrogate training step
+  SUR_INFER = 12,   // surrogate forward pass
+  NKIND = 13
 };
 bool enabled();
 void begin(int kind, hipStream_t st);

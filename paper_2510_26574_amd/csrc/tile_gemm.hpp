@@ -36,6 +36,14 @@ struct TileCfg {
   static_assert(BK % MM::KS == 0, "BK must be a multiple of the MFMA k");
 };
 
+// Whether a staged slice is k-contiguous in LDS: always for k-contiguous
+// global operands, and also for row-contiguous ones when the MFMA fragment
+// holds several consecutive k (bf16), in which case staging transposes.
+template <typename T, bool KC>
+struct LdsKC {
+  static constexpr bool value = KC || Mma<T>::EPL > 1;
+};
+
 // LDS layout of one staged operand slice (ROWS x BK):
 //   k-contiguous operand   -> s[row * LDK + k],  LDK = BK + 16 bytes of pad
 //   row-contiguous operand -> s[k * LDR + row],  LDR = ROWS + 16 elements of pad
@@ -51,8 +59,8 @@ struct SliceLayout {
 
 template <class Cfg, bool KCA, bool KCB>
 struct TileSmem {
-  typedef SliceLayout<typename Cfg::T, Cfg::BM, Cfg::BK, KCA> LA;
-  typedef SliceLayout<typename Cfg::T, Cfg::BN, Cfg::BK, KCB> LB;
+  typedef SliceLayout<typename Cfg::T, Cfg::BM, Cfg::BK, LdsKC<typename Cfg::T, KCA>::value> LA;
+  typedef SliceLayout<typename Cfg::T, Cfg::BN, Cfg::BK, LdsKC<typename Cfg::T, KCB>::value> LB;
   static constexpr int STAGE = LA::ELEMS + LB::ELEMS;  // one buffer (A then B)
   static constexpr size_t bytes = 2 * (size_t)STAGE * sizeof(typename Cfg::T);  // double buffered
 };
@@ -74,7 +82,8 @@ __device__ inline T scale_cvt(TG v, const double* ks, int64_t k) {
 // the current one.
 template <typename T, int ROWS, int BK, int NT, typename TG, bool KC>
 struct TileStage {
-  typedef SliceLayout<T, ROWS, BK, KC> L;
+  static constexpr bool LKC = LdsKC<T, KC>::value;
+  typedef SliceLayout<T, ROWS, BK, LKC> L;
   static constexpr int V = 16 / sizeof(TG);
   static constexpr int NV = KC ? ROWS * (BK / V) : BK * (ROWS / V);
   static constexpr int PER = (NV + NT - 1) / NT;
@@ -129,6 +138,13 @@ struct TileStage {
       if (NV % NT != 0 && vid >= NV) break;
       int row, kk;
       coords(vid, row, kk);
+      if constexpr (LKC != KC) {
+        // row-contiguous vector (rows row..row+V-1 at k = kk) into a
+        // k-contiguous slice: one element per row
+#pragma unroll
+        for (int j = 0; j < V; ++j) s[L::at(row + j, kk)] = scale_cvt<T>(buf[p][j], op.kscale, k0 + kk);
+        continue;
+      }
       T* dst = s + L::at(row, kk);  // the V elements run along the contiguous index
       if (op.kscale == nullptr && sizeof(T) == sizeof(TG)) {
         st v;
@@ -160,11 +176,10 @@ template <class Cfg, int ROWS, bool KC>
 __device__ inline typename Cfg::MM::frag load_frag(const typename Cfg::T* s, int row, int kk,
                                                    int lane) {
   typedef typename Cfg::MM MM;
-  typedef SliceLayout<typename Cfg::T, ROWS, Cfg::BK, KC> L;
+  typedef SliceLayout<typename Cfg::T, ROWS, Cfg::BK, LdsKC<typename Cfg::T, KC>::value> L;
   if constexpr (MM::EPL == 1) {
     return s[L::at(row, kk + (lane >> 4))];
   } else {
-    static_assert(KC, "multi-element fragments need a k-contiguous slice");
     return *reinterpret_cast<const typename MM::frag*>(s + L::at(row, kk + (lane >> 4) * MM::EPL));
   }
 }
