@@ -14,7 +14,9 @@ Timed paths (same uniforms):
   plain  every kernel in FP64 (the speedup denominator).
 
 Prints one JSON line.  Options: --gpus (must be 1), --steps, --warmup,
---workload {ks1m,ks100k,torus}, --no-cpu, --no-plain.
+--workload {ks1m,ks100k,torus}, --no-cpu, --no-plain.  `--form surrogate`
+instead trains the learned surrogate of the Nystrom extension on the
+workload's eigenvectors and measures it on held-out states (its own line).
 """
 import argparse
 import json
@@ -235,6 +237,125 @@ def parity(rp, torch, Xd, eps, w, mixed_res):
     }
 
 
+def ks_states(N, q, seed):
+    """KS delay-embedded states (cached under TMPDIR like the main workload)."""
+    from synth import ks_points
+
+    cache = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"rpchol_ks_{N}_{q}_{seed}.npy")
+    if os.path.exists(cache):
+        return np.load(cache)
+    X = ks_points(N, q=q, seed=seed)
+    try:
+        np.save(cache, X)
+    except OSError:
+        pass
+    return X
+
+
+SUR = dict(h=512, batch=4096, epochs=20, lr=1e-3, head_epochs=10, calib_N=100_000, calib_seed=1002,
+           test_N=1_000_000, test_seed=1001, init_seed=1000, log10_threshold=-2.0)
+
+
+def bench_surrogate(args, rp, torch):
+    """Learned surrogate of the Nystrom extension, trained on the eigenvectors
+    of the main workload (mixed form) and compared with the exact extension on
+    held-out KS states.  Prints one JSON line."""
+    from synth import uniform_stream
+
+    w = WORKLOADS[args.workload]
+    X, eps, u = make_inputs(w)
+    Xd, ud = torch.from_numpy(X).cuda(), torch.from_numpy(u).cuda()
+    N, d = X.shape
+    nev, h, B = w["nev"], SUR["h"], SUR["batch"]
+    epochs = args.sur_epochs
+    log("[surrogate] decomposition (mixed form)")
+    out, deg, eig = run_path(rp, torch, Xd, eps, ud, w, ("bf16", "f32", "f32"))
+    st = rp.status_sync(out["status"])
+    if st != 0:
+        raise RuntimeError(f"decomposition status {rp.STATUS_NAMES.get(st, st)}")
+    U = eig["U"]
+    scale = float(np.sqrt(N))
+    mean, rstd = rp.surrogate_standardize(Xd)
+    nu = rp.surrogate_init_uniforms(d, h, nev)
+    sur = rp.Surrogate(d, h, nev, uniforms=torch.from_numpy(uniform_stream(nu, seed=SUR["init_seed"])).cuda())
+    rng = np.random.default_rng(SUR["init_seed"])
+    perms = torch.from_numpy(np.stack([rng.permutation(N) for _ in range(epochs)])).cuda()
+    spe = -(-N // B)
+    losses = torch.zeros(epochs * spe, dtype=torch.float64, device="cuda")
+    log(f"[surrogate] training {epochs} epochs x {spe} steps (batch {B})")
+    # one untimed step on a copy-free warm-up is not possible without changing
+    # the weights, so the timing includes the first launch of each kernel
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in range(epochs):
+        sur.train_epoch(Xd, mean, rstd, perms[e], U, B, tscale=scale, lr=SUR["lr"],
+                        loss=losses[e * spe:(e + 1) * spe])
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    lc = losses.cpu().numpy()
+    log(f"[surrogate] trained in {t_train:.2f}s; loss {lc[0]:.4g} -> {lc[-spe:].mean():.4g}")
+    flops_step = 6.0 * B * (d * h + h * h + h * sur.layout["n3"])
+    # residual head on a calibration set
+    Xc = ks_states(SUR["calib_N"], w["q"], SUR["calib_seed"])
+    Xcd = torch.from_numpy(Xc).cuda()
+    ps = sur.infer(Xcd, mean, rstd)["Phi"]
+    pn = rp.nystrom_extend(Xcd, Xd, eps, out["pivots"], out["k"], out["F"], deg["c"], eig["E"])["Phi"]
+    tgt = rp.surrogate_residual_target(ps, pn, scale)
+    rngc = np.random.default_rng(SUR["calib_seed"])
+    for e in range(SUR["head_epochs"]):
+        sur.train_epoch(Xcd, mean, rstd, torch.from_numpy(rngc.permutation(len(Xc))).cuda(), tgt, B,
+                        phase=1, lr=SUR["lr"])
+    # held-out states
+    Y = ks_states(SUR["test_N"], w["q"], SUR["test_seed"])
+    Yd = torch.from_numpy(Y).cuda()
+    M = len(Y)
+
+    def timed_call(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps, r
+
+    log("[surrogate] held-out extension")
+    t_mlp, inf = timed_call(lambda: sur.infer(Yd, mean, rstd))
+    t_nys, nys = timed_call(lambda: rp.nystrom_extend(Yd, Xd, eps, out["pivots"], out["k"], out["F"],
+                                                      deg["c"], eig["E"]))
+    t_hyb, hyb = timed_call(lambda: sur.extend(Yd, Xd, eps, out["pivots"], out["k"], out["F"], deg["c"],
+                                               eig["E"], mean, rstd, scale,
+                                               log10_threshold=SUR["log10_threshold"]))
+    ref_rms = float(torch.sqrt(torch.mean((scale * nys["Phi"][:, :nev]) ** 2)).item())
+
+    def rms_err(phi):
+        pp = rp.surrogate_residual_target(phi, nys["Phi"], scale)
+        return float(torch.sqrt(torch.mean(torch.pow(10.0, 2.0 * pp))).item())
+
+    e_mlp, e_hyb = rms_err(inf["Phi"]), rms_err(hyb["Phi"])
+    pred = inf["res"].double()
+    true = rp.surrogate_residual_target(inf["Phi"], nys["Phi"], scale)
+    line = {
+        "metric": "learned surrogate of the Nystrom extension: training and extension throughput",
+        "form": "surrogate", "n_gpus": 1, "data": "synthetic", "dtype": "bf16",
+        "config": {"workload": f"train on KS N={N} d={d} (top {nev} eigenvectors x sqrt(N)); "
+                               f"held-out KS N={M} seed {SUR['test_seed']}",
+                   "mlp": f"{d}-{h}-{h}-{nev} GELU + residual head", "batch": B, "epochs": epochs,
+                   "lr": SUR["lr"], "fallback_log10_threshold": SUR["log10_threshold"]},
+        "train_s": t_train, "train_steps": epochs * spe, "train_steps_per_s": epochs * spe / t_train,
+        "train_tflops": flops_step * epochs * spe / t_train / 1e12,
+        "train_frac_bf16_peak": flops_step * epochs * spe / t_train / 1e12 / PEAK["bf16"],
+        "loss_first": float(lc[0]), "loss_last_epoch": float(lc[-spe:].mean()),
+        "heldout_rms_ref": ref_rms,
+        "heldout_rms_err_mlp": e_mlp, "heldout_rms_err_hybrid": e_hyb,
+        "heldout_rel_err_mlp": e_mlp / ref_rms, "heldout_rel_err_hybrid": e_hyb / ref_rms,
+        "fallback_fraction": hyb["n_fallback"] / M,
+        "residual_head_corr": float(torch.corrcoef(torch.stack([pred, true]))[0, 1].item()),
+        "points_per_s_mlp": M / t_mlp, "points_per_s_nystrom": M / t_nys, "points_per_s_hybrid": M / t_hyb,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,6 +367,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--form", default="headline", choices=["headline", "surrogate"],
+                    help="headline: the decomposition benchmark; surrogate: the learned extension")
+    ap.add_argument("--sur-epochs", type=int, default=SUR["epochs"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the method's data-parallel path is built and timed on a "
@@ -257,6 +381,9 @@ def main():
     import paper_2510_26574_amd as rp
 
     rp.load_library()
+    if args.form == "surrogate":
+        bench_surrogate(args, rp, torch)
+        return
     w = WORKLOADS[args.workload]
     X, eps, u = make_inputs(w)
     Xd = torch.from_numpy(X).cuda()

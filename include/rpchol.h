@@ -183,6 +183,65 @@ int nystrom_extend(const rpc_points* Y, const rpc_points* X, const int64_t* pivo
                    void* workspace, size_t workspace_bytes, int32_t* dev_status,
                    rpc_stream_t stream);
 
+/* ---- Batched form: many independent decompositions ----------------------
+ * A job is one full decomposition of its own points (rpchol_factor, then
+ * bistoch_degrees, then bistoch_eig, exactly as the three calls made one
+ * after the other) with its own output buffers, all device memory owned by
+ * the caller.  Small problems cannot fill the chip one at a time, so
+ * rpc_batched_run forks `stream` onto n_streams internal streams (created on
+ * first use per device, default priority, kept until the process ends),
+ * assigns the jobs longest-first (estimated N r (2 d + 3 r)) to the stream
+ * with the least assigned work, and joins them back into `stream`.  Jobs on
+ * one stream run in sequence and share one slice of the workspace.  Each
+ * job's dev_status is cleared when the job starts.  Results equal those of
+ * the single calls bit for bit.  On a host-side error the jobs issued before
+ * it still run and the first error is returned.
+ *
+ * rpc_batched_graph_create captures the same issue into a HIP graph (stream
+ * must not be the null stream; profiling must be off); every launch of the
+ * graph recomputes all jobs from their current inputs.  Buffers named in the
+ * job table must stay valid while the graph exists. */
+typedef struct {
+  rpc_points X;           /* points and bandwidth */
+  rpc_factor_opts factor; /* rank budget, block size, mode, dtypes, uniforms */
+  rpc_eig_opts eig;       /* nev, gamma, fix_const, dtypes */
+  void* F;                /* N x r, column-major, ldf (multiple of 8, >= N) */
+  int64_t ldf;
+  int64_t* pivots;        /* r */
+  double* rho;            /* N */
+  int32_t* k;             /* 1 */
+  double* c;              /* r */
+  double* d_tilde;        /* N */
+  double* q_tilde;        /* N */
+  void* U;                /* N x nev, column-major, ldu */
+  int64_t ldu;
+  double* lambda;         /* nev */
+  double* ext_E;          /* r x nev */
+  int32_t* dev_status;    /* 1, required */
+} rpc_job;
+
+typedef struct rpc_graph_s* rpc_graph;
+
+int rpc_job_workspace_size(const rpc_job* job, size_t* bytes);
+int rpc_batched_workspace_size(const rpc_job* jobs, int32_t n_jobs, int32_t n_streams,
+                               size_t* bytes);
+int rpc_batched_run(const rpc_job* jobs, int32_t n_jobs, int32_t n_streams, void* workspace,
+                    size_t workspace_bytes, rpc_stream_t stream);
+int rpc_batched_graph_create(const rpc_job* jobs, int32_t n_jobs, int32_t n_streams,
+                             void* workspace, size_t workspace_bytes, rpc_stream_t stream,
+                             rpc_graph* graph);
+int rpc_batched_graph_launch(rpc_graph graph, rpc_stream_t stream);
+int rpc_batched_graph_destroy(rpc_graph graph);
+
+/* Block-size autotuning: runs the job once untimed and `reps` times timed
+ * (HIP events on `stream`, synchronising) for each candidate block size b
+ * (the job's own b is ignored), writes the mean milliseconds to ms[i] (if
+ * non-NULL) and the fastest candidate to *best_b.  Overwrites the job's
+ * outputs; the workspace must cover every candidate. */
+int rpc_autotune_block(const rpc_job* job, const int32_t* candidates, int32_t n_candidates,
+                       int32_t reps, void* workspace, size_t workspace_bytes, rpc_stream_t stream,
+                       int32_t* best_b, double* ms);
+
 /* ---- Learned surrogate of the Nystrom extension -------------------------
  * The Nystrom extension above maps a new state y to the values of the
  * approximate eigenvectors at y.  The surrogate is a multilayer perceptron
@@ -229,10 +288,16 @@ typedef struct {
 /* Host only.  RPC_EINVAL for a shape outside the limits above. */
 int surrogate_layout(const sur_shape* shape, sur_layout* out);
 
-/* Prepare a freshly initialised parameter vector: zero the pad entries of
- * `params`, zero both AdamW moments, write the bf16 copy. */
-int surrogate_init(const sur_shape* shape, float* params, float* adam_m, float* adam_v,
-                   uint16_t* wbf16, rpc_stream_t stream);
+/* Initialisation.  With `uniforms` (device doubles in [0, 1), at least
+ * surrogate_init_uniforms() of them; fewer: RPC_EINVAL) every weight and bias
+ * becomes (2 u - 1) / sqrt(fan_in), u taken in the order W1, b1, W2, b2, W3,
+ * b3, wr, br (row-major within a matrix); with uniforms == NULL `params`
+ * already holds the initial values.  Pad entries are zeroed, both AdamW
+ * moments zeroed and the bf16 copy written. */
+int surrogate_init_uniforms(const sur_shape* shape, int64_t* count);
+int surrogate_init(const sur_shape* shape, const double* uniforms, int64_t n_uniforms,
+                   float* params, float* adam_m, float* adam_v, uint16_t* wbf16,
+                   rpc_stream_t stream);
 
 /* Per-feature mean and 1/(population standard deviation) of the N x d
  * float32 rows X (row-major, ldx >= d), in float64 (two passes); a constant
@@ -261,6 +326,18 @@ int surrogate_train_step(const sur_shape* shape, const sur_train_opts* opts, con
                          float* adam_v, uint16_t* wbf16, float* grad, double* loss,
                          void* workspace, size_t workspace_bytes, int32_t* dev_status,
                          rpc_stream_t stream);
+
+/* ceil(n_idx / batch) steps of surrogate_train_step over consecutive slices
+ * of idx (the last one ragged), with step numbers opts->step, opts->step + 1,
+ * ...; loss, if non-NULL, receives one device double per step.  The
+ * workspace is that of surrogate_train_step for `batch`. */
+int surrogate_train_epoch(const sur_shape* shape, const sur_train_opts* opts, const float* X,
+                          int64_t ldx, int64_t N, const double* mean, const double* rstd,
+                          const int64_t* idx, int64_t n_idx, int64_t batch, const void* T,
+                          int32_t t_dtype, int64_t ldt, double tscale, float* params,
+                          float* adam_m, float* adam_v, uint16_t* wbf16, double* loss,
+                          void* workspace, size_t workspace_bytes, int32_t* dev_status,
+                          rpc_stream_t stream);
 
 /* Forward pass over the M rows of Y (float32 row-major, ldy >= d): Phi (M x
  * n_out float32, column-major, ldphi >= M) and, if non-NULL, res (M float32,

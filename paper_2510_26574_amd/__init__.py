@@ -70,12 +70,15 @@ _SIGS = {
     "nystrom_extend": [_VP, _VP, _VP, _VP, _VP, _I32, _I64, _I32, _VP, _VP, _I32, _VP, _I64, _VP,
                        _SZ, _VP, _VP],
     "surrogate_layout": [_VP, _VP],
-    "surrogate_init": [_VP, _VP, _VP, _VP, _VP, _VP],
+    "surrogate_init_uniforms": [_VP, _VP],
+    "surrogate_init": [_VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP],
     "surrogate_standardize_workspace_size": [_I64, _I64, _VP],
     "surrogate_standardize": [_VP, _I64, _I64, _I64, _VP, _VP, _VP, _SZ, _VP],
     "surrogate_train_workspace_size": [_VP, _I64, _I32, _VP],
     "surrogate_train_step": [_VP, _VP, _VP, _I64, _I64, _VP, _VP, _VP, _I64, _VP, _I32, _I64,
                              ctypes.c_double, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP, _VP],
+    "surrogate_train_epoch": [_VP, _VP, _VP, _I64, _I64, _VP, _VP, _VP, _I64, _I64, _VP, _I32, _I64,
+                              ctypes.c_double, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP, _VP],
     "surrogate_infer_workspace_size": [_VP, _I64, _VP],
     "surrogate_infer": [_VP, _VP, _VP, _VP, _I64, _I64, _VP, _VP, _VP, _I64, _VP, _VP, _SZ, _VP,
                         _VP],
@@ -84,6 +87,13 @@ _SIGS = {
     "surrogate_extend": [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP, _VP, _VP, _VP, _I32,
                          _I64, _I32, _VP, _VP, _I32, ctypes.c_double, _VP, _I64, _VP, _VP, _VP,
                          _SZ, _VP, _VP],
+    "rpc_job_workspace_size": [_VP, _VP],
+    "rpc_batched_workspace_size": [_VP, _I32, _I32, _VP],
+    "rpc_batched_run": [_VP, _I32, _I32, _VP, _SZ, _VP],
+    "rpc_batched_graph_create": [_VP, _I32, _I32, _VP, _SZ, _VP, _VP],
+    "rpc_batched_graph_launch": [_VP, _VP],
+    "rpc_batched_graph_destroy": [_VP],
+    "rpc_autotune_block": [_VP, _VP, _I32, _I32, _VP, _SZ, _VP, _VP, _VP],
     "rpc_status_sync": [_VP, _VP],
     "rpc_version": [],
     "rpc_profile_enable": [ctypes.c_int],
@@ -273,6 +283,148 @@ def nystrom_extend(Y, X, eps, pivots, k, F, c, E, status=None, stream=None):
     return {"Phi": Phib.t(), "status": st}
 
 
+class rpc_job(ctypes.Structure):
+    _fields_ = [("X", rpc_points), ("factor", rpc_factor_opts), ("eig", rpc_eig_opts),
+                ("F", ctypes.c_void_p), ("ldf", ctypes.c_int64), ("pivots", ctypes.c_void_p),
+                ("rho", ctypes.c_void_p), ("k", ctypes.c_void_p), ("c", ctypes.c_void_p),
+                ("d_tilde", ctypes.c_void_p), ("q_tilde", ctypes.c_void_p), ("U", ctypes.c_void_p),
+                ("ldu", ctypes.c_int64), ("lambda_", ctypes.c_void_p), ("ext_E", ctypes.c_void_p),
+                ("dev_status", ctypes.c_void_p)]
+
+
+class Job:
+    """One decomposition of the batched form: its inputs, its output tensors
+    (allocated here) and the C job record pointing at them."""
+
+    def __init__(self, X, eps, r, b, nev, mode="sampled", uniforms=None, replay=None,
+                 gemm_dtype="f32", factor_dtype="f32", gram_dtype="f32", u_dtype="f32", tau=0.0,
+                 gamma=0.0):
+        torch = _torch()
+        N = X.shape[0]
+        dev = X.device
+        self.X, self.uniforms, self.replay = X, uniforms, replay
+        fdt = torch.float64 if factor_dtype == "f64" else torch.float32
+        udt = torch.float64 if u_dtype == "f64" else torch.float32
+        self.ldf = _ld(N)
+        self.Fbuf = torch.empty((r, self.ldf), dtype=fdt, device=dev)
+        self.pivots = torch.empty(r, dtype=torch.int64, device=dev)
+        self.rho = torch.empty(N, dtype=torch.float64, device=dev)
+        self.k = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.c = torch.empty(r, dtype=torch.float64, device=dev)
+        self.d = torch.empty(N, dtype=torch.float64, device=dev)
+        self.q = torch.empty(N, dtype=torch.float64, device=dev)
+        self.Ubuf = torch.empty((nev, self.ldf), dtype=udt, device=dev)
+        self.lam = torch.empty(nev, dtype=torch.float64, device=dev)
+        self.Ebuf = torch.empty((nev, r), dtype=torch.float64, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        fo = rpc_factor_opts(int(r), int(b), MODES[mode], DTYPES[gemm_dtype], DTYPES[factor_dtype], 0,
+                             float(tau), 0, 0, 0, 0, 0)
+        if mode == "sampled":
+            assert uniforms is not None and uniforms.dtype == torch.float64 and uniforms.is_cuda
+            fo.uniforms, fo.n_uniforms = uniforms.data_ptr(), uniforms.numel()
+        if mode == "replay":
+            assert replay is not None and replay.dtype == torch.int64 and replay.is_cuda
+            fo.replay, fo.n_replay = replay.data_ptr(), replay.numel()
+        eo = rpc_eig_opts(int(nev), 0, DTYPES[gram_dtype], DTYPES[u_dtype], float(gamma))
+        self.rec = rpc_job(_points(X, eps), fo, eo, self.Fbuf.data_ptr(), self.ldf,
+                           self.pivots.data_ptr(), self.rho.data_ptr(), self.k.data_ptr(),
+                           self.c.data_ptr(), self.d.data_ptr(), self.q.data_ptr(), self.Ubuf.data_ptr(),
+                           self.ldf, self.lam.data_ptr(), self.Ebuf.data_ptr(), self.status.data_ptr())
+
+    @property
+    def F(self):
+        return self.Fbuf[:, :self.X.shape[0]].t()
+
+    @property
+    def U(self):
+        return self.Ubuf[:, :self.X.shape[0]].t()
+
+    @property
+    def E(self):
+        return self.Ebuf.t()
+
+
+def _job_array(jobs):
+    arr = (rpc_job * len(jobs))()
+    for i, j in enumerate(jobs):
+        arr[i] = j.rec
+    return arr
+
+
+def batched_workspace(jobs, n_streams):
+    torch = _torch()
+    nb = ctypes.c_size_t(0)
+    _check(load_library().rpc_batched_workspace_size(_job_array(jobs), len(jobs), int(n_streams),
+                                                     ctypes.byref(nb)), "rpc_batched_workspace_size")
+    return _workspace(torch, nb.value, jobs[0].X.device)
+
+
+def batched_run(jobs, n_streams=4, workspace=None, stream=None):
+    """Run every job's decomposition, overlapped over n_streams streams."""
+    torch = _torch()
+    ws = workspace if workspace is not None else batched_workspace(jobs, n_streams)
+    _check(load_library().rpc_batched_run(_job_array(jobs), len(jobs), int(n_streams), _ptr(ws),
+                                          ws.numel(), _stream(torch, stream)), "rpc_batched_run")
+    return ws
+
+
+class BatchedGraph:
+    """The batched issue of `jobs` captured once into a HIP graph on a
+    non-default stream; launch() replays it on that stream."""
+
+    def __init__(self, jobs, n_streams=4, workspace=None, stream=None):
+        torch = _torch()
+        self.jobs = list(jobs)
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.ws = workspace if workspace is not None else batched_workspace(self.jobs, n_streams)
+        self._arr = _job_array(self.jobs)
+        g = ctypes.c_void_p(0)
+        self.stream.wait_stream(torch.cuda.current_stream())
+        _check(load_library().rpc_batched_graph_create(self._arr, len(self.jobs), int(n_streams),
+                                                       _ptr(self.ws), self.ws.numel(),
+                                                       ctypes.c_void_p(self.stream.cuda_stream),
+                                                       ctypes.byref(g)), "rpc_batched_graph_create")
+        self._g = g
+
+    def launch(self):
+        _check(load_library().rpc_batched_graph_launch(self._g, ctypes.c_void_p(self.stream.cuda_stream)),
+               "rpc_batched_graph_launch")
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if self._g:
+            load_library().rpc_batched_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune_block(job, candidates, reps=2, stream=None):
+    """(best b, {b: mean ms}) over the candidate block sizes for this job."""
+    torch = _torch()
+    lib = load_library()
+    need = 0
+    for b in candidates:
+        rec = rpc_job.from_buffer_copy(job.rec)
+        rec.factor.b = int(b)
+        nb = ctypes.c_size_t(0)
+        _check(lib.rpc_job_workspace_size(ctypes.byref(rec), ctypes.byref(nb)), "rpc_job_workspace_size")
+        need = max(need, nb.value)
+    ws = _workspace(torch, need, job.X.device)
+    cand = (ctypes.c_int32 * len(candidates))(*[int(b) for b in candidates])
+    ms = (ctypes.c_double * len(candidates))()
+    best = ctypes.c_int32(0)
+    _check(lib.rpc_autotune_block(ctypes.byref(job.rec), cand, len(candidates), int(reps), _ptr(ws), need,
+                                  _stream(torch, stream), ctypes.byref(best), ms), "rpc_autotune_block")
+    return best.value, {int(b): ms[i] for i, b in enumerate(candidates)}
+
+
 class sur_shape(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("h", ctypes.c_int32), ("n_out", ctypes.c_int32)]
 
@@ -299,26 +451,42 @@ def surrogate_layout(d, h, n_out):
     return {f: getattr(lay, f) for f, _ in sur_layout._fields_}
 
 
+def surrogate_init_uniforms(d, h, n_out):
+    """Number of uniforms the initialisation draws."""
+    n = ctypes.c_int64(0)
+    sh = sur_shape(int(d), int(h), int(n_out))
+    _check(load_library().surrogate_init_uniforms(ctypes.byref(sh), ctypes.byref(n)),
+           "surrogate_init_uniforms")
+    return n.value
+
+
 class Surrogate:
     """Parameter vector, AdamW moments and bf16 copy of one surrogate, in
     device memory (float32 / bfloat16 torch tensors owned here)."""
 
-    def __init__(self, d, h, n_out, init, device="cuda", stream=None):
+    def __init__(self, d, h, n_out, init=None, uniforms=None, device="cuda", stream=None):
+        """Either `init` (a full parameter vector in the layout) or `uniforms`
+        (device float64, surrogate_init_uniforms(d, h, n_out) of them)."""
         torch = _torch()
         lib = load_library()
         self.shape = sur_shape(int(d), int(h), int(n_out))
         self.layout = surrogate_layout(d, h, n_out)
         tot = self.layout["total"]
-        init = torch.as_tensor(init, dtype=torch.float32)
-        assert init.numel() == tot, f"initial parameter vector must have {tot} entries"
-        self.params = init.to(device).contiguous()
+        if init is not None:
+            init = torch.as_tensor(init, dtype=torch.float32)
+            assert init.numel() == tot, f"initial parameter vector must have {tot} entries"
+            self.params = init.to(device).contiguous()
+        else:
+            assert uniforms is not None and uniforms.dtype == torch.float64 and uniforms.is_cuda
+            self.params = torch.empty(tot, dtype=torch.float32, device=device)
         self.m = torch.empty(tot, dtype=torch.float32, device=device)
         self.v = torch.empty(tot, dtype=torch.float32, device=device)
         self.wbf16 = torch.empty(tot, dtype=torch.bfloat16, device=device)
-        self.step = 0
-        _check(lib.surrogate_init(ctypes.byref(self.shape), _ptr(self.params), _ptr(self.m),
-                                  _ptr(self.v), _ptr(self.wbf16), _stream(torch, stream)),
-               "surrogate_init")
+        self.steps = {0: 0, 1: 0}  # AdamW step counters, one per phase
+        nu = uniforms.numel() if init is None else 0
+        _check(lib.surrogate_init(ctypes.byref(self.shape), _ptr(None if init is not None else uniforms),
+                                  nu, _ptr(self.params), _ptr(self.m), _ptr(self.v), _ptr(self.wbf16),
+                                  _stream(torch, stream)), "surrogate_init")
         self._ws = {}
 
     def _wsbuf(self, key, nbytes, device):
@@ -336,8 +504,8 @@ class Surrogate:
         torch = _torch()
         lib = load_library()
         if step is None:
-            self.step += 1
-            step = self.step
+            self.steps[phase] += 1
+            step = self.steps[phase]
         B = idx.numel()
         assert idx.dtype == torch.int64 and X.dtype == torch.float32 and X.stride(1) == 1
         if phase == 0:
@@ -360,6 +528,40 @@ class Surrogate:
                                         _ptr(self.m), _ptr(self.v), _ptr(self.wbf16), _ptr(grad),
                                         _ptr(loss), _ptr(ws), nb.value, _ptr(st),
                                         _stream(torch, stream)), "surrogate_train_step")
+        return st
+
+    def train_epoch(self, X, mean, rstd, idx, T, batch, tscale=1.0, phase=0, lr=1e-3,
+                    betas=(0.9, 0.999), eps=1e-8, weight_decay=0.01, splits=0, loss=None,
+                    status=None, stream=None):
+        """ceil(len(idx) / batch) AdamW steps over consecutive slices of idx."""
+        torch = _torch()
+        lib = load_library()
+        n = idx.numel()
+        nsteps = -(-n // batch)
+        assert idx.dtype == torch.int64 and X.dtype == torch.float32 and X.stride(1) == 1
+        if phase == 0:
+            assert T.dim() == 2 and T.stride(0) == 1, "phase-0 targets must be column-major N x n_out"
+            ldt = T.stride(1) if T.shape[1] > 1 else T.shape[0]
+        else:
+            assert T.dim() == 1
+            ldt = T.shape[0]
+        if loss is not None:
+            assert loss.dtype == torch.float64 and loss.numel() >= nsteps
+        tcode = DTYPES["f64"] if T.dtype == torch.float64 else DTYPES["f32"]
+        opts = sur_train_opts(float(lr), float(betas[0]), float(betas[1]), float(eps),
+                              float(weight_decay), int(self.steps[phase] + 1), int(phase), int(splits))
+        nb = ctypes.c_size_t(0)
+        _check(lib.surrogate_train_workspace_size(ctypes.byref(self.shape), min(batch, n), int(splits),
+                                                  ctypes.byref(nb)), "surrogate_train_workspace_size")
+        ws = self._wsbuf("train", nb.value, X.device)
+        st = status if status is not None else torch.zeros(1, dtype=torch.int32, device=X.device)
+        _check(lib.surrogate_train_epoch(ctypes.byref(self.shape), ctypes.byref(opts), _ptr(X),
+                                         X.stride(0), X.shape[0], _ptr(mean), _ptr(rstd), _ptr(idx), n,
+                                         int(batch), _ptr(T), tcode, ldt, float(tscale),
+                                         _ptr(self.params), _ptr(self.m), _ptr(self.v),
+                                         _ptr(self.wbf16), _ptr(loss), _ptr(ws), nb.value, _ptr(st),
+                                         _stream(torch, stream)), "surrogate_train_epoch")
+        self.steps[phase] += nsteps
         return st
 
     def infer(self, Y, mean, rstd, with_res=True, status=None, stream=None):

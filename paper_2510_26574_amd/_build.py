@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librpchol.so")
-SOURCES = ["arpc.hip", "bistoch.hip", "nystrom.hip", "surrogate.hip", "profile.hip"]
+SOURCES = ["arpc.hip", "bistoch.hip", "nystrom.hip", "surrogate.hip", "batched.hip", "profile.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950",

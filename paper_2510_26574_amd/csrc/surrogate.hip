@@ -84,12 +84,46 @@ __device__ inline float gelu_grad_f(float x) {
          x * 0.39894228040143268f * expf(-0.5f * x * x);
 }
 
-__global__ void k_sur_init(Lay L, float* __restrict__ p, float* __restrict__ m,
-                           float* __restrict__ v, __bf16* __restrict__ wb) {
+// Index of parameter entry i in the initialisation stream (order W1, b1, W2,
+// b2, W3, b3, wr, br; row-major within a matrix) and its fan-in; -1 for pad.
+__device__ inline int64_t init_index(const Lay& L, int64_t i, int& fan) {
+  const int64_t d = L.d, h = L.h, no = L.nout;
+  const int64_t o2 = h * d + h, o3 = o2 + h * h + h;
+  if (i >= L.W1 && i < L.W1 + h * d) { fan = L.d; return i - L.W1; }
+  if (i >= L.b1 && i < L.b1 + h) { fan = L.d; return h * d + (i - L.b1); }
+  if (i >= L.W2 && i < L.W2 + h * h) { fan = L.h; return o2 + (i - L.W2); }
+  if (i >= L.b2 && i < L.b2 + h) { fan = L.h; return o2 + h * h + (i - L.b2); }
+  fan = L.h;
+  if (i >= L.W3 && i < L.W3 + (int64_t)L.n3 * h) {
+    const int64_t row = (i - L.W3) / h, col = (i - L.W3) % h;
+    if (row < no) return o3 + row * h + col;
+    if (row == no) return o3 + no * h + no + col;
+    return -1;
+  }
+  if (i >= L.b3 && i < L.b3 + L.n3) {
+    const int64_t j = i - L.b3;
+    if (j < no) return o3 + no * h + j;
+    if (j == no) return o3 + no * h + no + h;
+  }
+  return -1;
+}
+
+// Parameters from the uniform stream u (if given): (2 u - 1) / sqrt(fan_in);
+// pad entries zero; moments zero; bf16 copy.
+__global__ void k_sur_init(Lay L, const double* __restrict__ u, float* __restrict__ p,
+                           float* __restrict__ m, float* __restrict__ v,
+                           __bf16* __restrict__ wb) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= L.total) return;
-  float x = p[i];
-  if (entry_class(L, i) == 0) x = 0.0f;
+  int fan = 1;
+  const int64_t j = init_index(L, i, fan);
+  float x;
+  if (j < 0)
+    x = 0.0f;
+  else if (u)
+    x = (float)((2.0 * u[j] - 1.0) * (1.0 / sqrt((double)fan)));
+  else
+    x = p[i];
   p[i] = x;
   m[i] = 0.0f;
   v[i] = 0.0f;
@@ -528,13 +562,25 @@ int surrogate_layout(const sur_shape* shape, sur_layout* out) {
   return RPC_OK;
 }
 
-int surrogate_init(const sur_shape* shape, float* params, float* adam_m, float* adam_v,
-                   uint16_t* wbf16, rpc_stream_t stream) {
+int surrogate_init_uniforms(const sur_shape* shape, int64_t* count) {
   Lay L;
+  if (!count || !make_layout(shape, L)) return RPC_EINVAL;
+  const int64_t d = L.d, h = L.h, no = L.nout;
+  *count = h * d + h + h * h + h + no * h + no + h + 1;
+  return RPC_OK;
+}
+
+int surrogate_init(const sur_shape* shape, const double* uniforms, int64_t n_uniforms,
+                   float* params, float* adam_m, float* adam_v, uint16_t* wbf16,
+                   rpc_stream_t stream) {
+  Lay L;
+  int64_t need = 0;
   if (!make_layout(shape, L) || !params || !adam_m || !adam_v || !wbf16) return RPC_EINVAL;
+  surrogate_init_uniforms(shape, &need);
+  if (uniforms && n_uniforms < need) return RPC_EINVAL;
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_sur_init, dim3(nblk(L.total)), dim3(256), 0, st, L, params, adam_m, adam_v,
-                     reinterpret_cast<__bf16*>(wbf16));
+  hipLaunchKernelGGL(k_sur_init, dim3(nblk(L.total)), dim3(256), 0, st, L, uniforms, params, adam_m,
+                     adam_v, reinterpret_cast<__bf16*>(wbf16));
   RPC_LAUNCH_CHECK();
   return RPC_OK;
 }
@@ -663,6 +709,28 @@ int surrogate_train_step(const sur_shape* shape, const sur_train_opts* o, const 
   }
   RPC_LAUNCH_CHECK();
   prof::end(prof::SUR_TRAIN, st);
+  return RPC_OK;
+}
+
+int surrogate_train_epoch(const sur_shape* shape, const sur_train_opts* o, const float* X,
+                          int64_t ldx, int64_t N, const double* mean, const double* rstd,
+                          const int64_t* idx, int64_t n_idx, int64_t batch, const void* T,
+                          int32_t t_dtype, int64_t ldt, double tscale, float* params,
+                          float* adam_m, float* adam_v, uint16_t* wbf16, double* loss,
+                          void* workspace, size_t workspace_bytes, int32_t* dev_status,
+                          rpc_stream_t stream) {
+  if (!o || !idx || n_idx < 1 || batch < 1) return RPC_EINVAL;
+  sur_train_opts so = *o;
+  int64_t s = 0;
+  for (int64_t b0 = 0; b0 < n_idx; b0 += batch, ++s) {
+    const int64_t nb = n_idx - b0 < batch ? n_idx - b0 : batch;
+    so.step = o->step + s;
+    const int rc = surrogate_train_step(shape, &so, X, ldx, N, mean, rstd, idx + b0, nb, T, t_dtype,
+                                        ldt, tscale, params, adam_m, adam_v, wbf16, nullptr,
+                                        loss ? loss + s : nullptr, workspace, workspace_bytes,
+                                        dev_status, stream);
+    if (rc != RPC_OK) return rc;
+  }
   return RPC_OK;
 }
 

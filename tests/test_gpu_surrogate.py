@@ -312,3 +312,39 @@ def test_invalid_arguments(gpu):
     idx = torch.tensor([0, 5, 100], dtype=torch.int64, device="cuda")  # 100 is out of range
     st = c["sur"].train_step(c["dev"]["X"], c["dev"]["mu"], c["dev"]["rs"], idx, c["dev"]["T"], step=1)
     assert rp.status_sync(st) == rp.RPC_EINVAL
+
+
+def test_init_from_uniforms_matches_oracle(gpu):
+    torch, rp = gpu
+    d, h, n_out = 24, 128, 7
+    n = rp.surrogate_init_uniforms(d, h, n_out)
+    u = uniform_stream(n, seed=77)
+    sur = rp.Surrogate(d, h, n_out, uniforms=torch.from_numpy(u).cuda())
+    P = S.init_params(d, h, n_out, u)
+    lay = rp.surrogate_layout(d, h, n_out)
+    got = sur.params.cpu().numpy()
+    assert np.array_equal(got, _pack(P, lay, n_out).astype(np.float32))
+    assert not np.any(sur.m.cpu().numpy()) and not np.any(sur.v.cpu().numpy())
+    with pytest.raises(rp.RpcError):
+        rp.Surrogate(d, h, n_out, uniforms=torch.from_numpy(u[:-1]).cuda())
+
+
+def test_train_epoch_equals_steps(gpu):
+    torch, rp = gpu
+    a = _setup(gpu, seed=12)
+    b = _setup(gpu, seed=12)
+    idx = np.random.default_rng(1).permutation(500).astype(np.int64)
+    loss_e = torch.zeros(4, dtype=torch.float64, device="cuda")
+    a["sur"].train_epoch(a["dev"]["X"], a["dev"]["mu"], a["dev"]["rs"], torch.from_numpy(idx).cuda(),
+                         a["dev"]["T"], batch=128, loss=loss_e)  # 3 x 128 + 116
+    losses = []
+    for s in range(4):
+        lt = torch.zeros(1, dtype=torch.float64, device="cuda")
+        b["sur"].train_step(b["dev"]["X"], b["dev"]["mu"], b["dev"]["rs"],
+                            torch.from_numpy(idx[s * 128:(s + 1) * 128].copy()).cuda(), b["dev"]["T"],
+                            loss=lt)
+        losses.append(float(lt.item()))
+    assert a["sur"].steps[0] == 4 and b["sur"].steps[0] == 4
+    assert torch.equal(a["sur"].params, b["sur"].params)
+    assert torch.equal(a["sur"].v, b["sur"].v)
+    assert np.array_equal(loss_e.cpu().numpy(), np.array(losses))
