@@ -16,7 +16,9 @@ Timed paths (same uniforms):
 Prints one JSON line.  Options: --gpus (must be 1), --steps, --warmup,
 --workload {ks1m,ks100k,torus}, --no-cpu, --no-plain.  `--form surrogate`
 instead trains the learned surrogate of the Nystrom extension on the
-workload's eigenvectors and measures it on held-out states (its own line).
+workload's eigenvectors and measures it on held-out states (its own line);
+`--form batched` runs the batched form (512 decompositions of 64 smaller
+datasets at 8 bandwidths each).
 """
 import argparse
 import json
@@ -356,6 +358,122 @@ def bench_surrogate(args, rp, torch):
     print(json.dumps(line), flush=True)
 
 
+BATCH = dict(nev=16, n_streams=8, reps=3, datasets=64)
+
+
+def bench_batched(args, rp, torch):
+    """The batched form: 64 KS datasets of varied size, dimension and rank,
+    each at 8 bandwidths (512 decompositions, FP32), block sizes from the
+    autotuner.  Times one stream (jobs in sequence), the stream pool, and the
+    HIP-graph replay of the pool.  Prints one JSON line."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_2510_26574_amd import autotune
+    from synth import BANDWIDTH_MULTIPLIERS, batch_points, batch_specs, uniform_stream
+
+    specs = batch_specs(n_datasets=args.datasets)
+    t0 = time.perf_counter()
+
+    def points(sp):
+        cache = os.path.join(os.environ.get("TMPDIR", "/tmp"),
+                             f"rpchol_batch_{sp['seed']}_{sp['N']}_{sp['d']}_{sp['q']}.npz")
+        if os.path.exists(cache):
+            z = np.load(cache)
+            return z["X"], float(z["eps"])
+        X, eps = batch_points(sp)
+        try:
+            np.savez(cache, X=X, eps=eps)
+        except OSError:
+            pass
+        return X, eps
+
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        data = list(ex.map(points, specs))
+    log(f"[batched] {len(specs)} datasets, sum N = {sum(s['N'] for s in specs)} "
+        f"({time.perf_counter() - t0:.1f}s)")
+    Xd = [torch.from_numpy(X).cuda() for X, _ in data]
+    nev = BATCH["nev"]
+    probs, meta = [], []
+    for i, sp in enumerate(specs):
+        for j, m in enumerate(BANDWIDTH_MULTIPLIERS):
+            probs.append((sp["N"], sp["d"], sp["r"]))
+            meta.append((i, m, 8 * i + j))
+    us = {}
+
+    def uniforms(n, r):
+        if (n, r) not in us:
+            us[(n, r)] = torch.from_numpy(uniform_stream(2 * r, seed=n)).cuda()
+        return us[(n, r)]
+
+    def make_job(q, b):
+        i, m, n = meta[q]
+        sp = specs[i]
+        return rp.Job(Xd[i], m * data[i][1], sp["r"], b, nev, uniforms=uniforms(n, sp["r"]))
+
+    log("[batched] autotuning block sizes")
+    cache_path = os.path.join(os.environ.get("TMPDIR", "/tmp"), "rpchol_autotune.json")
+    bs, cache = autotune.tune(probs, make_job, cache_path=cache_path, reps=1)
+    jobs = [make_job(q, b) for q, b in enumerate(bs)]
+    ns = BATCH["n_streams"]
+    ws = rp.batched_workspace(jobs, ns)
+    log(f"[batched] {len(jobs)} jobs, workspace {ws.numel() / 1e9:.2f} GB")
+
+    def run(n_streams, reps):
+        rp.batched_run(jobs, n_streams=n_streams, workspace=ws)  # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            rp.batched_run(jobs, n_streams=n_streams, workspace=ws)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    t_serial = run(1, 1)
+    log(f"[batched] one stream {t_serial:.3f}s")
+    t_pool = run(ns, BATCH["reps"])
+    log(f"[batched] {ns} streams {t_pool:.3f}s")
+    st = [int(j.status.item()) for j in jobs]
+    t = time.perf_counter()
+    g = rp.BatchedGraph(jobs, n_streams=ns, workspace=ws)
+    t_capture = time.perf_counter() - t
+    g.launch()
+    g.synchronize()
+    t = time.perf_counter()
+    for _ in range(BATCH["reps"]):
+        g.launch()
+    g.synchronize()
+    t_graph = (time.perf_counter() - t) / BATCH["reps"]
+    log(f"[batched] graph {t_graph:.3f}s (capture {t_capture:.2f}s)")
+    st_g = [int(j.status.item()) for j in jobs]
+    g.close()
+    # spot check: three jobs against their single-call decomposition
+    same = True
+    for q in (0, len(jobs) // 2, len(jobs) - 1):
+        j = jobs[q]
+        out = rp.rpchol_factor(j.X, j.rec.X.eps, j.rec.factor.r, j.rec.factor.b, uniforms=j.uniforms,
+                               gemm_dtype="f32", factor_dtype="f32")
+        deg = rp.bistoch_degrees(out["F"], out["k"], status=out["status"])
+        eig = rp.bistoch_eig(out["F"], out["k"], deg["d"], deg["q"], nev, gram_dtype="f32", u_dtype="f32",
+                             status=out["status"])
+        same &= bool(torch.equal(eig["lam"], j.lam) and torch.equal(out["pivots"], j.pivots))
+    flops = sum(N * r * (2.0 * d + 3.0 * r) for N, d, r in probs)
+    line = {
+        "metric": "batched form: 512 decompositions (64 KS datasets x 8 bandwidths), seconds",
+        "form": "batched", "value": t_graph, "unit": "s", "higher_is_better": False, "n_gpus": 1,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{len(specs)} KS delay-embedding datasets (sum N = "
+                               f"{sum(s['N'] for s in specs)}, N 5e3..2e5, d in 32/128/512, "
+                               f"r in 64..512) x {len(BANDWIDTH_MULTIPLIERS)} bandwidths, top {nev}",
+                   "n_streams": ns, "blocks": {k: v["b"] for k, v in sorted(cache.items())}},
+        "jobs": len(jobs), "jobs_per_s": len(jobs) / t_graph,
+        "one_stream_s": t_serial, "stream_pool_s": t_pool, "graph_s": t_graph,
+        "graph_capture_s": t_capture, "speedup_graph_vs_one_stream": t_serial / t_graph,
+        "est_tflops_graph": flops / t_graph / 1e12,
+        "all_status_ok": all(x == 0 for x in st) and all(x == 0 for x in st_g),
+        "spot_check_equals_single_calls": same,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -367,8 +485,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--form", default="headline", choices=["headline", "surrogate"],
-                    help="headline: the decomposition benchmark; surrogate: the learned extension")
+    ap.add_argument("--form", default="headline", choices=["headline", "surrogate", "batched"],
+                    help="headline: the decomposition benchmark; surrogate: the learned extension; "
+                         "batched: 512 small decompositions")
+    ap.add_argument("--datasets", type=int, default=BATCH["datasets"])
     ap.add_argument("--sur-epochs", type=int, default=SUR["epochs"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -383,6 +503,9 @@ def main():
     rp.load_library()
     if args.form == "surrogate":
         bench_surrogate(args, rp, torch)
+        return
+    if args.form == "batched":
+        bench_batched(args, rp, torch)
         return
     w = WORKLOADS[args.workload]
     X, eps, u = make_inputs(w)

@@ -8,6 +8,7 @@ from .philox import philox4x32_10, uniform_stream
 from .torus import torus_points
 from .ks import ks_trajectory, delay_embed, ks_points
 from .bandwidth import median_sq_distance
+from .batch import batch_specs, batch_points, BANDWIDTH_MULTIPLIERS
 
 __all__ = [
     "philox4x32_10",
@@ -17,4 +18,7 @@ __all__ = [
     "delay_embed",
     "ks_points",
     "median_sq_distance",
+    "batch_specs",
+    "batch_points",
+    "BANDWIDTH_MULTIPLIERS",
 ]

@@ -97,3 +97,16 @@ def test_delay_embedding_layout():
     assert X.shape == (8, 6)
     assert np.array_equal(X[0], np.concatenate([s[2], s[1], s[0]]))
     assert np.array_equal(X[7], np.concatenate([s[9], s[8], s[7]]))
+
+
+def test_batch_specs_ranges_and_determinism():
+    from synth import BANDWIDTH_MULTIPLIERS, batch_specs
+
+    a, b = batch_specs(), batch_specs()
+    assert a == b and len(a) == 64 and len(BANDWIDTH_MULTIPLIERS) == 8
+    assert [s["seed"] for s in a] == list(range(1, 65))
+    for s in a:
+        assert 5000 <= s["N"] <= 200000
+        assert (s["d"], s["q"]) in ((32, 1), (128, 2), (512, 8))
+        assert s["r"] in (64, 128, 256, 512)
+    assert batch_specs(seed=1) != a
