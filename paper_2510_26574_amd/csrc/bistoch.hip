@@ -356,6 +356,7 @@ struct EigWs {
   int32_t* conv;
   double* delta;
   double* sk;
+  double* skq;  // split-K partials of the r x p block product
   size_t part_cap;
   int p;
 };
@@ -396,6 +397,7 @@ static size_t carve_eig(WsCursor& c, EigWs& w, int64_t N, int r, int nev, bool f
   w.conv = c.take<int32_t>(1);
   w.delta = c.take<double>(1);
   w.sk = c.take<double>((size_t)dense::SPLITK_MAX * p * p);
+  w.skq = c.take<double>((size_t)dense::SPLITK_MAX * r * p);
   return c.used;
 }
 
@@ -407,9 +409,14 @@ static void chol_qr(hipStream_t st, const double* Y, double* Q, int r, int p, Ei
                     int32_t* status, const int32_t* skip) {
   dense::gemm64_splitk<true, true>(st, p, p, r, Y, r, Y, r, w.Gp, p, 1.0, 0.0, w.sk, skip);
   hipLaunchKernelGGL(dense::k_chol_small, dim3(1), dim3(1024), 0, st, (const double*)w.Gp, (int64_t)p,
-                     p, w.Rinv, (int64_t)p, status, skip);
-  hipLaunchKernelGGL(dense::k_trsm_rows, dim3((unsigned)((r + 63) / 64)), dim3(64), 0, st, Y,
-                     (int64_t)r, r, p, (const double*)w.Rinv, (int64_t)p, Q, (int64_t)r, skip);
+                     p, w.Rinv, (int64_t)p, status, skip, 1);
+  if (p == dense::JMAX)
+    hipLaunchKernelGGL((dense::k_trsm_rows_reg<dense::JMAX>), dim3((unsigned)((r + 63) / 64)),
+                       dim3(64), 0, st, Y, (int64_t)r, r, (const double*)w.Rinv, (int64_t)p, Q,
+                       (int64_t)r, skip);
+  else
+    hipLaunchKernelGGL(dense::k_trsm_rows, dim3((unsigned)((r + 63) / 64)), dim3(64), 0, st, Y,
+                       (int64_t)r, r, p, (const double*)w.Rinv, (int64_t)p, Q, (int64_t)r, skip);
 }
 
 template <typename TG, typename TF, typename TU>
@@ -473,18 +480,29 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
     hipLaunchKernelGGL(k_fill_identity, dim3(nblk((int64_t)r * p)), dim3(256), 0, st, w.Q, r, p);
     // 12 orthonormalised products, then Rayleigh-Ritz + residual check; up to
     // 3 more rounds of 6 products if the check fails (device flag `conv`)
+    // The first products (from the identity start) can be ill-conditioned and
+    // get two column-scaled Cholesky QR passes; once the block spans the
+    // dominant subspace, Y = M Q has nearly orthogonal columns up to their
+    // scales and one scaled pass keeps Q orthonormal to working precision
+    // (the Rayleigh-Ritz residual check below guards the result).
+    int done = 0;
     auto products = [&](int count) {
-      for (int in = 0; in < count; ++in) {
-        dense::gemm64<false, true>(st, r, p, r, w.M, r, w.Q, r, w.Y, r, 1.0, 0.0, w.conv);
-        chol_qr(st, w.Y, w.Qt, r, p, w, status, w.conv);
-        chol_qr(st, w.Qt, w.Q, r, p, w, status, w.conv);
+      for (int in = 0; in < count; ++in, ++done) {
+        dense::gemm64_splitk<false, true>(st, r, p, r, w.M, r, w.Q, r, w.Y, r, 1.0, 0.0, w.skq,
+                                          w.conv);
+        if (done < 4) {
+          chol_qr(st, w.Y, w.Qt, r, p, w, status, w.conv);
+          chol_qr(st, w.Qt, w.Q, r, p, w, status, w.conv);
+        } else {
+          chol_qr(st, w.Y, w.Q, r, p, w, status, w.conv);
+        }
       }
     };
     products(12);
     const int max_rr = 4;
     for (int it = 0; it < max_rr; ++it) {
       if (it > 0) products(6);
-      dense::gemm64<false, true>(st, r, p, r, w.M, r, w.Q, r, w.Y, r, 1.0, 0.0, w.conv);
+      dense::gemm64_splitk<false, true>(st, r, p, r, w.M, r, w.Q, r, w.Y, r, 1.0, 0.0, w.skq, w.conv);
       dense::gemm64_splitk<true, true>(st, p, p, r, w.Q, r, w.Y, r, w.H, p, 1.0, 0.0, w.sk, w.conv);
       hipLaunchKernelGGL(dense::k_jacobi, dim3(1), dim3(1024), 0, st, (const double*)w.H,
                          (int64_t)p, p, w.theta, w.Wm, (int64_t)p, 40, jtol, status,

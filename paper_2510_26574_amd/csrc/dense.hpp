@@ -339,24 +339,79 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ A, i
 }
 
 // One-workgroup Cholesky G = R^T R of a p x p SPD matrix (p <= JMAX); writes
-// R (upper, column-major, ldr; zero below the diagonal).  On breakdown the
-// status is set.
+// R (upper, column-major, ldr; zero below the diagonal).  With `equil` the
+// factorisation runs on the equilibrated S G S, s_i = 1/sqrt(G_ii), and
+// R = L^T S^{-1} is written, which is the same factor in exact arithmetic
+// but keeps the pivots near 1 (Cholesky QR with column scaling).  On
+// breakdown the status is set.
 __global__ __launch_bounds__(1024) void k_chol_small(const double* __restrict__ G, int64_t ldg,
                                                      int p, double* __restrict__ R, int64_t ldr,
-                                                     int32_t* status, const int32_t* skip) {
+                                                     int32_t* status, const int32_t* skip,
+                                                     int equil = 0) {
   if (skip && *skip) return;
   constexpr int LDS = JMAX + 1;
   __shared__ double a[JMAX * LDS];
   __shared__ double piv[JMAX];
+  __shared__ double sc[JMAX];
   const int tid = threadIdx.x;
-  for (int e = tid; e < p * p; e += 1024) {
-    const int i = e % p, c = e / p;
-    a[i + c * LDS] = G[i + c * ldg];
+  if (tid < p) {
+    const double g = G[tid + (int64_t)tid * ldg];
+    sc[tid] = (equil && g > 0.0) ? 1.0 / sqrt(g) : 1.0;
   }
-  chol_block_lds(a, p, LDS, piv, status);  // lower L, R = L^T
+  __syncthreads();
   for (int e = tid; e < p * p; e += 1024) {
     const int i = e % p, c = e / p;
-    R[i + c * ldr] = (i <= c) ? a[c + i * LDS] : 0.0;
+    a[i + c * LDS] = G[i + c * ldg] * sc[i] * sc[c];
+  }
+  chol_block_lds(a, p, LDS, piv, status);  // lower L, R = L^T S^{-1}
+  for (int e = tid; e < p * p; e += 1024) {
+    const int i = e % p, c = e / p;
+    R[i + c * ldr] = (i <= c) ? a[c + i * LDS] / sc[c] : 0.0;
+  }
+}
+
+// Q = Y R^{-1} for p == P (R upper P x P, Y r x P, column-major): each
+// thread keeps its row of Y in registers and solves q R = y by forward
+// substitution, fully unrolled, with R broadcast from LDS; four partial
+// sums per dot product shorten the dependency chain.  64 rows per workgroup.
+template <int P>
+__global__ __launch_bounds__(64) void k_trsm_rows_reg(const double* __restrict__ Y, int64_t ldy,
+                                                      int rows, const double* __restrict__ R,
+                                                      int64_t ldr, double* __restrict__ Q,
+                                                      int64_t ldq, const int32_t* skip) {
+  if (skip && *skip) return;
+  __shared__ double Rs[P * P];
+  __shared__ double rdiag[P];
+  const int t = threadIdx.x;
+  for (int e = t; e < P * P; e += 64) {
+    const int i = e % P, c = e / P;
+    Rs[i + c * P] = R[i + c * ldr];
+  }
+  __syncthreads();
+  for (int j = t; j < P; j += 64) rdiag[j] = 1.0 / Rs[j + j * P];
+  __syncthreads();
+  const int row = blockIdx.x * 64 + t;
+  const bool ok = row < rows;
+  double q[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) q[j] = ok ? Y[row + (int64_t)j * ldy] : 0.0;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    double s0 = q[j], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+    for (int l = 0; l + 3 < j; l += 4) {
+      s0 -= q[l] * Rs[l + j * P];
+      s1 -= q[l + 1] * Rs[l + 1 + j * P];
+      s2 -= q[l + 2] * Rs[l + 2 + j * P];
+      s3 -= q[l + 3] * Rs[l + 3 + j * P];
+    }
+#pragma unroll
+    for (int l = (j / 4) * 4; l < j; ++l) s0 -= q[l] * Rs[l + j * P];
+    q[j] = ((s0 + s1) + (s2 + s3)) * rdiag[j];
+  }
+  if (ok) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) Q[row + (int64_t)j * ldq] = q[j];
   }
 }
 
