@@ -46,10 +46,13 @@ __device__ inline void upper_decode(int t, int nt, int& ti, int& tj) {
 
 template <typename T>
 struct SyrkTraits;
+// BK is a multiple of 16 k (four MFMA k-steps); the row stride LDK = BK + PAD
+// is 144 bytes (mod 256) so the 16 rows of a vector fragment read fall on
+// distinct banks.
 template <>
 struct SyrkTraits<float> {
   static constexpr int BK = 32;
-  static constexpr int PAD = 4;  // rows stay 16-byte aligned; fragment reads hit distinct banks
+  static constexpr int PAD = 4;
 };
 template <>
 struct SyrkTraits<double> {
@@ -137,6 +140,7 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_partial(const TF* __restrict__ 
   constexpr int BK = SyrkTraits<T>::BK;
   constexpr int LDK = BK + SyrkTraits<T>::PAD;
   constexpr bool F32 = sizeof(T) == 4;
+  static_assert(BK % (4 * Mma<T>::KS) == 0 && (LDK * sizeof(T)) % 16 == 0, "vector fragment reads");
   __shared__ __attribute__((aligned(16))) T As[2][TILE * LDK];
   __shared__ __attribute__((aligned(16))) T Bs[2][TILE * LDK];
   const int nt = n_tiles(r);
@@ -194,17 +198,27 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_partial(const TF* __restrict__ 
     }
     const T* Ac = As[buf];
     const T* Bc = diag ? As[buf] : Bs[buf];
+    // Four MFMA k-steps per LDS read: in step t lane group g = lane / 16
+    // takes k = kq + 4 g + t on both operands (only the pairing of A and B
+    // k-slots matters), so each lane reads its four k values as one vector.
+    typedef T v4t __attribute__((ext_vector_type(4)));
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += MM::KS) {
-      typename MM::frag fa[MI], fb[NI];
-#pragma unroll
-      for (int i = 0; i < MI; ++i) fa[i] = Ac[(wm * WTM + i * 16 + (lane & 15)) * LDK + kk + (lane >> 4)];
-#pragma unroll
-      for (int j = 0; j < NI; ++j) fb[j] = Bc[(wn * WTN + j * 16 + (lane & 15)) * LDK + kk + (lane >> 4)];
+    for (int kq = 0; kq < BK; kq += 4 * MM::KS) {
+      v4t fa[MI], fb[NI];
 #pragma unroll
       for (int i = 0; i < MI; ++i)
+        fa[i] = *reinterpret_cast<const v4t*>(Ac + (wm * WTM + i * 16 + (lane & 15)) * LDK + kq +
+                                               4 * (lane >> 4));
 #pragma unroll
-        for (int j = 0; j < NI; ++j) acc[i][j] = MM::mma(fa[i], fb[j], acc[i][j]);
+      for (int j = 0; j < NI; ++j)
+        fb[j] = *reinterpret_cast<const v4t*>(Bc + (wn * WTN + j * 16 + (lane & 15)) * LDK + kq +
+                                               4 * (lane >> 4));
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < NI; ++j) acc[i][j] = MM::mma(fa[i][t], fb[j][t], acc[i][j]);
     }
     if (more) {
       la.store(As[buf ^ 1], tid);
