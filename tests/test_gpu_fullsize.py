@@ -1,0 +1,156 @@
+"""Full-size parity: the KS delay-embedding problem at N = 1,000,000, d = 512,
+r = 1024, b = 128, top 64, in the mixed precision form and launch
+configuration the benchmark times.
+
+The oracle cannot run the whole method at this size, so the test checks:
+
+  * round 0 exactly against the oracle.  The residual diagonal is all ones
+    before the first round, so the proposals follow from the uniforms alone
+    (integer CDF).  The proposal block and Algorithm 3 run on the
+    bf16-rounded points, as in the mixed form (the accept decisions are taken
+    in the same precision on both sides).  F's first columns are checked at
+    sampled rows, to the fp32 kernel-entry bar 5e-5;
+  * properties that hold at any size, on all N rows where they are cheap:
+    valid distinct pivots with rho = 0 on them and rho >= 0; F(S, :) lower
+    triangular in pivot order; F at sampled rows against the closed form
+    K(n, S) chol(K(S, S))^{-T} (1e-2, the bf16 bar); the degrees against
+    F c and F F^T (1/d~) recomputed in float64; U orthonormal; the
+    eigen-residual |P~ u - lambda u| through the factored P~ = B C B^T;
+    lambda_1 = 1 with the constant eigenvector (P~ 1 = 1), to the fp32 Gram
+    form's bars (angles 1e-4, eigenvalues 1e-6).
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+from synth import ks_points, median_sq_distance, uniform_stream
+
+pytestmark = pytest.mark.gpu
+
+N, Q, R, B, NEV = 1_000_000, 8, 1024, 128, 64
+
+
+@pytest.fixture(scope="module")
+def run():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_26574_amd as rp
+
+    cache = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"rpchol_ks_{N}_{Q}_0.npy")
+    if os.path.exists(cache):
+        X = np.load(cache)
+    else:
+        X = ks_points(N, q=Q, seed=0)
+        try:
+            np.save(cache, X)
+        except OSError:
+            pass
+    eps = median_sq_distance(X, seed=0)
+    u = uniform_stream(2 * B * (R // B), seed=0)
+    Xd = torch.from_numpy(X).cuda()
+    out = rp.rpchol_factor(Xd, eps, R, B, uniforms=torch.from_numpy(u).cuda(), gemm_dtype="bf16",
+                           factor_dtype="f32")
+    deg = rp.bistoch_degrees(out["F"], out["k"], status=out["status"])
+    eig = rp.bistoch_eig(out["F"], out["k"], deg["d"], deg["q"], NEV, gram_dtype="f32",
+                         status=out["status"])
+    st = rp.status_sync(out["status"])
+    assert st == 0, rp.STATUS_NAMES.get(st, st)
+    Xb = torch.from_numpy(X).to(torch.bfloat16)  # the rounded points the mixed form uses
+
+    def Xr(idx):
+        return Xb[torch.as_tensor(np.asarray(idx, dtype=np.int64))].double().numpy()
+
+    return {"torch": torch, "X": X, "Xr": Xr, "eps": eps, "u": u, "out": out, "deg": deg, "eig": eig,
+            "k": int(out["k"].item())}
+
+
+def _rows(n=2000, seed=3):
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(N, n, replace=False))
+
+
+def test_round0_matches_oracle(run):
+    Xr, eps, u = run["Xr"], run["eps"], run["u"]
+    rho_q = oracle.quantize_rho(np.ones(N)).tolist()
+    props = np.array([oracle.inverse_cdf_pivot(rho_q, u[j]) for j in range(B)], dtype=np.int64)
+    H = oracle.gaussian_kernel(Xr(props), Xr(props), eps)
+    T, L = oracle.accept_reject(H, u[B:2 * B], props)
+    S0 = props[np.asarray(T, dtype=np.int64)]
+    nt0 = len(S0)
+    racc = run["out"]["round_accepted"].cpu().numpy()
+    piv = run["out"]["pivots"].cpu().numpy()
+    assert racc[0] == nt0 and np.array_equal(piv[:nt0], S0)
+    rows = _rows()
+    Kn = oracle.gaussian_kernel(Xr(rows), Xr(S0), eps)
+    F0 = sla.solve_triangular(L, Kn.T, lower=True).T
+    Fg = run["out"]["F"][rows][:, :nt0].double().cpu().numpy()
+    err = np.abs(Fg - F0).max() / np.abs(F0).max()
+    print(f"round 0: {nt0} accepted, F error {err:.3g}")
+    assert err <= 5e-5
+
+
+def test_factor_properties(run):
+    torch = run["torch"]
+    out, k, eps, Xr = run["out"], run["k"], run["eps"], run["Xr"]
+    piv = out["pivots"].cpu().numpy()
+    S = piv[:k]
+    assert 0 < k <= R and np.all(piv[k:] == -1)
+    assert len(np.unique(S)) == k and S.min() >= 0 and S.max() < N
+    rho = out["rho"].cpu().numpy()
+    assert np.all(rho >= 0) and np.all(rho[S] == 0)
+    assert int(out["round_accepted"].sum().item()) == k
+    FS = out["F"][torch.from_numpy(S).cuda()][:, :k].double().cpu().numpy()
+    assert np.abs(np.triu(FS, 1)).max() <= 1e-3 * np.abs(FS).max()
+    assert not out["F"][:, k:].any().item()
+    # closed form at sampled rows: F(n, :) = K(n, S) chol(K(S, S))^{-T}
+    XS = Xr(S)
+    KSS = oracle.gaussian_kernel(XS, XS, eps)
+    Lc = np.linalg.cholesky(KSS)
+    rows = _rows(1000, seed=4)
+    Fc = sla.solve_triangular(Lc, oracle.gaussian_kernel(Xr(rows), XS, eps).T, lower=True).T
+    Fg = out["F"][rows][:, :k].double().cpu().numpy()
+    up = np.abs(np.triu(FS, 1)).max() / np.abs(FS).max()
+    err = np.abs(Fg - Fc).max() / np.abs(Fc).max()
+    rerr = np.abs(rho[rows] - np.maximum(1.0 - (Fc * Fc).sum(axis=1), 0.0)).max()
+    print(f"k = {k}: F(S,:) upper {up:.3g}, closed-form F error {err:.3g}, rho error {rerr:.3g}")
+    assert err <= 1e-2
+    # residual diagonal: rho = 1 - |F(n, :)|^2 at the sampled rows
+    assert rerr <= 1e-2
+
+
+def test_degrees_and_eigenpairs(run):
+    torch = run["torch"]
+    out, deg, eig, k = run["out"], run["deg"], run["eig"], run["k"]
+    F = out["F"][:, :k].double()
+    one = torch.ones(N, dtype=torch.float64, device="cuda")
+    c = F.t() @ one
+    d = F @ c
+    q = F @ (F.t() @ (1.0 / d))
+    assert torch.max(torch.abs(deg["d"] - d) / d).item() <= 1e-9
+    assert torch.max(torch.abs(deg["q"] - q) / q).item() <= 1e-9
+    U = eig["U"].double()
+    lam = eig["lam"]
+    G = U.t() @ U
+    orth = torch.max(torch.abs(G - torch.eye(NEV, dtype=torch.float64, device="cuda"))).item()
+    # P~ U = B C B^T U with B = D~^{-1} F, C = F^T Q~^{-1} F
+    Bm = F / deg["d"][:, None]
+    C = F.t() @ (F / deg["q"][:, None])
+    PU = Bm @ (C @ (Bm.t() @ U))
+    res = torch.max(torch.linalg.norm(PU - U * lam[None, :], dim=0)).item()
+    u1 = torch.max(torch.abs(U[:, 0] * np.sqrt(N) - 1.0)).item()
+    print(f"orthonormality {orth:.3g}, eigen-residual {res:.3g}, lambda_1 - 1 {lam[0].item() - 1:.3g}, "
+          f"constant vector {u1:.3g}")
+    # everything after F runs in the fp32 Gram form, whose bars are subspace
+    # angles 1e-4 and eigenvalues 1e-6 relative: the loss of orthonormality and
+    # the constant vector's deviation are angles; a unit vector off its
+    # eigenvector by an angle a has residual <= a * lambda_1
+    assert orth <= 1e-4
+    assert res <= 1e-4 * lam[0].item()
+    assert abs(lam[0].item() - 1.0) <= 1e-6
+    assert u1 <= 1e-4
+    assert torch.all(lam[:-1] >= lam[1:]).item()
