@@ -614,40 +614,47 @@ __global__ __launch_bounds__(256) void k_cols_schur(const T* __restrict__ Xp,
 // ------------------------------------------------------------ solve + downdate
 // G = W L^{-T} in float64 (four waves stacked along rows, each holding full
 // rows), F(:, k + j) = G(:, j), rho = max(rho - sum_j G^2, 0).
+// G = W L^{-T} tile: 128 rows x the whole block (<= 128 columns), eight
+// waves of 32 x 64, float64 MFMA.  128 rows per workgroup amortise the copy
+// of L^{-1} each workgroup stages.
+typedef TileCfg<double, 128, 128, 16, 4, 2> SolveCfg;
+
 template <typename TF>
-__global__ __launch_bounds__(256) void k_solve_downdate(const TF* __restrict__ W, int64_t ldw,
+__global__ __launch_bounds__(SolveCfg::NT) void k_solve_downdate(const TF* __restrict__ W, int64_t ldw,
                                                         int64_t N, const double* __restrict__ Linv,
                                                         const int32_t* kptr, const int32_t* nTptr,
                                                         TF* __restrict__ F, int64_t ldf,
                                                         double* __restrict__ rho) {
-  typedef TileCfg<double, 64, 128, 16, 4, 1> Cfg;
+  typedef SolveCfg Cfg;
   const int nt = *nTptr;
   if (nt == 0) return;
   const int k = *kptr;
   extern __shared__ char smem_raw[];
   double* smem = reinterpret_cast<double*>(smem_raw);
+  __shared__ double red[Cfg::WAVES_N][Cfg::BM];
   const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM;
   GOperand<TF, false> A{W, ldw, N, nt, nullptr, true};
   GOperand<double, true> B{Linv, MAXB, nt, nt, nullptr, true};
   TileAcc<Cfg> acc;
   acc.zero();
   tile_mainloop<Cfg>(acc, A, B, m0, 0, 0, nt, smem);
-  // each lane holds 4 rows x (NI columns); sum squares over its columns, then
-  // across the 16 lanes that share those rows (fixed order: deterministic)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % Cfg::WAVES_M, wn = wave / Cfg::WAVES_M;
 #pragma unroll
   for (int j = 0; j < Cfg::NI; ++j)
 #pragma unroll
     for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int row = wave * Cfg::WTM + i * 16 + Cfg::MM::row(lane, e);
-        const int col = j * 16 + (lane & 15);
+        const int row = wm * Cfg::WTM + i * 16 + Cfg::MM::row(lane, e);
+        const int col = wn * Cfg::WTN + j * 16 + (lane & 15);
         const int64_t m = m0 + row;
         const double g = acc.a[i][j][e];
         if (m < N && col < nt) F[m + (int64_t)(k + col) * ldf] = (TF)g;
       }
-  // row sums: MI x 4 rows per lane
+  // squared row norms of G: each lane sums its columns, the 16 lanes sharing
+  // a row reduce by xor shuffles, then the column halves of the workgroup
+  // are added in a fixed order (deterministic)
 #pragma unroll
   for (int i = 0; i < Cfg::MI; ++i) {
 #pragma unroll
@@ -655,21 +662,27 @@ __global__ __launch_bounds__(256) void k_solve_downdate(const TF* __restrict__ W
       double s = 0.0;
 #pragma unroll
       for (int j = 0; j < Cfg::NI; ++j) {
-        const int col = j * 16 + (lane & 15);
+        const int col = wn * Cfg::WTN + j * 16 + (lane & 15);
         const double g = col < nt ? acc.a[i][j][e] : 0.0;
         s += g * g;
       }
-      // reduce over the 16 lanes with the same (lane >> 4)
       s += __shfl_xor(s, 1, 64);
       s += __shfl_xor(s, 2, 64);
       s += __shfl_xor(s, 4, 64);
       s += __shfl_xor(s, 8, 64);
-      const int row = wave * Cfg::WTM + i * 16 + Cfg::MM::row(lane, e);
-      const int64_t m = m0 + row;
-      if ((lane & 15) == 0 && m < N) {
-        double v = rho[m] - s;
-        rho[m] = v > 0.0 ? v : 0.0;
-      }
+      const int row = wm * Cfg::WTM + i * 16 + Cfg::MM::row(lane, e);
+      if ((lane & 15) == 0) red[wn][row] = s;
+    }
+  }
+  __syncthreads();
+  for (int row = threadIdx.x; row < Cfg::BM; row += Cfg::NT) {
+    const int64_t m = m0 + row;
+    if (m < N) {
+      double s = 0.0;
+#pragma unroll
+      for (int h = 0; h < Cfg::WAVES_N; ++h) s += red[h][row];
+      const double v = rho[m] - s;
+      rho[m] = v > 0.0 ? v : 0.0;
     }
   }
 }
@@ -774,7 +787,7 @@ static int run_factor(const rpc_points* X, const rpc_factor_opts* o, TF* F, int6
 
   typedef TileCfg<T, 128, 128, (sizeof(T) == 2 ? 64 : (sizeof(T) == 4 ? 32 : 16)), 2, 2> CfgK;
   typedef TileCfg<TF, 128, 128, (sizeof(TF) == 4 ? 32 : 16), 2, 2> CfgS;
-  typedef TileCfg<double, 64, 128, 16, 4, 1> CfgD;
+  typedef SolveCfg CfgD;
   const size_t smK = TileSmem<CfgK, true, true>::bytes;
   const size_t smS = TileSmem<CfgS, false, true>::bytes;
   const size_t smD = TileSmem<CfgD, false, true>::bytes;
@@ -848,7 +861,8 @@ static int run_factor(const rpc_points* X, const rpc_factor_opts* o, TF* F, int6
       RPC_LAUNCH_CHECK();
     }
     prof::begin(prof::SOLVE, st);
-    hipLaunchKernelGGL((k_solve_downdate<TF>), dim3((unsigned)((N + 63) / 64)), dim3(256), smD, st,
+    hipLaunchKernelGGL((k_solve_downdate<TF>), dim3((unsigned)((N + CfgD::BM - 1) / CfgD::BM)),
+                       dim3(CfgD::NT), smD, st,
                        (const TF*)w.W, w.ldw, N, w.Linv, k_out, w.nT, F, ldf, rho);
     RPC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_round_end, dim3(1), dim3(MAXB), 0, st, w.Si, k_out, w.nT, rho,

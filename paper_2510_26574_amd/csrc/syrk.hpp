@@ -47,11 +47,11 @@ __device__ inline void upper_decode(int t, int nt, int& ti, int& tj) {
 template <typename T>
 struct SyrkTraits;
 // BK is a multiple of 16 k (four MFMA k-steps); the row stride LDK = BK + PAD
-// is 144 bytes (mod 256) so the 16 rows of a vector fragment read fall on
-// distinct banks.
+// (272 bytes for float32, 144 for float64) puts the 16 rows of a vector
+// fragment read on distinct banks.
 template <>
 struct SyrkTraits<float> {
-  static constexpr int BK = 32;
+  static constexpr int BK = 64;
   static constexpr int PAD = 4;
 };
 template <>

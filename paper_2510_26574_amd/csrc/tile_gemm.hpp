@@ -84,7 +84,9 @@ template <typename T, int ROWS, int BK, int NT, typename TG, bool KC>
 struct TileStage {
   static constexpr bool LKC = LdsKC<T, KC>::value;
   typedef SliceLayout<T, ROWS, BK, LKC> L;
-  static constexpr int V = 16 / sizeof(TG);
+  // elements per vector: 16 bytes of the wider of the global and LDS types,
+  // so each lane's LDS store is one contiguous 16-byte (or narrower) write
+  static constexpr int V = 16 / (sizeof(TG) > sizeof(T) ? sizeof(TG) : sizeof(T));
   static constexpr int NV = KC ? ROWS * (BK / V) : BK * (ROWS / V);
   static constexpr int PER = (NV + NT - 1) / NT;
   static_assert(KC ? (BK % V == 0) : (ROWS % V == 0), "tile shape vs vector width");
@@ -146,15 +148,15 @@ struct TileStage {
         continue;
       }
       T* dst = s + L::at(row, kk);  // the V elements run along the contiguous index
+      st v;
       if (op.kscale == nullptr && sizeof(T) == sizeof(TG)) {
-        st v;
 #pragma unroll
         for (int j = 0; j < V; ++j) v[j] = (T)buf[p][j];
-        *reinterpret_cast<st*>(dst) = v;
       } else {
 #pragma unroll
-        for (int j = 0; j < V; ++j) dst[j] = scale_cvt<T>(buf[p][j], op.kscale, k0 + (KC ? kk + j : kk));
+        for (int j = 0; j < V; ++j) v[j] = scale_cvt<T>(buf[p][j], op.kscale, k0 + (KC ? kk + j : kk));
       }
+      *reinterpret_cast<st*>(dst) = v;
     }
   }
 };
