@@ -184,6 +184,36 @@ def pmc_traffic(kernel):
     return None
 
 
+def kernel_columns(rp, torch, Xd, eps, ud, w, d, steps):
+    """Kernel-column evaluation K(X, X_S) timed on its own: the factorisation
+    with the columns and the Schur update in separate kernels (the fused
+    kernel shares one accumulator between both products, so its time is not
+    the column evaluation's).  Flops 2 N d n_T per round (the exp epilogue
+    aside); bytes: the bf16 points read once per round plus the fp32 columns
+    written.  The ceiling is min(MFMA peak, AI x HBM bandwidth)."""
+    for _ in range(2):
+        rp.profile_enable(True)
+        rp.profile_reset()
+        out = rp.rpchol_factor(Xd, eps, w["r"], w["b"], uniforms=ud, gemm_dtype="bf16",
+                               factor_dtype="f32", unfused=True)
+        torch.cuda.synchronize()
+        prof = rp.profile_read()
+        rp.profile_enable(False)
+    nT = out["round_accepted"].cpu().numpy().astype(np.float64)
+    N = w["N"]
+    dp = -(-d // 32) * 32
+    ms, n = prof["kernel_cols"]
+    flops = float(np.sum(2.0 * N * d * nT))
+    byts = float(np.sum(N * dp * 2.0 + N * nT * 4.0))
+    sec = ms / 1e3
+    ai = flops / byts
+    ceil_tf = min(PEAK["bf16"], ai * PEAK["hbm"] / 1e3)
+    tf = flops / sec / 1e12
+    return {"ms_total": ms, "launches": n, "tflops": tf, "gbs": byts / sec / 1e9,
+            "frac_mfma_peak": tf / PEAK["bf16"], "ai_flop_per_byte": ai, "ceiling_tflops": ceil_tf,
+            "frac_ceiling": tf / ceil_tf, "frac_hbm_peak": byts / sec / 1e9 / PEAK["hbm"]}
+
+
 def cpu_baseline(X, eps, w, n_sample):
     """The float64 oracle timed on a leading-row sample, scaled linearly in N."""
     import oracle
@@ -530,6 +560,8 @@ def main():
         t_plain, res_p, prof_p = timed(rp, torch, Xd, eps, ud, w, plain, args.steps, args.warmup, profile=True)
         log(f"[bench] plain {t_plain * 1e3:.2f} ms/step")
         roof_p, per_kernel_p = roofline(w, X.shape[1], res_p, prof_p, args.steps, plain)
+    log("[bench] kernel columns alone (unfused path)")
+    kcols = kernel_columns(rp, torch, Xd, eps, ud, w, X.shape[1], args.steps)
     log("[bench] parity check")
     par = parity(rp, torch, Xd, eps, w, res_m)
     cpu = None
@@ -549,6 +581,7 @@ def main():
         "plain_fp64_s": t_plain,
         "speedup_vs_plain_fp64": (t_plain / t_mixed) if t_plain else None,
         "roofline": roof,
+        "kernel_columns_bf16": kcols,
         "cpu_baseline": cpu,
         "kernels_mixed": per_kernel,
         "kernels_plain_fp64": per_kernel_p if t_plain else None,

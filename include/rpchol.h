@@ -101,14 +101,21 @@ typedef struct {
  *  replay       device int64 ordered pivots (REPLAY only), n_replay <= r.
  *  round_accepted  optional device int32 array of ceil(r / b) entries (or
  *               ceil(n_replay / b) in replay mode) receiving the number of
- *               pivots accepted in each round; may be NULL. */
+ *               pivots accepted in each round; may be NULL.
+ *  flags        RPC_FACTOR_UNFUSED: evaluate the kernel columns and the Schur
+ *               update W -= F F_S^T in two kernels (W written, then read
+ *               back) instead of one fused kernel where both products share
+ *               an accumulator; results agree to rounding.  Meant for timing
+ *               the kernel-column evaluation on its own.  Other bits:
+ *               RPC_EINVAL. */
+#define RPC_FACTOR_UNFUSED 1
 typedef struct {
   int32_t r;
   int32_t b;
   int32_t mode;         /* rpc_mode */
   int32_t gemm_dtype;   /* rpc_dtype */
   int32_t factor_dtype; /* RPC_F64 or RPC_F32 */
-  int32_t pad_;
+  int32_t flags;        /* RPC_FACTOR_* bits, 0 by default */
   double tau;
   const double* uniforms;
   int64_t n_uniforms;

@@ -44,7 +44,7 @@ class rpc_points(ctypes.Structure):
 class rpc_factor_opts(ctypes.Structure):
     _fields_ = [("r", ctypes.c_int32), ("b", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("gemm_dtype", ctypes.c_int32), ("factor_dtype", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("flags", ctypes.c_int32), ("tau", ctypes.c_double),
                 ("uniforms", ctypes.c_void_p), ("n_uniforms", ctypes.c_int64),
                 ("replay", ctypes.c_void_p), ("n_replay", ctypes.c_int64),
                 ("round_accepted", ctypes.c_void_p)]
@@ -166,8 +166,11 @@ def status_sync(status, stream=None):
     return load_library().rpc_status_sync(_ptr(status), _stream(torch, stream))
 
 
+RPC_FACTOR_UNFUSED = 1
+
+
 def rpchol_factor(X, eps, r, b, mode="sampled", uniforms=None, replay=None, gemm_dtype="f64",
-                  factor_dtype="f64", tau=0.0, status=None, stream=None):
+                  factor_dtype="f64", tau=0.0, unfused=False, status=None, stream=None):
     """Algorithm 2 on the Gaussian kernel of the rows of X (N x d float32, CUDA).
 
     Returns dict: F (N x r view, column-major storage), pivots (r int64),
@@ -187,8 +190,8 @@ def rpchol_factor(X, eps, r, b, mode="sampled", uniforms=None, replay=None, gemm
     pts = _points(X, eps)
     nrounds = -(-(r if mode != "replay" else replay.numel()) // b)
     racc = torch.zeros(nrounds, dtype=torch.int32, device=dev)
-    opts = rpc_factor_opts(int(r), int(b), MODES[mode], DTYPES[gemm_dtype], DTYPES[factor_dtype], 0,
-                           float(tau), 0, 0, 0, 0, racc.data_ptr())
+    opts = rpc_factor_opts(int(r), int(b), MODES[mode], DTYPES[gemm_dtype], DTYPES[factor_dtype],
+                           RPC_FACTOR_UNFUSED if unfused else 0, float(tau), 0, 0, 0, 0, racc.data_ptr())
     if mode == "sampled":
         assert uniforms is not None and uniforms.dtype == torch.float64 and uniforms.is_cuda
         opts.uniforms = uniforms.data_ptr()

@@ -28,6 +28,7 @@ namespace {
 
 constexpr int CHUNK = 4096;  // rho entries per partial sum (pivot draw)
 constexpr int MAXB = 128;    // largest supported block size
+constexpr int kStages = 4;   // LDS stages of the direct-staged products (three in flight)
 constexpr double QSCALE = 1099511627776.0;  // 2^40
 
 __device__ inline unsigned long long quant_rho(double r) {
@@ -507,7 +508,7 @@ __global__ __launch_bounds__(Cfg::NT) void k_kernel_cols(const T* __restrict__ X
   GOperand<T, true> B{XSa, dp, nt, dp, nullptr, true};
   TileAcc<Cfg> acc;
   acc.zero();
-  tile_mainloop<Cfg>(acc, A, B, m0, n0, 0, dp, smem);
+  tile_mainloop_direct<Cfg, kStages>(acc, A, B, m0, n0, 0, dp, N, MAXB, smem);
   typedef typename Cfg::MM::acc_t AT;
   const AT ie = (AT)(1.0 / eps);
   for_each_acc<Cfg>(acc, [&](int row, int col, AT v) {
@@ -538,7 +539,7 @@ __global__ __launch_bounds__(Cfg::NT) void k_schur(const TF* __restrict__ F, int
   GOperand<TF, true> B{FSa, r, nt, k, nullptr, (r % (16 / (int)sizeof(TF))) == 0};
   TileAcc<Cfg> acc;
   acc.zero();
-  tile_mainloop<Cfg>(acc, A, B, m0, n0, 0, k, smem);
+  tile_mainloop_direct<Cfg, kStages>(acc, A, B, m0, n0, 0, k, N, MAXB, smem);
   for_each_acc<Cfg>(acc, [&](int row, int col, typename Cfg::MM::acc_t v) {
     const int64_t m = m0 + row, n = n0 + col;
     if (m < N && n < nt) W[m + n * ldw] -= (TF)v;
@@ -553,7 +554,7 @@ __global__ __launch_bounds__(Cfg::NT) void k_schur(const TF* __restrict__ F, int
 // into the same accumulators: W is written once instead of written, read
 // and written again.
 template <typename T, typename TN, typename TF, class CfgK, class CfgS>
-__global__ __launch_bounds__(256) void k_cols_schur(const T* __restrict__ Xp,
+__global__ __launch_bounds__(CfgK::NT) void k_cols_schur(const T* __restrict__ Xp,
                                                     const TN* __restrict__ xn, int64_t N,
                                                     int64_t dp, const T* __restrict__ XSa,
                                                     const TN* __restrict__ nsa,
@@ -577,7 +578,8 @@ __global__ __launch_bounds__(256) void k_cols_schur(const T* __restrict__ Xp,
   {
     GOperand<T, true> A{Xp, dp, N, dp, nullptr, true};
     GOperand<T, true> B{XSa, dp, nt, dp, nullptr, true};
-    tile_mainloop<CfgK>(acc, A, B, m0, 0, 0, dp, reinterpret_cast<typename CfgK::T*>(smem_raw));
+    tile_mainloop_direct<CfgK, kStages>(acc, A, B, m0, 0, 0, dp, N, MAXB,
+                                        reinterpret_cast<typename CfgK::T*>(smem_raw));
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave % CfgK::WAVES_M, wn = wave / CfgK::WAVES_M;
@@ -603,7 +605,8 @@ __global__ __launch_bounds__(256) void k_cols_schur(const T* __restrict__ Xp,
   if (k > 0) {
     GOperand<TF, false> A{F, ldf, N, k, nullptr, true};
     GOperand<TF, true> B{FSa, r, nt, k, nullptr, (r % (16 / (int)sizeof(TF))) == 0};
-    tile_mainloop<CfgS>(acs, A, B, m0, 0, 0, k, reinterpret_cast<typename CfgS::T*>(smem_raw));
+    tile_mainloop_direct<CfgS, kStages>(acs, A, B, m0, 0, 0, k, N, MAXB,
+                                        reinterpret_cast<typename CfgS::T*>(smem_raw));
   }
   for_each_acc<CfgS>(acs, [&](int row, int col, typename CfgS::MM::acc_t v) {
     const int64_t m = m0 + row;
@@ -785,11 +788,13 @@ static int run_factor(const rpc_points* X, const rpc_factor_opts* o, TF* F, int6
   hipLaunchKernelGGL(k_init_small, dim3(1), dim3(256), 0, st, pivots, r, k_out, w.nT, w.stop);
   RPC_LAUNCH_CHECK();
 
-  typedef TileCfg<T, 128, 128, (sizeof(T) == 2 ? 64 : (sizeof(T) == 4 ? 32 : 16)), 2, 2> CfgK;
-  typedef TileCfg<TF, 128, 128, (sizeof(TF) == 4 ? 32 : 16), 2, 2> CfgS;
+  // 128 x 128 tiles, eight waves of 64 x 32 (two per SIMD at one workgroup
+  // per CU, which the four-stage direct pipeline's LDS allows)
+  typedef TileCfg<T, 128, 128, (sizeof(T) == 2 ? 64 : (sizeof(T) == 4 ? 32 : 16)), 2, 4> CfgK;
+  typedef TileCfg<TF, 128, 128, (sizeof(TF) == 4 ? 32 : 16), 2, 4> CfgS;
   typedef SolveCfg CfgD;
-  const size_t smK = TileSmem<CfgK, true, true>::bytes;
-  const size_t smS = TileSmem<CfgS, false, true>::bytes;
+  const size_t smK = DirectSmem<CfgK, kStages, true, true>::bytes;
+  const size_t smS = DirectSmem<CfgS, kStages, false, true>::bytes;
   const size_t smD = TileSmem<CfgD, false, true>::bytes;
   const size_t smKS = smK > smS ? smK : smS;
   const unsigned gm = (unsigned)((N + 127) / 128);
@@ -839,15 +844,20 @@ static int run_factor(const rpc_points* X, const rpc_factor_opts* o, TF* F, int6
     hipLaunchKernelGGL(k_tri_inv, dim3(MAXB), dim3(64), 0, st, (const double*)w.Lc, w.nT, w.Linv);
     prof::end(prof::ACCEPT, st);
     RPC_LAUNCH_CHECK();
+    bool fused = false;
     if constexpr (kFusedColsSchur<T, TF>) {
-      prof::begin(prof::KERNEL_COLS, st);
-      hipLaunchKernelGGL((k_cols_schur<T, TN, TF, CfgK, CfgS>), dim3(gm), dim3(256), smKS, st,
-                         (const T*)w.Xp, (const TN*)w.xn, N, dp, (const T*)w.XSa, (const TN*)w.nsa,
-                         w.nT, X->eps, (const TF*)F, ldf, (const TF*)w.FSa, r, k_out, (TF*)w.W,
-                         w.ldw);
-      prof::end(prof::KERNEL_COLS, st);
-      RPC_LAUNCH_CHECK();
-    } else {
+      if (!(o->flags & RPC_FACTOR_UNFUSED)) {
+        fused = true;
+        prof::begin(prof::KERNEL_COLS, st);
+        hipLaunchKernelGGL((k_cols_schur<T, TN, TF, CfgK, CfgS>), dim3(gm), dim3(CfgK::NT), smKS, st,
+                           (const T*)w.Xp, (const TN*)w.xn, N, dp, (const T*)w.XSa,
+                           (const TN*)w.nsa, w.nT, X->eps, (const TF*)F, ldf, (const TF*)w.FSa, r,
+                           k_out, (TF*)w.W, w.ldw);
+        prof::end(prof::KERNEL_COLS, st);
+        RPC_LAUNCH_CHECK();
+      }
+    }
+    if (!fused) {
       prof::begin(prof::KERNEL_COLS, st);
       hipLaunchKernelGGL((k_kernel_cols<T, TN, TF, CfgK>), dim3(gm, 1), dim3(CfgK::NT), smK, st,
                          (const T*)w.Xp, (const TN*)w.xn, N, dp, (const T*)w.XSa, (const TN*)w.nsa,
@@ -894,6 +904,7 @@ static int check_factor_args(const rpc_points* X, const rpc_factor_opts* o) {
     if (!o->replay || o->n_replay < 1 || o->n_replay > o->r) return RPC_EINVAL;
   }
   if (!(o->tau >= 0.0)) return RPC_EINVAL;
+  if (o->flags & ~RPC_FACTOR_UNFUSED) return RPC_EINVAL;
   if (X->N > (int64_t)1 << 23) return RPC_EINVAL;  // keeps sum(rho_q) < 2^63
   return RPC_OK;
 }

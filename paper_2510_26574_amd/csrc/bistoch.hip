@@ -33,19 +33,49 @@ __global__ __launch_bounds__(1024) void k_coldot_partial(const TF* __restrict__ 
                                                          int64_t N, int r, const int32_t* kptr,
                                                          const double* __restrict__ wgt,
                                                          double* __restrict__ part) {
+  // one wave per (column, row chunk); 16-byte vector loads, four in flight
+  // per lane, so a wave keeps 4 KB of its column outstanding
+  constexpr int V = 16 / (int)sizeof(TF);
+  typedef TF vt __attribute__((ext_vector_type(V)));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = blockIdx.y * 16 + wave;
   if (col >= r) return;
   const int k = *kptr;
   const int64_t r0 = (int64_t)blockIdx.x * COLCHUNK;
-  double s = 0.0;
+  const int64_t r1 = r0 + COLCHUNK < N ? r0 + COLCHUNK : N;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   if (col < k) {
     const TF* f = F + (int64_t)col * ldf;
-    for (int64_t i = r0 + lane; i < r0 + COLCHUNK && i < N; i += 64) {
-      const double v = to_d(f[i]);
-      s += wgt ? v * wgt[i] : v;
+    const bool vec = (ldf % V) == 0;
+    int64_t i = r0;
+    if (vec) {
+      // full groups of 4 x 64 vectors
+      const int64_t step = 4 * 64 * V;
+      for (; i + step <= r1; i += step) {
+        vt a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = *reinterpret_cast<const vt*>(f + i + (u * 64 + lane) * V);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          double t = 0.0;
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            const int64_t n = i + (u * 64 + lane) * V + e;
+            t += wgt ? to_d(a[u][e]) * wgt[n] : to_d(a[u][e]);
+          }
+          if (u == 0) s0 += t;
+          if (u == 1) s1 += t;
+          if (u == 2) s2 += t;
+          if (u == 3) s3 += t;
+        }
+      }
+    }
+    for (int64_t n = i + lane; n < r1; n += 64) {
+      const double v = to_d(f[n]);
+      s0 += wgt ? v * wgt[n] : v;
     }
   }
+  double s = (s0 + s1) + (s2 + s3);
   s = wave_sum(s);
   if (lane == 0) part[(int64_t)blockIdx.x * r + col] = s;
 }

@@ -261,3 +261,170 @@ __device__ inline void for_each_acc(TileAcc<Cfg>& acc, Fn&& fn) {
         fn(row, col, acc.a[i][j][e]);
       }
 }
+
+// ------------------------------------------------- direct global->LDS staging
+// On gfx950 global_load_lds_dwordx4 copies 16 bytes per lane from any global
+// address straight into LDS: lane l of one wave instruction writes bytes
+// [16 l, 16 l + 16) after the instruction's wave-uniform LDS base.  A padded
+// slice (SliceLayout) is therefore filled chunk by chunk, line by line; the
+// pad chunk at the end of each line is filled from the line's first chunk.
+// No registers hold data in flight, so several stages can be outstanding at
+// once (the register-staged main loop above has one).
+#define RPC_GPTR(p) ((const void __attribute__((address_space(1)))*)(p))
+#define RPC_LPTR(p) ((void __attribute__((address_space(3)))*)(p))
+
+// s_waitcnt vmcnt(N) only (expcnt and lgkmcnt left at their no-wait maxima).
+template <int N>
+__device__ inline void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+__device__ inline void wait_vmcnt_dyn(int n) {
+  switch (n) {
+#define RPC_VMCASE(i) \
+  case i:             \
+    wait_vmcnt<i>();  \
+    break;
+    RPC_VMCASE(1) RPC_VMCASE(2) RPC_VMCASE(3) RPC_VMCASE(4) RPC_VMCASE(5) RPC_VMCASE(6)
+    RPC_VMCASE(7) RPC_VMCASE(8) RPC_VMCASE(9) RPC_VMCASE(10) RPC_VMCASE(11) RPC_VMCASE(12)
+    RPC_VMCASE(13) RPC_VMCASE(14) RPC_VMCASE(15) RPC_VMCASE(16) RPC_VMCASE(17) RPC_VMCASE(18)
+    RPC_VMCASE(19) RPC_VMCASE(20) RPC_VMCASE(21) RPC_VMCASE(22) RPC_VMCASE(23) RPC_VMCASE(24)
+    RPC_VMCASE(25) RPC_VMCASE(26) RPC_VMCASE(27) RPC_VMCASE(28) RPC_VMCASE(29) RPC_VMCASE(30)
+    RPC_VMCASE(31) RPC_VMCASE(32)
+#undef RPC_VMCASE
+    default:
+      wait_vmcnt<0>();  // anything else: wait for everything (always safe)
+  }
+}
+
+// Barrier between waves of the workgroup without the memory fence of
+// __syncthreads (which would wait for every outstanding global load); the
+// empty asm statements keep the compiler from moving memory accesses across.
+__device__ inline void lds_barrier() {
+  // lgkmcnt(0) only (vmcnt 63, expcnt 7): this wave's LDS reads are done
+  __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4));
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+template <typename T, int ROWS, int BK, bool KC, int NW>
+struct DirectSlice {
+  typedef SliceLayout<T, ROWS, BK, KC> L;
+  static constexpr int E = 16 / (int)sizeof(T);          // elements per chunk
+  static constexpr int PITCH = KC ? L::LDK : L::LDR;      // elements per LDS line
+  static constexpr int LINES = KC ? ROWS : BK;
+  static constexpr int CPL = PITCH / E;                   // chunks per line, pad included
+  static constexpr int DCPL = (KC ? BK : ROWS) / E;       // data chunks per line
+  static constexpr int WINST = LINES * CPL / 64;          // wave instructions per slice
+  static_assert(PITCH % E == 0 && (LINES * CPL) % 64 == 0 && DCPL < CPL, "direct slice shape");
+  __device__ static inline int count(int wave) { return wave < WINST ? (WINST - wave + NW - 1) / NW : 0; }
+  // rows r0 .. r0 + ROWS - 1 and k0 .. k0 + BK - 1 must be readable
+  __device__ static inline void issue(T* slice, const T* p, int64_t ld, int64_t r0, int64_t k0,
+                                      int wave, int lane) {
+    for (int q = wave; q < WINST; q += NW) {
+      const int c = q * 64 + lane;
+      const int line = c / CPL;
+      int j = c % CPL;
+      if (j >= DCPL) j = 0;
+      const T* g = KC ? p + (r0 + line) * ld + k0 + (int64_t)j * E
+                      : p + (r0 + (int64_t)j * E) + (k0 + line) * ld;
+      __builtin_amdgcn_global_load_lds(RPC_GPTR(g), RPC_LPTR(slice + q * 64 * E), 16, 0, 0);
+    }
+  }
+};
+
+// LDS bytes of the NS-stage direct pipeline.
+template <class Cfg, int NS, bool KCA, bool KCB>
+struct DirectSmem {
+  static constexpr size_t bytes = (size_t)NS * TileSmem<Cfg, KCA, KCB>::STAGE * sizeof(typename Cfg::T);
+};
+
+// acc += A(m0.., kb..ke) * B(n0.., kb..ke)^T like tile_mainloop, with NS-stage
+// direct staging (NS - 1 stages in flight).  Operands are read in their LDS
+// type (no conversion or scaling).  a_avail / b_avail: rows of A / B that may
+// be read (>= the valid rows; rows past the valid count feed only outputs
+// that the caller discards).  Tiles that would read past them, and a final
+// partial k-stage, go through the register-staged path with zero fill.
+// smem holds DirectSmem<Cfg, NS, KCA, KCB>::bytes.
+template <class Cfg, int NS, bool KCA, bool KCB>
+__device__ inline void tile_mainloop_direct(TileAcc<Cfg>& acc,
+                                            const GOperand<typename Cfg::T, KCA>& A,
+                                            const GOperand<typename Cfg::T, KCB>& B, int64_t m0,
+                                            int64_t n0, int64_t kb, int64_t ke, int64_t a_avail,
+                                            int64_t b_avail, typename Cfg::T* smem) {
+  typedef typename Cfg::T T;
+  typedef typename Cfg::MM MM;
+  typedef TileSmem<Cfg, KCA, KCB> SM;
+  constexpr int NW = Cfg::NT / 64;
+  typedef DirectSlice<T, Cfg::BM, Cfg::BK, KCA, NW> DA;
+  typedef DirectSlice<T, Cfg::BN, Cfg::BK, KCB, NW> DB;
+  static_assert(NS >= 2, "pipeline depth");
+  static_assert(LdsKC<T, KCA>::value == KCA && LdsKC<T, KCB>::value == KCB,
+                "direct staging keeps the global orientation in LDS");
+  if (kb >= ke) return;
+  const int64_t kend = ke < A.K ? (ke < B.K ? ke : B.K) : (A.K < B.K ? A.K : B.K);
+  const bool full_tile = m0 + Cfg::BM <= a_avail && n0 + Cfg::BN <= b_avail && A.vec && B.vec;
+  const int nfull = full_tile && kend > kb ? (int)((kend - kb) / Cfg::BK) : 0;
+  if (nfull == 0) {
+    tile_mainloop<Cfg>(acc, A, B, m0, n0, kb, ke, smem);
+    return;
+  }
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave % Cfg::WAVES_M, wn = wave / Cfg::WAVES_M;
+  const int per = DA::count(wave) + DB::count(wave);
+  auto issue = [&](int s) {
+    T* base = smem + (s % NS) * SM::STAGE;
+    const int64_t k0 = kb + (int64_t)s * Cfg::BK;
+    DA::issue(base, A.p, A.ld, m0, k0, wave, lane);
+    DB::issue(base + SM::LA::ELEMS, B.p, B.ld, n0, k0, wave, lane);
+  };
+  auto compute = [&](const T* As) {
+    const T* Bs = As + SM::LA::ELEMS;
+#pragma unroll
+    for (int kk = 0; kk < Cfg::BK; kk += MM::KS) {
+      typename MM::frag fa[Cfg::MI], fb[Cfg::NI];
+#pragma unroll
+      for (int i = 0; i < Cfg::MI; ++i)
+        fa[i] = load_frag<Cfg, Cfg::BM, KCA>(As, wm * Cfg::WTM + i * 16 + (lane & 15), kk, lane);
+#pragma unroll
+      for (int j = 0; j < Cfg::NI; ++j)
+        fb[j] = load_frag<Cfg, Cfg::BN, KCB>(Bs, wn * Cfg::WTN + j * 16 + (lane & 15), kk, lane);
+#pragma unroll
+      for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::NI; ++j) acc.a[i][j] = MM::mma(fa[i], fb[j], acc.a[i][j]);
+    }
+  };
+  // the caller's LDS may still be read by other waves (a previous product)
+  lds_barrier();
+  for (int s = 0; s < NS - 1 && s < nfull; ++s) issue(s);
+  for (int s = 0; s < nfull; ++s) {
+    const int ahead = (nfull - 1 - s) < (NS - 2) ? (nfull - 1 - s) : (NS - 2);
+    wait_vmcnt_dyn(ahead * per);  // this wave's chunks of stage s have landed
+    lds_barrier();                // ... and every other wave's; stage s - 1 is consumed
+    if (s + NS - 1 < nfull) issue(s + NS - 1);
+    compute(smem + (s % NS) * SM::STAGE);
+  }
+  const int64_t kt = kb + (int64_t)nfull * Cfg::BK;
+  if (kt < ke) {
+    // partial last stage: register-staged with zero fill, into a free buffer
+    TileStage<T, Cfg::BM, Cfg::BK, Cfg::NT, T, KCA> sa;
+    TileStage<T, Cfg::BN, Cfg::BK, Cfg::NT, T, KCB> sb;
+    GOperand<T, KCA> a = A;
+    GOperand<T, KCB> b = B;
+    a.K = ke < A.K ? ke : A.K;
+    b.K = ke < B.K ? ke : B.K;
+    sa.load(a, m0, kt, tid);
+    sb.load(b, n0, kt, tid);
+    T* buf = smem + (nfull % NS) * SM::STAGE;
+    lds_barrier();  // every wave is done with the buffer being overwritten
+    sa.store(buf, a, kt, tid);
+    sb.store(buf + SM::LA::ELEMS, b, kt, tid);
+    __syncthreads();
+    compute(buf);
+  }
+  lds_barrier();  // the caller may reuse smem
+}

@@ -56,6 +56,7 @@ def test_host_side_validation(lib):
         dict(n_uniforms=10),   # too few uniforms
         dict(gemm_dtype=7),
         dict(factor_dtype=2),  # bf16 storage of F is not offered
+        dict(flags=2),         # unknown option bit
     ]
     for kw in bad:
         o = rp.rpc_factor_opts(8, 2, rp.MODES["sampled"], 0, 0, 0, 0.0, 0x2000, 64, 0, 0, 0)
@@ -69,3 +70,22 @@ def test_host_side_validation(lib):
     eo = rp.rpc_eig_opts(16, 0, 0, 0, 0.0)
     assert lib.bistoch_eig_workspace_size(1000, 64, ctypes.byref(eo), ctypes.byref(nb)) == 0
     assert lib.nystrom_extend_workspace_size(10, 3, 64, 65, ctypes.byref(nb)) == rp.RPC_EINVAL
+    o = rp.rpc_factor_opts(8, 2, rp.MODES["sampled"], 0, 0, rp.RPC_FACTOR_UNFUSED, 0.0, 0x2000, 64, 0, 0, 0)
+    assert lib.rpchol_factor_workspace_size(ctypes.byref(pts), ctypes.byref(o), ctypes.byref(nb)) == 0
+
+
+def test_surrogate_and_batched_host_checks(lib):
+    import paper_2510_26574_amd as rp
+
+    lay = rp.surrogate_layout(512, 512, 64)
+    assert lay["n3"] == 80 and lay["total"] % 64 == 0
+    assert all(lay[k] % 64 == 0 for k in ("W1", "b1", "W2", "b2", "W3", "b3"))
+    assert lay["b3"] + lay["n3"] <= lay["total"]
+    assert rp.surrogate_init_uniforms(512, 512, 64) == 512 * 512 * 2 + 512 * 2 + 64 * 512 + 64 + 512 + 1
+    sh = rp.sur_shape(512, 512, 64)
+    nb = ctypes.c_size_t(0)
+    assert lib.surrogate_train_workspace_size(ctypes.byref(sh), 4096, 0, ctypes.byref(nb)) == 0
+    assert lib.surrogate_train_workspace_size(ctypes.byref(sh), 70000, 0, ctypes.byref(nb)) == rp.RPC_EINVAL
+    assert lib.surrogate_train_workspace_size(ctypes.byref(sh), 4096, 65, ctypes.byref(nb)) == rp.RPC_EINVAL
+    assert lib.surrogate_extend_workspace_size(ctypes.byref(sh), 1000, 512, 1024, 32, ctypes.byref(nb)) == rp.RPC_EINVAL
+    assert lib.rpc_batched_workspace_size(None, 0, 4, ctypes.byref(nb)) == rp.RPC_EINVAL

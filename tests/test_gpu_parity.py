@@ -270,3 +270,28 @@ def test_repeat_runs_bitwise_identical(gpu):
     _, k1, F1, p1, r1 = _run_factor(gpu, X, eps, 64, 16, "sampled", u=u)
     _, k2, F2, p2, r2 = _run_factor(gpu, X, eps, 64, 16, "sampled", u=u)
     assert k1 == k2 and np.array_equal(p1, p2) and np.array_equal(F1, F2) and np.array_equal(r1, r2)
+
+
+def test_unfused_columns_and_schur_agree(gpu):
+    """The two-kernel path (kernel columns, then the Schur update) and the fused
+    kernel give the same factor to float32 rounding (the fp32 bar, 5e-5)."""
+    torch, rp = gpu
+    from synth import ks_points
+
+    X = ks_points(6000, q=8, seed=21)
+    eps = median_sq_distance(X, seed=21)
+    u = uniform_stream(2 * 128, seed=21)
+    Xd = torch.from_numpy(X).cuda()
+    ud = torch.from_numpy(u).cuda()
+    fused = rp.rpchol_factor(Xd, eps, 128, 32, uniforms=ud, gemm_dtype="bf16", factor_dtype="f32")
+    assert rp.status_sync(fused["status"]) == 0
+    k = int(fused["k"].item())
+    rep = fused["pivots"][:k].clone()
+    un = rp.rpchol_factor(Xd, eps, 128, 32, mode="replay", replay=rep, gemm_dtype="bf16",
+                          factor_dtype="f32", unfused=True)
+    fu = rp.rpchol_factor(Xd, eps, 128, 32, mode="replay", replay=rep, gemm_dtype="bf16",
+                          factor_dtype="f32")
+    assert rp.status_sync(un["status"]) == 0 and rp.status_sync(fu["status"]) == 0
+    a = un["F"][:, :k].double().cpu().numpy()
+    b = fu["F"][:, :k].double().cpu().numpy()
+    assert np.abs(a - b).max() <= 5e-5 * np.abs(b).max()
