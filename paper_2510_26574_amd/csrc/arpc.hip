@@ -508,16 +508,16 @@ __global__ __launch_bounds__(Cfg::NT) void k_kernel_cols(const T* __restrict__ X
   GOperand<T, true> B{XSa, dp, nt, dp, nullptr, true};
   TileAcc<Cfg> acc;
   acc.zero();
-  tile_mainloop_direct<Cfg, kStages>(acc, A, B, m0, n0, 0, dp, N, MAXB, smem);
+  tile_mainloop_direct<Cfg, kStages>(acc, A, B, m0, n0, 0, dp, N, MAXB, smem, nt - (int)n0,
+                                     (int)blockIdx.x);
   typedef typename Cfg::MM::acc_t AT;
   const AT ie = (AT)(1.0 / eps);
-  for_each_acc<Cfg>(acc, [&](int row, int col, AT v) {
+  store_colmajor<Cfg, TW>(acc, smem, W, ldw, m0, n0, N, nt, [&](int row, int col, AT v) {
     const int64_t m = m0 + row, n = n0 + col;
-    if (m < N && n < nt) {
-      AT d2 = (AT)xn[m] + (AT)nsa[n] - (AT)2 * v;
-      d2 = d2 > (AT)0 ? d2 : (AT)0;
-      W[m + n * ldw] = (TW)exp(-d2 * ie);
-    }
+    if (m >= N || n >= nt) return (TW)0;
+    AT d2 = (AT)xn[m] + (AT)nsa[n] - (AT)2 * v;
+    d2 = d2 > (AT)0 ? d2 : (AT)0;
+    return (TW)exp(-d2 * ie);
   });
 }
 
@@ -539,7 +539,8 @@ __global__ __launch_bounds__(Cfg::NT) void k_schur(const TF* __restrict__ F, int
   GOperand<TF, true> B{FSa, r, nt, k, nullptr, (r % (16 / (int)sizeof(TF))) == 0};
   TileAcc<Cfg> acc;
   acc.zero();
-  tile_mainloop_direct<Cfg, kStages>(acc, A, B, m0, n0, 0, k, N, MAXB, smem);
+  tile_mainloop_direct<Cfg, kStages>(acc, A, B, m0, n0, 0, k, N, MAXB, smem, nt - (int)n0,
+                                     (int)blockIdx.x);
   for_each_acc<Cfg>(acc, [&](int row, int col, typename Cfg::MM::acc_t v) {
     const int64_t m = m0 + row, n = n0 + col;
     if (m < N && n < nt) W[m + n * ldw] -= (TF)v;
@@ -579,7 +580,8 @@ __global__ __launch_bounds__(CfgK::NT) void k_cols_schur(const T* __restrict__ X
     GOperand<T, true> A{Xp, dp, N, dp, nullptr, true};
     GOperand<T, true> B{XSa, dp, nt, dp, nullptr, true};
     tile_mainloop_direct<CfgK, kStages>(acc, A, B, m0, 0, 0, dp, N, MAXB,
-                                        reinterpret_cast<typename CfgK::T*>(smem_raw));
+                                        reinterpret_cast<typename CfgK::T*>(smem_raw), nt,
+                                        (int)blockIdx.x);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave % CfgK::WAVES_M, wn = wave / CfgK::WAVES_M;
@@ -606,17 +608,15 @@ __global__ __launch_bounds__(CfgK::NT) void k_cols_schur(const T* __restrict__ X
     GOperand<TF, false> A{F, ldf, N, k, nullptr, true};
     GOperand<TF, true> B{FSa, r, nt, k, nullptr, (r % (16 / (int)sizeof(TF))) == 0};
     tile_mainloop_direct<CfgS, kStages>(acs, A, B, m0, 0, 0, k, N, MAXB,
-                                        reinterpret_cast<typename CfgS::T*>(smem_raw));
+                                        reinterpret_cast<typename CfgS::T*>(smem_raw), nt,
+                                        (int)blockIdx.x);
   }
-  for_each_acc<CfgS>(acs, [&](int row, int col, typename CfgS::MM::acc_t v) {
-    const int64_t m = m0 + row;
-    if (m < N && col < nt) W[m + (int64_t)col * ldw] = (TF)(-v);
-  });
+  store_colmajor<CfgS, TF>(acs, smem_raw, W, ldw, m0, 0, N, nt,
+                           [&](int, int, typename CfgS::MM::acc_t v) { return (TF)(-v); });
 }
 
 // ------------------------------------------------------------ solve + downdate
-// G = W L^{-T} in float64 (four waves stacked along rows, each holding full
-// rows), F(:, k + j) = G(:, j), rho = max(rho - sum_j G^2, 0).
+// F(:, k + j) = G(:, j), rho = max(rho - sum_j G^2, 0), with
 // G = W L^{-T} tile: 128 rows x the whole block (<= 128 columns), eight
 // waves of 32 x 64, float64 MFMA.  128 rows per workgroup amortise the copy
 // of L^{-1} each workgroup stages.

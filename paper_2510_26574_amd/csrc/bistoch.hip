@@ -171,6 +171,22 @@ __global__ __launch_bounds__(1024) void k_shift_diag(double* M, int r, double* d
   if (threadIdx.x == 0) *delta = dl;
 }
 
+// After the first Rayleigh-Ritz step: shift the iteration matrix down by
+// sigma = theta_{p-1} / 2 (half the smallest Ritz value of the block, which
+// approximates the first eigenvalue outside it).  Eigenvalues near zero then
+// map to magnitudes no larger than the ones just below the block, so the
+// convergence ratio of the wanted eigenvalues falls from lambda_{p+1} /
+// lambda_i to (lambda_{p+1} - sigma) / (lambda_i - sigma).  The total shift
+// stays in *delta for the final correction of the eigenvalues.
+__global__ __launch_bounds__(1024) void k_shift_down(double* M, int r, const double* theta, int p,
+                                                     double* delta, const int32_t* skip) {
+  if (skip && *skip) return;
+  const double sg = 0.5 * theta[p - 1];
+  if (!(sg > 0.0)) return;
+  for (int i = threadIdx.x; i < r; i += 1024) M[i + (int64_t)i * r] -= sg;
+  if (threadIdx.x == 0) *delta -= sg;
+}
+
 __global__ void k_unshift(double* theta, int n, const double* delta) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) theta[i] -= *delta;
@@ -438,15 +454,11 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 static void chol_qr(hipStream_t st, const double* Y, double* Q, int r, int p, EigWs& w,
                     int32_t* status, const int32_t* skip) {
   dense::gemm64_splitk<true, true>(st, p, p, r, Y, r, Y, r, w.Gp, p, 1.0, 0.0, w.sk, skip);
+  // column-scaled Cholesky of the Gram and the explicit inverse of its
+  // triangular factor in one workgroup; Q = Y R^{-1} as an MFMA product
   hipLaunchKernelGGL(dense::k_chol_small, dim3(1), dim3(1024), 0, st, (const double*)w.Gp, (int64_t)p,
-                     p, w.Rinv, (int64_t)p, status, skip, 1);
-  if (p == dense::JMAX)
-    hipLaunchKernelGGL((dense::k_trsm_rows_reg<dense::JMAX>), dim3((unsigned)((r + 63) / 64)),
-                       dim3(64), 0, st, Y, (int64_t)r, r, (const double*)w.Rinv, (int64_t)p, Q,
-                       (int64_t)r, skip);
-  else
-    hipLaunchKernelGGL(dense::k_trsm_rows, dim3((unsigned)((r + 63) / 64)), dim3(64), 0, st, Y,
-                       (int64_t)r, r, p, (const double*)w.Rinv, (int64_t)p, Q, (int64_t)r, skip);
+                     p, w.Rinv, (int64_t)p, status, skip, 1, 1);
+  dense::gemm64<false, true>(st, r, p, p, Y, r, w.Rinv, p, Q, r, 1.0, 0.0, skip);
 }
 
 template <typename TG, typename TF, typename TU>
@@ -544,6 +556,9 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
                          (const int32_t*)w.conv);
       hipLaunchKernelGGL(k_ritz_check, dim3(1), dim3(1024), 0, st, (const double*)w.T1,
                          (const double*)w.Q, (const double*)w.theta, r, nev, 1e-10, w.conv);
+      if (it == 0)
+        hipLaunchKernelGGL(k_shift_down, dim3(1), dim3(1024), 0, st, w.M, r, (const double*)w.theta,
+                           p, w.delta, (const int32_t*)w.conv);
     }
     hipLaunchKernelGGL(k_unshift, dim3(1), dim3(128), 0, st, w.theta, p, (const double*)w.delta);
     hipLaunchKernelGGL(k_flag_noconv, dim3(1), dim3(1), 0, st, (const int32_t*)w.conv, status);

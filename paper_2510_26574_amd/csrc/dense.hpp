@@ -95,6 +95,83 @@ __device__ inline void chol_block_lds(double* a, int n, int lda_s, double* piv, 
   __syncthreads();
 }
 
+// Broadcast lane `src` (wave-uniform) of a double held in a VGPR pair.
+__device__ inline double bcast_lane(double v, int src) {
+  const unsigned long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffull), src);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Same factorisation (L with the square roots applied, lower triangle of `a`)
+// for n <= 128 + 8, blocked by panels of 8 columns: wave 0 loads a panel
+// into registers (lane l holds panel rows j0 + l and j0 + l + 64), factors it
+// right-looking with the pivot-row values broadcast by readlane, and writes
+// it back; then every thread applies the panel to the trailing lower
+// triangle.  Two workgroup barriers per panel.  A pivot <= 0 sets
+// RPC_EBREAKDOWN and is replaced by 1.
+__device__ inline void chol_panel_lds(double* a, int n, int lda_s, int32_t* status) {
+  constexpr int W = 8;
+  const int nth = blockDim.x, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  __syncthreads();
+  for (int j0 = 0; j0 < n; j0 += W) {
+    const int jw = n - j0 < W ? n - j0 : W;
+    if (wave == 0) {
+      double P0[W], P1[W];  // rows j0 + lane, j0 + lane + 64
+      const int i0 = j0 + lane, i1 = j0 + lane + 64;
+#pragma unroll
+      for (int q = 0; q < W; ++q) {
+        P0[q] = (q < jw && i0 < n) ? a[i0 + (j0 + q) * lda_s] : 0.0;
+        P1[q] = (q < jw && i1 < n) ? a[i1 + (j0 + q) * lda_s] : 0.0;
+      }
+#pragma unroll
+      for (int jj = 0; jj < W; ++jj) {
+        if (jj < jw) {
+          double p = bcast_lane(P0[jj], jj);  // diagonal (j0 + jj, j0 + jj)
+          if (!(p > 0.0)) {
+            if (lane == 0) set_status(status, RPC_EBREAKDOWN);
+            p = 1.0;
+          }
+          const double d = sqrt(p), rd = 1.0 / d;
+          // column jj: rows below the diagonal scaled, the diagonal set to d
+          P0[jj] = lane > jj ? P0[jj] * rd : (lane == jj ? d : P0[jj]);
+          P1[jj] = P1[jj] * rd;
+#pragma unroll
+          for (int c2 = jj + 1; c2 < W; ++c2) {
+            if (c2 < jw) {
+              const double f = bcast_lane(P0[jj], c2);  // L(j0 + c2, j0 + jj)
+              if (lane >= c2) P0[c2] -= P0[jj] * f;
+              P1[c2] -= P1[jj] * f;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < W; ++q) {
+        if (q < jw && i0 < n && lane >= q) a[i0 + (j0 + q) * lda_s] = P0[q];
+        if (q < jw && i1 < n) a[i1 + (j0 + q) * lda_s] = P1[q];
+      }
+    }
+    __syncthreads();
+    // trailing lower triangle: columns c >= j0 + jw, rows i >= c
+    const int t0 = j0 + jw;
+    const int rows = nth / 32, ty = tid / 32, tx = tid % 32;
+    for (int ii = t0 + ty; ii < n; ii += rows) {
+      double li[W];
+#pragma unroll
+      for (int q = 0; q < W; ++q) li[q] = q < jw ? a[ii + (j0 + q) * lda_s] : 0.0;
+      for (int ci = t0 + tx; ci <= ii; ci += 32) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) t += li[q] * a[ci + (j0 + q) * lda_s];
+        a[ii + ci * lda_s] -= t;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Factor the NB x NB diagonal block starting at (j0, j0) of A (n x n, ld).
 __global__ __launch_bounds__(256) void k_chol_diag(double* A, int64_t ld, int n, int j0,
                                                    int32_t* status) {
@@ -106,7 +183,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* A, int64_t ld, int n,
     int i = e % nb, c = e / nb;
     a[i + c * LDS] = A[(j0 + i) + (int64_t)(j0 + c) * ld];
   }
-  chol_block_lds(a, nb, LDS, piv, status);
+  chol_panel_lds(a, nb, LDS, status);
   for (int e = threadIdx.x; e < nb * nb; e += 256) {
     int i = e % nb, c = e / nb;
     A[(j0 + i) + (int64_t)(j0 + c) * ld] = i >= c ? a[i + c * LDS] : 0.0;
@@ -347,10 +424,11 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ A, i
 __global__ __launch_bounds__(1024) void k_chol_small(const double* __restrict__ G, int64_t ldg,
                                                      int p, double* __restrict__ R, int64_t ldr,
                                                      int32_t* status, const int32_t* skip,
-                                                     int equil = 0) {
+                                                     int equil = 0, int inverse = 0) {
   if (skip && *skip) return;
   constexpr int LDS = JMAX + 1;
   __shared__ double a[JMAX * LDS];
+  __shared__ double xi[JMAX * LDS];
   __shared__ double piv[JMAX];
   __shared__ double sc[JMAX];
   const int tid = threadIdx.x;
@@ -363,10 +441,36 @@ __global__ __launch_bounds__(1024) void k_chol_small(const double* __restrict__ 
     const int i = e % p, c = e / p;
     a[i + c * LDS] = G[i + c * ldg] * sc[i] * sc[c];
   }
-  chol_block_lds(a, p, LDS, piv, status);  // lower L, R = L^T S^{-1}
+  chol_panel_lds(a, p, LDS, status);  // lower L, R = L^T S^{-1}
+  if (!inverse) {
+    for (int e = tid; e < p * p; e += 1024) {
+      const int i = e % p, c = e / p;
+      R[i + c * ldr] = (i <= c) ? a[c + i * LDS] / sc[c] : 0.0;
+    }
+    return;
+  }
+  // X = L^{-1} by forward substitution, one column per group of 8 lanes
+  // (partial dot products over every 8th index, joined by xor shuffles; all
+  // 8 lanes hold the sum and store the same value).  Then
+  // R^{-1} = S L^{-T} = S X^T (upper).
+  const int g = tid >> 3, sub = tid & 7;
+  if (g < p) {
+    const int j = g;
+    double* x = xi + j * LDS;
+    x[j] = 1.0 / a[j + j * LDS];
+    for (int i = j + 1; i < p; ++i) {
+      double t = 0.0;
+      for (int q = j + sub; q < i; q += 8) t += a[i + q * LDS] * x[q];
+      t += __shfl_xor(t, 1, 64);
+      t += __shfl_xor(t, 2, 64);
+      t += __shfl_xor(t, 4, 64);
+      x[i] = -t / a[i + i * LDS];
+    }
+  }
+  __syncthreads();
   for (int e = tid; e < p * p; e += 1024) {
     const int i = e % p, c = e / p;
-    R[i + c * ldr] = (i <= c) ? a[c + i * LDS] / sc[c] : 0.0;
+    R[i + c * ldr] = (i <= c) ? sc[i] * xi[c + i * LDS] : 0.0;  // (S X^T)(i, c) = s_i X(c, i)
   }
 }
 

@@ -347,12 +347,20 @@ struct DirectSmem {
 // that the caller discards).  Tiles that would read past them, and a final
 // partial k-stage, go through the register-staged path with zero fill.
 // smem holds DirectSmem<Cfg, NS, KCA, KCB>::bytes.
+//
+// n_active: output columns n0 .. n0 + n_active - 1 are wanted; a wave whose
+// whole column slice lies beyond them skips its MFMAs (it still loads and
+// synchronises with the workgroup) and leaves its accumulators unchanged.
+// rot: the full k-stages are visited starting at stage rot mod (their count)
+// and wrapping around, so workgroups that share an operand (all of them read
+// the same pivot rows) do not all hit the same L2 lines at the same time.
 template <class Cfg, int NS, bool KCA, bool KCB>
 __device__ inline void tile_mainloop_direct(TileAcc<Cfg>& acc,
                                             const GOperand<typename Cfg::T, KCA>& A,
                                             const GOperand<typename Cfg::T, KCB>& B, int64_t m0,
                                             int64_t n0, int64_t kb, int64_t ke, int64_t a_avail,
-                                            int64_t b_avail, typename Cfg::T* smem) {
+                                            int64_t b_avail, typename Cfg::T* smem,
+                                            int n_active = 1 << 30, int rot = 0) {
   typedef typename Cfg::T T;
   typedef typename Cfg::MM MM;
   typedef TileSmem<Cfg, KCA, KCB> SM;
@@ -375,13 +383,17 @@ __device__ inline void tile_mainloop_direct(TileAcc<Cfg>& acc,
   const int wave = tid >> 6;
   const int wm = wave % Cfg::WAVES_M, wn = wave / Cfg::WAVES_M;
   const int per = DA::count(wave) + DB::count(wave);
+  const bool idle = wn * Cfg::WTN >= n_active;
+  const int r0s = rot % nfull;
   auto issue = [&](int s) {
     T* base = smem + (s % NS) * SM::STAGE;
-    const int64_t k0 = kb + (int64_t)s * Cfg::BK;
+    const int ps = s + r0s < nfull ? s + r0s : s + r0s - nfull;  // stage in k order
+    const int64_t k0 = kb + (int64_t)ps * Cfg::BK;
     DA::issue(base, A.p, A.ld, m0, k0, wave, lane);
     DB::issue(base + SM::LA::ELEMS, B.p, B.ld, n0, k0, wave, lane);
   };
   auto compute = [&](const T* As) {
+    if (idle) return;
     const T* Bs = As + SM::LA::ELEMS;
 #pragma unroll
     for (int kk = 0; kk < Cfg::BK; kk += MM::KS) {
@@ -427,4 +439,56 @@ __device__ inline void tile_mainloop_direct(TileAcc<Cfg>& acc,
     compute(buf);
   }
   lds_barrier();  // the caller may reuse smem
+}
+
+// ----------------------------------------------- coalesced column-major store
+// The MFMA accumulator layout spreads one store instruction over 16 columns,
+// a few scattered rows each.  Column-major outputs are therefore staged per
+// wave through LDS ([col][row], odd pitch) and written back one column
+// segment per instruction, WTM consecutive rows at a time.  `val(row, col,
+// v)` gives the value for tile-local (row, col); entries outside [0, M) x
+// [0, N) (global) are not written.  smem must be free (no other wave still
+// reading it) and hold ColStoreSmem<Cfg, TO>::bytes.
+template <class Cfg, typename TO>
+struct ColStoreSmem {
+  static constexpr int LDP = Cfg::WTM + 1;
+  static constexpr size_t bytes = (size_t)(Cfg::NT / 64) * Cfg::WTN * LDP * sizeof(TO);
+};
+
+template <class Cfg, typename TO, typename Fn>
+__device__ inline void store_colmajor(TileAcc<Cfg>& acc, void* smem, TO* __restrict__ out,
+                                      int64_t ld, int64_t m0, int64_t n0, int64_t M, int64_t N,
+                                      Fn&& val) {
+  constexpr int LDP = ColStoreSmem<Cfg, TO>::LDP;
+  static_assert(64 % Cfg::WTM == 0 || Cfg::WTM % 64 == 0, "wave tile rows vs wave width");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % Cfg::WAVES_M, wn = wave / Cfg::WAVES_M;
+  TO* s = reinterpret_cast<TO*>(smem) + (size_t)wave * Cfg::WTN * LDP;
+  for_each_acc<Cfg>(acc, [&](int row, int col, typename Cfg::MM::acc_t v) {
+    s[(col - wn * Cfg::WTN) * LDP + (row - wm * Cfg::WTM)] = val(row, col, v);
+  });
+  // the wave reads back what its own lanes wrote: LDS operations of one wave
+  // complete in order; the asm statements keep the compiler from reordering
+  asm volatile("" ::: "memory");
+  const int64_t mb = m0 + wm * Cfg::WTM, nb = n0 + wn * Cfg::WTN;
+  if constexpr (Cfg::WTM >= 64) {
+#pragma unroll 4
+    for (int c = 0; c < Cfg::WTN; ++c) {
+      const int64_t n = nb + c;
+#pragma unroll
+      for (int rr = 0; rr < Cfg::WTM; rr += 64) {
+        const int64_t m = mb + rr + lane;
+        if (m < M && n < N) out[m + n * ld] = s[c * LDP + rr + lane];
+      }
+    }
+  } else {
+    constexpr int CPI = 64 / Cfg::WTM;  // columns per store instruction
+    const int r = lane % Cfg::WTM, cq = lane / Cfg::WTM;
+#pragma unroll 4
+    for (int c = 0; c < Cfg::WTN; c += CPI) {
+      const int64_t m = mb + r, n = nb + c + cq;
+      if (m < M && n < N) out[m + n * ld] = s[(c + cq) * LDP + r];
+    }
+  }
+  asm volatile("" ::: "memory");
 }
