@@ -277,26 +277,40 @@ __global__ void k_flag_noconv(const int32_t* conv, int32_t* status) {
 }
 
 // U = diag(dinv) F Z   (F: N x r, Z: r x nev column-major; dinv may be null)
+// U = D~^{-1} F Z tile: 128 rows x 64 eigenvectors, eight waves of 64 x 16,
+// Z converted to the product type beforehand; U written column by column.
+template <typename T>
+using FormUCfg = TileCfg<T, 128, 64, (sizeof(T) == 4 ? 32 : 16), 2, 4>;
+
 template <typename T, typename TF, typename TU>
-__global__ __launch_bounds__(256) void k_form_u(const TF* __restrict__ F, int64_t ldf, int64_t N,
-                                                int r, const double* __restrict__ Z, int nev,
-                                                const double* __restrict__ dinv,
-                                                TU* __restrict__ U, int64_t ldu,
-                                                const int32_t* kptr) {
-  typedef TileCfg<T, 128, 64, 16, 2, 2> Cfg;
+__global__ __launch_bounds__(FormUCfg<T>::NT) void k_form_u(const TF* __restrict__ F, int64_t ldf,
+                                                            int64_t N, int r,
+                                                            const T* __restrict__ Zt, int nev,
+                                                            const double* __restrict__ dinv,
+                                                            TU* __restrict__ U, int64_t ldu,
+                                                            const int32_t* kptr) {
+  typedef FormUCfg<T> Cfg;
   extern __shared__ char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM, n0 = (int64_t)blockIdx.y * Cfg::BN;
   const int kk = kptr ? *kptr : r;  // columns >= k of F are zero
-  GOperand<TF, false> A{F, ldf, N, kk, nullptr, true};
-  GOperand<double, true> B{Z, r, nev, kk, nullptr, (r % 2) == 0};
+  GOperand<T, true> B{Zt, r, nev, kk, nullptr, (r % (16 / (int)sizeof(T))) == 0};
   TileAcc<Cfg> acc;
   acc.zero();
+  GOperand<TF, false> A{F, ldf, N, kk, nullptr, true};
   tile_mainloop<Cfg>(acc, A, B, m0, n0, 0, kk, smem);
-  for_each_acc<Cfg>(acc, [&](int row, int col, typename Cfg::MM::acc_t v) {
-    const int64_t m = m0 + row, n = n0 + col;
-    if (m < N && n < nev) U[m + n * ldu] = (TU)(dinv ? (double)v * dinv[m] : (double)v);
-  });
+  store_colmajor<Cfg, TU>(acc, smem_raw, U, ldu, m0, n0, N, nev,
+                          [&](int row, int, typename Cfg::MM::acc_t v) {
+                            const int64_t m = m0 + row;
+                            if (m >= N) return (TU)0;
+                            return (TU)(dinv ? (double)v * dinv[m] : (double)v);
+                          });
+}
+
+template <typename T>
+__global__ void k_cvt(const double* __restrict__ src, T* __restrict__ dst, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) dst[e] = (T)src[e];
 }
 
 // Column sign: find the largest |U[:, j]| (lowest index on ties).
@@ -578,11 +592,16 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   dense::trsm_lt(st, w.Gs, r, r, w.Z, r, nev);
   hipLaunchKernelGGL(k_scale_rows, dim3(nblk((int64_t)r * nev)), dim3(256), 0, st, w.Z, (int64_t)r,
                      r, nev, (const double*)w.s, 0);
-  typedef TileCfg<TG, 128, 64, 16, 2, 2> CfgU;
-  const dim3 gu((unsigned)((N + 127) / 128), (unsigned)((nev + 63) / 64));
-  const size_t smU = TileSmem<CfgU, false, true>::bytes;
-  hipLaunchKernelGGL((k_form_u<TG, TF, TU>), gu, dim3(256), smU, st, F, ldf, N, r,
-                     (const double*)w.Z, nev, (const double*)w.sd, U, ldu, k);
+  typedef FormUCfg<TG> CfgU;
+  const dim3 gu((unsigned)((N + CfgU::BM - 1) / CfgU::BM), (unsigned)((nev + CfgU::BN - 1) / CfgU::BN));
+  size_t smU = TileSmem<CfgU, false, true>::bytes;
+  if (ColStoreSmem<CfgU, TU>::bytes > smU) smU = ColStoreSmem<CfgU, TU>::bytes;
+  // Z in the product type (the scratch T2 is free until the extension matrix)
+  TG* Zt = reinterpret_cast<TG*>(w.T2);
+  hipLaunchKernelGGL((k_cvt<TG>), dim3(nblk((int64_t)r * nev)), dim3(256), 0, st, (const double*)w.Z,
+                     Zt, (int64_t)r * nev);
+  hipLaunchKernelGGL((k_form_u<TG, TF, TU>), gu, dim3(CfgU::NT), smU, st, F, ldf, N, r,
+                     (const TG*)Zt, nev, (const double*)w.sd, U, ldu, k);
   RPC_LAUNCH_CHECK();
 
   if (o->fix_const) {
