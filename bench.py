@@ -211,7 +211,9 @@ def kernel_columns(rp, torch, Xd, eps, ud, w, d, steps):
     tf = flops / sec / 1e12
     return {"ms_total": ms, "launches": n, "tflops": tf, "gbs": byts / sec / 1e9,
             "frac_mfma_peak": tf / PEAK["bf16"], "ai_flop_per_byte": ai, "ceiling_tflops": ceil_tf,
-            "frac_ceiling": tf / ceil_tf, "frac_hbm_peak": byts / sec / 1e9 / PEAK["hbm"]}
+            "frac_ceiling": tf / ceil_tf, "frac_hbm_peak": byts / sec / 1e9 / PEAK["hbm"],
+            "algorithmic_bytes_per_launch": byts / max(n, 1),
+            "traffic": pmc_traffic("k_kernel_cols")}
 
 
 def cpu_baseline(X, eps, w, n_sample):
