@@ -132,12 +132,27 @@ typedef struct {
  *             by a QR with positive diag(R) (Algorithm 1, optional lines).
  *  gram_dtype F64 or F32: arithmetic of the two N-long Gram products
  *             (float64 accumulation across row chunks in both cases).
- *  u_dtype    F64 or F32 storage of U. */
+ *  u_dtype    F64 or F32 storage of U.
+ *  normalization  RPC_BISTOCHASTIC (default), or RPC_SYMMETRIC: the
+ *             eigenpairs of L~ = D~^{-1/2} K~ D~^{-1/2} (the paper's symmetric
+ *             normalisation), computed with B = D~^{-1/2} F and C = I (one
+ *             Gram product instead of two; q~ is not read).  Its leading
+ *             eigenpair is (1, D~^{1/2} 1 / |D~^{1/2} 1|).  fix_const is not
+ *             defined for it (RPC_EINVAL); ext_E is then R^T V Lambda^{-1}, the
+ *             matrix of the extension f(y)^T E / sqrt(c^T f(y)), which
+ *             nystrom_extend (built for P~) does not apply. */
+typedef enum {
+  RPC_BISTOCHASTIC = 0, /* P~ = D~^{-1} K~ Q~^{-1} K~ D~^{-1} (Algorithm 1) */
+  RPC_SYMMETRIC = 1     /* L~ = D~^{-1/2} K~ D~^{-1/2} (symmetric normalisation) */
+} rpc_normalization;
+
 typedef struct {
   int32_t nev;
   int32_t fix_const;
   int32_t gram_dtype;
   int32_t u_dtype;
+  int32_t normalization; /* rpc_normalization */
+  int32_t reserved_;     /* must be 0 */
   double gamma;
 } rpc_eig_opts;
 

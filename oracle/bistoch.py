@@ -158,7 +158,8 @@ def symmetric_eig(F, nev):
     Q, R = np.linalg.qr(B, mode="reduced")
     lam, V = np.linalg.eigh(R @ R.T)
     lam, V = lam[::-1], V[:, ::-1]
-    return {"U": sign_normalize(Q @ V[:, :nev]), "lam": lam[:nev].copy(), "d": d}
+    return {"U": sign_normalize(Q @ V[:, :nev]), "lam": lam[:nev].copy(), "lam_all": lam.copy(),
+            "d": d}
 
 
 def gaussian_dense(X, eps):

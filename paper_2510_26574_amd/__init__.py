@@ -50,9 +50,13 @@ class rpc_factor_opts(ctypes.Structure):
                 ("round_accepted", ctypes.c_void_p)]
 
 
+NORMALIZATIONS = {"bistochastic": 0, "symmetric": 1}
+
+
 class rpc_eig_opts(ctypes.Structure):
     _fields_ = [("nev", ctypes.c_int32), ("fix_const", ctypes.c_int32),
                 ("gram_dtype", ctypes.c_int32), ("u_dtype", ctypes.c_int32),
+                ("normalization", ctypes.c_int32), ("reserved_", ctypes.c_int32),
                 ("gamma", ctypes.c_double)]
 
 
@@ -241,8 +245,10 @@ def bistoch_degrees(F, k, status=None, stream=None):
 
 
 def bistoch_eig(F, k, d, q, nev, gamma=0.0, fix_const=False, gram_dtype="f64", u_dtype="f64",
-                status=None, stream=None):
-    """Top-nev eigenpairs of P~ (Algorithm 1). Returns U (N x nev view), lam, E."""
+                normalization="bistochastic", status=None, stream=None):
+    """Top-nev eigenpairs of P~ (Algorithm 1), or of L~ = D~^{-1/2} K~ D~^{-1/2}
+    with normalization="symmetric" (q may then be None).  Returns U (N x nev
+    view), lam, E."""
     torch = _torch()
     lib = load_library()
     code, N, ldf, r = _factor_args(F)
@@ -253,7 +259,8 @@ def bistoch_eig(F, k, d, q, nev, gamma=0.0, fix_const=False, gram_dtype="f64", u
     lam = torch.empty(nev, dtype=torch.float64, device=dev)
     E = torch.empty((nev, r), dtype=torch.float64, device=dev)
     st = status if status is not None else torch.zeros(1, dtype=torch.int32, device=dev)
-    opts = rpc_eig_opts(int(nev), 1 if fix_const else 0, DTYPES[gram_dtype], DTYPES[u_dtype], float(gamma))
+    opts = rpc_eig_opts(int(nev), 1 if fix_const else 0, DTYPES[gram_dtype], DTYPES[u_dtype],
+                        NORMALIZATIONS[normalization], 0, float(gamma))
     nb = ctypes.c_size_t(0)
     _check(lib.bistoch_eig_workspace_size(N, r, ctypes.byref(opts), ctypes.byref(nb)),
            "bistoch_eig_workspace_size")
@@ -328,7 +335,7 @@ class Job:
         if mode == "replay":
             assert replay is not None and replay.dtype == torch.int64 and replay.is_cuda
             fo.replay, fo.n_replay = replay.data_ptr(), replay.numel()
-        eo = rpc_eig_opts(int(nev), 0, DTYPES[gram_dtype], DTYPES[u_dtype], float(gamma))
+        eo = rpc_eig_opts(int(nev), 0, DTYPES[gram_dtype], DTYPES[u_dtype], 0, 0, float(gamma))
         self.rec = rpc_job(_points(X, eps), fo, eo, self.Fbuf.data_ptr(), self.ldf,
                            self.pivots.data_ptr(), self.rho.data_ptr(), self.k.data_ptr(),
                            self.c.data_ptr(), self.d.data_ptr(), self.q.data_ptr(), self.Ubuf.data_ptr(),

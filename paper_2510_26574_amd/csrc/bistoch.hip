@@ -259,15 +259,31 @@ __global__ void k_recip(const double* __restrict__ x, double* __restrict__ y, in
   if (i < n) y[i] = 1.0 / x[i];
 }
 
-// Row scales of the two Grams in the product type: 1/d~ and 1/sqrt(q~).
+// Row scales of the Grams in the product type: 1/d~ and 1/sqrt(q~)
+// (bistochastic), or 1/sqrt(d~) alone (symmetric; qt unused).
 template <typename T>
 __global__ void k_gram_scales(const double* __restrict__ dt, const double* __restrict__ qt,
-                              T* __restrict__ sd, T* __restrict__ sq, int64_t n) {
+                              T* __restrict__ sd, T* __restrict__ sq, int64_t n, int sym) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) {
-    sd[i] = (T)(1.0 / dt[i]);
-    sq[i] = (T)(1.0 / sqrt(qt[i]));
+    sd[i] = (T)(sym ? 1.0 / sqrt(dt[i]) : 1.0 / dt[i]);
+    if (!sym) sq[i] = (T)(1.0 / sqrt(qt[i]));
   }
+}
+
+// y = 1 / sqrt(x)
+__global__ void k_rsqrt(const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = 1.0 / sqrt(x[i]);
+}
+
+// C = I on the leading k x k block, zero elsewhere (symmetric normalisation).
+__global__ void k_eye_k(double* __restrict__ C, int r, const int32_t* kptr) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * r) return;
+  const int i = (int)(e % r), j = (int)(e / r);
+  const int k = *kptr;
+  C[e] = (i == j && i < k) ? 1.0 : 0.0;
 }
 
 __global__ void k_set_int(int32_t* p, int32_t v) { *p = v; }
@@ -489,22 +505,29 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   if (!syrk::gram2_fits<TG>(N, r, w.part_cap) ||
       (o->fix_const && !syrk::gram2_fits<double>(N, nev, w.part_cap)))
     return RPC_EWORKSPACE;
+  const int sym = o->normalization == RPC_SYMMETRIC;
   prof::begin(prof::SMALL, st);
-  hipLaunchKernelGGL(k_recip, dim3(nblk(N)), dim3(256), 0, st, dt, w.sd, N);
-  hipLaunchKernelGGL(k_recip, dim3(nblk(N)), dim3(256), 0, st, qt, w.sq, N);
+  // w.sd holds the row scale of B: 1/d~ (bistochastic) or 1/sqrt(d~) (symmetric)
+  if (sym)
+    hipLaunchKernelGGL(k_rsqrt, dim3(nblk(N)), dim3(256), 0, st, dt, w.sd, N);
+  else
+    hipLaunchKernelGGL(k_recip, dim3(nblk(N)), dim3(256), 0, st, dt, w.sd, N);
   hipLaunchKernelGGL((k_gram_scales<TG>), dim3(nblk(N)), dim3(256), 0, st, dt, qt, (TG*)w.ssd,
-                     (TG*)w.ssq, N);
+                     (TG*)w.ssq, N, sym);
   prof::end(prof::SMALL, st);
 
-  // ---- the two N-long Grams: G_B = (D~^{-1} F)^T (D~^{-1} F), C = (Q~^{-1/2} F)^T (Q~^{-1/2} F)
+  // ---- the N-long Grams: G_B = B^T B with B = D~^{-1} F (or D~^{-1/2} F), and
+  // C = (Q~^{-1/2} F)^T (Q~^{-1/2} F) (bistochastic) or C = I (symmetric)
+  const int nz = sym ? 1 : 2;
   prof::begin(prof::GRAM, st);
-  syrk::gram2_partial<TG, TF>(st, F, ldf, N, r, 2, (const TG*)w.ssd, (const TG*)w.ssq, w.part,
+  syrk::gram2_partial<TG, TF>(st, F, ldf, N, r, nz, (const TG*)w.ssd, (const TG*)w.ssq, w.part,
                               w.part1, k);
   prof::end(prof::GRAM, st);
   const unsigned grr = nblk((int64_t)r * r);
   RPC_LAUNCH_CHECK();
   prof::begin(prof::SMALL, st);
-  syrk::gram2_reduce<TG>(st, N, r, 2, w.part, w.part1, w.GB, w.C, k);
+  syrk::gram2_reduce<TG>(st, N, r, nz, w.part, w.part1, w.GB, w.C, k);
+  if (sym) hipLaunchKernelGGL(k_eye_k, dim3(grr), dim3(256), 0, st, w.C, r, k);
   hipLaunchKernelGGL((k_gram_finish<TF>), dim3(grr), dim3(256), 0, st, w.GB, w.C, w.Gs, w.Cs, w.s,
                      r, k, F, ldf, N, (const double*)w.sd, o->gamma, 0);
   hipLaunchKernelGGL((k_gram_finish<TF>), dim3(grr), dim3(256), 0, st, w.GB, w.C, w.Gs, w.Cs, w.s,
@@ -692,6 +715,9 @@ static int check_eig_opts(int64_t N, int r, const rpc_eig_opts* o) {
   if (o->u_dtype != RPC_F64 && o->u_dtype != RPC_F32) return RPC_EINVAL;
   if (o->fix_const && o->u_dtype != RPC_F64) return RPC_EINVAL;
   if (!(o->gamma >= 0.0)) return RPC_EINVAL;
+  if (o->normalization != RPC_BISTOCHASTIC && o->normalization != RPC_SYMMETRIC) return RPC_EINVAL;
+  if (o->normalization == RPC_SYMMETRIC && o->fix_const) return RPC_EINVAL;
+  if (o->reserved_ != 0) return RPC_EINVAL;
   return RPC_OK;
 }
 
@@ -734,7 +760,8 @@ extern "C" int bistoch_eig(const void* F, int32_t fdt, int64_t N, int64_t ldf, i
   int rc = check_eig_opts(N, r, o);
   if (rc) return rc;
   (void)c;
-  if (!F || !k || !dt || !qt || !U || !lambda || !ext_E || !status) return RPC_EINVAL;
+  if (!F || !k || !dt || !U || !lambda || !ext_E || !status) return RPC_EINVAL;
+  if (!qt && !(o && o->normalization == RPC_SYMMETRIC)) return RPC_EINVAL;
   if (ldf < N || ldf % 8 != 0 || ldu < N || ldu % 8 != 0) return RPC_EINVAL;
   if (fdt != RPC_F64 && fdt != RPC_F32) return RPC_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);

@@ -65,10 +65,15 @@ def test_host_side_validation(lib):
         assert lib.rpchol_factor_workspace_size(ctypes.byref(pts), ctypes.byref(o), ctypes.byref(nb)) == rp.RPC_EINVAL, kw
     p2 = rp.rpc_points(100, 3, 3, 0x1000, 0.0)  # eps <= 0
     assert lib.rpchol_factor_workspace_size(ctypes.byref(p2), ctypes.byref(opts), ctypes.byref(nb)) == rp.RPC_EINVAL
-    eo = rp.rpc_eig_opts(200, 0, 0, 0, 0.0)  # nev > r
+    eo = rp.rpc_eig_opts(200, 0, 0, 0, 0, 0, 0.0)  # nev > r
     assert lib.bistoch_eig_workspace_size(1000, 64, ctypes.byref(eo), ctypes.byref(nb)) == rp.RPC_EINVAL
-    eo = rp.rpc_eig_opts(16, 0, 0, 0, 0.0)
+    eo = rp.rpc_eig_opts(16, 0, 0, 0, 0, 0, 0.0)
     assert lib.bistoch_eig_workspace_size(1000, 64, ctypes.byref(eo), ctypes.byref(nb)) == 0
+    for bad in (dict(normalization=2), dict(normalization=1, fix_const=1), dict(reserved_=1)):
+        eo = rp.rpc_eig_opts(16, 0, 0, 0, 0, 0, 0.0)
+        for kk, v in bad.items():
+            setattr(eo, kk, v)
+        assert lib.bistoch_eig_workspace_size(1000, 64, ctypes.byref(eo), ctypes.byref(nb)) == rp.RPC_EINVAL, bad
     assert lib.nystrom_extend_workspace_size(10, 3, 64, 65, ctypes.byref(nb)) == rp.RPC_EINVAL
     o = rp.rpc_factor_opts(8, 2, rp.MODES["sampled"], 0, 0, rp.RPC_FACTOR_UNFUSED, 0.0, 0x2000, 64, 0, 0, 0)
     assert lib.rpchol_factor_workspace_size(ctypes.byref(pts), ctypes.byref(o), ctypes.byref(nb)) == 0

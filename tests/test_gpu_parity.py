@@ -295,3 +295,43 @@ def test_unfused_columns_and_schur_agree(gpu):
     a = un["F"][:, :k].double().cpu().numpy()
     b = fu["F"][:, :k].double().cpu().numpy()
     assert np.abs(a - b).max() <= 5e-5 * np.abs(b).max()
+
+
+def _sym_case(gpu, X, eps, r, b, nev, seed, gram="f64"):
+    torch, rp = gpu
+    u = uniform_stream(2 * b * (-(-r // b)), seed=seed)
+    ref = oracle.arpc(X, eps, r=r, b=b, mode="sampled", uniforms=u)
+    out, k, F, piv, rho = _run_factor(gpu, X, eps, r, b, "sampled", u=u)
+    deg = rp.bistoch_degrees(out["F"], out["k"])
+    eig = rp.bistoch_eig(out["F"], out["k"], deg["d"], None, nev, gram_dtype=gram,
+                         normalization="symmetric")
+    assert rp.status_sync(eig["status"]) == 0
+    return ref, out, deg, eig, oracle.symmetric_eig(ref["F"], nev)
+
+
+def test_symmetric_normalization_c1_f64(gpu):
+    """L~ = D~^{-1/2} K~ D~^{-1/2}: eigenpairs against the oracle's QR route,
+    and the exact leading pair (1, D~^{1/2} 1 / |D~^{1/2} 1|)."""
+    X, eps = _torus_case(seed=3)
+    nev = 16
+    ref, out, deg, eig, res = _sym_case(gpu, X, eps, 64, 8, nev, seed=31)
+    lam = eig["lam"].cpu().numpy()
+    assert np.abs(lam / res["lam"] - 1).max() < 1e-10
+    U = eig["U"].cpu().numpy()
+    m = _gap_index(res["lam_all"], nev)
+    assert _angle(U[:, :m], res["U"][:, :m]) < 1e-8
+    assert abs(lam[0] - 1.0) < 1e-12
+    sd = np.sqrt(deg["d"].cpu().numpy())
+    assert np.abs(U[:, 0] - sd / np.linalg.norm(sd)).max() < 1e-10
+
+
+def test_symmetric_normalization_subspace_path(gpu):
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((3000, 6)).astype(np.float32)
+    eps = median_sq_distance(X, seed=9)
+    nev = 24
+    ref, out, deg, eig, res = _sym_case(gpu, X, eps, 160, 32, nev, seed=32)
+    lam = eig["lam"].cpu().numpy()
+    assert np.abs(lam / res["lam"] - 1).max() < 1e-10
+    m = _gap_index(res["lam_all"], nev)
+    assert _angle(eig["U"].cpu().numpy()[:, :m], res["U"][:, :m]) < 1e-8
