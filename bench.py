@@ -18,7 +18,8 @@ Prints one JSON line.  Options: --gpus (must be 1), --steps, --warmup,
 instead trains the learned surrogate of the Nystrom extension on the
 workload's eigenvectors and measures it on held-out states (its own line);
 `--form batched` runs the batched form (512 decompositions of 64 smaller
-datasets at 8 bandwidths each).
+datasets at 8 bandwidths each); `--form paper` runs the paper's own
+vector-valued KS workload (r = 4096) and reports its trace error.
 """
 import argparse
 import json
@@ -390,6 +391,75 @@ def bench_surrogate(args, rp, torch):
     print(json.dumps(line), flush=True)
 
 
+PAPER_VSA = dict(n_time=512, J=64, eps=32.0, r=4096, b=64, nev=64, seed=0, trace_err=0.0891, tau=1e-6)
+
+
+def bench_paper(args, rp, torch):
+    """The paper's own workload: vector-valued delay embedding of a KS
+    trajectory (512 times x 64 grid points = 32 768 product states in R^64),
+    ARPC with r = 4096, b = 64 in float32, then Algorithm 1 (top 64).  The
+    paper reports a trace error of 8.91% on its own trajectory and random
+    draws (one A100, float32); that figure is quoted as context.
+
+    Two readings of the bandwidth are run.  With exp(-|.|^2 / eps), eps = 32
+    (the value the section states) the trace error lands near the paper's
+    figure and is the timed line; eps J = 2048 (the kernel as printed) makes
+    the kernel numerically low rank on this trajectory (trace error ~1e-7),
+    which float32 cannot resolve, so it runs in float64 and is reported with
+    its status.  Prints one JSON line."""
+    from synth import uniform_stream, vsa_points
+
+    c = PAPER_VSA
+    t0 = time.perf_counter()
+    X = vsa_points(n_time=c["n_time"], J=c["J"])
+    N, d = X.shape
+    log(f"[paper] VSA points {N} x {d} ({time.perf_counter() - t0:.1f}s)")
+    r, b = c["r"], c["b"]
+    u = uniform_stream(2 * b * (-(-r // b)), seed=c["seed"])
+    Xd, ud = torch.from_numpy(X).cuda(), torch.from_numpy(u).cuda()
+
+    def one(eps_run, prec, tau):
+        g, f, gr = prec
+
+        def run():
+            out = rp.rpchol_factor(Xd, eps_run, r, b, uniforms=ud, gemm_dtype=g, factor_dtype=f, tau=tau)
+            deg = rp.bistoch_degrees(out["F"], out["k"], status=out["status"])
+            eig = rp.bistoch_eig(out["F"], out["k"], deg["d"], deg["q"], c["nev"], gram_dtype=gr,
+                                 status=out["status"])
+            return out, deg, eig
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            out, deg, eig = run()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / args.steps
+        st = rp.status_sync(out["status"])
+        lam = eig["lam"].cpu().numpy()
+        return {"eps": eps_run, "precision": {"gemm": g, "factor": f, "gram": gr}, "tau": tau,
+                "seconds": dt, "status": rp.STATUS_NAMES.get(st, st),
+                "accepted_pivots": int(out["k"].item()),
+                "trace_error": float(out["rho"].sum().item() / N),
+                "lam_head": [float(x) for x in lam[:6]], "lam_64": float(lam[-1])}
+
+    # float32 factor storage: proposals whose updated pivot falls to the
+    # float32 noise floor are rejected (tau = 1e-6 max diag K, diag K = 1)
+    main = one(c["eps"], ("f32", "f32", "f32"), c["tau"])
+    low_rank = one(c["eps"] * c["J"], ("f64", "f64", "f64"), 0.0)
+    line = {
+        "metric": "paper workload (vector-valued KS delay embedding): seconds and trace error",
+        "form": "paper", "value": main["seconds"], "unit": "s", "higher_is_better": False, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"VSA KS N*M={N} d=J={d} r={r} b={b} nev={c['nev']}"},
+        "kernel_eps": main,
+        "kernel_eps_times_J": low_rank,
+        "paper_trace_error_context": {"value": c["trace_err"], "hardware": "1x NVIDIA A100 40 GiB, fp32",
+                                      "note": "the authors' trajectory, random draws and regularised QR"},
+    }
+    print(json.dumps(line), flush=True)
+
+
 BATCH = dict(nev=16, n_streams=8, reps=3, datasets=64)
 
 
@@ -517,9 +587,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--form", default="headline", choices=["headline", "surrogate", "batched"],
+    ap.add_argument("--form", default="headline", choices=["headline", "surrogate", "batched", "paper"],
                     help="headline: the decomposition benchmark; surrogate: the learned extension; "
-                         "batched: 512 small decompositions")
+                         "batched: 512 small decompositions; paper: the paper's own VSA workload")
     ap.add_argument("--datasets", type=int, default=BATCH["datasets"])
     ap.add_argument("--sur-epochs", type=int, default=SUR["epochs"])
     args = ap.parse_args()
@@ -538,6 +608,9 @@ def main():
         return
     if args.form == "batched":
         bench_batched(args, rp, torch)
+        return
+    if args.form == "paper":
+        bench_paper(args, rp, torch)
         return
     w = WORKLOADS[args.workload]
     X, eps, u = make_inputs(w)

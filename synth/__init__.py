@@ -9,6 +9,7 @@ from .torus import torus_points
 from .ks import ks_trajectory, delay_embed, ks_points
 from .bandwidth import median_sq_distance
 from .batch import batch_specs, batch_points, BANDWIDTH_MULTIPLIERS
+from .vsa import vsa_points, vsa_initial_field
 
 __all__ = [
     "philox4x32_10",
@@ -21,4 +22,6 @@ __all__ = [
     "batch_specs",
     "batch_points",
     "BANDWIDTH_MULTIPLIERS",
+    "vsa_points",
+    "vsa_initial_field",
 ]

@@ -110,3 +110,18 @@ def test_batch_specs_ranges_and_determinism():
         assert (s["d"], s["q"]) in ((32, 1), (128, 2), (512, 8))
         assert s["r"] in (64, 128, 256, 512)
     assert batch_specs(seed=1) != a
+
+
+def test_vsa_points_layout():
+    from synth import ks_trajectory, vsa_initial_field, vsa_points
+
+    u0 = vsa_initial_field()
+    # leading four Fourier modes only, coefficient 0.6 (mean zero)
+    c = np.fft.fft(u0) / len(u0)
+    assert np.allclose(c[1:5].real, 0.6) and np.allclose(np.abs(c[5:-4]), 0, atol=1e-12)
+    assert abs(c[0]) < 1e-12
+    P = vsa_points(n_time=20, J=8, spinup=100, every=4)
+    assert P.shape == (20 * 64, 8) and P.dtype == np.float32
+    s = ks_trajectory(27, spinup=100, every=4, u0=u0, dtype=np.float64)
+    n, x = 5, 17
+    assert np.allclose(P[n * 64 + x], s[n:n + 8, x][::-1].astype(np.float32))
