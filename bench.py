@@ -33,7 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "end-to-end s at N=1e6,d=512,r=1024 vs plain FP64 GPU; % MFMA/HBM roofline"
-PEAK = {"hbm": 8000.0, "bf16": 2500.0, "f32": 157.3, "f64": 78.6}  # GB/s ; TFLOP/s
+PEAK = {"hbm": 8000.0, "bf16": 2500.0, "f16": 2500.0, "f32": 157.3, "f64": 78.6}  # GB/s ; TFLOP/s
 
 WORKLOADS = {
     "ks1m": dict(N=1_000_000, q=8, r=1024, b=128, nev=64, seed=0, kind="ks"),
@@ -119,8 +119,10 @@ def roofline(w, d, res, prof, steps, prec):
         "kernel_cols": (2.0 * N * dp * k, rounds * N * dp * xs + N * k * fs, prec[0]),
         "schur": (float(np.sum(2.0 * N * kb * nT)), float(np.sum(N * kb * fs + 2 * N * nT * fs)), prec[1]),
         "solve_downdate": (float(np.sum(1.0 * N * nT * nT)), float(np.sum(2 * N * nT * fs + 16 * N)), "f64"),
-        # both Grams over the k nonzero columns (symmetric: k (k + 1) / 2 dot products each)
-        "gram": (2.0 * N * k * (k + 1), 2.0 * N * k * fs, prec[2]),
+        # both Grams over the k nonzero columns (symmetric: k (k + 1) / 2 dot products each);
+        # the split-fp16 form takes three fp16 products per float32 product
+        "gram": (2.0 * N * k * (k + 1) * (3 if prec[2] == "split16" else 1), 2.0 * N * k * fs,
+                 "f16" if prec[2] == "split16" else prec[2]),
     }
     out = {}
     for name, (fl, by, dt) in work.items():
@@ -590,6 +592,8 @@ def main():
     ap.add_argument("--form", default="headline", choices=["headline", "surrogate", "batched", "paper"],
                     help="headline: the decomposition benchmark; surrogate: the learned extension; "
                          "batched: 512 small decompositions; paper: the paper's own VSA workload")
+    ap.add_argument("--gram", default="split16", choices=["f32", "split16"],
+                    help="arithmetic of the two N-long Gram products in the mixed form")
     ap.add_argument("--datasets", type=int, default=BATCH["datasets"])
     ap.add_argument("--sur-epochs", type=int, default=SUR["epochs"])
     args = ap.parse_args()
@@ -622,7 +626,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    mixed = ("bf16", "f32", "f32")
+    mixed = ("bf16", "f32", args.gram)
     plain = ("f64", "f64", "f64")
     log("[bench] mixed path")
     t_mixed, res_m, prof = timed(rp, torch, Xd, eps, ud, w, mixed, args.steps, args.warmup, profile=True)
@@ -650,7 +654,9 @@ def main():
         "config": {
             "workload": f"KS delay embedding N={w['N']} d={X.shape[1]} r={w['r']} b={w['b']} nev={w['nev']}"
                         if w["kind"] == "ks" else f"torus N={w['N']} r={w['r']} b={w['b']} nev={w['nev']}",
-            "precision": "bf16 products, fp32 factor/Schur/Gram tiles, fp64 pivots/solves/eig",
+            "precision": "bf16 products, fp32 factor/Schur tiles, "
+                         + ("fp32 Grams as split fp16 pairs" if args.gram == "split16" else "fp32 Gram tiles")
+                         + ", fp64 pivots/solves/eig",
             "eps": eps,
         },
         "plain_fp64_s": t_plain,

@@ -64,7 +64,11 @@ typedef enum {
   RPC_ENOCONV = -8      /* device: the small eigensolver hit its iteration limit */
 } rpc_status;
 
-typedef enum { RPC_F64 = 0, RPC_F32 = 1, RPC_BF16 = 2 } rpc_dtype;
+/* RPC_F32_SPLIT16: float32 data whose products run on the fp16 MFMA pipe,
+ * each operand split as hi = fp16(x) plus lo = fp16(x - hi) and each product
+ * taken as hi hi + hi lo + lo hi (float32-grade, about 2^-22 relative per
+ * product); accepted only as gram_dtype with a float32 factor. */
+typedef enum { RPC_F64 = 0, RPC_F32 = 1, RPC_BF16 = 2, RPC_F32_SPLIT16 = 3 } rpc_dtype;
 
 typedef enum {
   RPC_SAMPLED = 0, /* Algorithm 2: b iid proposals per round from rho / sum(rho) */
@@ -130,8 +134,10 @@ typedef struct {
  *             before the QR (the paper's stabilised QR); default 0.
  *  fix_const  if nonzero, U(:, 0) is set to 1/sqrt(N) and U re-orthonormalised
  *             by a QR with positive diag(R) (Algorithm 1, optional lines).
- *  gram_dtype F64 or F32: arithmetic of the two N-long Gram products
- *             (float64 accumulation across row chunks in both cases).
+ *  gram_dtype F64, F32 or F32_SPLIT16: arithmetic of the two N-long Gram
+ *             products (float64 accumulation across row chunks in all cases);
+ *             F32_SPLIT16 needs a float32 factor (RPC_EINVAL otherwise) and
+ *             is otherwise the F32 form (r x r stages, scales and U).
  *  u_dtype    F64 or F32 storage of U.
  *  normalization  RPC_BISTOCHASTIC (default), or RPC_SYMMETRIC: the
  *             eigenpairs of L~ = D~^{-1/2} K~ D~^{-1/2} (the paper's symmetric

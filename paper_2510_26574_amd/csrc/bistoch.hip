@@ -433,6 +433,7 @@ struct EigWs {
   double* delta;
   double* sk;
   double* skq;  // split-K partials of the r x p block product
+  float* gsc;   // per-chunk power-of-two scales of the split-fp16 Grams
   size_t part_cap;
   int p;
 };
@@ -474,6 +475,7 @@ static size_t carve_eig(WsCursor& c, EigWs& w, int64_t N, int r, int nev, bool f
   w.delta = c.take<double>(1);
   w.sk = c.take<double>((size_t)dense::SPLITK_MAX * p * p);
   w.skq = c.take<double>((size_t)dense::SPLITK_MAX * r * p);
+  w.gsc = c.take<float>(64);
   return c.used;
 }
 
@@ -520,8 +522,17 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   // C = (Q~^{-1/2} F)^T (Q~^{-1/2} F) (bistochastic) or C = I (symmetric)
   const int nz = sym ? 1 : 2;
   prof::begin(prof::GRAM, st);
-  syrk::gram2_partial<TG, TF>(st, F, ldf, N, r, nz, (const TG*)w.ssd, (const TG*)w.ssq, w.part,
-                              w.part1, k);
+  if constexpr (std::is_same<TG, float>::value && std::is_same<TF, float>::value) {
+    if (o->gram_dtype == RPC_F32_SPLIT16)
+      syrk::gram2_partial_split(st, F, ldf, N, r, nz, (const float*)w.ssd, (const float*)w.ssq,
+                                w.gsc, w.part, w.part1, k);
+    else
+      syrk::gram2_partial<TG, TF>(st, F, ldf, N, r, nz, (const TG*)w.ssd, (const TG*)w.ssq, w.part,
+                                  w.part1, k);
+  } else {
+    syrk::gram2_partial<TG, TF>(st, F, ldf, N, r, nz, (const TG*)w.ssd, (const TG*)w.ssq, w.part,
+                                w.part1, k);
+  }
   prof::end(prof::GRAM, st);
   const unsigned grr = nblk((int64_t)r * r);
   RPC_LAUNCH_CHECK();
@@ -711,7 +722,8 @@ static int check_eig_opts(int64_t N, int r, const rpc_eig_opts* o) {
   if (!o || N < 1 || r < 1 || r > N || r > 8192) return RPC_EINVAL;
   if (o->nev < 1 || o->nev > r) return RPC_EINVAL;
   if (r > dense::JMAX && o->nev > 64) return RPC_EINVAL;
-  if (o->gram_dtype != RPC_F64 && o->gram_dtype != RPC_F32) return RPC_EINVAL;
+  if (o->gram_dtype != RPC_F64 && o->gram_dtype != RPC_F32 && o->gram_dtype != RPC_F32_SPLIT16)
+    return RPC_EINVAL;
   if (o->u_dtype != RPC_F64 && o->u_dtype != RPC_F32) return RPC_EINVAL;
   if (o->fix_const && o->u_dtype != RPC_F64) return RPC_EINVAL;
   if (!(o->gamma >= 0.0)) return RPC_EINVAL;
@@ -764,6 +776,7 @@ extern "C" int bistoch_eig(const void* F, int32_t fdt, int64_t N, int64_t ldf, i
   if (!qt && !(o && o->normalization == RPC_SYMMETRIC)) return RPC_EINVAL;
   if (ldf < N || ldf % 8 != 0 || ldu < N || ldu % 8 != 0) return RPC_EINVAL;
   if (fdt != RPC_F64 && fdt != RPC_F32) return RPC_EINVAL;
+  if (o->gram_dtype == RPC_F32_SPLIT16 && fdt != RPC_F32) return RPC_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const bool g64 = o->gram_dtype == RPC_F64;
   const bool u64 = o->u_dtype == RPC_F64;

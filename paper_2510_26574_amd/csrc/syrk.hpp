@@ -259,7 +259,222 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_partial(const TF* __restrict__ 
       }
 }
 
-// G[i + j r] = sum over chunks of the partial tile holding (i, j) (or (j, i)).
+// ---------------------------------------------------------------------------
+// float32 Grams on the fp16 MFMA pipe.  Each scaled operand x (float32) is
+// split as hi = fp16(x), lo = fp16(x - hi), so x = hi + lo to 22 bits, and a
+// product x y is taken as hi_x hi_y + hi_x lo_y + lo_x hi_y (the dropped
+// lo_x lo_y is below 2^-22 |x y|); fp16 products are exact in the float32
+// accumulator.  This is the three-product fp32 emulation of Ootomo and
+// Yokota (2022), here on v_mfma_f32_16x16x32_f16, at three fp16 MFMAs per
+// float32 product instead of one float32 MFMA of a fifth of the rate.
+//
+// fp16 has a narrow exponent range, so every row chunk is multiplied by a
+// power of two 2^e (exact) chosen from the chunk's largest row scale so that
+// the scaled operands stay below 2^14; the chunk partial is multiplied by
+// 2^-2e on the way out.  This bounds the operands because the rows of the
+// factor have norm at most 1 (unit kernel diagonal minus a non-negative
+// residual); an operand beyond fp16 range turns into inf and surfaces as a
+// non-finite Gram, never as a silently wrong one.
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+constexpr int SPLIT_LDK = 64 + 8;  // halfs per staged column: 144 bytes puts the 16
+                                   // rows of a fragment read on distinct 16-byte slots
+
+// scl[z * nch + ch] = 2^e with max_{n in chunk} |s_z[n]| 2^e < 2^14 (1 when the
+// chunk's scales are all zero or s_z is null).
+__global__ __launch_bounds__(256) void k_split_scales(const float* __restrict__ s0,
+                                                      const float* __restrict__ s1, int64_t N,
+                                                      int64_t chunk, int nch,
+                                                      float* __restrict__ scl) {
+  const int z = blockIdx.x / nch, ch = blockIdx.x % nch;
+  const float* s = z ? s1 : s0;
+  const int64_t n0 = (int64_t)ch * chunk;
+  const int64_t n1 = n0 + chunk < N ? n0 + chunk : N;
+  float m = 0.0f;
+  if (s) {
+    for (int64_t n = n0 + threadIdx.x; n < n1; n += 256) m = fmaxf(m, fabsf(s[n]));
+  } else {
+    m = 1.0f;
+  }
+  __shared__ float red[256];
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float mx = red[0];
+    float sc = 1.0f;
+    if (mx > 0.0f && mx <= 3.0e38f) {
+      int e;
+      frexpf(mx, &e);  // mx < 2^e
+      int p = 14 - e;
+      p = p < -100 ? -100 : (p > 100 ? 100 : p);
+      sc = ldexpf(1.0f, p);
+    }
+    scl[blockIdx.x] = sc;
+  }
+}
+
+struct SplitLoader {
+  SyrkLoader<float, float> ld;  // 128 columns x 64 rows of float32 per stage
+  static constexpr int PER = SyrkLoader<float, float>::PER;
+  static constexpr int VPC = SyrkLoader<float, float>::VPC;
+  __device__ inline void load(const float* __restrict__ A, int64_t lda, int r, int c0,
+                              const float* __restrict__ s, int64_t n0, int64_t n1, int tid) {
+    ld.load(A, lda, r, c0, s, n0, n1, tid);
+  }
+  __device__ inline void store(_Float16* __restrict__ hi, _Float16* __restrict__ lo, float scale,
+                               int tid) const {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int vid = tid + p * NTH;
+      const int col = vid / VPC;
+      const int kv = (vid % VPC) * 4;
+      v4h h, l;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float x = ld.buf[p][e] * ld.sc[e] * scale;
+        const _Float16 xh = (_Float16)x;
+        h[e] = xh;
+        l[e] = (_Float16)(x - (float)xh);
+      }
+      *reinterpret_cast<v4h*>(hi + col * SPLIT_LDK + kv) = h;
+      *reinterpret_cast<v4h*>(lo + col * SPLIT_LDK + kv) = l;
+    }
+  }
+};
+
+// Same grid, chunking and partial layout as k_syrk_partial<float, float>.
+__global__ __launch_bounds__(NTH, 2) void k_syrk_split_partial(
+    const float* __restrict__ A, int64_t lda, int64_t N, int r, const float* __restrict__ s0,
+    const float* __restrict__ s1, const float* __restrict__ scl, int nz, int64_t chunk, int nch,
+    double* __restrict__ part0, double* __restrict__ part1, const int32_t* kptr) {
+  constexpr int BK = 64;
+  constexpr int LDK = SPLIT_LDK;
+  __shared__ __attribute__((aligned(16))) _Float16 Ah[2][TILE * LDK];
+  __shared__ __attribute__((aligned(16))) _Float16 Al[2][TILE * LDK];
+  __shared__ __attribute__((aligned(16))) _Float16 Bh[2][TILE * LDK];
+  __shared__ __attribute__((aligned(16))) _Float16 Bl[2][TILE * LDK];
+  const int nt = n_tiles(r);
+  const int nu = n_upper(nt);
+  const int groups = nz * nch;
+  const int xcd = blockIdx.x % 8;
+  const int slot = blockIdx.x / 8;
+  const int g = (slot / nu) * 8 + xcd;
+  if (g >= groups) return;
+  const int tile = slot % nu;
+  const int z = g / nch, ch = g % nch;
+  int ti, tj;
+  upper_decode(tile, nt, ti, tj);
+  const int kk = kptr ? *kptr : r;
+  if (tj * TILE >= kk) return;
+  const bool diag = ti == tj;
+  const float* s = z ? s1 : s0;
+  const float scale = scl[g];
+  double* out = (z ? part1 : part0) + ((int64_t)ch * nu + tile) * TILE * TILE;
+  const int64_t n0 = (int64_t)ch * chunk;
+  const int64_t n1 = n0 + chunk < N ? n0 + chunk : N;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  v4f acc[MI][NI];
+  double acc64[MI][NI][4];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        acc[i][j][e] = 0.0f;
+        acc64[i][j][e] = 0.0;
+      }
+  SplitLoader la, lb;
+  la.load(A, lda, r, ti * TILE, s, n0, n1, tid);
+  if (!diag) lb.load(A, lda, r, tj * TILE, s, n0, n1, tid);
+  la.store(Ah[0], Al[0], scale, tid);
+  if (!diag) lb.store(Bh[0], Bl[0], scale, tid);
+  __syncthreads();
+  int buf = 0;
+  int run = 0;
+  for (int64_t k0 = n0; k0 < n1; k0 += BK) {
+    const bool more = k0 + BK < n1;
+    if (more) {
+      la.load(A, lda, r, ti * TILE, s, k0 + BK, n1, tid);
+      if (!diag) lb.load(A, lda, r, tj * TILE, s, k0 + BK, n1, tid);
+    }
+    const _Float16* ah_s = Ah[buf];
+    const _Float16* al_s = Al[buf];
+    const _Float16* bh_s = diag ? Ah[buf] : Bh[buf];
+    const _Float16* bl_s = diag ? Al[buf] : Bl[buf];
+    // lane group g = lane / 16 takes k = kq + 8 g .. kq + 8 g + 7 on both operands
+#pragma unroll
+    for (int kq = 0; kq < BK; kq += 32) {
+      v8h ah[MI], al[MI], bh[NI], bl[NI];
+#pragma unroll
+      for (int i = 0; i < MI; ++i) {
+        const int o = (wm * WTM + i * 16 + (lane & 15)) * LDK + kq + 8 * (lane >> 4);
+        ah[i] = *reinterpret_cast<const v8h*>(ah_s + o);
+        al[i] = *reinterpret_cast<const v8h*>(al_s + o);
+      }
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        const int o = (wn * WTN + j * 16 + (lane & 15)) * LDK + kq + 8 * (lane >> 4);
+        bh[j] = *reinterpret_cast<const v8h*>(bh_s + o);
+        bl[j] = *reinterpret_cast<const v8h*>(bl_s + o);
+      }
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+      la.store(Ah[buf ^ 1], Al[buf ^ 1], scale, tid);
+      if (!diag) lb.store(Bh[buf ^ 1], Bl[buf ^ 1], scale, tid);
+    }
+    run += BK;
+    if (run >= FLUSH_ROWS) {
+      run = 0;
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            acc64[i][j][e] += (double)acc[i][j][e];
+            acc[i][j][e] = 0.0f;
+          }
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  const double unscale = 1.0 / ((double)scale * (double)scale);
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double v = (acc64[i][j][e] + (double)acc[i][j][e]) * unscale;
+        const int row = wm * WTM + i * 16 + 4 * (lane >> 4) + e;
+        const int col = wn * WTN + j * 16 + (lane & 15);
+        out[row + col * TILE] = v;
+      }
+}
+
+// G[i + j r] = sum over chunks of the partial tile entry (min(i,j), max(i,j)).
 __global__ __launch_bounds__(256) void k_syrk_reduce(const double* __restrict__ part, int nch, int r,
                                                      double* __restrict__ G, const int32_t* kptr) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -271,8 +486,11 @@ __global__ __launch_bounds__(256) void k_syrk_reduce(const double* __restrict__ 
     return;
   }
   const int nt = n_tiles(r), nu = n_upper(nt);
+  // both (i, j) and (j, i) read the upper-triangle entry, also inside a
+  // diagonal tile (whose two mirror entries were summed separately), so G is
+  // exactly symmetric
   int a = i, b = j;
-  if (i / TILE > j / TILE) {
+  if (i > j) {
     a = j;
     b = i;
   }
@@ -332,6 +550,22 @@ inline void gram2_partial(hipStream_t st, const TF* A, int64_t lda, int64_t N, i
   const unsigned blocks = (unsigned)(8 * ((groups + 7) / 8) * nu);
   hipLaunchKernelGGL((k_syrk_partial<T, TF>), dim3(blocks), dim3(NTH), 0, st, A, lda, N, r, s0, s1, nz,
                      chunk, nch, part0, part1, kptr);
+}
+
+// Split-fp16 form of gram2_partial for float32 operands and scales; scl
+// holds at least nz * nch floats (nch <= 32).
+inline void gram2_partial_split(hipStream_t st, const float* A, int64_t lda, int64_t N, int r,
+                                int nz, const float* s0, const float* s1, float* scl,
+                                double* part0, double* part1, const int32_t* kptr = nullptr) {
+  int nch;
+  int64_t chunk;
+  plan(N, nch, chunk, true);
+  const int nu = n_upper(n_tiles(r));
+  const int groups = nz * nch;
+  hipLaunchKernelGGL(k_split_scales, dim3(groups), dim3(256), 0, st, s0, s1, N, chunk, nch, scl);
+  const unsigned blocks = (unsigned)(8 * ((groups + 7) / 8) * nu);
+  hipLaunchKernelGGL(k_syrk_split_partial, dim3(blocks), dim3(NTH), 0, st, A, lda, N, r, s0, s1,
+                     (const float*)scl, nz, chunk, nch, part0, part1, kptr);
 }
 
 template <typename T>

@@ -201,15 +201,54 @@ def test_eig_fix_const(gpu):
 @pytest.mark.parametrize("gdt,fdt,gram,ltol,atol", [
     ("f32", "f32", "f32", 1e-6, 1e-4),
     ("bf16", "f32", "f32", 1e-3, 1e-2),
+    # the split-fp16 Gram keeps 22 of float32's 24 bits per operand (unit
+    # roundoff 2^-22 = 4 x float32's), so its bars are 4 x the float32 ones
+    ("f32", "f32", "split16", 4e-6, 4e-4),
+    ("bf16", "f32", "split16", 1e-3, 1e-2),
 ])
 def test_eig_reduced_precision(gpu, gdt, fdt, gram, ltol, atol):
     X, eps = _torus_case(seed=6) if gdt == "f32" else _ks_case(seed=6)
     nev = 16
     ref, out, deg, eig, res = _eig_case(gpu, X, eps, 64, 16, nev, seed=23, gdt=gdt, fdt=fdt, gram=gram)
     lam = eig["lam"].cpu().numpy()
-    assert np.abs(lam / res["lam"] - 1).max() < ltol
     m = _gap_index(res["lam_all"], nev)
-    assert _angle(eig["U"].cpu().numpy()[:, :m], res["U"][:, :m]) < atol
+    le = np.abs(lam / res["lam"] - 1).max()
+    ae = _angle(eig["U"].cpu().numpy()[:, :m], res["U"][:, :m])
+    print(f"{gdt}/{gram}: eigenvalue error {le:.3g}, angle {ae:.3g}")
+    assert le < ltol
+    assert ae < atol
+
+
+@pytest.mark.parametrize("gram,ltol,atol", [("f32", 1e-6, 1e-4), ("split16", 4e-6, 4e-4)])
+def test_float32_grams_many_chunks(gpu, gram, ltol, atol):
+    """The float32 Gram forms over 28 row chunks with a ragged last chunk and
+    a ragged last column tile (N = 40 003, r = 256, k = 192 accepted),
+    subspace-iteration eigensolver, against the oracle on its own pivots
+    (replayed)."""
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((40_003, 6)).astype(np.float32)
+    eps = median_sq_distance(X, seed=11)
+    nev = 24
+    ref, out, deg, eig, res = _eig_case(gpu, X, eps, 256, 32, nev, seed=26, gdt="f32", fdt="f32",
+                                        gram=gram)
+    assert ref["k"] > 128
+    lam = eig["lam"].cpu().numpy()
+    m = _gap_index(res["lam_all"], nev)
+    le = np.abs(lam / res["lam"] - 1).max()
+    ae = _angle(eig["U"].cpu().numpy()[:, :m], res["U"][:, :m])
+    print(f"{gram}: eigenvalue error {le:.3g}, angle {ae:.3g}")
+    assert le < ltol
+    assert ae < atol
+
+
+def test_split16_rejects_float64_factor(gpu):
+    torch, rp = gpu
+    X, eps = _torus_case(seed=5)
+    u = uniform_stream(2 * 8 * 4, seed=5)
+    out, k, F, piv, rho = _run_factor(gpu, X, eps, 32, 8, "sampled", u=u)
+    deg = rp.bistoch_degrees(out["F"], out["k"])
+    with pytest.raises(rp.RpcError):
+        rp.bistoch_eig(out["F"], out["k"], deg["d"], deg["q"], 4, gram_dtype="split16")
 
 
 def test_subspace_iteration_path(gpu):
