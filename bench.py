@@ -114,9 +114,18 @@ def roofline(w, d, res, prof, steps, prec):
     gsz = {"bf16": 2, "f32": 4, "f64": 8}
     xs, fs = gsz[prec[0]], gsz[prec[1]]
     rounds = len(nT)
+    # the columns kernel of the benchmark runs fused with the Schur update
+    # (W = K(X, X_S) - F F_S^T written once): its work is the distance product
+    # (2 N dp per column), the Schur product (2 N kb per column; three fp16
+    # products each when the distance product is bf16, which puts both on the
+    # 2.5 PFLOP/s pipe) and its bytes X per round, the F panel, W once
+    split = prec[0] == "bf16" and prec[1] == "f32"
+    schur_fl = float(np.sum(2.0 * N * kb * nT))
+    schur_by = float(np.sum(N * kb * fs))
     work = {
         # flops, bytes, bound-dtype
-        "kernel_cols": (2.0 * N * dp * k, rounds * N * dp * xs + N * k * fs, prec[0]),
+        "kernel_cols": (2.0 * N * dp * k + schur_fl * (3 if split else 1),
+                        rounds * N * dp * xs + schur_by + N * k * fs, prec[0]),
         "schur": (float(np.sum(2.0 * N * kb * nT)), float(np.sum(N * kb * fs + 2 * N * nT * fs)), prec[1]),
         "solve_downdate": (float(np.sum(1.0 * N * nT * nT)), float(np.sum(2 * N * nT * fs + 16 * N)), "f64"),
         # both Grams over the k nonzero columns (symmetric: k (k + 1) / 2 dot products each);

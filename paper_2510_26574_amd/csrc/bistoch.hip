@@ -623,7 +623,7 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   // ---- Z = R^{-1} V = S L'^{-T} V ;  U = D~^{-1} F Z
   hipLaunchKernelGGL(k_copy_cols, dim3(nblk((int64_t)r * nev)), dim3(256), 0, st,
                      (const double*)w.V, (int64_t)r, w.Z, (int64_t)r, r, nev, (const int32_t*)nullptr);
-  dense::trsm_lt(st, w.Gs, r, r, w.Z, r, nev);
+  dense::trsm_lt(st, w.Gs, r, r, w.Z, r, nev, w.sk);  // w.sk holds >= SPLITK_MAX NB nev doubles
   hipLaunchKernelGGL(k_scale_rows, dim3(nblk((int64_t)r * nev)), dim3(256), 0, st, w.Z, (int64_t)r,
                      r, nev, (const double*)w.s, 0);
   typedef FormUCfg<TG> CfgU;

@@ -236,35 +236,47 @@ inline void cholesky(hipStream_t st, double* A, int64_t ld, int n, int32_t* stat
 }
 
 // Diagonal block of the back substitution L^T X = B: rows i0..i0+nb of X
-// (n x m, column-major ldx) solve L_ii^T x = b.  One wave per column, lane l
-// holding x_l; each row costs one wave reduction.
+// (n x m, column-major ldx) solve L_ii^T x = b.  One wave per right-hand
+// side, lane l holding x_l, right-looking from the bottom: once row ii is
+// solved (x_ii = b_ii / L(ii,ii) on lane ii) it is broadcast and every lane
+// l < ii subtracts L(ii, l) x_ii, so a row costs one broadcast and one
+// multiply-add instead of a wave reduction.
 __global__ __launch_bounds__(1024) void k_trsm_ut_diag(const double* L, int64_t ld, int i0, int nb,
                                                        double* X, int64_t ldx, int m) {
-  __shared__ double Ls[NB * NB];
+  constexpr int LDS = NB + 1;  // lanes reading row ii of the block walk distinct banks
+  __shared__ double Ls[NB * LDS];
+  __shared__ double rd[NB];
   for (int e = threadIdx.x; e < nb * nb; e += 1024) {
     int i = e % nb, c = e / nb;
-    Ls[i + c * NB] = L[(i0 + i) + (int64_t)(i0 + c) * ld];
+    Ls[i + c * LDS] = L[(i0 + i) + (int64_t)(i0 + c) * ld];
   }
+  __syncthreads();
+  if (threadIdx.x < nb) rd[threadIdx.x] = 1.0 / Ls[threadIdx.x + threadIdx.x * LDS];
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = blockIdx.x * 16 + wave;
   if (col >= m) return;
   double* xc = X + i0 + (int64_t)col * ldx;
   double x = lane < nb ? xc[lane] : 0.0;
-  double sol = 0.0;
   for (int ii = nb - 1; ii >= 0; --ii) {
-    // (L^T)(ii, l) = L(l, ii), l > ii already solved
-    const double part = (lane > ii && lane < nb) ? Ls[lane + ii * NB] * sol : 0.0;
-    const double s = wave_sum(part);
-    const double v = (__shfl(x, ii, 64) - s) / Ls[ii + ii * NB];
-    if (lane == ii) sol = v;
+    const double xi = bcast_lane(x, ii) * rd[ii];
+    if (lane == ii) x = xi;
+    // (L^T)(l, ii) = L(ii, l)
+    if (lane < ii) x -= Ls[ii + lane * LDS] * xi;
   }
-  if (lane < nb) xc[lane] = sol;
+  if (lane < nb) xc[lane] = x;
 }
 
+template <bool KCA, bool KCB>
+inline void gemm64_splitk(hipStream_t st, int64_t M, int64_t N, int64_t K, const double* A,
+                          int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
+                          double alpha, double beta, double* part, const int32_t* skip = nullptr);
+
 // Solve L^T X = B in place (L lower n x n column-major; X n x m column-major).
+// `part` (SPLITK_MAX * NB * m doubles, or null) lets the block updates split
+// their long k range over several workgroups.
 inline void trsm_lt(hipStream_t st, const double* L, int64_t ld, int n, double* X, int64_t ldx,
-                    int m) {
+                    int m, double* part = nullptr) {
   const int nblk = (n + NB - 1) / NB;
   for (int ib = nblk - 1; ib >= 0; --ib) {
     const int i0 = ib * NB;
@@ -273,8 +285,12 @@ inline void trsm_lt(hipStream_t st, const double* L, int64_t ld, int n, double* 
     if (below > 0) {
       // X_i -= L[below, i]^T X_below :
       //   A(i, l) = L[(i0+nb+l) + (i0+i) ld],  B(col, l) = X[(i0+nb+l) + col ldx]
-      gemm64<true, true>(st, nb, m, below, L + (i0 + nb) + (int64_t)i0 * ld, ld, X + (i0 + nb), ldx,
-                         X + i0, ldx, -1.0, 1.0);
+      if (part)
+        gemm64_splitk<true, true>(st, nb, m, below, L + (i0 + nb) + (int64_t)i0 * ld, ld,
+                                  X + (i0 + nb), ldx, X + i0, ldx, -1.0, 1.0, part, nullptr);
+      else
+        gemm64<true, true>(st, nb, m, below, L + (i0 + nb) + (int64_t)i0 * ld, ld, X + (i0 + nb),
+                           ldx, X + i0, ldx, -1.0, 1.0);
     }
     hipLaunchKernelGGL(k_trsm_ut_diag, dim3((m + 15) / 16), dim3(1024), 0, st, L, ld, i0, nb, X,
                        ldx, m);
@@ -596,7 +612,7 @@ constexpr int SPLITK_MAX = 16;
 template <bool KCA, bool KCB>
 inline void gemm64_splitk(hipStream_t st, int64_t M, int64_t N, int64_t K, const double* A,
                           int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
-                          double alpha, double beta, double* part, const int32_t* skip = nullptr) {
+                          double alpha, double beta, double* part, const int32_t* skip) {
   if (M <= 0 || N <= 0) return;
   int splits = (int)((K + 63) / 64);
   if (splits > SPLITK_MAX) splits = SPLITK_MAX;

@@ -188,7 +188,11 @@ __device__ inline typename Cfg::MM::frag load_frag(const typename Cfg::T* s, int
 
 // acc += A(m0.., kb..ke) * B(n0.., kb..ke)^T over the k range [kb, ke).
 // smem must hold TileSmem<Cfg, KCA, KCB>::bytes.
-template <class Cfg, typename TGA, bool KCA, typename TGB, bool KCB>
+// LOWER_B: B(n, k) = 0 for k > n (a lower-triangular right factor, as in a
+// product with an inverse Cholesky factor): an MFMA whose k-step lies wholly
+// above its 16 columns, or whose columns are all past B's valid rows, is
+// skipped (a wave-uniform branch).
+template <class Cfg, typename TGA, bool KCA, typename TGB, bool KCB, bool LOWER_B = false>
 __device__ inline void tile_mainloop(TileAcc<Cfg>& acc, const GOperand<TGA, KCA>& A,
                                      const GOperand<TGB, KCB>& B, int64_t m0, int64_t n0,
                                      int64_t kb, int64_t ke, typename Cfg::T* smem) {
@@ -230,9 +234,14 @@ __device__ inline void tile_mainloop(TileAcc<Cfg>& acc, const GOperand<TGA, KCA>
       for (int j = 0; j < Cfg::NI; ++j)
         fb[j] = load_frag<Cfg, Cfg::BN, KCB>(Bs, wn * Cfg::WTN + j * 16 + (lane & 15), kk, lane);
 #pragma unroll
-      for (int i = 0; i < Cfg::MI; ++i)
+      for (int j = 0; j < Cfg::NI; ++j) {
+        if constexpr (LOWER_B) {
+          const int64_t c0 = n0 + wn * Cfg::WTN + j * 16;
+          if (k0 + kk >= c0 + 16 || c0 >= b.rows) continue;
+        }
 #pragma unroll
-        for (int j = 0; j < Cfg::NI; ++j) acc.a[i][j] = MM::mma(fa[i], fb[j], acc.a[i][j]);
+        for (int i = 0; i < Cfg::MI; ++i) acc.a[i][j] = MM::mma(fa[i], fb[j], acc.a[i][j]);
+      }
     }
     if (more) {
       T* nA = smem + (buf ^ 1) * SM::STAGE;
