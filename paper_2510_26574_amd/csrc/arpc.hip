@@ -459,30 +459,36 @@ __global__ __launch_bounds__(1024) void k_accept_reject(
   if (tid == 0) *nTptr = nt;
 }
 
-// L^{-1} of the accepted block, one workgroup (one wave) per column c:
-//   x_c = 1 / L(c,c),  x_j = -(sum_{l=c}^{j-1} L(j,l) x_l) / L(j,j),
-// lane l keeping x_l and x_{l+64}; each row costs one wave reduction.
+// L^{-1} of the accepted block, one workgroup (one wave) per column c, by
+// right-looking forward substitution L x = e_c: lane l keeps x_l and
+// x_{l+64}; once x_j = b_j / L(j,j) is known it is broadcast and every row
+// i > j subtracts L(i,j) x_j, so a row costs one broadcast and two
+// multiply-adds instead of a wave reduction.
 __global__ __launch_bounds__(64) void k_tri_inv(const double* __restrict__ Lc,
                                                 const int32_t* nTptr, double* __restrict__ Linv) {
-  constexpr int LDS = MAXB + 1;
+  constexpr int LDS = MAXB + 1;  // column walks (lane i reading L(i, j)) spread over banks
   __shared__ double Ls[MAXB * LDS];
+  __shared__ double rd[MAXB];
   const int c = blockIdx.x, lane = threadIdx.x;
   const int nt = *nTptr;
   double x0 = 0.0, x1 = 0.0;
   if (c < nt) {
     for (int j = c; j < nt; ++j)
       for (int l = c + lane; l <= j; l += 64) Ls[j * LDS + l] = Lc[j * MAXB + l];
+    for (int j = c + lane; j < nt; j += 64) rd[j] = 1.0 / Lc[j * MAXB + j];
     __syncthreads();
+    // b = e_c
+    if (lane == (c & 63)) {
+      if (c < 64) x0 = 1.0; else x1 = 1.0;
+    }
     for (int j = c; j < nt; ++j) {
-      double part = 0.0;
-      if (lane >= c && lane < j) part += Ls[j * LDS + lane] * x0;
-      if (lane + 64 >= c && lane + 64 < j) part += Ls[j * LDS + lane + 64] * x1;
-      const double sum = wave_sum(part);
-      const double ljj = Ls[j * LDS + j];
-      const double v = (j == c) ? 1.0 / ljj : -sum / ljj;
+      const double bj = bcast_lane(j < 64 ? x0 : x1, j & 63);
+      const double xj = bj * rd[j];
       if (lane == (j & 63)) {
-        if (j < 64) x0 = v; else x1 = v;
+        if (j < 64) x0 = xj; else x1 = xj;
       }
+      if (lane > j && lane < nt) x0 -= Ls[lane * LDS + j] * xj;
+      if (lane + 64 > j && lane + 64 < nt) x1 -= Ls[(lane + 64) * LDS + j] * xj;
     }
   }
   Linv[lane * MAXB + c] = x0;

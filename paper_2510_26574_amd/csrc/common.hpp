@@ -90,6 +90,14 @@ __device__ inline double to_d(T x) { return (double)x; }
 template <>
 __device__ inline double to_d<__bf16>(__bf16 x) { return (double)(float)x; }
 
+// Broadcast lane `src` (wave-uniform) of a double held in a VGPR pair.
+__device__ inline double bcast_lane(double v, int src) {
+  const unsigned long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffull), src);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
 // ------------------------------------------------------ wave reductions
 __device__ inline double wave_sum(double v) {
 #pragma unroll

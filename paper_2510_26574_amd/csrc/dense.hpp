@@ -95,14 +95,6 @@ __device__ inline void chol_block_lds(double* a, int n, int lda_s, double* piv, 
   __syncthreads();
 }
 
-// Broadcast lane `src` (wave-uniform) of a double held in a VGPR pair.
-__device__ inline double bcast_lane(double v, int src) {
-  const unsigned long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffull), src);
-  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
-  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-
 // Same factorisation (L with the square roots applied, lower triangle of `a`)
 // for n <= 128 + 8, blocked by panels of 8 columns: wave 0 loads a panel
 // into registers (lane l holds panel rows j0 + l and j0 + l + 64), factors it
