@@ -899,6 +899,214 @@ __global__ __launch_bounds__(SolveCfg::NT) void k_solve_downdate(const TF* __res
   }
 }
 
+// ------------------------------------------------------------ split-fp16 solve
+// Mixed form (bf16 distance product, float32 factor): G = W L^{-T} on the
+// fp16 MFMA pipe as split pairs (three products per float32 product).  W
+// already carries the bf16 kernel-entry error, which the solve amplifies by
+// |L^{-1}| like any rounding in W, so the 2^-22 product error of the split
+// form stays below it.
+//
+// k_split_linv: one workgroup scales L^{-1} (MAXB x MAXB, row-major [n][k],
+// zero past nT) by the power of two 2^e that puts its largest magnitude
+// below 2^14 and writes the hi/lo fp16 halves and 2^e.
+__global__ __launch_bounds__(256) void k_split_linv(const double* __restrict__ Linv,
+                                                    const int32_t* nTptr, _Float16* __restrict__ Lh,
+                                                    _Float16* __restrict__ Ll, float* __restrict__ lsc) {
+  __shared__ double red[256];
+  const int nt = *nTptr;
+  double m = 0.0;
+  for (int e = threadIdx.x; e < MAXB * MAXB; e += 256) {
+    const int n = e / MAXB, k = e % MAXB;
+    if (n < nt && k < nt) m = fmax(m, fabs(Linv[e]));
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  const double mx = red[0];
+  double sc = 1.0;
+  if (mx > 0.0 && mx < 1e300) {
+    int ex;
+    frexp(mx, &ex);  // mx < 2^ex
+    int q = 14 - ex;
+    q = q < -100 ? -100 : (q > 100 ? 100 : q);
+    sc = ldexp(1.0, q);
+  }
+  for (int e = threadIdx.x; e < MAXB * MAXB; e += 256) {
+    const int n = e / MAXB, k = e % MAXB;
+    const double x = (n < nt && k < nt) ? Linv[e] * sc : 0.0;
+    const _Float16 h = (_Float16)x;
+    Lh[e] = h;
+    Ll[e] = (_Float16)(x - (double)h);
+  }
+  if (threadIdx.x == 0) lsc[0] = (float)sc;
+}
+
+// F(:, k + j) = G(:, j) and rho -= rownorms(G)^2 like k_solve_downdate, with
+// G from split pairs.  k (<= MAXB) runs in two halves of 64: W (float32,
+// scaled by 2^12; |W| <= 1 up to rounding since it is a residual kernel) and
+// the pre-split L^{-1} are staged as [row][k] fp16 pairs in one LDS buffer
+// (SolveSplit::bytes, which lets two workgroups share a CU), the second
+// half's reads in flight while the first half's MFMAs run.
+struct SolveSplit {
+  static constexpr int BK = 64;
+  static constexpr int LDK = BK + 8;  // 144-byte rows: fragment reads on distinct 16-byte slots
+  static constexpr int EL = MAXB * LDK;
+  static constexpr size_t bytes = 4 * (size_t)EL * sizeof(_Float16);
+};
+typedef TileCfg<__bf16, 128, 128, 64, 4, 2> SolveSplitCfg;  // fp32 accumulators, 8 waves of 32 x 64
+
+__global__ __launch_bounds__(512, 2) void k_solve_split(const float* __restrict__ W, int64_t ldw,
+                                                        int64_t N, const _Float16* __restrict__ Lh,
+                                                        const _Float16* __restrict__ Ll,
+                                                        const float* __restrict__ lsc,
+                                                        const int32_t* kptr, const int32_t* nTptr,
+                                                        float* __restrict__ F, int64_t ldf,
+                                                        double* __restrict__ rho) {
+  typedef SolveSplitCfg Cfg;
+  static_assert(Cfg::NT == 512 && Cfg::BM == MAXB && Cfg::BN == MAXB, "one 128 x 128 tile");
+  constexpr int BK = SolveSplit::BK, LDK = SolveSplit::LDK, EL = SolveSplit::EL;
+  const int nt = *nTptr;
+  if (nt == 0) return;
+  const int k = *kptr;
+  extern __shared__ char smem_raw[];
+  _Float16* sm = reinterpret_cast<_Float16*>(smem_raw);
+  __shared__ double red[Cfg::WAVES_N][Cfg::BM];
+  const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int arow = tid & 127, ag = tid >> 7;  // A: row, k groups ag and ag + 4 of a half
+  const int brow = tid >> 2, bg = tid & 3;    // B: row, k groups bg and bg + 4 of a half
+  const int64_t am = m0 + arow;
+  float a0[2][8], a1[2][8];
+  v8h_t bh0[2], bl0[2], bh1[2], bl1[2];
+  auto load = [&](float (&a)[2][8], v8h_t (&bh)[2], v8h_t (&bl)[2], int kb) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k0 = kb + 8 * (ag + 4 * h);
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        a[h][e] = (am < N && k0 + e < nt) ? W[am + (int64_t)(k0 + e) * ldw] : 0.0f;
+      const int kk0 = kb + 8 * (bg + 4 * h);
+      bh[h] = *reinterpret_cast<const v8h_t*>(Lh + brow * MAXB + kk0);
+      bl[h] = *reinterpret_cast<const v8h_t*>(Ll + brow * MAXB + kk0);
+    }
+  };
+  auto store = [&](const float (&a)[2][8], const v8h_t (&bh)[2], const v8h_t (&bl)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      v8h_t hi, lo;
+      split8(a[h], hi, lo);
+      const int o = arow * LDK + 8 * (ag + 4 * h);
+      *reinterpret_cast<v8h_t*>(sm + o) = hi;
+      *reinterpret_cast<v8h_t*>(sm + EL + o) = lo;
+      const int ob = brow * LDK + 8 * (bg + 4 * h);
+      *reinterpret_cast<v8h_t*>(sm + 2 * EL + ob) = bh[h];
+      *reinterpret_cast<v8h_t*>(sm + 3 * EL + ob) = bl[h];
+    }
+  };
+  const int wm = wave % Cfg::WAVES_M, wn = wave / Cfg::WAVES_M;
+  TileAcc<Cfg> acc;
+  acc.zero();
+  auto compute = [&](int kb) {
+    const int ke = nt - kb < BK ? nt - kb : BK;
+    for (int kq = 0; kq < ke; kq += 32) {
+      v8h_t ah[Cfg::MI], al[Cfg::MI], fh[Cfg::NI], fl[Cfg::NI];
+#pragma unroll
+      for (int i = 0; i < Cfg::MI; ++i) {
+        const int o = (wm * Cfg::WTM + i * 16 + (lane & 15)) * LDK + kq + 8 * (lane >> 4);
+        ah[i] = *reinterpret_cast<const v8h_t*>(sm + o);
+        al[i] = *reinterpret_cast<const v8h_t*>(sm + EL + o);
+      }
+#pragma unroll
+      for (int j = 0; j < Cfg::NI; ++j) {
+        const int o = (wn * Cfg::WTN + j * 16 + (lane & 15)) * LDK + kq + 8 * (lane >> 4);
+        fh[j] = *reinterpret_cast<const v8h_t*>(sm + 2 * EL + o);
+        fl[j] = *reinterpret_cast<const v8h_t*>(sm + 3 * EL + o);
+      }
+#pragma unroll
+      for (int j = 0; j < Cfg::NI; ++j) {
+        // L^{-1} is lower triangular: columns c0 .. c0 + 15 need k <= c0 + 15
+        const int c0 = wn * Cfg::WTN + j * 16;
+        if (kb + kq >= c0 + 16 || c0 >= nt) continue;
+#pragma unroll
+        for (int i = 0; i < Cfg::MI; ++i) {
+          acc.a[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], fh[j], acc.a[i][j], 0, 0, 0);
+          acc.a[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], fl[j], acc.a[i][j], 0, 0, 0);
+          acc.a[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], fh[j], acc.a[i][j], 0, 0, 0);
+        }
+      }
+    }
+  };
+  load(a0, bh0, bl0, 0);
+  if (nt > BK) load(a1, bh1, bl1, BK);
+  store(a0, bh0, bl0);
+  __syncthreads();
+  compute(0);
+  if (nt > BK) {
+    __syncthreads();
+    store(a1, bh1, bl1);
+    __syncthreads();
+    compute(BK);
+  }
+  // unscale; each lane holds rows 4 (lane / 16) .. + 3 of one column per
+  // 16 x 16 block, stored as one 16-byte write (ldf and the row offset are
+  // multiples of 4)
+  const float un = 1.0f / (SchurSplit::SC * lsc[0]);  // both factors are powers of two
+#pragma unroll
+  for (int j = 0; j < Cfg::NI; ++j)
+#pragma unroll
+    for (int i = 0; i < Cfg::MI; ++i) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc.a[i][j][e] *= un;
+      const int row = wm * Cfg::WTM + i * 16 + 4 * (lane >> 4);
+      const int col = wn * Cfg::WTN + j * 16 + (lane & 15);
+      const int64_t m = m0 + row;
+      if (col < nt) {
+        float* dst = F + m + (int64_t)(k + col) * ldf;
+        if (m + 4 <= N) {
+          *reinterpret_cast<v4f*>(dst) = acc.a[i][j];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (m + e < N) dst[e] = acc.a[i][j][e];
+        }
+      }
+    }
+  // squared row norms of G (float64 sums), reduced as in k_solve_downdate
+#pragma unroll
+  for (int i = 0; i < Cfg::MI; ++i) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      double sq = 0.0;
+#pragma unroll
+      for (int j = 0; j < Cfg::NI; ++j) {
+        const int col = wn * Cfg::WTN + j * 16 + (lane & 15);
+        const double g = col < nt ? (double)acc.a[i][j][e] : 0.0;
+        sq += g * g;
+      }
+      sq += __shfl_xor(sq, 1, 64);
+      sq += __shfl_xor(sq, 2, 64);
+      sq += __shfl_xor(sq, 4, 64);
+      sq += __shfl_xor(sq, 8, 64);
+      const int row = wm * Cfg::WTM + i * 16 + Cfg::MM::row(lane, e);
+      if ((lane & 15) == 0) red[wn][row] = sq;
+    }
+  }
+  __syncthreads();
+  for (int row = tid; row < Cfg::BM; row += Cfg::NT) {
+    const int64_t m = m0 + row;
+    if (m < N) {
+      double sq = 0.0;
+#pragma unroll
+      for (int h = 0; h < Cfg::WAVES_N; ++h) sq += red[h][row];
+      const double v = rho[m] - sq;
+      rho[m] = v > 0.0 ? v : 0.0;
+    }
+  }
+}
+
 __global__ void k_round_end(const int64_t* __restrict__ Si, int32_t* kptr, const int32_t* nTptr,
                             double* __restrict__ rho, int32_t* round_acc, int round) {
   const int nt = *nTptr;
@@ -939,6 +1147,9 @@ struct FactorWs {
   double* H;
   double* Lc;
   double* Linv;
+  _Float16* Lh;  // split-fp16 halves of L^{-1} and their power-of-two scale
+  _Float16* Ll;
+  float* lsc;
   int64_t* Si;
   void* XSa;
   void* nsa;
@@ -968,6 +1179,9 @@ static size_t carve(WsCursor& c, FactorWs& w, int64_t N, int64_t d, int r) {
   w.H = c.take<double>((size_t)MAXB * MAXB);
   w.Lc = c.take<double>((size_t)MAXB * MAXB);
   w.Linv = c.take<double>((size_t)MAXB * MAXB);
+  w.Lh = c.take<_Float16>((size_t)MAXB * MAXB);
+  w.Ll = c.take<_Float16>((size_t)MAXB * MAXB);
+  w.lsc = c.take<float>(1);
   w.Si = c.take<int64_t>(MAXB);
   w.XSa = c.take<T>((size_t)MAXB * w.dp);
   w.nsa = c.take<TN>(MAXB);
@@ -1083,9 +1297,19 @@ static int run_factor(const rpc_points* X, const rpc_factor_opts* o, TF* F, int6
       RPC_LAUNCH_CHECK();
     }
     prof::begin(prof::SOLVE, st);
-    hipLaunchKernelGGL((k_solve_downdate<TF>), dim3((unsigned)((N + CfgD::BM - 1) / CfgD::BM)),
-                       dim3(CfgD::NT), smD, st,
-                       (const TF*)w.W, w.ldw, N, w.Linv, k_out, w.nT, F, ldf, rho);
+    if constexpr (std::is_same<T, __bf16>::value && std::is_same<TF, float>::value) {
+      // mixed form: the solve on the fp16 pipe as split pairs
+      hipLaunchKernelGGL(k_split_linv, dim3(1), dim3(256), 0, st, (const double*)w.Linv, w.nT, w.Lh,
+                         w.Ll, w.lsc);
+      hipLaunchKernelGGL(k_solve_split, dim3((unsigned)((N + MAXB - 1) / MAXB)), dim3(512),
+                         SolveSplit::bytes, st, (const float*)w.W, w.ldw, N, (const _Float16*)w.Lh,
+                         (const _Float16*)w.Ll, (const float*)w.lsc, k_out, w.nT, (float*)F, ldf,
+                         rho);
+    } else {
+      hipLaunchKernelGGL((k_solve_downdate<TF>), dim3((unsigned)((N + CfgD::BM - 1) / CfgD::BM)),
+                         dim3(CfgD::NT), smD, st,
+                         (const TF*)w.W, w.ldw, N, w.Linv, k_out, w.nT, F, ldf, rho);
+    }
     RPC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_round_end, dim3(1), dim3(MAXB), 0, st, w.Si, k_out, w.nT, rho,
                        o->round_accepted, i);
