@@ -22,6 +22,7 @@
 
 #include "common.hpp"
 #include "profile.hpp"
+#include "split16.hpp"
 #include "tile_gemm.hpp"
 
 namespace {
@@ -29,6 +30,7 @@ namespace {
 constexpr int CHUNK = 4096;  // rho entries per partial sum (pivot draw)
 constexpr int MAXB = 128;    // largest supported block size
 constexpr int kStages = 4;   // LDS stages of the direct-staged products (three in flight)
+constexpr int kStagesSplit = 2;  // the mixed form's fused kernel: two workgroups per CU
 constexpr double QSCALE = 1099511627776.0;  // 2^40
 
 __device__ inline unsigned long long quant_rho(double r) {
@@ -56,13 +58,34 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, int64
   if (n >= N) return;
   double s = 0.0;
   bool bad = false;
-  for (int64_t j = lane; j < dp; j += 64) {
-    float v = j < d ? X[n * ldx + j] : 0.0f;
-    if (!isfinite(v)) bad = true;
-    T c = cvt<T>(v);
-    Xp[n * dp + j] = c;
-    double cd = to_d(c);
-    s += cd * cd;
+  // rows without padding, 8-float aligned: each lane converts 8 consecutive
+  // columns per pass with two 16-byte loads and one vector store
+  const bool vec = d == dp && (ldx % 8) == 0 && (((uintptr_t)X) & 31) == 0;
+  if (vec) {
+    typedef T tv __attribute__((ext_vector_type(8)));
+    for (int64_t j0 = (int64_t)lane * 8; j0 < dp; j0 += 512) {
+      const v4f u0 = *reinterpret_cast<const v4f*>(X + n * ldx + j0);
+      const v4f u1 = *reinterpret_cast<const v4f*>(X + n * ldx + j0 + 4);
+      tv c;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float v = e < 4 ? u0[e] : u1[e - 4];
+        if (!isfinite(v)) bad = true;
+        c[e] = cvt<T>(v);
+        const double cd = to_d(c[e]);
+        s += cd * cd;
+      }
+      *reinterpret_cast<tv*>(Xp + n * dp + j0) = c;
+    }
+  } else {
+    for (int64_t j = lane; j < dp; j += 64) {
+      float v = j < d ? X[n * ldx + j] : 0.0f;
+      if (!isfinite(v)) bad = true;
+      T c = cvt<T>(v);
+      Xp[n * dp + j] = c;
+      double cd = to_d(c);
+      s += cd * cd;
+    }
   }
   s = wave_sum(s);
   if (__any(bad) && lane == 0) set_status(status, RPC_ENONFINITE);
@@ -553,179 +576,6 @@ __global__ __launch_bounds__(Cfg::NT) void k_schur(const TF* __restrict__ F, int
   });
 }
 
-// ------------------------------------------------------------ split-fp16 Schur product
-// acc += 2^24 F(m0:m0+128, :k) FSa(:nt, :k)^T on the fp16 MFMA pipe, for a
-// float32 factor.  Each operand element x is scaled by 2^12 (exact; |x| <= 1
-// because the rows of F have norm at most 1) and split into hi = fp16(x) and
-// lo = fp16(x - hi); a product is taken as hi hi + hi lo + lo hi (unit
-// roundoff 2^-22, the three-product float32 emulation of Ootomo and Yokota,
-// 2022), at three fp16 MFMAs per product against one float32 MFMA of a fifth
-// of the rate.  The 16x16x32 fp16 MFMA shares its accumulator layout with the
-// bf16 one of the kernel-column product.
-//
-// Staging through registers, double buffered, 64 k per stage:
-//   A (F, column-major): thread t holds row t % 128 at k groups t / 128 and
-//     t / 128 + 4 (8 consecutive k each; every load is a 256-byte row run
-//     across the wave);
-//   B (FSa, k-contiguous rows): thread t holds row t / 4 at k groups t % 4
-//     and t % 4 + 4;
-// both land in LDS as [row][k] fp16 pairs (hi and lo arrays, 144-byte rows),
-// so every MFMA operand is one 16-byte read.
-struct SchurSplit {
-  static constexpr int BK = 64;
-  static constexpr int LDK = BK + 8;
-  static constexpr int ELEMS = 128 * LDK;
-  static constexpr size_t bytes = 2 * 4 * (size_t)ELEMS * sizeof(_Float16);
-  static constexpr float SC = 4096.0f;  // 2^12 per operand
-};
-typedef _Float16 v8h_t __attribute__((ext_vector_type(8)));
-
-__device__ inline void split8(const float (&x)[8], v8h_t& hi, v8h_t& lo) {
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const float v = x[e] * SchurSplit::SC;
-    const _Float16 h = (_Float16)v;
-    hi[e] = h;
-    lo[e] = (_Float16)(v - (float)h);
-  }
-}
-
-// Register ring of two stages: the global reads of stage s + 2 are issued
-// while the MFMAs consume stage s, and stage s + 1 is converted into LDS after
-// them.  begin() issues the reads of the first two stages, so a caller can
-// overlap their latency with other work before run().
-template <class Cfg>
-struct SchurSplitPipe {
-  static_assert(Cfg::NT == 512 && Cfg::BM == 128 && Cfg::BN == 128, "eight waves, 128 x 128");
-  static constexpr int BK = SchurSplit::BK, LDK = SchurSplit::LDK, EL = SchurSplit::ELEMS;
-  const float* __restrict__ F;
-  int64_t ldf, N;
-  const float* __restrict__ FSa;
-  int r, nt, k;
-  int64_t m0;
-  float a0[2][8], b0[2][8], a1[2][8], b1[2][8];
-
-  __device__ inline void load(float (&a)[2][8], float (&b)[2][8], int kb) const {
-    const int tid = threadIdx.x;
-    const int arow = tid & 127, ag = tid >> 7;
-    const int brow = tid >> 2, bg = tid & 3;
-    const int64_t am = m0 + arow;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k0 = kb + 8 * (ag + 4 * h);
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-        a[h][e] = (am < N && k0 + e < k) ? F[am + (int64_t)(k0 + e) * ldf] : 0.0f;
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k0 = kb + 8 * (bg + 4 * h);
-      const float* p = FSa + (int64_t)brow * r + k0;
-      if (brow < nt && k0 + 8 <= k && (r % 4) == 0) {
-        const v4f u = *reinterpret_cast<const v4f*>(p);
-        const v4f w = *reinterpret_cast<const v4f*>(p + 4);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          b[h][e] = u[e];
-          b[h][4 + e] = w[e];
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) b[h][e] = (brow < nt && k0 + e < k) ? p[e] : 0.0f;
-      }
-    }
-  }
-
-  __device__ inline void store(const float (&a)[2][8], const float (&b)[2][8], _Float16* sm,
-                               int buf) const {
-    const int tid = threadIdx.x;
-    const int arow = tid & 127, ag = tid >> 7;
-    const int brow = tid >> 2, bg = tid & 3;
-    _Float16* base = sm + (size_t)buf * 4 * EL;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      v8h_t hi, lo;
-      split8(a[h], hi, lo);
-      const int o = arow * LDK + 8 * (ag + 4 * h);
-      *reinterpret_cast<v8h_t*>(base + o) = hi;
-      *reinterpret_cast<v8h_t*>(base + EL + o) = lo;
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      v8h_t hi, lo;
-      split8(b[h], hi, lo);
-      const int o = brow * LDK + 8 * (bg + 4 * h);
-      *reinterpret_cast<v8h_t*>(base + 2 * EL + o) = hi;
-      *reinterpret_cast<v8h_t*>(base + 3 * EL + o) = lo;
-    }
-  }
-
-  __device__ inline void compute(TileAcc<Cfg>& acc, const _Float16* sm, int buf) const {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave % Cfg::WAVES_M, wn = wave / Cfg::WAVES_M;
-    if (wn * Cfg::WTN >= nt) return;  // this wave's columns are all beyond the block
-    const _Float16* base = sm + (size_t)buf * 4 * EL;
-#pragma unroll
-    for (int kq = 0; kq < BK; kq += 32) {
-      v8h_t ah[Cfg::MI], al[Cfg::MI], bh[Cfg::NI], bl[Cfg::NI];
-#pragma unroll
-      for (int i = 0; i < Cfg::MI; ++i) {
-        const int o = (wm * Cfg::WTM + i * 16 + (lane & 15)) * LDK + kq + 8 * (lane >> 4);
-        ah[i] = *reinterpret_cast<const v8h_t*>(base + o);
-        al[i] = *reinterpret_cast<const v8h_t*>(base + EL + o);
-      }
-#pragma unroll
-      for (int j = 0; j < Cfg::NI; ++j) {
-        const int o = (wn * Cfg::WTN + j * 16 + (lane & 15)) * LDK + kq + 8 * (lane >> 4);
-        bh[j] = *reinterpret_cast<const v8h_t*>(base + 2 * EL + o);
-        bl[j] = *reinterpret_cast<const v8h_t*>(base + 3 * EL + o);
-      }
-#pragma unroll
-      for (int i = 0; i < Cfg::MI; ++i)
-#pragma unroll
-        for (int j = 0; j < Cfg::NI; ++j)
-          acc.a[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc.a[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < Cfg::MI; ++i)
-#pragma unroll
-        for (int j = 0; j < Cfg::NI; ++j)
-          acc.a[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl[j], acc.a[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < Cfg::MI; ++i)
-#pragma unroll
-        for (int j = 0; j < Cfg::NI; ++j)
-          acc.a[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh[j], acc.a[i][j], 0, 0, 0);
-    }
-  }
-
-  __device__ inline void begin() {
-    load(a0, b0, 0);
-    if (BK < k) load(a1, b1, BK);
-  }
-
-  // acc += 2^24 F(m0.., :k) FSa(:nt, :k)^T; begin() must have been called.
-  __device__ inline void run(TileAcc<Cfg>& acc, char* smem_raw) {
-    _Float16* sm = reinterpret_cast<_Float16*>(smem_raw);
-    const int ns = (k + BK - 1) / BK;
-    __syncthreads();  // the LDS may still be read by the preceding product
-    store(a0, b0, sm, 0);
-    __syncthreads();
-    // stage s sits in LDS buffer s & 1; even stages pass through (a0, b0),
-    // odd ones through (a1, b1)
-    for (int s = 0; s < ns; s += 2) {
-      if (s + 2 < ns) load(a0, b0, (s + 2) * BK);
-      compute(acc, sm, 0);
-      if (s + 1 < ns) store(a1, b1, sm, 1);
-      __syncthreads();
-      if (s + 1 >= ns) break;
-      if (s + 3 < ns) load(a1, b1, (s + 3) * BK);
-      compute(acc, sm, 1);
-      if (s + 2 < ns) store(a0, b0, sm, 0);
-      __syncthreads();
-    }
-  }
-};
-
 // ------------------------------------------------------------ fused columns + Schur
 // When the distance product and the Schur update accumulate in the same
 // register layout (bf16/f32 products with an f32 factor, or f64 with f64),
@@ -733,8 +583,11 @@ struct SchurSplitPipe {
 // exp epilogue in registers, and continues accumulating -F(:, :k) F(S_i, :k)^T
 // into the same accumulators: W is written once instead of written, read
 // and written again.
+// SPLIT: the mixed form's variant, sized for two workgroups per CU (four
+// waves per SIMD: at most 128 VGPRs; two
+// direct stages for the distance product, the single-buffer split Schur).
 template <typename T, typename TN, typename TF, class CfgK, class CfgS, bool SPLIT>
-__global__ __launch_bounds__(CfgK::NT) void k_cols_schur(const T* __restrict__ Xp,
+__global__ __launch_bounds__(CfgK::NT, SPLIT ? 4 : 1) void k_cols_schur(const T* __restrict__ Xp,
                                                     const TN* __restrict__ xn, int64_t N,
                                                     int64_t dp, const T* __restrict__ XSa,
                                                     const TN* __restrict__ nsa,
@@ -758,15 +611,15 @@ __global__ __launch_bounds__(CfgK::NT) void k_cols_schur(const T* __restrict__ X
   {
     GOperand<T, true> A{Xp, dp, N, dp, nullptr, true};
     GOperand<T, true> B{XSa, dp, nt, dp, nullptr, true};
-    tile_mainloop_direct<CfgK, kStages>(acc, A, B, m0, 0, 0, dp, N, MAXB,
-                                        reinterpret_cast<typename CfgK::T*>(smem_raw), nt,
-                                        (int)blockIdx.x);
+    tile_mainloop_direct<CfgK, SPLIT ? kStagesSplit : kStages>(
+        acc, A, B, m0, 0, 0, dp, N, MAXB, reinterpret_cast<typename CfgK::T*>(smem_raw), nt,
+        (int)blockIdx.x);
   }
   // split form: the first two stages of the Schur reads go out before the
   // exp epilogue, which hides their latency
   SchurSplitPipe<CfgK> pipe{(const float*)F, ldf, N, (const float*)FSa, r, nt, k, m0};
   if constexpr (SPLIT) {
-    if (k > 0) pipe.begin();
+    if (k > 0) pipe.begin1();
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave % CfgK::WAVES_M, wn = wave / CfgK::WAVES_M;
@@ -799,7 +652,7 @@ __global__ __launch_bounds__(CfgK::NT) void k_cols_schur(const T* __restrict__ X
         for (int j = 0; j < CfgK::NI; ++j)
 #pragma unroll
           for (int e = 0; e < 4; ++e) acc.a[i][j][e] *= 16777216.0f;
-      pipe.run(acc, smem_raw);
+      pipe.run1(acc, smem_raw);
 #pragma unroll
       for (int i = 0; i < CfgK::MI; ++i)
 #pragma unroll
@@ -1273,9 +1126,15 @@ static int run_factor(const rpc_points* X, const rpc_factor_opts* o, TF* F, int6
         fused = true;
         prof::begin(prof::KERNEL_COLS, st);
         constexpr bool split = std::is_same<T, __bf16>::value && std::is_same<TF, float>::value;
-        static_assert(!split || SchurSplit::bytes <= DirectSmem<CfgK, kStages, true, true>::bytes,
-                      "the split Schur stages fit the columns' LDS");
-        hipLaunchKernelGGL((k_cols_schur<T, TN, TF, CfgK, CfgS, split>), dim3(gm), dim3(CfgK::NT), smKS, st,
+        // the split variant needs the larger of two direct stages, one split
+        // Schur buffer and the column-store staging (two workgroups per CU)
+        constexpr size_t smSplit0 = DirectSmem<CfgK, kStagesSplit, true, true>::bytes;
+        constexpr size_t smSplit1 = SchurSplit::bytes / 2 > ColStoreSmem<CfgK, TF>::bytes
+                                        ? SchurSplit::bytes / 2 : ColStoreSmem<CfgK, TF>::bytes;
+        constexpr size_t smSplit = smSplit0 > smSplit1 ? smSplit0 : smSplit1;
+        static_assert(!split || 2 * smSplit <= 160 * 1024, "two workgroups per CU");
+        hipLaunchKernelGGL((k_cols_schur<T, TN, TF, CfgK, CfgS, split>), dim3(gm), dim3(CfgK::NT),
+                           split ? smSplit : smKS, st,
                            (const T*)w.Xp, (const TN*)w.xn, N, dp, (const T*)w.XSa,
                            (const TN*)w.nsa, w.nT, X->eps, (const TF*)F, ldf, (const TF*)w.FSa, r,
                            k_out, (TF*)w.W, w.ldw);

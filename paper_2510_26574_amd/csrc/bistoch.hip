@@ -20,6 +20,7 @@
 #include "common.hpp"
 #include "dense.hpp"
 #include "profile.hpp"
+#include "split16.hpp"
 #include "syrk.hpp"
 #include "tile_gemm.hpp"
 
@@ -321,6 +322,80 @@ __global__ __launch_bounds__(FormUCfg<T>::NT) void k_form_u(const TF* __restrict
                             if (m >= N) return (TU)0;
                             return (TU)(dinv ? (double)v * dinv[m] : (double)v);
                           });
+}
+
+// U = diag(dinv) F Zt^T for the split-fp16 Gram form, on the fp16 MFMA pipe
+// as split pairs (the Schur operands' pipe: F column-major, Zt with
+// k-contiguous rows of leading dimension r).  F is scaled by 2^12 (its rows
+// have norm at most 1), Zt by the power of two zsc[0] that puts its largest
+// magnitude below 2^14.  Single LDS buffer, two workgroups per CU; each lane
+// writes its four consecutive rows of a column directly.
+typedef TileCfg<__bf16, 128, 128, 64, 2, 4> FormUSplitCfg;
+
+template <typename TU>
+__global__ __launch_bounds__(512, 4) void k_form_u_split(const float* __restrict__ F, int64_t ldf,
+                                                         int64_t N, int r, const float* __restrict__ Zt,
+                                                         int nev, const float* __restrict__ zsc,
+                                                         const double* __restrict__ dinv,
+                                                         TU* __restrict__ U, int64_t ldu,
+                                                         const int32_t* kptr) {
+  typedef FormUSplitCfg Cfg;
+  extern __shared__ char smem_raw[];
+  const int kk = *kptr;
+  const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM;
+  const int n0 = blockIdx.y * Cfg::BN;
+  TileAcc<Cfg> acc;
+  acc.zero();
+  const float zs = zsc[0];
+  if (kk > 0) {
+    SchurSplitPipe<Cfg> pipe{F, ldf, N, Zt + (int64_t)n0 * r, r, nev - n0, kk, m0, zs};
+    pipe.begin1();
+    pipe.run1(acc, smem_raw);
+  }
+  const float un = 1.0f / (SchurSplit::SC * zs);  // both powers of two
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % Cfg::WAVES_M, wn = wave / Cfg::WAVES_M;
+#pragma unroll
+  for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+    for (int j = 0; j < Cfg::NI; ++j) {
+      const int col = n0 + wn * Cfg::WTN + j * 16 + (lane & 15);
+      if (col >= nev) continue;
+      const int64_t m = m0 + wm * Cfg::WTM + i * 16 + 4 * (lane >> 4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (m + e < N) {
+          const double v = (double)(acc.a[i][j][e] * un);
+          U[m + e + (int64_t)col * ldu] = (TU)(dinv ? v * dinv[m + e] : v);
+        }
+      }
+    }
+}
+
+// out[0] = 2^e with max |x| 2^e < 2^14 (1 when x is all zero), one workgroup.
+__global__ __launch_bounds__(1024) void k_pow2_scale(const float* __restrict__ x, int64_t n,
+                                                     float* __restrict__ out) {
+  __shared__ float red[1024];
+  float m = 0.0f;
+  for (int64_t e = threadIdx.x; e < n; e += 1024) m = fmaxf(m, fabsf(x[e]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float mx = red[0];
+    float sc = 1.0f;
+    if (mx > 0.0f && mx <= 3.0e38f) {
+      int ex;
+      frexpf(mx, &ex);
+      int q = 14 - ex;
+      q = q < -100 ? -100 : (q > 100 ? 100 : q);
+      sc = ldexpf(1.0f, q);
+    }
+    out[0] = sc;
+  }
 }
 
 template <typename T>
@@ -634,8 +709,22 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   TG* Zt = reinterpret_cast<TG*>(w.T2);
   hipLaunchKernelGGL((k_cvt<TG>), dim3(nblk((int64_t)r * nev)), dim3(256), 0, st, (const double*)w.Z,
                      Zt, (int64_t)r * nev);
-  hipLaunchKernelGGL((k_form_u<TG, TF, TU>), gu, dim3(CfgU::NT), smU, st, F, ldf, N, r,
-                     (const TG*)Zt, nev, (const double*)w.sd, U, ldu, k);
+  bool split_u = false;
+  if constexpr (std::is_same<TG, float>::value && std::is_same<TF, float>::value) {
+    if (o->gram_dtype == RPC_F32_SPLIT16) {
+      // the split-fp16 form forms U on the fp16 pipe as well
+      split_u = true;
+      hipLaunchKernelGGL(k_pow2_scale, dim3(1), dim3(1024), 0, st, (const float*)Zt,
+                         (int64_t)r * nev, w.gsc);
+      const dim3 gs((unsigned)((N + 127) / 128), (unsigned)((nev + 127) / 128));
+      hipLaunchKernelGGL((k_form_u_split<TU>), gs, dim3(512), SchurSplit::bytes / 2, st,
+                         (const float*)F, ldf, N, r, (const float*)Zt, nev, (const float*)w.gsc,
+                         (const double*)w.sd, U, ldu, k);
+    }
+  }
+  if (!split_u)
+    hipLaunchKernelGGL((k_form_u<TG, TF, TU>), gu, dim3(CfgU::NT), smU, st, F, ldf, N, r,
+                       (const TG*)Zt, nev, (const double*)w.sd, U, ldu, k);
   RPC_LAUNCH_CHECK();
 
   if (o->fix_const) {

@@ -1,0 +1,200 @@
+// Float32 products on the fp16 MFMA pipe as split pairs, for gfx950.
+//
+// Each operand element x is scaled by a power of two (exact) and split into
+// hi = fp16(x) and lo = fp16(x - hi), so x = hi + lo to 22 bits; a product x y
+// is taken as hi_x hi_y + hi_x lo_y + lo_x hi_y (the dropped lo_x lo_y is below
+// 2^-22 |x y|), each term an exact fp16 product accumulated in float32 by
+// v_mfma_f32_16x16x32_f16.  This is the three-product float32 emulation of
+// Ootomo and Yokota (2022): three fp16 MFMAs per float32 product against one
+// float32 MFMA of a fifth of the rate.
+#pragma once
+#include "common.hpp"
+#include "tile_gemm.hpp"
+
+// acc += 2^24 F(m0:m0+128, :k) FSa(:nt, :k)^T on the fp16 MFMA pipe, for a
+// float32 factor.  Each operand element x is scaled by 2^12 (exact; |x| <= 1
+// because the rows of F have norm at most 1) and split into hi = fp16(x) and
+// lo = fp16(x - hi); a product is taken as hi hi + hi lo + lo hi (unit
+// roundoff 2^-22, the three-product float32 emulation of Ootomo and Yokota,
+// 2022), at three fp16 MFMAs per product against one float32 MFMA of a fifth
+// of the rate.  The 16x16x32 fp16 MFMA shares its accumulator layout with the
+// bf16 one of the kernel-column product.
+//
+// Staging through registers, double buffered, 64 k per stage:
+//   A (F, column-major): thread t holds row t % 128 at k groups t / 128 and
+//     t / 128 + 4 (8 consecutive k each; every load is a 256-byte row run
+//     across the wave);
+//   B (FSa, k-contiguous rows): thread t holds row t / 4 at k groups t % 4
+//     and t % 4 + 4;
+// both land in LDS as [row][k] fp16 pairs (hi and lo arrays, 144-byte rows),
+// so every MFMA operand is one 16-byte read.
+struct SchurSplit {
+  static constexpr int BK = 64;
+  static constexpr int LDK = BK + 8;
+  static constexpr int ELEMS = 128 * LDK;
+  static constexpr size_t bytes = 2 * 4 * (size_t)ELEMS * sizeof(_Float16);
+  static constexpr float SC = 4096.0f;  // 2^12 per operand
+};
+typedef _Float16 v8h_t __attribute__((ext_vector_type(8)));
+
+__device__ inline void split8(const float (&x)[8], v8h_t& hi, v8h_t& lo,
+                              float sc = SchurSplit::SC) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float v = x[e] * sc;
+    const _Float16 h = (_Float16)v;
+    hi[e] = h;
+    lo[e] = (_Float16)(v - (float)h);
+  }
+}
+
+// Register ring of two stages: the global reads of stage s + 2 are issued
+// while the MFMAs consume stage s, and stage s + 1 is converted into LDS after
+// them.  begin() issues the reads of the first two stages, so a caller can
+// overlap their latency with other work before run().
+template <class Cfg>
+struct SchurSplitPipe {
+  static_assert(Cfg::NT == 512 && Cfg::BM == 128 && Cfg::BN == 128, "eight waves, 128 x 128");
+  static constexpr int BK = SchurSplit::BK, LDK = SchurSplit::LDK, EL = SchurSplit::ELEMS;
+  const float* __restrict__ F;
+  int64_t ldf, N;
+  const float* __restrict__ FSa;
+  int r, nt, k;
+  int64_t m0;
+  float bsc = SchurSplit::SC;  // power-of-two scale of the B operand (A: SchurSplit::SC)
+  float a0[2][8], b0[2][8], a1[2][8], b1[2][8];
+
+  __device__ inline void load(float (&a)[2][8], float (&b)[2][8], int kb) const {
+    const int tid = threadIdx.x;
+    const int arow = tid & 127, ag = tid >> 7;
+    const int brow = tid >> 2, bg = tid & 3;
+    const int64_t am = m0 + arow;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k0 = kb + 8 * (ag + 4 * h);
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        a[h][e] = (am < N && k0 + e < k) ? F[am + (int64_t)(k0 + e) * ldf] : 0.0f;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k0 = kb + 8 * (bg + 4 * h);
+      const float* p = FSa + (int64_t)brow * r + k0;
+      if (brow < nt && k0 + 8 <= k && (r % 4) == 0) {
+        const v4f u = *reinterpret_cast<const v4f*>(p);
+        const v4f w = *reinterpret_cast<const v4f*>(p + 4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          b[h][e] = u[e];
+          b[h][4 + e] = w[e];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) b[h][e] = (brow < nt && k0 + e < k) ? p[e] : 0.0f;
+      }
+    }
+  }
+
+  __device__ inline void store(const float (&a)[2][8], const float (&b)[2][8], _Float16* sm,
+                               int buf) const {
+    const int tid = threadIdx.x;
+    const int arow = tid & 127, ag = tid >> 7;
+    const int brow = tid >> 2, bg = tid & 3;
+    _Float16* base = sm + (size_t)buf * 4 * EL;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      v8h_t hi, lo;
+      split8(a[h], hi, lo);
+      const int o = arow * LDK + 8 * (ag + 4 * h);
+      *reinterpret_cast<v8h_t*>(base + o) = hi;
+      *reinterpret_cast<v8h_t*>(base + EL + o) = lo;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      v8h_t hi, lo;
+      split8(b[h], hi, lo, bsc);
+      const int o = brow * LDK + 8 * (bg + 4 * h);
+      *reinterpret_cast<v8h_t*>(base + 2 * EL + o) = hi;
+      *reinterpret_cast<v8h_t*>(base + 3 * EL + o) = lo;
+    }
+  }
+
+  __device__ inline void compute(TileAcc<Cfg>& acc, const _Float16* sm, int buf) const {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave % Cfg::WAVES_M, wn = wave / Cfg::WAVES_M;
+    if (wn * Cfg::WTN >= nt) return;  // this wave's columns are all beyond the block
+    const _Float16* base = sm + (size_t)buf * 4 * EL;
+#pragma unroll
+    for (int kq = 0; kq < BK; kq += 32) {
+      // B fragments for the whole k-step, A fragments one row block at a time
+      // (fewer live registers)
+      v8h_t bh[Cfg::NI], bl[Cfg::NI];
+#pragma unroll
+      for (int j = 0; j < Cfg::NI; ++j) {
+        const int o = (wn * Cfg::WTN + j * 16 + (lane & 15)) * LDK + kq + 8 * (lane >> 4);
+        bh[j] = *reinterpret_cast<const v8h_t*>(base + 2 * EL + o);
+        bl[j] = *reinterpret_cast<const v8h_t*>(base + 3 * EL + o);
+      }
+#pragma unroll
+      for (int i = 0; i < Cfg::MI; ++i) {
+        const int o = (wm * Cfg::WTM + i * 16 + (lane & 15)) * LDK + kq + 8 * (lane >> 4);
+        const v8h_t ah = *reinterpret_cast<const v8h_t*>(base + o);
+        const v8h_t al = *reinterpret_cast<const v8h_t*>(base + EL + o);
+#pragma unroll
+        for (int j = 0; j < Cfg::NI; ++j) {
+          acc.a[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[j], acc.a[i][j], 0, 0, 0);
+          acc.a[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[j], acc.a[i][j], 0, 0, 0);
+          acc.a[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[j], acc.a[i][j], 0, 0, 0);
+        }
+      }
+    }
+  }
+
+  __device__ inline void begin() {
+    load(a0, b0, 0);
+    if (BK < k) load(a1, b1, BK);
+  }
+
+  // Single-buffer form (half the LDS, so two workgroups share a CU): one
+  // stage of register prefetch, stage s + 1 converted after stage s's MFMAs.
+  __device__ inline void begin1() { load(a0, b0, 0); }
+  __device__ inline void run1(TileAcc<Cfg>& acc, char* smem_raw) {
+    _Float16* sm = reinterpret_cast<_Float16*>(smem_raw);
+    const int ns = (k + BK - 1) / BK;
+    __syncthreads();  // the LDS may still be read by the preceding product
+    store(a0, b0, sm, 0);
+    __syncthreads();
+    for (int s = 0; s < ns; ++s) {
+      if (s + 1 < ns) load(a0, b0, (s + 1) * BK);
+      compute(acc, sm, 0);
+      __syncthreads();  // every wave is done with the buffer (the caller reuses it too)
+      if (s + 1 < ns) {
+        store(a0, b0, sm, 0);
+        __syncthreads();
+      }
+    }
+  }
+
+  // acc += 2^24 F(m0.., :k) FSa(:nt, :k)^T; begin() must have been called.
+  __device__ inline void run(TileAcc<Cfg>& acc, char* smem_raw) {
+    _Float16* sm = reinterpret_cast<_Float16*>(smem_raw);
+    const int ns = (k + BK - 1) / BK;
+    __syncthreads();  // the LDS may still be read by the preceding product
+    store(a0, b0, sm, 0);
+    __syncthreads();
+    // stage s sits in LDS buffer s & 1; even stages pass through (a0, b0),
+    // odd ones through (a1, b1)
+    for (int s = 0; s < ns; s += 2) {
+      if (s + 2 < ns) load(a0, b0, (s + 2) * BK);
+      compute(acc, sm, 0);
+      if (s + 1 < ns) store(a1, b1, sm, 1);
+      __syncthreads();
+      if (s + 1 >= ns) break;
+      if (s + 3 < ns) load(a1, b1, (s + 3) * BK);
+      compute(acc, sm, 1);
+      if (s + 2 < ns) store(a0, b0, sm, 0);
+      __syncthreads();
+    }
+  }
+};
+

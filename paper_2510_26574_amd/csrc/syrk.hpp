@@ -390,34 +390,21 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_split_partial(
         acc[i][j][e] = 0.0f;
         acc64[i][j][e] = 0.0;
       }
-  SplitLoader la, lb;
-  la.load(A, lda, r, ti * TILE, s, n0, n1, tid);
-  if (!diag) lb.load(A, lda, r, tj * TILE, s, n0, n1, tid);
-  la.store(Ah[0], Al[0], scale, tid);
-  if (!diag) lb.store(Bh[0], Bl[0], scale, tid);
-  __syncthreads();
-  int buf = 0;
-  int run = 0;
-  for (int64_t k0 = n0; k0 < n1; k0 += BK) {
-    const bool more = k0 + BK < n1;
-    if (more) {
-      la.load(A, lda, r, ti * TILE, s, k0 + BK, n1, tid);
-      if (!diag) lb.load(A, lda, r, tj * TILE, s, k0 + BK, n1, tid);
-    }
+  // register ring of two stages: the reads of stage q + 2 are issued while
+  // the MFMAs consume stage q; stage q sits in LDS buffer q & 1 and passes
+  // through loader set q & 1
+  SplitLoader la0, lb0, la1, lb1;
+  const int nst = (int)((n1 - n0 + BK - 1) / BK);
+  auto compute = [&](int buf) {
     const _Float16* ah_s = Ah[buf];
     const _Float16* al_s = Al[buf];
     const _Float16* bh_s = diag ? Ah[buf] : Bh[buf];
     const _Float16* bl_s = diag ? Al[buf] : Bl[buf];
-    // lane group g = lane / 16 takes k = kq + 8 g .. kq + 8 g + 7 on both operands
+    // lane group g = lane / 16 takes k = kq + 8 g .. kq + 8 g + 7 on both operands;
+    // B fragments for the whole k-step, A fragments one row block at a time
 #pragma unroll
     for (int kq = 0; kq < BK; kq += 32) {
-      v8h ah[MI], al[MI], bh[NI], bl[NI];
-#pragma unroll
-      for (int i = 0; i < MI; ++i) {
-        const int o = (wm * WTM + i * 16 + (lane & 15)) * LDK + kq + 8 * (lane >> 4);
-        ah[i] = *reinterpret_cast<const v8h*>(ah_s + o);
-        al[i] = *reinterpret_cast<const v8h*>(al_s + o);
-      }
+      v8h bh[NI], bl[NI];
 #pragma unroll
       for (int j = 0; j < NI; ++j) {
         const int o = (wn * WTN + j * 16 + (lane & 15)) * LDK + kq + 8 * (lane >> 4);
@@ -425,25 +412,21 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_split_partial(
         bl[j] = *reinterpret_cast<const v8h*>(bl_s + o);
       }
 #pragma unroll
-      for (int i = 0; i < MI; ++i)
+      for (int i = 0; i < MI; ++i) {
+        const int o = (wm * WTM + i * 16 + (lane & 15)) * LDK + kq + 8 * (lane >> 4);
+        const v8h ah = *reinterpret_cast<const v8h*>(ah_s + o);
+        const v8h al = *reinterpret_cast<const v8h*>(al_s + o);
 #pragma unroll
-        for (int j = 0; j < NI; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < MI; ++i)
-#pragma unroll
-        for (int j = 0; j < NI; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < MI; ++i)
-#pragma unroll
-        for (int j = 0; j < NI; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < NI; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[j], acc[i][j], 0, 0, 0);
+        }
+      }
     }
-    if (more) {
-      la.store(Ah[buf ^ 1], Al[buf ^ 1], scale, tid);
-      if (!diag) lb.store(Bh[buf ^ 1], Bl[buf ^ 1], scale, tid);
-    }
+  };
+  int run = 0;
+  auto flush = [&]() {
     run += BK;
     if (run >= FLUSH_ROWS) {
       run = 0;
@@ -457,8 +440,40 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_split_partial(
             acc[i][j][e] = 0.0f;
           }
     }
+  };
+  la0.load(A, lda, r, ti * TILE, s, n0, n1, tid);
+  if (!diag) lb0.load(A, lda, r, tj * TILE, s, n0, n1, tid);
+  if (nst > 1) {
+    la1.load(A, lda, r, ti * TILE, s, n0 + BK, n1, tid);
+    if (!diag) lb1.load(A, lda, r, tj * TILE, s, n0 + BK, n1, tid);
+  }
+  la0.store(Ah[0], Al[0], scale, tid);
+  if (!diag) lb0.store(Bh[0], Bl[0], scale, tid);
+  __syncthreads();
+  for (int q = 0; q < nst; q += 2) {
+    if (q + 2 < nst) {
+      la0.load(A, lda, r, ti * TILE, s, n0 + (int64_t)(q + 2) * BK, n1, tid);
+      if (!diag) lb0.load(A, lda, r, tj * TILE, s, n0 + (int64_t)(q + 2) * BK, n1, tid);
+    }
+    compute(0);
+    if (q + 1 < nst) {
+      la1.store(Ah[1], Al[1], scale, tid);
+      if (!diag) lb1.store(Bh[1], Bl[1], scale, tid);
+    }
+    flush();
     __syncthreads();
-    buf ^= 1;
+    if (q + 1 >= nst) break;
+    if (q + 3 < nst) {
+      la1.load(A, lda, r, ti * TILE, s, n0 + (int64_t)(q + 3) * BK, n1, tid);
+      if (!diag) lb1.load(A, lda, r, tj * TILE, s, n0 + (int64_t)(q + 3) * BK, n1, tid);
+    }
+    compute(1);
+    if (q + 2 < nst) {
+      la0.store(Ah[0], Al[0], scale, tid);
+      if (!diag) lb0.store(Bh[0], Bl[0], scale, tid);
+    }
+    flush();
+    __syncthreads();
   }
   const double unscale = 1.0 / ((double)scale * (double)scale);
 #pragma unroll
