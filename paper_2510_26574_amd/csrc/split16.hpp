@@ -41,10 +41,10 @@ __device__ inline void split8(const float (&x)[8], v8h_t& hi, v8h_t& lo,
                               float sc = SchurSplit::SC) {
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    const float v = x[e] * sc;
-    const _Float16 h = (_Float16)v;
+    // hi = fp16(x sc); lo = fp16(x sc - hi), the remainder formed exactly by the fma
+    const _Float16 h = (_Float16)(x[e] * sc);
     hi[e] = h;
-    lo[e] = (_Float16)(v - (float)h);
+    lo[e] = (_Float16)__builtin_fmaf(x[e], sc, -(float)h);
   }
 }
 

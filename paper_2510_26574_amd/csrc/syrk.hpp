@@ -327,6 +327,9 @@ struct SplitLoader {
   }
   __device__ inline void store(_Float16* __restrict__ hi, _Float16* __restrict__ lo, float scale,
                                int tid) const {
+    float ss[4];  // row scale times the chunk's power of two (the same rows for every p)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ss[e] = ld.sc[e] * scale;
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
       const int vid = tid + p * NTH;
@@ -335,10 +338,11 @@ struct SplitLoader {
       v4h h, l;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const float x = ld.buf[p][e] * ld.sc[e] * scale;
-        const _Float16 xh = (_Float16)x;
+        // hi = fp16(x s); lo = fp16(x s - hi) with the remainder formed exactly by the fma
+        const float x = ld.buf[p][e];
+        const _Float16 xh = (_Float16)(x * ss[e]);
         h[e] = xh;
-        l[e] = (_Float16)(x - (float)xh);
+        l[e] = (_Float16)__builtin_fmaf(x, ss[e], -(float)xh);
       }
       *reinterpret_cast<v4h*>(hi + col * SPLIT_LDK + kv) = h;
       *reinterpret_cast<v4h*>(lo + col * SPLIT_LDK + kv) = l;
