@@ -39,11 +39,17 @@ __global__ __launch_bounds__(1024) void k_coldot_partial(const TF* __restrict__ 
   constexpr int V = 16 / (int)sizeof(TF);
   typedef TF vt __attribute__((ext_vector_type(V)));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * COLCHUNK;
+  const int64_t r1 = r0 + COLCHUNK < N ? r0 + COLCHUNK : N;
+  // the chunk's weights, read once per workgroup (its 16 columns share them)
+  __shared__ double ws[COLCHUNK];
+  if (wgt) {
+    for (int64_t n = r0 + threadIdx.x; n < r1; n += 1024) ws[n - r0] = wgt[n];
+    __syncthreads();
+  }
   const int col = blockIdx.y * 16 + wave;
   if (col >= r) return;
   const int k = *kptr;
-  const int64_t r0 = (int64_t)blockIdx.x * COLCHUNK;
-  const int64_t r1 = r0 + COLCHUNK < N ? r0 + COLCHUNK : N;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   if (col < k) {
     const TF* f = F + (int64_t)col * ldf;
@@ -62,7 +68,7 @@ __global__ __launch_bounds__(1024) void k_coldot_partial(const TF* __restrict__ 
 #pragma unroll
           for (int e = 0; e < V; ++e) {
             const int64_t n = i + (u * 64 + lane) * V + e;
-            t += wgt ? to_d(a[u][e]) * wgt[n] : to_d(a[u][e]);
+            t += wgt ? to_d(a[u][e]) * ws[n - r0] : to_d(a[u][e]);
           }
           if (u == 0) s0 += t;
           if (u == 1) s1 += t;
@@ -73,7 +79,7 @@ __global__ __launch_bounds__(1024) void k_coldot_partial(const TF* __restrict__ 
     }
     for (int64_t n = i + lane; n < r1; n += 64) {
       const double v = to_d(f[n]);
-      s0 += wgt ? v * wgt[n] : v;
+      s0 += wgt ? v * ws[n - r0] : v;
     }
   }
   double s = (s0 + s1) + (s2 + s3);
