@@ -127,7 +127,9 @@ def roofline(w, d, res, prof, steps, prec):
         "kernel_cols": (2.0 * N * dp * k + schur_fl * (3 if split else 1),
                         rounds * N * dp * xs + schur_by + N * k * fs, prec[0]),
         "schur": (float(np.sum(2.0 * N * kb * nT)), float(np.sum(N * kb * fs + 2 * N * nT * fs)), prec[1]),
-        "solve_downdate": (float(np.sum(1.0 * N * nT * nT)), float(np.sum(2 * N * nT * fs + 16 * N)), "f64"),
+        # the mixed form's solve runs as split fp16 pairs (three products each)
+        "solve_downdate": (float(np.sum(1.0 * N * nT * nT)) * (3 if split else 1),
+                           float(np.sum(2 * N * nT * fs + 16 * N)), "f16" if split else "f64"),
         # both Grams over the k nonzero columns (symmetric: k (k + 1) / 2 dot products each);
         # the split-fp16 form takes three fp16 products per float32 product
         "gram": (2.0 * N * k * (k + 1) * (3 if prec[2] == "split16" else 1), 2.0 * N * k * fs,
@@ -157,13 +159,15 @@ def roofline(w, d, res, prof, steps, prec):
     else:
         ach, peak, unit = o["gbs"], PEAK["hbm"], "GB/s"
     line = {"bound": o["bound"], "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
-            "traffic": pmc_traffic(KERNEL_NAMES.get(dom)), "kernel": dom,
+            "traffic": pmc_traffic(KERNEL_NAMES.get((dom, prec[2]))), "kernel": dom,
             "avg_launch_ms": o["ms_per_step"] / nl}
     return line, out
 
 
-# profile class -> kernel the class brackets (mixed form) as named by rocprofv3
-KERNEL_NAMES = {"gram": "k_syrk_partial<float, float>"}
+# (profile class, Gram arithmetic) -> kernel the class brackets in the mixed
+# form, as named by rocprofv3
+KERNEL_NAMES = {("gram", "split16"): "k_syrk_split_partial", ("gram", "f32"): "k_syrk_partial<float, float>",
+                ("kernel_cols", "split16"): "k_cols_schurIDF16b", ("kernel_cols", "f32"): "k_cols_schurIDF16b"}
 
 
 def pmc_traffic(kernel):
