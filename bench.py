@@ -522,56 +522,68 @@ def bench_batched(args, rp, torch):
             us[(n, r)] = torch.from_numpy(uniform_stream(2 * r, seed=n)).cuda()
         return us[(n, r)]
 
-    def make_job(q, b):
+    def make_job(q, b, shared_x=False):
         i, m, n = meta[q]
         sp = specs[i]
-        return rp.Job(Xd[i], m * data[i][1], sp["r"], b, nev, uniforms=uniforms(n, sp["r"]))
+        return rp.Job(Xd[i], m * data[i][1], sp["r"], b, nev, uniforms=uniforms(n, sp["r"]),
+                      shared_x=shared_x)
 
     log("[batched] autotuning block sizes")
     cache_path = os.path.join(os.environ.get("TMPDIR", "/tmp"), "rpchol_autotune.json")
     bs, cache = autotune.tune(probs, make_job, cache_path=cache_path, reps=1)
-    jobs = [make_job(q, b) for q, b in enumerate(bs)]
     ns = BATCH["n_streams"]
-    ws = rp.batched_workspace(jobs, ns)
-    log(f"[batched] {len(jobs)} jobs, workspace {ws.numel() / 1e9:.2f} GB")
 
-    def run(n_streams, reps):
-        rp.batched_run(jobs, n_streams=n_streams, workspace=ws)  # warm-up
-        torch.cuda.synchronize()
+    def measure(jobs, tag):
+        ws = rp.batched_workspace(jobs, ns)
+        log(f"[batched] {tag}: {len(jobs)} jobs, workspace {ws.numel() / 1e9:.2f} GB")
+
+        def run(n_streams, reps):
+            rp.batched_run(jobs, n_streams=n_streams, workspace=ws)  # warm-up
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                rp.batched_run(jobs, n_streams=n_streams, workspace=ws)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) / reps
+
+        t_serial = run(1, 1)
+        log(f"[batched] {tag}: one stream {t_serial:.3f}s")
+        t_pool = run(ns, BATCH["reps"])
+        log(f"[batched] {tag}: {ns} streams {t_pool:.3f}s")
+        st = [int(j.status.item()) for j in jobs]
         t = time.perf_counter()
-        for _ in range(reps):
-            rp.batched_run(jobs, n_streams=n_streams, workspace=ws)
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t) / reps
-
-    t_serial = run(1, 1)
-    log(f"[batched] one stream {t_serial:.3f}s")
-    t_pool = run(ns, BATCH["reps"])
-    log(f"[batched] {ns} streams {t_pool:.3f}s")
-    st = [int(j.status.item()) for j in jobs]
-    t = time.perf_counter()
-    g = rp.BatchedGraph(jobs, n_streams=ns, workspace=ws)
-    t_capture = time.perf_counter() - t
-    g.launch()
-    g.synchronize()
-    t = time.perf_counter()
-    for _ in range(BATCH["reps"]):
+        g = rp.BatchedGraph(jobs, n_streams=ns, workspace=ws)
+        t_capture = time.perf_counter() - t
         g.launch()
-    g.synchronize()
-    t_graph = (time.perf_counter() - t) / BATCH["reps"]
-    log(f"[batched] graph {t_graph:.3f}s (capture {t_capture:.2f}s)")
-    st_g = [int(j.status.item()) for j in jobs]
-    g.close()
-    # spot check: three jobs against their single-call decomposition
-    same = True
-    for q in (0, len(jobs) // 2, len(jobs) - 1):
-        j = jobs[q]
-        out = rp.rpchol_factor(j.X, j.rec.X.eps, j.rec.factor.r, j.rec.factor.b, uniforms=j.uniforms,
-                               gemm_dtype="f32", factor_dtype="f32")
-        deg = rp.bistoch_degrees(out["F"], out["k"], status=out["status"])
-        eig = rp.bistoch_eig(out["F"], out["k"], deg["d"], deg["q"], nev, gram_dtype="f32", u_dtype="f32",
-                             status=out["status"])
-        same &= bool(torch.equal(eig["lam"], j.lam) and torch.equal(out["pivots"], j.pivots))
+        g.synchronize()
+        t = time.perf_counter()
+        for _ in range(BATCH["reps"]):
+            g.launch()
+        g.synchronize()
+        t_graph = (time.perf_counter() - t) / BATCH["reps"]
+        log(f"[batched] {tag}: graph {t_graph:.3f}s (capture {t_capture:.2f}s)")
+        st_g = [int(j.status.item()) for j in jobs]
+        g.close()
+        # spot check: three jobs against their single-call decomposition
+        same = True
+        for q in (0, len(jobs) // 2, len(jobs) - 1):
+            j = jobs[q]
+            shared = bool(j.rec.factor.flags & rp.RPC_FACTOR_SHARED_X)
+            out = rp.rpchol_factor(j.X, j.rec.X.eps, j.rec.factor.r, j.rec.factor.b, uniforms=j.uniforms,
+                                   gemm_dtype="f32", factor_dtype="f32", shared_x=shared)
+            deg = rp.bistoch_degrees(out["F"], out["k"], status=out["status"])
+            eig = rp.bistoch_eig(out["F"], out["k"], deg["d"], deg["q"], nev, gram_dtype="f32", u_dtype="f32",
+                                 status=out["status"])
+            same &= bool(torch.equal(eig["lam"], j.lam) and torch.equal(out["pivots"], j.pivots))
+        del ws
+        return {"one_stream_s": t_serial, "stream_pool_s": t_pool, "graph_s": t_graph,
+                "graph_capture_s": t_capture, "all_status_ok": all(x == 0 for x in st + st_g),
+                "spot_check_equals_single_calls": same}
+
+    indep = measure([make_job(q, b) for q, b in enumerate(bs)], "independent")
+    shared = measure([make_job(q, b, shared_x=True) for q, b in enumerate(bs)], "shared points")
+    best = "shared_points" if shared["graph_s"] < indep["graph_s"] else "independent_jobs"
+    t_graph = min(shared["graph_s"], indep["graph_s"])
     flops = sum(N * r * (2.0 * d + 3.0 * r) for N, d, r in probs)
     line = {
         "metric": "batched form: 512 decompositions (64 KS datasets x 8 bandwidths), seconds",
@@ -580,13 +592,13 @@ def bench_batched(args, rp, torch):
         "config": {"workload": f"{len(specs)} KS delay-embedding datasets (sum N = "
                                f"{sum(s['N'] for s in specs)}, N 5e3..2e5, d in 32/128/512, "
                                f"r in 64..512) x {len(BANDWIDTH_MULTIPLIERS)} bandwidths, top {nev}",
-                   "n_streams": ns, "blocks": {k: v["b"] for k, v in sorted(cache.items())}},
-        "jobs": len(jobs), "jobs_per_s": len(jobs) / t_graph,
-        "one_stream_s": t_serial, "stream_pool_s": t_pool, "graph_s": t_graph,
-        "graph_capture_s": t_capture, "speedup_graph_vs_one_stream": t_serial / t_graph,
+                   "n_streams": ns, "blocks": {k: v["b"] for k, v in sorted(cache.items())},
+                   "timed_configuration": best,
+                   "shared_points_configuration": "the 8 bandwidths of a dataset factorised as one group"},
+        "jobs": len(probs), "jobs_per_s": len(probs) / t_graph,
+        "shared_points": shared, "independent_jobs": indep,
+        "speedup_graph_vs_one_stream": (shared if best == "shared_points" else indep)["one_stream_s"] / t_graph,
         "est_tflops_graph": flops / t_graph / 1e12,
-        "all_status_ok": all(x == 0 for x in st) and all(x == 0 for x in st_g),
-        "spot_check_equals_single_calls": same,
     }
     print(json.dumps(line), flush=True)
 

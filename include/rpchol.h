@@ -110,9 +110,15 @@ typedef struct {
  *               update W -= F F_S^T in two kernels (W written, then read
  *               back) instead of one fused kernel where both products share
  *               an accumulator; results agree to rounding.  Meant for timing
- *               the kernel-column evaluation on its own.  Other bits:
- *               RPC_EINVAL. */
+ *               the kernel-column evaluation on its own.
+ *               RPC_FACTOR_SHARED_X: the job may share its kernel-column pass
+ *               with other jobs on the same points (rpchol_factor_group,
+ *               rpc_batched_run); the factorisation then uses the two-kernel
+ *               arithmetic of RPC_FACTOR_UNFUSED, so a job factorised alone
+ *               with this bit equals the same job factorised in a group, bit
+ *               for bit.  Other bits: RPC_EINVAL. */
 #define RPC_FACTOR_UNFUSED 1
+#define RPC_FACTOR_SHARED_X 2
 typedef struct {
   int32_t r;
   int32_t b;
@@ -172,6 +178,28 @@ int rpchol_factor_workspace_size(const rpc_points* X, const rpc_factor_opts* opt
 int rpchol_factor(const rpc_points* X, const rpc_factor_opts* opts, void* F, int64_t ldf,
                   int64_t* pivots, double* rho, int32_t* k_out, void* workspace,
                   size_t workspace_bytes, int32_t* dev_status, rpc_stream_t stream);
+
+/* ---- Algorithm 2 for several bandwidths on the same points ------------
+ * The data sets of the method are often decomposed at several bandwidths
+ * (the batched form's 8 per data set).  rpchol_factor_group runs n_group
+ * (1..16) factorisations of the same points X (X->eps is ignored) with
+ * bandwidths eps[g] (host array) and options opts[g] (host array of host
+ * pointers) in lockstep: the points are converted once, and each round's
+ * kernel columns of all jobs are computed in one launch whose workgroups for
+ * one tile of rows run together, so X is read from HBM once per round for the
+ * group (per-column bandwidth in the exp epilogue).  Every job must use the
+ * same r, b, mode (SAMPLED or GREEDY), gemm_dtype, factor_dtype, tau and
+ * flags, with RPC_FACTOR_SHARED_X set; uniforms and round_accepted may differ.
+ * Outputs are per job (host arrays of device pointers), each exactly what
+ * rpchol_factor returns for that job alone (bit for bit); F leading
+ * dimension ldf is common.  The workspace holds the converted points once and
+ * the round state of every job. */
+int rpchol_factor_group_workspace_size(const rpc_points* X, const rpc_factor_opts* opts,
+                                       int32_t n_group, size_t* bytes);
+int rpchol_factor_group(const rpc_points* X, const double* eps, const rpc_factor_opts* const* opts,
+                        int32_t n_group, void* const* F, int64_t ldf, int64_t* const* pivots,
+                        double* const* rho, int32_t* const* k_out, int32_t* const* dev_status,
+                        void* workspace, size_t workspace_bytes, rpc_stream_t stream);
 
 /* ---- Algorithm 1: normalisation vectors -------------------------------
  * c = F^T 1 (r doubles), d~ = F c (N doubles, asserted > 0, RPC_EDEGREE),

@@ -98,6 +98,9 @@ _SIGS = {
     "rpc_batched_graph_launch": [_VP, _VP],
     "rpc_batched_graph_destroy": [_VP],
     "rpc_autotune_block": [_VP, _VP, _I32, _I32, _VP, _SZ, _VP, _VP, _VP],
+    "rpchol_factor_group_workspace_size": [_VP, _VP, _I32, _VP],
+    "rpchol_factor_group": [_VP, _VP, _VP, _I32, _VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, _SZ,
+                            _VP],
     "rpc_status_sync": [_VP, _VP],
     "rpc_version": [],
     "rpc_profile_enable": [ctypes.c_int],
@@ -171,10 +174,11 @@ def status_sync(status, stream=None):
 
 
 RPC_FACTOR_UNFUSED = 1
+RPC_FACTOR_SHARED_X = 2
 
 
 def rpchol_factor(X, eps, r, b, mode="sampled", uniforms=None, replay=None, gemm_dtype="f64",
-                  factor_dtype="f64", tau=0.0, unfused=False, status=None, stream=None):
+                  factor_dtype="f64", tau=0.0, unfused=False, shared_x=False, status=None, stream=None):
     """Algorithm 2 on the Gaussian kernel of the rows of X (N x d float32, CUDA).
 
     Returns dict: F (N x r view, column-major storage), pivots (r int64),
@@ -195,7 +199,8 @@ def rpchol_factor(X, eps, r, b, mode="sampled", uniforms=None, replay=None, gemm
     nrounds = -(-(r if mode != "replay" else replay.numel()) // b)
     racc = torch.zeros(nrounds, dtype=torch.int32, device=dev)
     opts = rpc_factor_opts(int(r), int(b), MODES[mode], DTYPES[gemm_dtype], DTYPES[factor_dtype],
-                           RPC_FACTOR_UNFUSED if unfused else 0, float(tau), 0, 0, 0, 0, racc.data_ptr())
+                           (RPC_FACTOR_UNFUSED if unfused else 0) | (RPC_FACTOR_SHARED_X if shared_x else 0),
+                           float(tau), 0, 0, 0, 0, racc.data_ptr())
     if mode == "sampled":
         assert uniforms is not None and uniforms.dtype == torch.float64 and uniforms.is_cuda
         opts.uniforms = uniforms.data_ptr()
@@ -213,6 +218,63 @@ def rpchol_factor(X, eps, r, b, mode="sampled", uniforms=None, replay=None, gemm
            "rpchol_factor")
     return {"F": Fbuf[:, :N].t(), "Fbuf": Fbuf, "ldf": ldf, "pivots": piv, "rho": rho, "k": k,
             "status": st, "round_accepted": racc, "workspace": ws}
+
+
+def rpchol_factor_group(X, eps_list, r, b, uniforms_list, gemm_dtype="f32", factor_dtype="f32", tau=0.0,
+                        mode="sampled", stream=None):
+    """Algorithm 2 for several bandwidths of the same points in lockstep
+    (rpchol_factor_group: one pass over X per round for the whole group).
+    Returns one dict per bandwidth, as rpchol_factor does."""
+    torch = _torch()
+    lib = load_library()
+    G = len(eps_list)
+    N = X.shape[0]
+    dev = X.device
+    fdt = torch.float64 if factor_dtype == "f64" else torch.float32
+    ldf = _ld(N)
+    nrounds = -(-r // b)
+    outs, opts = [], []
+    for g in range(G):
+        o = {"Fbuf": torch.empty((r, ldf), dtype=fdt, device=dev),
+             "pivots": torch.empty(r, dtype=torch.int64, device=dev),
+             "rho": torch.empty(N, dtype=torch.float64, device=dev),
+             "k": torch.zeros(1, dtype=torch.int32, device=dev),
+             "status": torch.zeros(1, dtype=torch.int32, device=dev),
+             "round_accepted": torch.zeros(nrounds, dtype=torch.int32, device=dev), "ldf": ldf}
+        o["F"] = o["Fbuf"][:, :N].t()
+        fo = rpc_factor_opts(int(r), int(b), MODES[mode], DTYPES[gemm_dtype], DTYPES[factor_dtype],
+                             RPC_FACTOR_SHARED_X, float(tau), 0, 0, 0, 0, o["round_accepted"].data_ptr())
+        if mode == "sampled":
+            u = uniforms_list[g]
+            assert u.dtype == torch.float64 and u.is_cuda
+            fo.uniforms, fo.n_uniforms = u.data_ptr(), u.numel()
+        outs.append(o)
+        opts.append(fo)
+    pts = _points(X, eps_list[0])
+    nb = ctypes.c_size_t(0)
+    _check(lib.rpchol_factor_group_workspace_size(ctypes.byref(pts), ctypes.byref(opts[0]), G,
+                                                  ctypes.byref(nb)), "rpchol_factor_group_workspace_size")
+    ws = _workspace(torch, nb.value, dev)
+
+    keep = []
+
+    def arr(ctype, vals):
+        a = (ctype * G)(*vals)
+        keep.append(a)
+        return ctypes.cast(a, ctypes.c_void_p)
+
+    eps_a = arr(ctypes.c_double, [float(e) for e in eps_list])
+    opt_a = arr(ctypes.c_void_p, [ctypes.addressof(o) for o in opts])
+    F_a = arr(ctypes.c_void_p, [o["Fbuf"].data_ptr() for o in outs])
+    p_a = arr(ctypes.c_void_p, [o["pivots"].data_ptr() for o in outs])
+    r_a = arr(ctypes.c_void_p, [o["rho"].data_ptr() for o in outs])
+    k_a = arr(ctypes.c_void_p, [o["k"].data_ptr() for o in outs])
+    s_a = arr(ctypes.c_void_p, [o["status"].data_ptr() for o in outs])
+    _check(lib.rpchol_factor_group(ctypes.byref(pts), eps_a, opt_a, G, F_a, ldf, p_a, r_a, k_a, s_a,
+                                   _ptr(ws), nb.value, _stream(torch, stream)), "rpchol_factor_group")
+    for o in outs:
+        o["workspace"] = ws
+    return outs
 
 
 def _factor_args(F):
@@ -308,7 +370,7 @@ class Job:
 
     def __init__(self, X, eps, r, b, nev, mode="sampled", uniforms=None, replay=None,
                  gemm_dtype="f32", factor_dtype="f32", gram_dtype="f32", u_dtype="f32", tau=0.0,
-                 gamma=0.0):
+                 gamma=0.0, shared_x=False):
         torch = _torch()
         N = X.shape[0]
         dev = X.device
@@ -327,8 +389,8 @@ class Job:
         self.lam = torch.empty(nev, dtype=torch.float64, device=dev)
         self.Ebuf = torch.empty((nev, r), dtype=torch.float64, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
-        fo = rpc_factor_opts(int(r), int(b), MODES[mode], DTYPES[gemm_dtype], DTYPES[factor_dtype], 0,
-                             float(tau), 0, 0, 0, 0, 0)
+        fo = rpc_factor_opts(int(r), int(b), MODES[mode], DTYPES[gemm_dtype], DTYPES[factor_dtype],
+                             RPC_FACTOR_SHARED_X if shared_x else 0, float(tau), 0, 0, 0, 0, 0)
         if mode == "sampled":
             assert uniforms is not None and uniforms.dtype == torch.float64 and uniforms.is_cuda
             fo.uniforms, fo.n_uniforms = uniforms.data_ptr(), uniforms.numel()

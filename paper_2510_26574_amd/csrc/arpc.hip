@@ -1014,13 +1014,20 @@ struct FactorWs {
   int64_t dp;
 };
 
+// Workspace: the converted points (shared by jobs on the same points) and
+// the per-job round state.
+template <typename T, typename TN>
+static void carve_shared(WsCursor& c, FactorWs& w, int64_t N, int64_t d) {
+  w.dp = (int64_t)align_up((size_t)d, 32);
+  w.Xp = c.take<T>((size_t)N * w.dp);
+  w.xn = c.take<TN>((size_t)N);
+}
+
 template <typename T, typename TN, typename TF>
-static size_t carve(WsCursor& c, FactorWs& w, int64_t N, int64_t d, int r) {
+static void carve_job(WsCursor& c, FactorWs& w, int64_t N, int64_t d, int r) {
   w.dp = (int64_t)align_up((size_t)d, 32);
   w.ldw = (int64_t)align_up((size_t)N, 8);
   const int nb = (int)((N + CHUNK - 1) / CHUNK);
-  w.Xp = c.take<T>((size_t)N * w.dp);
-  w.xn = c.take<TN>((size_t)N);
   w.W = c.take<TF>((size_t)w.ldw * MAXB);
   w.part = c.take<unsigned long long>((size_t)nb);
   w.pv = c.take<double>((size_t)nb);
@@ -1042,7 +1049,168 @@ static size_t carve(WsCursor& c, FactorWs& w, int64_t N, int64_t d, int r) {
   w.nT = c.take<int32_t>(1);
   w.stop = c.take<int32_t>(1);
   w.tot = c.take<unsigned long long>(1);
+}
+
+template <typename T, typename TN, typename TF>
+static size_t carve(WsCursor& c, FactorWs& w, int64_t N, int64_t d, int r) {
+  carve_shared<T, TN>(c, w, N, d);
+  carve_job<T, TN, TF>(c, w, N, d, r);
   return c.used;
+}
+
+// One factorisation's arguments and round state.
+template <typename T, typename TN, typename TF>
+struct FJob {
+  rpc_points X;  // eps is this job's
+  const rpc_factor_opts* o;
+  TF* F;
+  int64_t ldf;
+  int64_t* pivots;
+  double* rho;
+  int32_t* k_out;
+  int32_t* status;
+  FactorWs w;
+};
+
+// 128 x 128 tiles, eight waves of 64 x 32 (two per SIMD at one workgroup per
+// CU, which the four-stage direct pipeline's LDS allows)
+template <typename T, typename TF>
+struct FCfg {
+  typedef TileCfg<T, 128, 128, (sizeof(T) == 2 ? 64 : (sizeof(T) == 4 ? 32 : 16)), 2, 4> K;
+  typedef TileCfg<TF, 128, 128, (sizeof(TF) == 4 ? 32 : 16), 2, 4> S;
+};
+
+static int n_rounds(const rpc_factor_opts* o) {
+  if (o->mode == RPC_REPLAY) return (int)((o->n_replay + o->b - 1) / o->b);
+  return (o->r + o->b - 1) / o->b;
+}
+
+static int round_block(const rpc_factor_opts* o, int i) {
+  const int b = o->b;
+  if (o->mode == RPC_REPLAY)
+    return (int)(o->n_replay - (int64_t)i * b < b ? o->n_replay - (int64_t)i * b : b);
+  return o->r - i * b < b ? o->r - i * b : b;
+}
+
+// Round i, part 1: proposals, the proposal block, Algorithm 3, L^{-1}.
+template <typename T, typename TN, typename TF>
+static void phase_select(FJob<T, TN, TF>& j, int i, hipStream_t st) {
+  const rpc_factor_opts* o = j.o;
+  FactorWs& w = j.w;
+  const int64_t N = j.X.N;
+  const int r = o->r, b = o->b;
+  const int nb = (int)((N + CHUNK - 1) / CHUNK);
+  const int64_t dp = w.dp;
+  const int bi = round_block(o, i);
+  const double* z = nullptr;
+  prof::begin(prof::PIVOT, st);
+  if (o->mode == RPC_SAMPLED) {
+    hipLaunchKernelGGL(k_rho_partial, dim3(nb), dim3(256), 0, st, j.rho, N, w.part, w.stop);
+    hipLaunchKernelGGL(k_draw_scan, dim3(1), dim3(1024), 0, st, w.part, nb, w.tot, w.stop);
+    hipLaunchKernelGGL(k_draw_find, dim3(bi), dim3(256), 0, st, j.rho, N,
+                       (const unsigned long long*)w.part, nb, (const unsigned long long*)w.tot,
+                       o->uniforms + (int64_t)2 * b * i, w.prop, w.stop);
+    z = o->uniforms + (int64_t)2 * b * i + b;
+  } else if (o->mode == RPC_GREEDY) {
+    hipLaunchKernelGGL(k_argmax_partial, dim3(nb), dim3(256), 0, st, j.rho, N, w.pv, w.pi, w.stop);
+    hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(256), 0, st, w.pv, w.pi, nb, w.prop, w.stop);
+    z = nullptr;
+  } else {
+    hipLaunchKernelGGL(k_replay_props, dim3(1), dim3(MAXB), 0, st, o->replay, (int64_t)i * b, bi, N,
+                       w.prop, j.status, w.stop);
+  }
+  prof::end(prof::PIVOT, st);
+  prof::begin(prof::ACCEPT, st);
+  hipLaunchKernelGGL((k_gather<T, TN, TF>), dim3(bi), dim3(256), 0, st, (const T*)w.Xp,
+                     (const TN*)w.xn, dp, (const TF*)j.F, j.ldf, r, w.prop, bi, j.k_out, w.stop,
+                     (T*)w.XS, (TN*)w.ns, (TF*)w.FS, N, j.status);
+  const unsigned hb = (unsigned)((bi + 15) / 16);
+  hipLaunchKernelGGL((k_pivot_block<T, TF>), dim3(hb, hb), dim3(256), 0, st, (const T*)w.XS, dp,
+                     (const TF*)w.FS, r, bi, j.k_out, w.stop, j.X.eps, MAXB, w.H);
+  hipLaunchKernelGGL((k_accept_reject<T, TN, TF>), dim3(1), dim3(1024), 0, st, w.H, bi, w.prop, z,
+                     o->tau, o->mode, (const T*)w.XS, dp, (const TN*)w.ns, (const TF*)w.FS, r,
+                     j.k_out, w.nT, w.stop, j.pivots, w.Lc, w.Si, (T*)w.XSa, (TN*)w.nsa,
+                     (TF*)w.FSa, j.status);
+  hipLaunchKernelGGL(k_tri_inv, dim3(MAXB), dim3(64), 0, st, (const double*)w.Lc, w.nT, w.Linv);
+  prof::end(prof::ACCEPT, st);
+}
+
+// Round i, part 2 (unfused form): the Schur update W -= F(:, :k) F(S_i, :k)^T.
+template <typename T, typename TN, typename TF>
+static void phase_schur(FJob<T, TN, TF>& j, hipStream_t st) {
+  typedef typename FCfg<T, TF>::S CfgS;
+  const size_t smS = DirectSmem<CfgS, kStages, false, true>::bytes;
+  const unsigned gm = (unsigned)((j.X.N + 127) / 128);
+  FactorWs& w = j.w;
+  prof::begin(prof::SCHUR, st);
+  hipLaunchKernelGGL((k_schur<TF, CfgS>), dim3(gm, 1), dim3(CfgS::NT), smS, st, (const TF*)j.F,
+                     j.ldf, j.X.N, (const TF*)w.FSa, j.o->r, j.k_out, w.nT, (TF*)w.W, w.ldw);
+  prof::end(prof::SCHUR, st);
+}
+
+// Round i, part 2: W = K(X, X_{S_i}) - F(:, :k) F(S_i, :k)^T, fused in one
+// kernel unless the options ask for the separate column and Schur kernels.
+template <typename T, typename TN, typename TF>
+static void phase_columns(FJob<T, TN, TF>& j, hipStream_t st) {
+  typedef typename FCfg<T, TF>::K CfgK;
+  typedef typename FCfg<T, TF>::S CfgS;
+  const int64_t N = j.X.N;
+  FactorWs& w = j.w;
+  const size_t smK = DirectSmem<CfgK, kStages, true, true>::bytes;
+  const size_t smS = DirectSmem<CfgS, kStages, false, true>::bytes;
+  const size_t smKS = smK > smS ? smK : smS;
+  const unsigned gm = (unsigned)((N + 127) / 128);
+  if constexpr (kFusedColsSchur<T, TF>) {
+    if (!(j.o->flags & (RPC_FACTOR_UNFUSED | RPC_FACTOR_SHARED_X))) {
+      prof::begin(prof::KERNEL_COLS, st);
+      constexpr bool split = std::is_same<T, __bf16>::value && std::is_same<TF, float>::value;
+      // the split variant needs the larger of two direct stages, one split
+      // Schur buffer and the column-store staging (two workgroups per CU)
+      constexpr size_t smSplit0 = DirectSmem<CfgK, kStagesSplit, true, true>::bytes;
+      constexpr size_t smSplit1 = SchurSplit::bytes / 2 > ColStoreSmem<CfgK, TF>::bytes
+                                      ? SchurSplit::bytes / 2 : ColStoreSmem<CfgK, TF>::bytes;
+      constexpr size_t smSplit = smSplit0 > smSplit1 ? smSplit0 : smSplit1;
+      static_assert(!split || 2 * smSplit <= 160 * 1024, "two workgroups per CU");
+      hipLaunchKernelGGL((k_cols_schur<T, TN, TF, CfgK, CfgS, split>), dim3(gm), dim3(CfgK::NT),
+                         split ? smSplit : smKS, st, (const T*)w.Xp, (const TN*)w.xn, N, w.dp,
+                         (const T*)w.XSa, (const TN*)w.nsa, w.nT, j.X.eps, (const TF*)j.F, j.ldf,
+                         (const TF*)w.FSa, j.o->r, j.k_out, (TF*)w.W, w.ldw);
+      prof::end(prof::KERNEL_COLS, st);
+      return;
+    }
+  }
+  prof::begin(prof::KERNEL_COLS, st);
+  hipLaunchKernelGGL((k_kernel_cols<T, TN, TF, CfgK>), dim3(gm, 1), dim3(CfgK::NT), smK, st,
+                     (const T*)w.Xp, (const TN*)w.xn, N, w.dp, (const T*)w.XSa, (const TN*)w.nsa,
+                     w.nT, j.X.eps, (TF*)w.W, w.ldw);
+  prof::end(prof::KERNEL_COLS, st);
+  phase_schur(j, st);
+}
+
+// Round i, part 3: G = W L^{-T} into F, rho -= rownorms(G)^2, rho(S_i) = 0.
+template <typename T, typename TN, typename TF>
+static void phase_solve(FJob<T, TN, TF>& j, int i, hipStream_t st) {
+  typedef SolveCfg CfgD;
+  const int64_t N = j.X.N;
+  FactorWs& w = j.w;
+  const size_t smD = TileSmem<CfgD, false, true>::bytes;
+  prof::begin(prof::SOLVE, st);
+  if constexpr (std::is_same<T, __bf16>::value && std::is_same<TF, float>::value) {
+    // mixed form: the solve on the fp16 pipe as split pairs
+    hipLaunchKernelGGL(k_split_linv, dim3(1), dim3(256), 0, st, (const double*)w.Linv, w.nT, w.Lh,
+                       w.Ll, w.lsc);
+    hipLaunchKernelGGL(k_solve_split, dim3((unsigned)((N + MAXB - 1) / MAXB)), dim3(512),
+                       SolveSplit::bytes, st, (const float*)w.W, w.ldw, N, (const _Float16*)w.Lh,
+                       (const _Float16*)w.Ll, (const float*)w.lsc, j.k_out, w.nT, (float*)j.F,
+                       j.ldf, j.rho);
+  } else {
+    hipLaunchKernelGGL((k_solve_downdate<TF>), dim3((unsigned)((N + CfgD::BM - 1) / CfgD::BM)),
+                       dim3(CfgD::NT), smD, st, (const TF*)w.W, w.ldw, N, w.Linv, j.k_out, w.nT,
+                       j.F, j.ldf, j.rho);
+  }
+  hipLaunchKernelGGL(k_round_end, dim3(1), dim3(MAXB), 0, st, w.Si, j.k_out, w.nT, j.rho,
+                     j.o->round_accepted, i);
+  prof::end(prof::SOLVE, st);
 }
 
 template <typename T, typename TN, typename TF>
@@ -1050,133 +1218,156 @@ static int run_factor(const rpc_points* X, const rpc_factor_opts* o, TF* F, int6
                       int64_t* pivots, double* rho, int32_t* k_out, void* ws, size_t ws_bytes,
                       int32_t* status, hipStream_t st) {
   WsCursor cur{(char*)ws, 0, ws_bytes, true};
-  FactorWs w;
-  carve<T, TN, TF>(cur, w, X->N, X->d, o->r);
+  FJob<T, TN, TF> j{*X, o, F, ldf, pivots, rho, k_out, status, FactorWs{}};
+  carve<T, TN, TF>(cur, j.w, X->N, X->d, o->r);
   if (!cur.ok) return RPC_EWORKSPACE;
   const int64_t N = X->N;
-  const int r = o->r, b = o->b;
-  const int nb = (int)((N + CHUNK - 1) / CHUNK);
-  const int64_t dp = w.dp;
-
   hipLaunchKernelGGL((k_prep<T, TN>), dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, X->X, N,
-                     X->d, X->ldx, dp, (T*)w.Xp, (TN*)w.xn, rho, status);
+                     X->d, X->ldx, j.w.dp, (T*)j.w.Xp, (TN*)j.w.xn, rho, status);
+  hipLaunchKernelGGL(k_init_small, dim3(1), dim3(256), 0, st, pivots, o->r, k_out, j.w.nT, j.w.stop);
   RPC_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_init_small, dim3(1), dim3(256), 0, st, pivots, r, k_out, w.nT, w.stop);
-  RPC_LAUNCH_CHECK();
-
-  // 128 x 128 tiles, eight waves of 64 x 32 (two per SIMD at one workgroup
-  // per CU, which the four-stage direct pipeline's LDS allows)
-  typedef TileCfg<T, 128, 128, (sizeof(T) == 2 ? 64 : (sizeof(T) == 4 ? 32 : 16)), 2, 4> CfgK;
-  typedef TileCfg<TF, 128, 128, (sizeof(TF) == 4 ? 32 : 16), 2, 4> CfgS;
-  typedef SolveCfg CfgD;
-  const size_t smK = DirectSmem<CfgK, kStages, true, true>::bytes;
-  const size_t smS = DirectSmem<CfgS, kStages, false, true>::bytes;
-  const size_t smD = TileSmem<CfgD, false, true>::bytes;
-  const size_t smKS = smK > smS ? smK : smS;
-  const unsigned gm = (unsigned)((N + 127) / 128);
-
-  int t;
-  if (o->mode == RPC_REPLAY)
-    t = (int)((o->n_replay + b - 1) / b);
-  else
-    t = (r + b - 1) / b;
+  const int t = n_rounds(o);
   for (int i = 0; i < t; ++i) {
-    int bi;
-    if (o->mode == RPC_REPLAY)
-      bi = (int)(o->n_replay - (int64_t)i * b < b ? o->n_replay - (int64_t)i * b : b);
-    else
-      bi = r - i * b < b ? r - i * b : b;
-    const double* z = nullptr;
-    prof::begin(prof::PIVOT, st);
-    if (o->mode == RPC_SAMPLED) {
-      hipLaunchKernelGGL(k_rho_partial, dim3(nb), dim3(256), 0, st, rho, N, w.part, w.stop);
-      hipLaunchKernelGGL(k_draw_scan, dim3(1), dim3(1024), 0, st, w.part, nb, w.tot, w.stop);
-      hipLaunchKernelGGL(k_draw_find, dim3(bi), dim3(256), 0, st, rho, N,
-                         (const unsigned long long*)w.part, nb, (const unsigned long long*)w.tot,
-                         o->uniforms + (int64_t)2 * b * i, w.prop, w.stop);
-      z = o->uniforms + (int64_t)2 * b * i + b;
-    } else if (o->mode == RPC_GREEDY) {
-      hipLaunchKernelGGL(k_argmax_partial, dim3(nb), dim3(256), 0, st, rho, N, w.pv, w.pi, w.stop);
-      hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(256), 0, st, w.pv, w.pi, nb, w.prop, w.stop);
-      z = nullptr;
-    } else {
-      hipLaunchKernelGGL(k_replay_props, dim3(1), dim3(MAXB), 0, st, o->replay, (int64_t)i * b, bi,
-                         N, w.prop, status, w.stop);
-    }
-    prof::end(prof::PIVOT, st);
-    RPC_LAUNCH_CHECK();
-    prof::begin(prof::ACCEPT, st);
-    hipLaunchKernelGGL((k_gather<T, TN, TF>), dim3(bi), dim3(256), 0, st, (const T*)w.Xp,
-                       (const TN*)w.xn, dp, (const TF*)F, ldf, r, w.prop, bi, k_out, w.stop,
-                       (T*)w.XS, (TN*)w.ns, (TF*)w.FS, N, status);
-    const unsigned hb = (unsigned)((bi + 15) / 16);
-    hipLaunchKernelGGL((k_pivot_block<T, TF>), dim3(hb, hb), dim3(256), 0, st, (const T*)w.XS, dp,
-                       (const TF*)w.FS, r, bi, k_out, w.stop, X->eps, MAXB, w.H);
-    RPC_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_accept_reject<T, TN, TF>), dim3(1), dim3(1024), 0, st, w.H, bi, w.prop,
-                       z, o->tau, o->mode, (const T*)w.XS, dp, (const TN*)w.ns,
-                       (const TF*)w.FS, r, k_out, w.nT, w.stop, pivots, w.Lc, w.Si, (T*)w.XSa,
-                       (TN*)w.nsa, (TF*)w.FSa, status);
-    hipLaunchKernelGGL(k_tri_inv, dim3(MAXB), dim3(64), 0, st, (const double*)w.Lc, w.nT, w.Linv);
-    prof::end(prof::ACCEPT, st);
-    RPC_LAUNCH_CHECK();
-    bool fused = false;
-    if constexpr (kFusedColsSchur<T, TF>) {
-      if (!(o->flags & RPC_FACTOR_UNFUSED)) {
-        fused = true;
-        prof::begin(prof::KERNEL_COLS, st);
-        constexpr bool split = std::is_same<T, __bf16>::value && std::is_same<TF, float>::value;
-        // the split variant needs the larger of two direct stages, one split
-        // Schur buffer and the column-store staging (two workgroups per CU)
-        constexpr size_t smSplit0 = DirectSmem<CfgK, kStagesSplit, true, true>::bytes;
-        constexpr size_t smSplit1 = SchurSplit::bytes / 2 > ColStoreSmem<CfgK, TF>::bytes
-                                        ? SchurSplit::bytes / 2 : ColStoreSmem<CfgK, TF>::bytes;
-        constexpr size_t smSplit = smSplit0 > smSplit1 ? smSplit0 : smSplit1;
-        static_assert(!split || 2 * smSplit <= 160 * 1024, "two workgroups per CU");
-        hipLaunchKernelGGL((k_cols_schur<T, TN, TF, CfgK, CfgS, split>), dim3(gm), dim3(CfgK::NT),
-                           split ? smSplit : smKS, st,
-                           (const T*)w.Xp, (const TN*)w.xn, N, dp, (const T*)w.XSa,
-                           (const TN*)w.nsa, w.nT, X->eps, (const TF*)F, ldf, (const TF*)w.FSa, r,
-                           k_out, (TF*)w.W, w.ldw);
-        prof::end(prof::KERNEL_COLS, st);
-        RPC_LAUNCH_CHECK();
-      }
-    }
-    if (!fused) {
-      prof::begin(prof::KERNEL_COLS, st);
-      hipLaunchKernelGGL((k_kernel_cols<T, TN, TF, CfgK>), dim3(gm, 1), dim3(CfgK::NT), smK, st,
-                         (const T*)w.Xp, (const TN*)w.xn, N, dp, (const T*)w.XSa, (const TN*)w.nsa,
-                         w.nT, X->eps, (TF*)w.W, w.ldw);
-      prof::end(prof::KERNEL_COLS, st);
-      RPC_LAUNCH_CHECK();
-      prof::begin(prof::SCHUR, st);
-      hipLaunchKernelGGL((k_schur<TF, CfgS>), dim3(gm, 1), dim3(CfgS::NT), smS, st, (const TF*)F, ldf,
-                         N, (const TF*)w.FSa, r, k_out, w.nT, (TF*)w.W, w.ldw);
-      prof::end(prof::SCHUR, st);
-      RPC_LAUNCH_CHECK();
-    }
-    prof::begin(prof::SOLVE, st);
-    if constexpr (std::is_same<T, __bf16>::value && std::is_same<TF, float>::value) {
-      // mixed form: the solve on the fp16 pipe as split pairs
-      hipLaunchKernelGGL(k_split_linv, dim3(1), dim3(256), 0, st, (const double*)w.Linv, w.nT, w.Lh,
-                         w.Ll, w.lsc);
-      hipLaunchKernelGGL(k_solve_split, dim3((unsigned)((N + MAXB - 1) / MAXB)), dim3(512),
-                         SolveSplit::bytes, st, (const float*)w.W, w.ldw, N, (const _Float16*)w.Lh,
-                         (const _Float16*)w.Ll, (const float*)w.lsc, k_out, w.nT, (float*)F, ldf,
-                         rho);
-    } else {
-      hipLaunchKernelGGL((k_solve_downdate<TF>), dim3((unsigned)((N + CfgD::BM - 1) / CfgD::BM)),
-                         dim3(CfgD::NT), smD, st,
-                         (const TF*)w.W, w.ldw, N, w.Linv, k_out, w.nT, F, ldf, rho);
-    }
-    RPC_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(MAXB), 0, st, w.Si, k_out, w.nT, rho,
-                       o->round_accepted, i);
-    prof::end(prof::SOLVE, st);
+    phase_select(j, i, st);
+    phase_columns(j, st);
+    phase_solve(j, i, st);
     RPC_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL((k_zero_tail<TF>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, F, ldf,
-                     N, r, k_out);
+                     N, o->r, k_out);
+  RPC_LAUNCH_CHECK();
+  return RPC_OK;
+}
+
+// ------------------------------------------------------------ shared points
+// Kernel columns of a group of factorisations of the same points at
+// different bandwidths, in one launch per round: workgroup (job g, row tile)
+// computes W_g = K_g(X tile, X_{S_g}) exactly as k_kernel_cols does for job g
+// alone (same main loop and epilogue, job g's eps per column).  The
+// workgroups of all jobs for one row tile are adjacent and on the same XCD,
+// so each tile of X is fetched from HBM once per round for the group and
+// served from that XCD's L2 to the other bandwidths.
+constexpr int MAX_GROUP = 16;
+
+template <typename T, typename TN, typename TW>
+struct ColGroup {
+  const T* XSa[MAX_GROUP];
+  const TN* nsa[MAX_GROUP];
+  const int32_t* nT[MAX_GROUP];
+  TW* W[MAX_GROUP];
+  double eps[MAX_GROUP];
+  int G;
+};
+
+template <typename T, typename TN, typename TW, class Cfg>
+__global__ __launch_bounds__(Cfg::NT) void k_kernel_cols_group(const T* __restrict__ Xp,
+                                                               const TN* __restrict__ xn, int64_t N,
+                                                               int64_t dp, int tiles,
+                                                               ColGroup<T, TN, TW> grp, int64_t ldw) {
+  const int xcd = blockIdx.x % 8;
+  const int slot = blockIdx.x / 8;
+  const int g = slot % grp.G;
+  const int tile = (slot / grp.G) * 8 + xcd;
+  if (tile >= tiles) return;
+  const int nt = *grp.nT[g];
+  if (nt == 0) return;
+  extern __shared__ char smem_raw[];
+  typename Cfg::T* smem = reinterpret_cast<typename Cfg::T*>(smem_raw);
+  const int64_t m0 = (int64_t)tile * Cfg::BM;
+  GOperand<T, true> A{Xp, dp, N, dp, nullptr, true};
+  GOperand<T, true> B{grp.XSa[g], dp, nt, dp, nullptr, true};
+  TileAcc<Cfg> acc;
+  acc.zero();
+  tile_mainloop_direct<Cfg, kStages>(acc, A, B, m0, 0, 0, dp, N, MAXB, smem, nt, tile);
+  typedef typename Cfg::MM::acc_t AT;
+  const AT ie = (AT)(1.0 / grp.eps[g]);
+  const TN* nsa = grp.nsa[g];
+  store_colmajor<Cfg, TW>(acc, smem, grp.W[g], ldw, m0, 0, N, nt, [&](int row, int col, AT v) {
+    const int64_t m = m0 + row, n = col;
+    if (m >= N || n >= nt) return (TW)0;
+    AT d2 = (AT)xn[m] + (AT)nsa[n] - (AT)2 * v;
+    d2 = d2 > (AT)0 ? d2 : (AT)0;
+    return (TW)exp(-d2 * ie);
+  });
+}
+
+__global__ void k_fill_rho(double* rho, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < N) rho[i] = 1.0;
+}
+
+__global__ void k_status_from(const int32_t* src, int32_t* dst) {
+  if (*src != RPC_OK) set_status(dst, *src);
+}
+
+template <typename T, typename TN, typename TF>
+static size_t group_ws(int64_t N, int64_t d, int r, int G) {
+  WsCursor c{nullptr, 0, 0, true};
+  FactorWs w;
+  carve_shared<T, TN>(c, w, N, d);
+  for (int g = 0; g < G; ++g) carve_job<T, TN, TF>(c, w, N, d, r);
+  return c.used;
+}
+
+template <typename T, typename TN, typename TF>
+static int run_factor_group(const rpc_points* X, const double* eps, const rpc_factor_opts* const* opts,
+                            int G, void* const* F, int64_t ldf, int64_t* const* pivots,
+                            double* const* rho, int32_t* const* k_out, int32_t* const* status,
+                            void* ws, size_t ws_bytes, hipStream_t st) {
+  typedef typename FCfg<T, TF>::K CfgK;
+  WsCursor cur{(char*)ws, 0, ws_bytes, true};
+  FactorWs shared;
+  carve_shared<T, TN>(cur, shared, X->N, X->d);
+  FJob<T, TN, TF> jobs[MAX_GROUP];
+  for (int g = 0; g < G; ++g) {
+    jobs[g] = FJob<T, TN, TF>{*X, opts[g], (TF*)F[g], ldf, pivots[g], rho[g], k_out[g], status[g],
+                              FactorWs{}};
+    jobs[g].X.eps = eps[g];
+    carve_job<T, TN, TF>(cur, jobs[g].w, X->N, X->d, opts[g]->r);
+    jobs[g].w.Xp = shared.Xp;
+    jobs[g].w.xn = shared.xn;
+  }
+  if (!cur.ok) return RPC_EWORKSPACE;
+  const int64_t N = X->N;
+  const int64_t dp = shared.dp;
+  // the points are converted once; every job starts from rho = 1
+  hipLaunchKernelGGL((k_prep<T, TN>), dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, X->X, N,
+                     X->d, X->ldx, dp, (T*)shared.Xp, (TN*)shared.xn, rho[0], status[0]);
+  for (int g = 0; g < G; ++g) {
+    if (g > 0) {
+      hipLaunchKernelGGL(k_fill_rho, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, rho[g], N);
+      hipLaunchKernelGGL(k_status_from, dim3(1), dim3(1), 0, st, (const int32_t*)status[0], status[g]);
+    }
+    hipLaunchKernelGGL(k_init_small, dim3(1), dim3(256), 0, st, pivots[g], opts[g]->r, k_out[g],
+                       jobs[g].w.nT, jobs[g].w.stop);
+  }
+  RPC_LAUNCH_CHECK();
+  ColGroup<T, TN, TF> grp{};
+  grp.G = G;
+  for (int g = 0; g < G; ++g) {
+    grp.XSa[g] = (const T*)jobs[g].w.XSa;
+    grp.nsa[g] = (const TN*)jobs[g].w.nsa;
+    grp.nT[g] = jobs[g].w.nT;
+    grp.W[g] = (TF*)jobs[g].w.W;
+    grp.eps[g] = eps[g];
+  }
+  const int tiles = (int)((N + 127) / 128);
+  const unsigned blocks = (unsigned)(8 * ((tiles + 7) / 8) * G);
+  const size_t smK = DirectSmem<CfgK, kStages, true, true>::bytes;
+  const int t = n_rounds(opts[0]);
+  for (int i = 0; i < t; ++i) {
+    for (int g = 0; g < G; ++g) phase_select(jobs[g], i, st);
+    prof::begin(prof::KERNEL_COLS, st);
+    hipLaunchKernelGGL((k_kernel_cols_group<T, TN, TF, CfgK>), dim3(blocks), dim3(CfgK::NT), smK, st,
+                       (const T*)shared.Xp, (const TN*)shared.xn, N, dp, tiles, grp, jobs[0].w.ldw);
+    prof::end(prof::KERNEL_COLS, st);
+    for (int g = 0; g < G; ++g) phase_schur(jobs[g], st);
+    for (int g = 0; g < G; ++g) phase_solve(jobs[g], i, st);
+    RPC_LAUNCH_CHECK();
+  }
+  for (int g = 0; g < G; ++g)
+    hipLaunchKernelGGL((k_zero_tail<TF>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
+                       (TF*)F[g], ldf, N, opts[g]->r, k_out[g]);
   RPC_LAUNCH_CHECK();
   return RPC_OK;
 }
@@ -1199,7 +1390,7 @@ static int check_factor_args(const rpc_points* X, const rpc_factor_opts* o) {
     if (!o->replay || o->n_replay < 1 || o->n_replay > o->r) return RPC_EINVAL;
   }
   if (!(o->tau >= 0.0)) return RPC_EINVAL;
-  if (o->flags & ~RPC_FACTOR_UNFUSED) return RPC_EINVAL;
+  if (o->flags & ~(RPC_FACTOR_UNFUSED | RPC_FACTOR_SHARED_X)) return RPC_EINVAL;
   if (X->N > (int64_t)1 << 23) return RPC_EINVAL;  // keeps sum(rho_q) < 2^63
   return RPC_OK;
 }
@@ -1245,5 +1436,66 @@ extern "C" int rpchol_factor(const rpc_points* X, const rpc_factor_opts* o, void
     typedef typename std::remove_pointer<decltype(tn)>::type TN;
     typedef typename std::remove_pointer<decltype(tf)>::type TF;
     return run_factor<T, TN, TF>(X, o, (TF*)F, ldf, pivots, rho, k_out, ws, ws_bytes, status, st);
+  });
+}
+
+namespace {
+// Group options: every job as rpchol_factor accepts it, sharing everything
+// but the uniforms and round_accepted, SAMPLED or GREEDY, with SHARED_X set.
+int check_group_args(const rpc_points* X, const double* eps, const rpc_factor_opts* const* opts,
+                     int32_t G) {
+  if (!X || !opts || !eps || G < 1 || G > MAX_GROUP) return RPC_EINVAL;
+  for (int g = 0; g < G; ++g) {
+    if (!opts[g]) return RPC_EINVAL;
+    rpc_points Xg = *X;
+    Xg.eps = eps[g];
+    const int rc = check_factor_args(&Xg, opts[g]);
+    if (rc) return rc;
+    const rpc_factor_opts* a = opts[0];
+    const rpc_factor_opts* o = opts[g];
+    if (!(o->flags & RPC_FACTOR_SHARED_X)) return RPC_EINVAL;
+    if (o->mode == RPC_REPLAY) return RPC_EINVAL;
+    if (o->r != a->r || o->b != a->b || o->mode != a->mode || o->gemm_dtype != a->gemm_dtype ||
+        o->factor_dtype != a->factor_dtype || o->tau != a->tau || o->flags != a->flags)
+      return RPC_EINVAL;
+  }
+  return RPC_OK;
+}
+}  // namespace
+
+extern "C" int rpchol_factor_group_workspace_size(const rpc_points* X, const rpc_factor_opts* o,
+                                                  int32_t n_group, size_t* bytes) {
+  if (!X || !o || !bytes || n_group < 1 || n_group > MAX_GROUP) return RPC_EINVAL;
+  rpc_points X1 = *X;  // the points' eps is not used by a group
+  X1.eps = 1.0;
+  int rc = check_factor_args(&X1, o);
+  if (rc) return rc;
+  return dispatch(o, [&](auto* t, auto* tn, auto* tf) {
+    typedef typename std::remove_pointer<decltype(t)>::type T;
+    typedef typename std::remove_pointer<decltype(tn)>::type TN;
+    typedef typename std::remove_pointer<decltype(tf)>::type TF;
+    *bytes = group_ws<T, TN, TF>(X->N, X->d, o->r, n_group);
+    return (int)RPC_OK;
+  });
+}
+
+extern "C" int rpchol_factor_group(const rpc_points* X, const double* eps,
+                                   const rpc_factor_opts* const* opts, int32_t n_group,
+                                   void* const* F, int64_t ldf, int64_t* const* pivots,
+                                   double* const* rho, int32_t* const* k_out,
+                                   int32_t* const* status, void* ws, size_t ws_bytes,
+                                   rpc_stream_t stream) {
+  int rc = check_group_args(X, eps, opts, n_group);
+  if (rc) return rc;
+  if (!F || !pivots || !rho || !k_out || !status || ldf < X->N || ldf % 8 != 0) return RPC_EINVAL;
+  for (int g = 0; g < n_group; ++g)
+    if (!F[g] || !pivots[g] || !rho[g] || !k_out[g] || !status[g]) return RPC_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  return dispatch(opts[0], [&](auto* t, auto* tn, auto* tf) {
+    typedef typename std::remove_pointer<decltype(t)>::type T;
+    typedef typename std::remove_pointer<decltype(tn)>::type TN;
+    typedef typename std::remove_pointer<decltype(tf)>::type TF;
+    return run_factor_group<T, TN, TF>(X, eps, opts, n_group, F, ldf, pivots, rho, k_out, status,
+                                       ws, ws_bytes, st);
   });
 }

@@ -1,7 +1,8 @@
-// Batched form: many independent decompositions (rpchol_factor,
-// bistoch_degrees, bistoch_eig per job) issued over a pool of streams so that
-// small jobs overlap on the chip, optionally captured once into a HIP graph
-// and replayed.  Jobs are assigned longest-first to the stream with the least
+// Batched form: many decompositions (rpchol_factor, bistoch_degrees,
+// bistoch_eig per job; jobs on shared points factorised together by
+// rpchol_factor_group) issued over a pool of streams so that small jobs
+// overlap on the chip, optionally captured once into a HIP graph and
+// replayed.  Jobs are assigned longest-first to the stream with the least
 // estimated work (LPT list scheduling); each stream reuses one slice of the
 // caller's workspace for its jobs, which run in sequence on it.
 #include <algorithm>
@@ -70,11 +71,62 @@ double job_cost(const rpc_job* j) {
   return N * r * (2.0 * d + 3.0 * r);
 }
 
+// Jobs flagged RPC_FACTOR_SHARED_X that use the same points (pointer, N, d,
+// ldx) and the same factor options apart from eps and the uniforms form one
+// unit: their factorisations run together (rpchol_factor_group), then each
+// job's degrees and eigenpairs in turn.  Every other job is a unit of one.
+constexpr int MAX_UNIT = 16;
+
+bool same_group(const rpc_job* a, const rpc_job* b) {
+  const rpc_factor_opts &p = a->factor, &q = b->factor;
+  return (p.flags & RPC_FACTOR_SHARED_X) && (q.flags & RPC_FACTOR_SHARED_X) && a->X.X == b->X.X &&
+         a->X.N == b->X.N && a->X.d == b->X.d && a->X.ldx == b->X.ldx && p.r == q.r &&
+         p.b == q.b && p.mode == q.mode && p.mode != RPC_REPLAY && p.gemm_dtype == q.gemm_dtype &&
+         p.factor_dtype == q.factor_dtype && p.tau == q.tau && p.flags == q.flags &&
+         a->ldf == b->ldf;
+}
+
+std::vector<std::vector<int>> make_units(const rpc_job* jobs, int n) {
+  std::vector<std::vector<int>> units;
+  std::vector<char> used(n, 0);
+  for (int i = 0; i < n; ++i) {
+    if (used[i]) continue;
+    std::vector<int> u{i};
+    used[i] = 1;
+    for (int j = i + 1; j < n && (int)u.size() < MAX_UNIT; ++j)
+      if (!used[j] && same_group(&jobs[i], &jobs[j])) {
+        u.push_back(j);
+        used[j] = 1;
+      }
+    units.push_back(u);
+  }
+  return units;
+}
+
+int unit_ws(const rpc_job* jobs, const std::vector<int>& u, size_t* bytes) {
+  size_t m = 0;
+  for (int j : u) {
+    size_t b = 0;
+    const int rc = job_ws(&jobs[j], &b);
+    if (rc) return rc;
+    m = std::max(m, b);
+  }
+  if (u.size() > 1) {
+    size_t g = 0;
+    const int rc = rpchol_factor_group_workspace_size(&jobs[u[0]].X, &jobs[u[0]].factor,
+                                                      (int32_t)u.size(), &g);
+    if (rc) return rc;
+    m = std::max(m, align_up(g, 256));
+  }
+  *bytes = m;
+  return RPC_OK;
+}
+
 int per_stream_bytes(const rpc_job* jobs, int n, size_t* out) {
   size_t m = 0;
-  for (int i = 0; i < n; ++i) {
+  for (const auto& u : make_units(jobs, n)) {
     size_t b = 0;
-    const int rc = job_ws(&jobs[i], &b);
+    const int rc = unit_ws(jobs, u, &b);
     if (rc) return rc;
     m = std::max(m, b);
   }
@@ -82,19 +134,56 @@ int per_stream_bytes(const rpc_job* jobs, int n, size_t* out) {
   return RPC_OK;
 }
 
-int issue_job(const rpc_job* j, void* ws, size_t wsb, hipStream_t s) {
-  rpc_stream_t rs = reinterpret_cast<rpc_stream_t>(s);
-  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, j->dev_status);
-  RPC_LAUNCH_CHECK();
-  int rc = rpchol_factor(&j->X, &j->factor, j->F, j->ldf, j->pivots, j->rho, j->k, ws, wsb,
-                         j->dev_status, rs);
-  if (rc) return rc;
-  rc = bistoch_degrees(j->F, j->factor.factor_dtype, j->X.N, j->ldf, j->factor.r, j->k, j->c,
-                       j->d_tilde, j->q_tilde, ws, wsb, j->dev_status, rs);
+int issue_eig(const rpc_job* j, void* ws, size_t wsb, rpc_stream_t rs) {
+  int rc = bistoch_degrees(j->F, j->factor.factor_dtype, j->X.N, j->ldf, j->factor.r, j->k, j->c,
+                           j->d_tilde, j->q_tilde, ws, wsb, j->dev_status, rs);
   if (rc) return rc;
   return bistoch_eig(j->F, j->factor.factor_dtype, j->X.N, j->ldf, j->factor.r, j->k, j->c,
                      j->d_tilde, j->q_tilde, &j->eig, j->U, j->ldu, j->lambda, j->ext_E, ws, wsb,
                      j->dev_status, rs);
+}
+
+int issue_unit(const rpc_job* jobs, const std::vector<int>& u, void* ws, size_t wsb, hipStream_t s) {
+  rpc_stream_t rs = reinterpret_cast<rpc_stream_t>(s);
+  for (int j : u) hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, jobs[j].dev_status);
+  RPC_LAUNCH_CHECK();
+  int rc;
+  if (u.size() == 1) {
+    const rpc_job* j = &jobs[u[0]];
+    rc = rpchol_factor(&j->X, &j->factor, j->F, j->ldf, j->pivots, j->rho, j->k, ws, wsb,
+                       j->dev_status, rs);
+  } else {
+    const int G = (int)u.size();
+    double eps[MAX_UNIT];
+    const rpc_factor_opts* opts[MAX_UNIT];
+    void* F[MAX_UNIT];
+    int64_t* piv[MAX_UNIT];
+    double* rho[MAX_UNIT];
+    int32_t* k[MAX_UNIT];
+    int32_t* st[MAX_UNIT];
+    for (int g = 0; g < G; ++g) {
+      const rpc_job* j = &jobs[u[g]];
+      eps[g] = j->X.eps;
+      opts[g] = &j->factor;
+      F[g] = j->F;
+      piv[g] = j->pivots;
+      rho[g] = j->rho;
+      k[g] = j->k;
+      st[g] = j->dev_status;
+    }
+    rc = rpchol_factor_group(&jobs[u[0]].X, eps, opts, G, F, jobs[u[0]].ldf, piv, rho, k, st, ws,
+                             wsb, rs);
+  }
+  if (rc) return rc;
+  for (int j : u) {
+    rc = issue_eig(&jobs[j], ws, wsb, rs);
+    if (rc) return rc;
+  }
+  return RPC_OK;
+}
+
+int issue_job(const rpc_job* j, void* ws, size_t wsb, hipStream_t s) {
+  return issue_unit(j, std::vector<int>{0}, ws, wsb, s);
 }
 
 // Fork onto the pool streams, issue every job, join back into `origin`.
@@ -109,25 +198,30 @@ int issue_all(const rpc_job* jobs, int n, int ns, void* ws, size_t wsb, hipStrea
   DevicePool* p = nullptr;
   rc = pool_for_current(ns, &p);
   if (rc) return rc;
-  // longest first onto the least loaded stream
-  std::vector<int> order(n);
+  // units (jobs, or groups of jobs on shared points), longest first onto the
+  // least loaded stream
+  const std::vector<std::vector<int>> units = make_units(jobs, n);
+  const int nu = (int)units.size();
+  std::vector<double> cost(nu, 0.0);
+  for (int i = 0; i < nu; ++i)
+    for (int j : units[i]) cost[i] += job_cost(&jobs[j]);
+  std::vector<int> order(nu);
   std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return job_cost(&jobs[a]) > job_cost(&jobs[b]); });
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
   std::vector<double> load(ns, 0.0);
   std::vector<std::vector<int>> lists(ns);
-  for (int j : order) {
+  for (int u : order) {
     const int s = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    lists[s].push_back(j);
-    load[s] += job_cost(&jobs[j]);
+    lists[s].push_back(u);
+    load[s] += cost[u];
   }
   RPC_HIP_CHECK(hipEventRecord(p->fork, origin));
   for (int s = 0; s < ns; ++s) RPC_HIP_CHECK(hipStreamWaitEvent(p->s[s], p->fork, 0));
   int first_err = RPC_OK;
   for (int s = 0; s < ns; ++s) {
     char* base = (char*)ws + per * (size_t)s;
-    for (int j : lists[s]) {
-      rc = issue_job(&jobs[j], base, per, p->s[s]);
+    for (int u : lists[s]) {
+      rc = issue_unit(jobs, units[u], base, per, p->s[s]);
       if (rc && !first_err) first_err = rc;
       if (rc) break;
     }

@@ -56,7 +56,7 @@ def test_host_side_validation(lib):
         dict(n_uniforms=10),   # too few uniforms
         dict(gemm_dtype=7),
         dict(factor_dtype=2),  # bf16 storage of F is not offered
-        dict(flags=2),         # unknown option bit
+        dict(flags=4),         # unknown option bit
     ]
     for kw in bad:
         o = rp.rpc_factor_opts(8, 2, rp.MODES["sampled"], 0, 0, 0, 0.0, 0x2000, 64, 0, 0, 0)
@@ -80,6 +80,28 @@ def test_host_side_validation(lib):
     assert lib.nystrom_extend_workspace_size(10, 3, 64, 65, ctypes.byref(nb)) == rp.RPC_EINVAL
     o = rp.rpc_factor_opts(8, 2, rp.MODES["sampled"], 0, 0, rp.RPC_FACTOR_UNFUSED, 0.0, 0x2000, 64, 0, 0, 0)
     assert lib.rpchol_factor_workspace_size(ctypes.byref(pts), ctypes.byref(o), ctypes.byref(nb)) == 0
+    # group of factorisations on shared points: sizes and option checks (host side only)
+    og = rp.rpc_factor_opts(8, 2, rp.MODES["sampled"], 0, 0, rp.RPC_FACTOR_SHARED_X, 0.0, 0x2000, 64, 0, 0, 0)
+    n1 = ctypes.c_size_t(0)
+    assert lib.rpchol_factor_group_workspace_size(ctypes.byref(pts), ctypes.byref(og), 1, ctypes.byref(n1)) == 0
+    n4 = ctypes.c_size_t(0)
+    assert lib.rpchol_factor_group_workspace_size(ctypes.byref(pts), ctypes.byref(og), 4, ctypes.byref(n4)) == 0
+    assert n1.value < n4.value < 4 * n1.value  # the converted points are shared
+    for g in (0, 17):
+        assert lib.rpchol_factor_group_workspace_size(ctypes.byref(pts), ctypes.byref(og), g,
+                                                      ctypes.byref(n1)) == rp.RPC_EINVAL
+    og2 = rp.rpc_factor_opts(16, 2, rp.MODES["sampled"], 0, 0, rp.RPC_FACTOR_SHARED_X, 0.0, 0x2000, 64, 0, 0, 0)
+    og3 = rp.rpc_factor_opts(8, 2, rp.MODES["sampled"], 0, 0, 0, 0.0, 0x2000, 64, 0, 0, 0)
+    eps2 = (ctypes.c_double * 2)(1.0, 2.0)
+    fake = (ctypes.c_void_p * 2)(0x4000, 0x5000)
+    for other in (og2, og3):  # different r; SHARED_X missing
+        opts2 = (ctypes.c_void_p * 2)(ctypes.addressof(og), ctypes.addressof(other))
+        rc = lib.rpchol_factor_group(ctypes.byref(pts), ctypes.cast(eps2, ctypes.c_void_p),
+                                     ctypes.cast(opts2, ctypes.c_void_p), 2, ctypes.cast(fake, ctypes.c_void_p),
+                                     104, ctypes.cast(fake, ctypes.c_void_p), ctypes.cast(fake, ctypes.c_void_p),
+                                     ctypes.cast(fake, ctypes.c_void_p), ctypes.cast(fake, ctypes.c_void_p),
+                                     None, 0, None)
+        assert rc == rp.RPC_EINVAL
 
 
 def test_surrogate_and_batched_host_checks(lib):
