@@ -520,8 +520,13 @@ __global__ __launch_bounds__(64) void k_tri_inv(const double* __restrict__ Lc,
 
 // ------------------------------------------------------------ kernel columns
 // W[n][j] = exp(-max(0, xn[n] + nsa[j] - 2 <Xp[n], XSa[j]>) / eps), j < nT.
+// bf16 products: two direct stages and at most 128 VGPRs, so two workgroups
+// share a CU and one's prologue and epilogue overlap the other's stream of X.
+template <typename T>
+constexpr int cols_stages() { return sizeof(T) == 2 ? kStagesSplit : kStages; }
+
 template <typename T, typename TN, typename TW, class Cfg>
-__global__ __launch_bounds__(Cfg::NT) void k_kernel_cols(const T* __restrict__ Xp,
+__global__ __launch_bounds__(Cfg::NT, sizeof(T) == 2 ? 4 : 1) void k_kernel_cols(const T* __restrict__ Xp,
                                                          const TN* __restrict__ xn, int64_t N,
                                                          int64_t dp, const T* __restrict__ XSa,
                                                          const TN* __restrict__ nsa,
@@ -537,8 +542,8 @@ __global__ __launch_bounds__(Cfg::NT) void k_kernel_cols(const T* __restrict__ X
   GOperand<T, true> B{XSa, dp, nt, dp, nullptr, true};
   TileAcc<Cfg> acc;
   acc.zero();
-  tile_mainloop_direct<Cfg, kStages>(acc, A, B, m0, n0, 0, dp, N, MAXB, smem, nt - (int)n0,
-                                     (int)blockIdx.x);
+  tile_mainloop_direct<Cfg, cols_stages<T>()>(acc, A, B, m0, n0, 0, dp, N, MAXB, smem, nt - (int)n0,
+                                              (int)blockIdx.x);
   typedef typename Cfg::MM::acc_t AT;
   const AT ie = (AT)(1.0 / eps);
   store_colmajor<Cfg, TW>(acc, smem, W, ldw, m0, n0, N, nt, [&](int row, int col, AT v) {
@@ -1179,8 +1184,12 @@ static void phase_columns(FJob<T, TN, TF>& j, hipStream_t st) {
       return;
     }
   }
+  // LDS of the column kernel: its direct stages or the column-store staging
+  constexpr size_t smC0 = DirectSmem<CfgK, cols_stages<T>(), true, true>::bytes;
+  constexpr size_t smC1 = ColStoreSmem<CfgK, TF>::bytes;
+  constexpr size_t smC = smC0 > smC1 ? smC0 : smC1;
   prof::begin(prof::KERNEL_COLS, st);
-  hipLaunchKernelGGL((k_kernel_cols<T, TN, TF, CfgK>), dim3(gm, 1), dim3(CfgK::NT), smK, st,
+  hipLaunchKernelGGL((k_kernel_cols<T, TN, TF, CfgK>), dim3(gm, 1), dim3(CfgK::NT), smC, st,
                      (const T*)w.Xp, (const TN*)w.xn, N, w.dp, (const T*)w.XSa, (const TN*)w.nsa,
                      w.nT, j.X.eps, (TF*)w.W, w.ldw);
   prof::end(prof::KERNEL_COLS, st);
@@ -1260,7 +1269,7 @@ struct ColGroup {
 };
 
 template <typename T, typename TN, typename TW, class Cfg>
-__global__ __launch_bounds__(Cfg::NT) void k_kernel_cols_group(const T* __restrict__ Xp,
+__global__ __launch_bounds__(Cfg::NT, sizeof(T) == 2 ? 4 : 1) void k_kernel_cols_group(const T* __restrict__ Xp,
                                                                const TN* __restrict__ xn, int64_t N,
                                                                int64_t dp, int tiles,
                                                                ColGroup<T, TN, TW> grp, int64_t ldw) {
@@ -1278,7 +1287,7 @@ __global__ __launch_bounds__(Cfg::NT) void k_kernel_cols_group(const T* __restri
   GOperand<T, true> B{grp.XSa[g], dp, nt, dp, nullptr, true};
   TileAcc<Cfg> acc;
   acc.zero();
-  tile_mainloop_direct<Cfg, kStages>(acc, A, B, m0, 0, 0, dp, N, MAXB, smem, nt, tile);
+  tile_mainloop_direct<Cfg, cols_stages<T>()>(acc, A, B, m0, 0, 0, dp, N, MAXB, smem, nt, tile);
   typedef typename Cfg::MM::acc_t AT;
   const AT ie = (AT)(1.0 / grp.eps[g]);
   const TN* nsa = grp.nsa[g];
@@ -1353,7 +1362,9 @@ static int run_factor_group(const rpc_points* X, const double* eps, const rpc_fa
   }
   const int tiles = (int)((N + 127) / 128);
   const unsigned blocks = (unsigned)(8 * ((tiles + 7) / 8) * G);
-  const size_t smK = DirectSmem<CfgK, kStages, true, true>::bytes;
+  constexpr size_t smC0 = DirectSmem<CfgK, cols_stages<T>(), true, true>::bytes;
+  constexpr size_t smC1 = ColStoreSmem<CfgK, TF>::bytes;
+  constexpr size_t smK = smC0 > smC1 ? smC0 : smC1;
   const int t = n_rounds(opts[0]);
   for (int i = 0; i < t; ++i) {
     for (int g = 0; g < G; ++g) phase_select(jobs[g], i, st);
