@@ -651,17 +651,17 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
     hipLaunchKernelGGL(k_fill_identity, dim3(nblk((int64_t)r * p)), dim3(256), 0, st, w.Q, r, p);
     // 12 orthonormalised products, then Rayleigh-Ritz + residual check; up to
     // 3 more rounds of 6 products if the check fails (device flag `conv`)
-    // The first products (from the identity start) can be ill-conditioned and
-    // get two column-scaled Cholesky QR passes; once the block spans the
-    // dominant subspace, Y = M Q has nearly orthogonal columns up to their
-    // scales and one scaled pass keeps Q orthonormal to working precision
-    // (the Rayleigh-Ritz residual check below guards the result).
+    // The first product (from the identity start) can be ill-conditioned and
+    // gets two column-scaled Cholesky QR passes; afterwards one scaled pass
+    // keeps the span of the block (its orthonormality is restored by every
+    // pass and checked where it matters, at the Rayleigh-Ritz step, whose
+    // residual check guards the result).
     int done = 0;
     auto products = [&](int count) {
       for (int in = 0; in < count; ++in, ++done) {
         dense::gemm64_splitk<false, true>(st, r, p, r, w.M, r, w.Q, r, w.Y, r, 1.0, 0.0, w.skq,
                                           w.conv);
-        if (done < 4) {
+        if (done < 1) {
           chol_qr(st, w.Y, w.Qt, r, p, w, status, w.conv);
           chol_qr(st, w.Qt, w.Q, r, p, w, status, w.conv);
         } else {
