@@ -67,7 +67,8 @@ typedef enum {
 /* RPC_F32_SPLIT16: float32 data whose products run on the fp16 MFMA pipe,
  * each operand split as hi = fp16(x) plus lo = fp16(x - hi) and each product
  * taken as hi hi + hi lo + lo hi (float32-grade, about 2^-22 relative per
- * product); accepted only as gram_dtype with a float32 factor. */
+ * product); accepted as gemm_dtype and as gram_dtype, in both cases with a
+ * float32 factor. */
 typedef enum { RPC_F64 = 0, RPC_F32 = 1, RPC_BF16 = 2, RPC_F32_SPLIT16 = 3 } rpc_dtype;
 
 typedef enum {
@@ -93,7 +94,13 @@ typedef struct {
  *               F64 (points upcast exactly), F32, or BF16 (points rounded to
  *               bf16; squared norms of the rounded points in fp32; the result
  *               is the exact Gaussian kernel of the rounded points up to fp32
- *               accumulation).  The pivot block H uses the same points.
+ *               accumulation), or F32_SPLIT16 (float32 points, the inner
+ *               products as split fp16 pairs after scaling both operands by
+ *               one power of two chosen from max |x| (exact): float32-grade
+ *               columns at the fp16 MFMA rate; the Schur update is split
+ *               likewise, the pivot-block solve stays float64; needs
+ *               factor_dtype F32).
+ *               The pivot block H uses the same points in float64.
  *  factor_dtype F64 or F32: storage of F and arithmetic of the Schur update.
  *               Pivot selection, the pivot-block Cholesky, the triangular
  *               solve and the residual diagonal are float64 in every mode.
@@ -189,7 +196,8 @@ int rpchol_factor(const rpc_points* X, const rpc_factor_opts* opts, void* F, int
  * one tile of rows run together, so X is read from HBM once per round for the
  * group (per-column bandwidth in the exp epilogue).  Every job must use the
  * same r, b, mode (SAMPLED or GREEDY), gemm_dtype, factor_dtype, tau and
- * flags, with RPC_FACTOR_SHARED_X set; uniforms and round_accepted may differ.
+ * flags, with RPC_FACTOR_SHARED_X set, and a gemm_dtype other than
+ * F32_SPLIT16; uniforms and round_accepted may differ.
  * Outputs are per job (host arrays of device pointers), each exactly what
  * rpchol_factor returns for that job alone (bit for bit); F leading
  * dimension ldf is common.  The workspace holds the converted points once and

@@ -26,7 +26,7 @@ STATUS_NAMES = {
     0: "RPC_OK", -1: "RPC_EINVAL", -2: "RPC_EWORKSPACE", -3: "RPC_EHIP", -4: "RPC_EDEGREE",
     -5: "RPC_EQDEGREE", -6: "RPC_EBREAKDOWN", -7: "RPC_ENONFINITE", -8: "RPC_ENOCONV",
 }
-DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "split16": 3}  # split16: float32 products as split fp16 pairs (Gram only)
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "split16": 3}  # split16: float32 products as split fp16 pairs
 MODES = {"sampled": 0, "greedy": 1, "replay": 2}
 
 

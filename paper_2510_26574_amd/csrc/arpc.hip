@@ -47,16 +47,19 @@ struct RoundState {
 // Xp[n][:] = points converted to the product type, zero-padded to dp columns;
 // xn[n] = squared norm of the converted row (computed in float64, stored in
 // the epilogue type).  Also initialises rho = 1 (diag of the Gaussian kernel),
-// pivots = -1 and the counters.
+// pivots = -1 and the counters.  xmax (optional, cleared beforehand): the
+// largest finite |x| over all points, as float bits (non-negative floats
+// order like their bit patterns).
 template <typename T, typename TN>
 __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, int64_t N, int64_t d,
                                               int64_t ldx, int64_t dp, T* __restrict__ Xp,
                                               TN* __restrict__ xn, double* __restrict__ rho,
-                                              int32_t* status) {
+                                              int32_t* status, unsigned* xmax) {
   const int lane = threadIdx.x & 63;
   const int64_t n = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (n >= N) return;
   double s = 0.0;
+  float amax = 0.0f;
   bool bad = false;
   // rows without padding, 8-float aligned: each lane converts 8 consecutive
   // columns per pass with two 16-byte loads and one vector store
@@ -71,6 +74,7 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, int64
       for (int e = 0; e < 8; ++e) {
         const float v = e < 4 ? u0[e] : u1[e - 4];
         if (!isfinite(v)) bad = true;
+        else amax = fmaxf(amax, fabsf(v));
         c[e] = cvt<T>(v);
         const double cd = to_d(c[e]);
         s += cd * cd;
@@ -81,6 +85,7 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, int64
     for (int64_t j = lane; j < dp; j += 64) {
       float v = j < d ? X[n * ldx + j] : 0.0f;
       if (!isfinite(v)) bad = true;
+      else amax = fmaxf(amax, fabsf(v));
       T c = cvt<T>(v);
       Xp[n * dp + j] = c;
       double cd = to_d(c);
@@ -89,11 +94,20 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, int64
   }
   s = wave_sum(s);
   if (__any(bad) && lane == 0) set_status(status, RPC_ENONFINITE);
+  if (xmax) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, RPC_WAVE));
+    // the running maximum settles early: most rows skip the atomic
+    if (lane == 0 && __float_as_uint(amax) > *(volatile unsigned*)xmax)
+      atomicMax(xmax, __float_as_uint(amax));
+  }
   if (lane == 0) {
     xn[n] = (TN)s;
     rho[n] = 1.0;
   }
 }
+
+__global__ void k_clear_u32(unsigned* p) { *p = 0u; }
 
 __global__ void k_init_small(int64_t* pivots, int r, int32_t* k, int32_t* nT, int32_t* stop) {
   for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < r; i += blockDim.x * gridDim.x) pivots[i] = -1;
@@ -681,6 +695,77 @@ __global__ __launch_bounds__(CfgK::NT, SPLIT ? 4 : 1) void k_cols_schur(const T*
                            [&](int, int, typename CfgS::MM::acc_t v) { return (TF)(-v); });
 }
 
+// ------------------------------------------------------------ split-fp16 distance product
+// The float32-grade form of the kernel columns: the points stay float32 and
+// the inner products <x, s> run on the fp16 MFMA pipe as split pairs (three
+// products, unit roundoff 2^-22), both operands scaled by one power of two
+// s_X chosen from max |x| (so that |x s_X| < 2^15; exact).  xmax is that
+// maximum as float bits, from the preparation pass.
+__device__ inline float point_scale(const unsigned* xmax) {
+  const float am = __uint_as_float(*xmax);
+  if (!(am > 0.0f) || !isfinite(am)) return 1.0f;
+  int e;
+  frexpf(am, &e);  // am = f 2^e, f in [0.5, 1)
+  e = e < -100 ? -100 : e;
+  return ldexpf(1.0f, 15 - e);
+}
+
+// SCHUR: W = K(X, X_S) - F(:, :k) F(S, :k)^T in one pass (the Schur product
+// split as in the mixed form's fused kernel); otherwise W = K(X, X_S).  Two
+// workgroups per CU: single-buffered split stages, at most 128 VGPRs.
+template <class Cfg, bool SCHUR>
+__global__ __launch_bounds__(Cfg::NT, 4) void k_cols_split(const float* __restrict__ Xp,
+                                                  const float* __restrict__ xn, int64_t N,
+                                                  int64_t dp, const float* __restrict__ XSa,
+                                                  const float* __restrict__ nsa,
+                                                  const int32_t* nTptr, double eps,
+                                                  const unsigned* xmax,
+                                                  const float* __restrict__ F, int64_t ldf,
+                                                  const float* __restrict__ FSa, int r,
+                                                  const int32_t* kptr, float* __restrict__ W,
+                                                  int64_t ldw) {
+  const int nt = *nTptr;
+  if (nt == 0) return;
+  extern __shared__ char smem_raw[];
+  const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM;
+  const float sx = point_scale(xmax), isx = 1.0f / sx;
+  TileAcc<Cfg> acc;
+  acc.zero();
+  {
+    SchurSplitPipe<Cfg, true> dist{Xp, dp, N, XSa, (int)dp, nt, (int)dp, m0, sx, sx};
+    dist.begin1();
+    dist.run1(acc, smem_raw);  // acc = s_X^2 <x, s>
+  }
+  const int k = SCHUR ? *kptr : 0;
+  SchurSplitPipe<Cfg> pipe{F, ldf, N, FSa, r, nt, k, m0};
+  if (k > 0) pipe.begin1();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % Cfg::WAVES_M, wn = wave / Cfg::WAVES_M;
+  const float ie = (float)(1.0 / eps);
+  // exp epilogue, negated and in the Schur product's units of 2^24
+#pragma unroll
+  for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+    for (int j = 0; j < Cfg::NI; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t m = m0 + wm * Cfg::WTM + i * 16 + Cfg::MM::row(lane, e);
+        const int n = wn * Cfg::WTN + j * 16 + (lane & 15);
+        float v = 0.0f;
+        if (m < N && n < nt) {
+          const float ip = acc.a[i][j][e] * isx * isx;  // two steps: s_X^-2 may underflow
+          float d2 = xn[m] + nsa[n] - 2.0f * ip;
+          d2 = d2 > 0.0f ? d2 : 0.0f;
+          v = -exp(-d2 * ie) * 16777216.0f;
+        }
+        acc.a[i][j][e] = v;
+      }
+  if (k > 0) pipe.run1(acc, smem_raw);
+  // run1 ends on a barrier, so the column staging may reuse the LDS
+  store_colmajor<Cfg, float>(acc, smem_raw, W, ldw, m0, 0, N, nt,
+                             [&](int, int, float v) { return -v * (1.0f / 16777216.0f); });
+}
+
 // ------------------------------------------------------------ solve + downdate
 // F(:, k + j) = G(:, j), rho = max(rho - sum_j G^2, 0), with
 // G = W L^{-T} tile: 128 rows x the whole block (<= 128 columns), eight
@@ -1015,6 +1100,7 @@ struct FactorWs {
   int32_t* nT;
   int32_t* stop;
   unsigned long long* tot;
+  unsigned* xmax;  // max |x| of the points (split-fp16 distance form)
   int64_t ldw;
   int64_t dp;
 };
@@ -1026,6 +1112,7 @@ static void carve_shared(WsCursor& c, FactorWs& w, int64_t N, int64_t d) {
   w.dp = (int64_t)align_up((size_t)d, 32);
   w.Xp = c.take<T>((size_t)N * w.dp);
   w.xn = c.take<TN>((size_t)N);
+  w.xmax = c.take<unsigned>(1);
 }
 
 template <typename T, typename TN, typename TF>
@@ -1165,6 +1252,32 @@ static void phase_columns(FJob<T, TN, TF>& j, hipStream_t st) {
   const size_t smS = DirectSmem<CfgS, kStages, false, true>::bytes;
   const size_t smKS = smK > smS ? smK : smS;
   const unsigned gm = (unsigned)((N + 127) / 128);
+  if constexpr (std::is_same<T, float>::value && std::is_same<TF, float>::value) {
+    if (j.o->gemm_dtype == RPC_F32_SPLIT16) {
+      // float32 points, split-fp16 distance and Schur products
+      typedef typename FCfg<__bf16, float>::K Cfg;
+      constexpr size_t sm = SchurSplit::bytes / 2 > ColStoreSmem<Cfg, float>::bytes
+                                ? SchurSplit::bytes / 2 : ColStoreSmem<Cfg, float>::bytes;
+      static_assert(2 * sm <= 160 * 1024, "two workgroups per CU");
+      const bool fused = !(j.o->flags & (RPC_FACTOR_UNFUSED | RPC_FACTOR_SHARED_X));
+      prof::begin(prof::KERNEL_COLS, st);
+      if (fused)
+        hipLaunchKernelGGL((k_cols_split<Cfg, true>), dim3(gm), dim3(Cfg::NT), sm, st,
+                           (const float*)w.Xp, (const float*)w.xn, N, w.dp, (const float*)w.XSa,
+                           (const float*)w.nsa, w.nT, j.X.eps, (const unsigned*)w.xmax,
+                           (const float*)j.F, j.ldf, (const float*)w.FSa, j.o->r, j.k_out,
+                           (float*)w.W, w.ldw);
+      else
+        hipLaunchKernelGGL((k_cols_split<Cfg, false>), dim3(gm), dim3(Cfg::NT), sm, st,
+                           (const float*)w.Xp, (const float*)w.xn, N, w.dp, (const float*)w.XSa,
+                           (const float*)w.nsa, w.nT, j.X.eps, (const unsigned*)w.xmax,
+                           (const float*)j.F, j.ldf, (const float*)w.FSa, j.o->r, j.k_out,
+                           (float*)w.W, w.ldw);
+      prof::end(prof::KERNEL_COLS, st);
+      if (!fused) phase_schur(j, st);
+      return;
+    }
+  }
   if constexpr (kFusedColsSchur<T, TF>) {
     if (!(j.o->flags & (RPC_FACTOR_UNFUSED | RPC_FACTOR_SHARED_X))) {
       prof::begin(prof::KERNEL_COLS, st);
@@ -1204,8 +1317,12 @@ static void phase_solve(FJob<T, TN, TF>& j, int i, hipStream_t st) {
   FactorWs& w = j.w;
   const size_t smD = TileSmem<CfgD, false, true>::bytes;
   prof::begin(prof::SOLVE, st);
-  if constexpr (std::is_same<T, __bf16>::value && std::is_same<TF, float>::value) {
-    // mixed form: the solve on the fp16 pipe as split pairs
+  // mixed form: the solve on the fp16 pipe as split pairs.  The float32-grade
+  // forms (float32 and split-fp16 distances) keep the float64 solve: it
+  // multiplies the columns' rounding errors by up to the condition of the
+  // pivot block, and a split product's 2^-22 there dominates their error.
+  constexpr bool split = std::is_same<T, __bf16>::value && std::is_same<TF, float>::value;
+  if (split) {
     hipLaunchKernelGGL(k_split_linv, dim3(1), dim3(256), 0, st, (const double*)w.Linv, w.nT, w.Lh,
                        w.Ll, w.lsc);
     hipLaunchKernelGGL(k_solve_split, dim3((unsigned)((N + MAXB - 1) / MAXB)), dim3(512),
@@ -1231,8 +1348,11 @@ static int run_factor(const rpc_points* X, const rpc_factor_opts* o, TF* F, int6
   carve<T, TN, TF>(cur, j.w, X->N, X->d, o->r);
   if (!cur.ok) return RPC_EWORKSPACE;
   const int64_t N = X->N;
+  const bool split = o->gemm_dtype == RPC_F32_SPLIT16;
+  if (split) hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(1), 0, st, j.w.xmax);
   hipLaunchKernelGGL((k_prep<T, TN>), dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, X->X, N,
-                     X->d, X->ldx, j.w.dp, (T*)j.w.Xp, (TN*)j.w.xn, rho, status);
+                     X->d, X->ldx, j.w.dp, (T*)j.w.Xp, (TN*)j.w.xn, rho, status,
+                     split ? j.w.xmax : nullptr);
   hipLaunchKernelGGL(k_init_small, dim3(1), dim3(256), 0, st, pivots, o->r, k_out, j.w.nT, j.w.stop);
   RPC_LAUNCH_CHECK();
   const int t = n_rounds(o);
@@ -1341,7 +1461,7 @@ static int run_factor_group(const rpc_points* X, const double* eps, const rpc_fa
   const int64_t dp = shared.dp;
   // the points are converted once; every job starts from rho = 1
   hipLaunchKernelGGL((k_prep<T, TN>), dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, X->X, N,
-                     X->d, X->ldx, dp, (T*)shared.Xp, (TN*)shared.xn, rho[0], status[0]);
+                     X->d, X->ldx, dp, (T*)shared.Xp, (TN*)shared.xn, rho[0], status[0], nullptr);
   for (int g = 0; g < G; ++g) {
     if (g > 0) {
       hipLaunchKernelGGL(k_fill_rho, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, rho[g], N);
@@ -1389,10 +1509,12 @@ static int check_factor_args(const rpc_points* X, const rpc_factor_opts* o) {
   if (o->r < 1 || o->r > X->N || o->b < 1 || o->b > MAXB) return RPC_EINVAL;
   if (o->mode == RPC_GREEDY && o->b != 1) return RPC_EINVAL;
   if (o->mode != RPC_SAMPLED && o->mode != RPC_GREEDY && o->mode != RPC_REPLAY) return RPC_EINVAL;
-  if (o->gemm_dtype != RPC_F64 && o->gemm_dtype != RPC_F32 && o->gemm_dtype != RPC_BF16)
+  if (o->gemm_dtype != RPC_F64 && o->gemm_dtype != RPC_F32 && o->gemm_dtype != RPC_BF16 &&
+      o->gemm_dtype != RPC_F32_SPLIT16)
     return RPC_EINVAL;
   if (o->factor_dtype != RPC_F64 && o->factor_dtype != RPC_F32) return RPC_EINVAL;
   if (o->gemm_dtype == RPC_F64 && o->factor_dtype != RPC_F64) return RPC_EINVAL;
+  if (o->gemm_dtype == RPC_F32_SPLIT16 && o->factor_dtype != RPC_F32) return RPC_EINVAL;
   if (o->mode == RPC_SAMPLED) {
     const int64_t t = (o->r + o->b - 1) / o->b;
     if (!o->uniforms || o->n_uniforms < 2 * (int64_t)o->b * t) return RPC_EINVAL;
@@ -1409,6 +1531,7 @@ static int check_factor_args(const rpc_points* X, const rpc_factor_opts* o) {
 template <typename Fn>
 static int dispatch(const rpc_factor_opts* o, Fn&& fn) {
   if (o->gemm_dtype == RPC_F64) return fn((double*)0, (double*)0, (double*)0);
+  if (o->gemm_dtype == RPC_F32_SPLIT16) return fn((float*)0, (float*)0, (float*)0);
   if (o->gemm_dtype == RPC_F32) {
     if (o->factor_dtype == RPC_F32) return fn((float*)0, (float*)0, (float*)0);
     return fn((float*)0, (float*)0, (double*)0);
@@ -1465,7 +1588,7 @@ int check_group_args(const rpc_points* X, const double* eps, const rpc_factor_op
     const rpc_factor_opts* a = opts[0];
     const rpc_factor_opts* o = opts[g];
     if (!(o->flags & RPC_FACTOR_SHARED_X)) return RPC_EINVAL;
-    if (o->mode == RPC_REPLAY) return RPC_EINVAL;
+    if (o->mode == RPC_REPLAY || o->gemm_dtype == RPC_F32_SPLIT16) return RPC_EINVAL;
     if (o->r != a->r || o->b != a->b || o->mode != a->mode || o->gemm_dtype != a->gemm_dtype ||
         o->factor_dtype != a->factor_dtype || o->tau != a->tau || o->flags != a->flags)
       return RPC_EINVAL;
@@ -1481,6 +1604,7 @@ extern "C" int rpchol_factor_group_workspace_size(const rpc_points* X, const rpc
   X1.eps = 1.0;
   int rc = check_factor_args(&X1, o);
   if (rc) return rc;
+  if (o->gemm_dtype == RPC_F32_SPLIT16) return RPC_EINVAL;  // not offered for groups
   return dispatch(o, [&](auto* t, auto* tn, auto* tf) {
     typedef typename std::remove_pointer<decltype(t)>::type T;
     typedef typename std::remove_pointer<decltype(tn)>::type TN;

@@ -52,7 +52,10 @@ __device__ inline void split8(const float (&x)[8], v8h_t& hi, v8h_t& lo,
 // while the MFMAs consume stage s, and stage s + 1 is converted into LDS after
 // them.  begin() issues the reads of the first two stages, so a caller can
 // overlap their latency with other work before run().
-template <class Cfg>
+// A_ROWS: A is k-contiguous too (A[m * ldf + l], the points of a distance
+// product), loaded like B: thread t holds row t / 4 at k groups t % 4 and
+// t % 4 + 4.
+template <class Cfg, bool A_ROWS = false>
 struct SchurSplitPipe {
   static_assert(Cfg::NT == 512 && Cfg::BM == 128 && Cfg::BN == 128, "eight waves, 128 x 128");
   static constexpr int BK = SchurSplit::BK, LDK = SchurSplit::LDK, EL = SchurSplit::ELEMS;
@@ -61,50 +64,61 @@ struct SchurSplitPipe {
   const float* __restrict__ FSa;
   int r, nt, k;
   int64_t m0;
-  float bsc = SchurSplit::SC;  // power-of-two scale of the B operand (A: SchurSplit::SC)
+  float bsc = SchurSplit::SC;  // power-of-two scale of the B operand
+  float asc = SchurSplit::SC;  // and of the A operand
   float a0[2][8], b0[2][8], a1[2][8], b1[2][8];
 
-  __device__ inline void load(float (&a)[2][8], float (&b)[2][8], int kb) const {
-    const int tid = threadIdx.x;
-    const int arow = tid & 127, ag = tid >> 7;
-    const int brow = tid >> 2, bg = tid & 3;
-    const int64_t am = m0 + arow;
+  // rows [row of this thread] of a k-contiguous operand (stride ld, `rows`
+  // rows), 8 consecutive k at k groups g and g + 4 of the stage at kb
+  __device__ inline void load_rows(float (&x)[2][8], const float* __restrict__ P, int64_t ld,
+                                   int64_t row, int64_t rows, int kb, int g) const {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int k0 = kb + 8 * (ag + 4 * h);
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-        a[h][e] = (am < N && k0 + e < k) ? F[am + (int64_t)(k0 + e) * ldf] : 0.0f;
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k0 = kb + 8 * (bg + 4 * h);
-      const float* p = FSa + (int64_t)brow * r + k0;
-      if (brow < nt && k0 + 8 <= k && (r % 4) == 0) {
+      const int k0 = kb + 8 * (g + 4 * h);
+      const float* p = P + row * ld + k0;
+      if (row < rows && k0 + 8 <= k && (ld % 4) == 0) {
         const v4f u = *reinterpret_cast<const v4f*>(p);
         const v4f w = *reinterpret_cast<const v4f*>(p + 4);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          b[h][e] = u[e];
-          b[h][4 + e] = w[e];
+          x[h][e] = u[e];
+          x[h][4 + e] = w[e];
         }
       } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) b[h][e] = (brow < nt && k0 + e < k) ? p[e] : 0.0f;
+        for (int e = 0; e < 8; ++e) x[h][e] = (row < rows && k0 + e < k) ? p[e] : 0.0f;
       }
     }
+  }
+
+  __device__ inline void load(float (&a)[2][8], float (&b)[2][8], int kb) const {
+    const int tid = threadIdx.x;
+    if constexpr (A_ROWS) {
+      load_rows(a, F, ldf, m0 + (tid >> 2), N, kb, tid & 3);
+    } else {
+      const int arow = tid & 127, ag = tid >> 7;
+      const int64_t am = m0 + arow;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k0 = kb + 8 * (ag + 4 * h);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          a[h][e] = (am < N && k0 + e < k) ? F[am + (int64_t)(k0 + e) * ldf] : 0.0f;
+      }
+    }
+    load_rows(b, FSa, r, tid >> 2, nt, kb, tid & 3);
   }
 
   __device__ inline void store(const float (&a)[2][8], const float (&b)[2][8], _Float16* sm,
                                int buf) const {
     const int tid = threadIdx.x;
-    const int arow = tid & 127, ag = tid >> 7;
+    const int arow = A_ROWS ? tid >> 2 : tid & 127, ag = A_ROWS ? tid & 3 : tid >> 7;
     const int brow = tid >> 2, bg = tid & 3;
     _Float16* base = sm + (size_t)buf * 4 * EL;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       v8h_t hi, lo;
-      split8(a[h], hi, lo);
+      split8(a[h], hi, lo, asc);
       const int o = arow * LDK + 8 * (ag + 4 * h);
       *reinterpret_cast<v8h_t*>(base + o) = hi;
       *reinterpret_cast<v8h_t*>(base + EL + o) = lo;

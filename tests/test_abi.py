@@ -57,6 +57,7 @@ def test_host_side_validation(lib):
         dict(gemm_dtype=7),
         dict(factor_dtype=2),  # bf16 storage of F is not offered
         dict(flags=4),         # unknown option bit
+        dict(gemm_dtype=3),    # split-fp16 distances need a float32 factor
     ]
     for kw in bad:
         o = rp.rpc_factor_opts(8, 2, rp.MODES["sampled"], 0, 0, 0, 0.0, 0x2000, 64, 0, 0, 0)
@@ -80,6 +81,12 @@ def test_host_side_validation(lib):
     assert lib.nystrom_extend_workspace_size(10, 3, 64, 65, ctypes.byref(nb)) == rp.RPC_EINVAL
     o = rp.rpc_factor_opts(8, 2, rp.MODES["sampled"], 0, 0, rp.RPC_FACTOR_UNFUSED, 0.0, 0x2000, 64, 0, 0, 0)
     assert lib.rpchol_factor_workspace_size(ctypes.byref(pts), ctypes.byref(o), ctypes.byref(nb)) == 0
+    o = rp.rpc_factor_opts(8, 2, rp.MODES["sampled"], rp.DTYPES["split16"], rp.DTYPES["f32"], 0, 0.0,
+                           0x2000, 64, 0, 0, 0)  # split-fp16 distances, float32 factor
+    assert lib.rpchol_factor_workspace_size(ctypes.byref(pts), ctypes.byref(o), ctypes.byref(nb)) == 0
+    o.flags = rp.RPC_FACTOR_SHARED_X  # not offered for a group on shared points
+    assert lib.rpchol_factor_group_workspace_size(ctypes.byref(pts), ctypes.byref(o), 2,
+                                                  ctypes.byref(nb)) == rp.RPC_EINVAL
     # group of factorisations on shared points: sizes and option checks (host side only)
     og = rp.rpc_factor_opts(8, 2, rp.MODES["sampled"], 0, 0, rp.RPC_FACTOR_SHARED_X, 0.0, 0x2000, 64, 0, 0, 0)
     n1 = ctypes.c_size_t(0)

@@ -159,3 +159,45 @@ def test_degrees_and_eigenpairs(run):
     assert abs(lam[0].item() - 1.0) <= EIG
     assert u1 <= ANG
     assert torch.all(lam[:-1] >= lam[1:]).item()
+
+
+def test_split16_distance_form(run):
+    """The float32-grade form (float32 points, split-fp16 distance and Schur
+    products) at full size: round 0 against the oracle on the float32 points
+    (the proposal block and Algorithm 3 in float64 on both sides), and F at
+    sampled rows, after round 0 and whole against the closed form
+    K(n, S) chol(K(S, S))^{-T}, to 2e-4 (the float32 kernel-entry bar 5e-5
+    times 4 for the split form's unit roundoff 2^-22)."""
+    import paper_2510_26574_amd as rp
+
+    torch, X, eps, u = run["torch"], run["X"], run["eps"], run["u"]
+    out = rp.rpchol_factor(torch.from_numpy(X).cuda(), eps, R, B, uniforms=torch.from_numpy(u).cuda(),
+                           gemm_dtype="split16", factor_dtype="f32")
+    st = rp.status_sync(out["status"])
+    assert st == 0, rp.STATUS_NAMES.get(st, st)
+
+    def Xf(idx):
+        return X[np.asarray(idx, dtype=np.int64)].astype(np.float64)
+
+    rho_q = oracle.quantize_rho(np.ones(N)).tolist()
+    props = np.array([oracle.inverse_cdf_pivot(rho_q, u[j]) for j in range(B)], dtype=np.int64)
+    H = oracle.gaussian_kernel(Xf(props), Xf(props), eps)
+    T, L = oracle.accept_reject(H, u[B:2 * B], props)
+    S0 = props[np.asarray(T, dtype=np.int64)]
+    nt0 = len(S0)
+    piv = out["pivots"].cpu().numpy()
+    assert out["round_accepted"][0].item() == nt0 and np.array_equal(piv[:nt0], S0)
+    rows = _rows(seed=5)
+    F0 = sla.solve_triangular(L, oracle.gaussian_kernel(Xf(rows), Xf(S0), eps).T, lower=True).T
+    Fg = out["F"][rows][:, :nt0].double().cpu().numpy()
+    err0 = np.abs(Fg - F0).max() / np.abs(F0).max()
+    k = int(out["k"].item())
+    S = piv[:k]
+    assert len(np.unique(S)) == k
+    Lc = np.linalg.cholesky(oracle.gaussian_kernel(Xf(S), Xf(S), eps))
+    rows = _rows(1000, seed=6)
+    Fc = sla.solve_triangular(Lc, oracle.gaussian_kernel(Xf(rows), Xf(S), eps).T, lower=True).T
+    err = np.abs(out["F"][rows][:, :k].double().cpu().numpy() - Fc).max() / np.abs(Fc).max()
+    print(f"split16 distances: round 0 F error {err0:.3g}; k = {k}, closed-form F error {err:.3g}")
+    assert err0 <= 2e-4
+    assert err <= 2e-4

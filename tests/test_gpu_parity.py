@@ -142,14 +142,20 @@ def _ks_case(n=2000, seed=0, q=8):
     return X, median_sq_distance(X, seed=seed)
 
 
-@pytest.mark.parametrize("gdt,fdt,ftol", [("f32", "f32", 5e-5), ("bf16", "f32", 1e-2)])
-def test_replay_reduced_precision(gpu, gdt, fdt, ftol):
-    X, eps = _torus_case(seed=4) if gdt == "f32" else _ks_case(seed=4)
+# split16: float32 points with split-fp16 distance and Schur products (unit
+# roundoff 2^-22 per product), so 4 x the float32 bar
+@pytest.mark.parametrize("gdt,fdt,case,ftol", [("f32", "f32", "torus", 5e-5), ("bf16", "f32", "ks", 1e-2),
+                                               ("split16", "f32", "torus", 2e-4),
+                                               ("split16", "f32", "ks", 2e-4)])
+def test_replay_reduced_precision(gpu, gdt, fdt, case, ftol):
+    X, eps = _torus_case(seed=4) if case == "torus" else _ks_case(seed=4)
     u = uniform_stream(2 * 16 * 4, seed=4)
     ref = oracle.arpc(X, eps, r=64, b=16, mode="sampled", uniforms=u)
     out, k, F, piv, rho = _run_factor(gpu, X, eps, 64, 16, "replay", replay=ref["S"], gdt=gdt, fdt=fdt)
     assert k == ref["k"]
-    assert np.abs(F[:, :k] - ref["F"]).max() / np.abs(ref["F"]).max() < ftol
+    err = np.abs(F[:, :k] - ref["F"]).max() / np.abs(ref["F"]).max()
+    print(f"{gdt}/{case}: F error {err:.3g}")
+    assert err < ftol
 
 
 def _eig_case(gpu, X, eps, r, b, nev, seed, gdt="f64", fdt="f64", gram="f64", fix_const=False):
@@ -198,23 +204,26 @@ def test_eig_fix_const(gpu):
     assert _angle(U, res["U"]) < 1e-8
 
 
-@pytest.mark.parametrize("gdt,fdt,gram,ltol,atol", [
-    ("f32", "f32", "f32", 1e-6, 1e-4),
-    ("bf16", "f32", "f32", 1e-3, 1e-2),
+@pytest.mark.parametrize("gdt,fdt,gram,case,ltol,atol", [
+    ("f32", "f32", "f32", "torus", 1e-6, 1e-4),
+    ("bf16", "f32", "f32", "ks", 1e-3, 1e-2),
     # the split-fp16 Gram keeps 22 of float32's 24 bits per operand (unit
     # roundoff 2^-22 = 4 x float32's), so its bars are 4 x the float32 ones
-    ("f32", "f32", "split16", 4e-6, 4e-4),
-    ("bf16", "f32", "split16", 1e-3, 1e-2),
+    ("f32", "f32", "split16", "torus", 4e-6, 4e-4),
+    ("bf16", "f32", "split16", "ks", 1e-3, 1e-2),
+    # split-fp16 distances, Schur products and Grams: the same 2^-22 bars
+    ("split16", "f32", "split16", "torus", 4e-6, 4e-4),
+    ("split16", "f32", "split16", "ks", 4e-6, 4e-4),
 ])
-def test_eig_reduced_precision(gpu, gdt, fdt, gram, ltol, atol):
-    X, eps = _torus_case(seed=6) if gdt == "f32" else _ks_case(seed=6)
+def test_eig_reduced_precision(gpu, gdt, fdt, gram, case, ltol, atol):
+    X, eps = _torus_case(seed=6) if case == "torus" else _ks_case(seed=6)
     nev = 16
     ref, out, deg, eig, res = _eig_case(gpu, X, eps, 64, 16, nev, seed=23, gdt=gdt, fdt=fdt, gram=gram)
     lam = eig["lam"].cpu().numpy()
     m = _gap_index(res["lam_all"], nev)
     le = np.abs(lam / res["lam"] - 1).max()
     ae = _angle(eig["U"].cpu().numpy()[:, :m], res["U"][:, :m])
-    print(f"{gdt}/{gram}: eigenvalue error {le:.3g}, angle {ae:.3g}")
+    print(f"{gdt}/{gram}/{case}: eigenvalue error {le:.3g}, angle {ae:.3g}")
     assert le < ltol
     assert ae < atol
 
@@ -311,9 +320,11 @@ def test_repeat_runs_bitwise_identical(gpu):
     assert k1 == k2 and np.array_equal(p1, p2) and np.array_equal(F1, F2) and np.array_equal(r1, r2)
 
 
-def test_unfused_columns_and_schur_agree(gpu):
+@pytest.mark.parametrize("gdt", ["bf16", "split16"])
+def test_unfused_columns_and_schur_agree(gpu, gdt):
     """The two-kernel path (kernel columns, then the Schur update) and the fused
-    kernel give the same factor to float32 rounding (the fp32 bar, 5e-5)."""
+    kernel give the same factor to float32 rounding (the fp32 bar, 5e-5; the
+    split form's fused Schur product is split, the separate one float32)."""
     torch, rp = gpu
     from synth import ks_points
 
@@ -322,18 +333,44 @@ def test_unfused_columns_and_schur_agree(gpu):
     u = uniform_stream(2 * 128, seed=21)
     Xd = torch.from_numpy(X).cuda()
     ud = torch.from_numpy(u).cuda()
-    fused = rp.rpchol_factor(Xd, eps, 128, 32, uniforms=ud, gemm_dtype="bf16", factor_dtype="f32")
+    fused = rp.rpchol_factor(Xd, eps, 128, 32, uniforms=ud, gemm_dtype=gdt, factor_dtype="f32")
     assert rp.status_sync(fused["status"]) == 0
     k = int(fused["k"].item())
     rep = fused["pivots"][:k].clone()
-    un = rp.rpchol_factor(Xd, eps, 128, 32, mode="replay", replay=rep, gemm_dtype="bf16",
+    un = rp.rpchol_factor(Xd, eps, 128, 32, mode="replay", replay=rep, gemm_dtype=gdt,
                           factor_dtype="f32", unfused=True)
-    fu = rp.rpchol_factor(Xd, eps, 128, 32, mode="replay", replay=rep, gemm_dtype="bf16",
+    fu = rp.rpchol_factor(Xd, eps, 128, 32, mode="replay", replay=rep, gemm_dtype=gdt,
                           factor_dtype="f32")
     assert rp.status_sync(un["status"]) == 0 and rp.status_sync(fu["status"]) == 0
     a = un["F"][:, :k].double().cpu().numpy()
     b = fu["F"][:, :k].double().cpu().numpy()
+    print(f"{gdt}: unfused vs fused {np.abs(a - b).max() / np.abs(b).max():.3g}")
     assert np.abs(a - b).max() <= 5e-5 * np.abs(b).max()
+
+
+@pytest.mark.parametrize("e", [20, -20])
+def test_split16_distances_scale_free(gpu, e):
+    """The split-fp16 distance form scales both operands by a power of two
+    chosen from max |x|: points scaled by 2^e with eps scaled by 2^(2e) give
+    the same kernel, and the same factor and pivots bit for bit (every scaling
+    on the way is exact)."""
+    torch, rp = gpu
+    from synth import ks_points
+
+    X = ks_points(3000, q=6, seed=31)
+    eps = median_sq_distance(X, seed=31)
+    u = uniform_stream(2 * 32 * 3, seed=31)
+    ud = torch.from_numpy(u).cuda()
+    outs = []
+    for s in (0, e):
+        Xs = (X.astype(np.float64) * 2.0 ** s).astype(np.float32)
+        o = rp.rpchol_factor(torch.from_numpy(Xs).cuda(), eps * 4.0 ** s, 96, 32, uniforms=ud,
+                             gemm_dtype="split16", factor_dtype="f32")
+        assert rp.status_sync(o["status"]) == 0
+        outs.append(o)
+    a, b = outs
+    assert a["k"].item() == b["k"].item()
+    assert torch.equal(a["pivots"], b["pivots"]) and torch.equal(a["F"], b["F"])
 
 
 def _sym_case(gpu, X, eps, r, b, nev, seed, gram="f64"):
