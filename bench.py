@@ -232,6 +232,34 @@ def kernel_columns(rp, torch, Xd, eps, ud, w, d, steps):
             "traffic": pmc_traffic("k_kernel_cols")}
 
 
+def factor_forms(rp, torch, Xd, eps, ud, w, reps=3):
+    """The factorisation alone (rpchol_factor, float32 factor) in its three
+    product forms: bf16 distances (the benchmark's), split-fp16 distances
+    (float32-grade at the fp16 MFMA rate) and float32 MFMA distances.  Each
+    form's F is compared with the float64 path replaying that form's pivots."""
+    res = {}
+    for gemm in ("bf16", "split16", "f32"):
+        def run():
+            return rp.rpchol_factor(Xd, eps, w["r"], w["b"], uniforms=ud, gemm_dtype=gemm,
+                                    factor_dtype="f32")
+        out = run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = run()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        st = rp.status_sync(out["status"])
+        k = int(out["k"].item())
+        ref = rp.rpchol_factor(Xd, eps, w["r"], w["b"], mode="replay", replay=out["pivots"][:k].clone(),
+                               gemm_dtype="f64", factor_dtype="f64")
+        F64 = ref["F"][:, :k]
+        err = ((out["F"][:, :k].double() - F64).abs().max() / F64.abs().max()).item()
+        res[gemm] = {"ms": dt * 1e3, "k": k, "status": st, "F_rel_err_vs_fp64_replay": err}
+        del out, ref, F64
+    return res
+
+
 def cpu_baseline(X, eps, w, n_sample):
     """The float64 oracle timed on a leading-row sample, scaled linearly in N."""
     import oracle
@@ -666,6 +694,8 @@ def main():
         roof_p, per_kernel_p = roofline(w, X.shape[1], res_p, prof_p, args.steps, plain)
     log("[bench] kernel columns alone (unfused path)")
     kcols = kernel_columns(rp, torch, Xd, eps, ud, w, X.shape[1], args.steps)
+    log("[bench] factorisation product forms")
+    forms = factor_forms(rp, torch, Xd, eps, ud, w)
     log("[bench] parity check")
     par = parity(rp, torch, Xd, eps, w, res_m)
     cpu = None
@@ -688,6 +718,7 @@ def main():
         "speedup_vs_plain_fp64": (t_plain / t_mixed) if t_plain else None,
         "roofline": roof,
         "kernel_columns_bf16": kcols,
+        "factor_forms": forms,
         "cpu_baseline": cpu,
         "kernels_mixed": per_kernel,
         "kernels_plain_fp64": per_kernel_p if t_plain else None,
