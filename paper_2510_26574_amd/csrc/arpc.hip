@@ -603,8 +603,9 @@ __global__ __launch_bounds__(Cfg::NT) void k_schur(const TF* __restrict__ F, int
 // into the same accumulators: W is written once instead of written, read
 // and written again.
 // SPLIT: the mixed form's variant, sized for two workgroups per CU (four
-// waves per SIMD: at most 128 VGPRs; two
-// direct stages for the distance product, the single-buffer split Schur).
+// waves per SIMD: at most 128 VGPRs; two direct stages for the distance
+// product, then the single-buffer split Schur product with only F in the
+// register ring).
 template <typename T, typename TN, typename TF, class CfgK, class CfgS, bool SPLIT>
 __global__ __launch_bounds__(CfgK::NT, SPLIT ? 4 : 1) void k_cols_schur(const T* __restrict__ Xp,
                                                     const TN* __restrict__ xn, int64_t N,
@@ -634,11 +635,11 @@ __global__ __launch_bounds__(CfgK::NT, SPLIT ? 4 : 1) void k_cols_schur(const T*
         acc, A, B, m0, 0, 0, dp, N, MAXB, reinterpret_cast<typename CfgK::T*>(smem_raw), nt,
         (int)blockIdx.x);
   }
-  // split form: the first two stages of the Schur reads go out before the
-  // exp epilogue, which hides their latency
+  // split form: the first stage of the Schur product's F reads goes out
+  // before the exp epilogue, which hides its latency
   SchurSplitPipe<CfgK> pipe{(const float*)F, ldf, N, (const float*)FSa, r, nt, k, m0};
   if constexpr (SPLIT) {
-    if (k > 0) pipe.begin1();
+    if (k > 0) pipe.begin1a();
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave % CfgK::WAVES_M, wn = wave / CfgK::WAVES_M;
@@ -671,7 +672,7 @@ __global__ __launch_bounds__(CfgK::NT, SPLIT ? 4 : 1) void k_cols_schur(const T*
         for (int j = 0; j < CfgK::NI; ++j)
 #pragma unroll
           for (int e = 0; e < 4; ++e) acc.a[i][j][e] *= 16777216.0f;
-      pipe.run1(acc, smem_raw);
+      pipe.run1b(acc, smem_raw);
 #pragma unroll
       for (int i = 0; i < CfgK::MI; ++i)
 #pragma unroll
@@ -738,7 +739,7 @@ __global__ __launch_bounds__(Cfg::NT, 4) void k_cols_split(const float* __restri
   }
   const int k = SCHUR ? *kptr : 0;
   SchurSplitPipe<Cfg> pipe{F, ldf, N, FSa, r, nt, k, m0};
-  if (k > 0) pipe.begin1();
+  if (k > 0) pipe.begin1a();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave % Cfg::WAVES_M, wn = wave / Cfg::WAVES_M;
   const float ie = (float)(1.0 / eps);
@@ -760,8 +761,8 @@ __global__ __launch_bounds__(Cfg::NT, 4) void k_cols_split(const float* __restri
         }
         acc.a[i][j][e] = v;
       }
-  if (k > 0) pipe.run1(acc, smem_raw);
-  // run1 ends on a barrier, so the column staging may reuse the LDS
+  if (k > 0) pipe.run1b(acc, smem_raw);
+  // run1 and run1b end on a barrier, so the column staging may reuse the LDS
   store_colmajor<Cfg, float>(acc, smem_raw, W, ldw, m0, 0, N, nt,
                              [&](int, int, float v) { return -v * (1.0f / 16777216.0f); });
 }

@@ -91,7 +91,7 @@ struct SchurSplitPipe {
     }
   }
 
-  __device__ inline void load(float (&a)[2][8], float (&b)[2][8], int kb) const {
+  __device__ inline void load_a(float (&a)[2][8], int kb) const {
     const int tid = threadIdx.x;
     if constexpr (A_ROWS) {
       load_rows(a, F, ldf, m0 + (tid >> 2), N, kb, tid & 3);
@@ -106,7 +106,14 @@ struct SchurSplitPipe {
           a[h][e] = (am < N && k0 + e < k) ? F[am + (int64_t)(k0 + e) * ldf] : 0.0f;
       }
     }
+  }
+  __device__ inline void load_b(float (&b)[2][8], int kb) const {
+    const int tid = threadIdx.x;
     load_rows(b, FSa, r, tid >> 2, nt, kb, tid & 3);
+  }
+  __device__ inline void load(float (&a)[2][8], float (&b)[2][8], int kb) const {
+    load_a(a, kb);
+    load_b(b, kb);
   }
 
   __device__ inline void store(const float (&a)[2][8], const float (&b)[2][8], _Float16* sm,
@@ -183,6 +190,30 @@ struct SchurSplitPipe {
       compute(acc, sm, 0);
       __syncthreads();  // every wave is done with the buffer (the caller reuses it too)
       if (s + 1 < ns) {
+        store(a0, b0, sm, 0);
+        __syncthreads();
+      }
+    }
+  }
+
+  // Single-buffer form with only A in the register ring: B (a few hundred KB
+  // shared by every workgroup, so served from L2) is read after the stage's
+  // MFMAs, which keeps its 16 registers out of the loop's live set (the
+  // fused column kernels then fit 128 VGPRs without spilling).
+  __device__ inline void begin1a() { load_a(a0, 0); }
+  __device__ inline void run1b(TileAcc<Cfg>& acc, char* smem_raw) {
+    _Float16* sm = reinterpret_cast<_Float16*>(smem_raw);
+    const int ns = (k + BK - 1) / BK;
+    __syncthreads();  // the LDS may still be read by the preceding product
+    load_b(b0, 0);
+    store(a0, b0, sm, 0);
+    __syncthreads();
+    for (int s = 0; s < ns; ++s) {
+      if (s + 1 < ns) load_a(a0, (s + 1) * BK);
+      compute(acc, sm, 0);
+      __syncthreads();  // every wave is done with the buffer (the caller reuses it too)
+      if (s + 1 < ns) {
+        load_b(b0, (s + 1) * BK);
         store(a0, b0, sm, 0);
         __syncthreads();
       }
