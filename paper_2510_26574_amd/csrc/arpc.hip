@@ -496,24 +496,35 @@ __global__ __launch_bounds__(1024) void k_accept_reject(
   if (tid == 0) *nTptr = nt;
 }
 
-// L^{-1} of the accepted block, one workgroup (one wave) per column c, by
-// right-looking forward substitution L x = e_c: lane l keeps x_l and
+// L^{-1} of the accepted block, one workgroup per column c: four waves stage
+// the rows of L it needs, then the first wave runs the right-looking forward
+// substitution L x = e_c: lane l keeps x_l and
 // x_{l+64}; once x_j = b_j / L(j,j) is known it is broadcast and every row
 // i > j subtracts L(i,j) x_j, so a row costs one broadcast and two
 // multiply-adds instead of a wave reduction.
-__global__ __launch_bounds__(64) void k_tri_inv(const double* __restrict__ Lc,
-                                                const int32_t* nTptr, double* __restrict__ Linv) {
+__global__ __launch_bounds__(256) void k_tri_inv(const double* __restrict__ Lc,
+                                                 const int32_t* nTptr, double* __restrict__ Linv) {
   constexpr int LDS = MAXB + 1;  // column walks (lane i reading L(i, j)) spread over banks
   __shared__ double Ls[MAXB * LDS];
   __shared__ double rd[MAXB];
-  const int c = blockIdx.x, lane = threadIdx.x;
+  const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   const int nt = *nTptr;
+  if (c < nt) {
+    // rows c .. nt-1 of L, entries c .. j of row j; whole rows are read so
+    // that the four waves' loads coalesce and many are in flight at once
+    const int rows = nt - c;
+#pragma unroll 4
+    for (int e = tid; e < rows * MAXB; e += 256) {
+      const int j = c + e / MAXB, l = e % MAXB;
+      const double v = Lc[j * MAXB + l];
+      if (l >= c && l <= j) Ls[j * LDS + l] = v;
+      if (l == j) rd[j] = 1.0 / v;
+    }
+  }
+  __syncthreads();
+  if (tid >= 64) return;  // the substitution runs in the first wave
   double x0 = 0.0, x1 = 0.0;
   if (c < nt) {
-    for (int j = c; j < nt; ++j)
-      for (int l = c + lane; l <= j; l += 64) Ls[j * LDS + l] = Lc[j * MAXB + l];
-    for (int j = c + lane; j < nt; j += 64) rd[j] = 1.0 / Lc[j * MAXB + j];
-    __syncthreads();
     // b = e_c
     if (lane == (c & 63)) {
       if (c < 64) x0 = 1.0; else x1 = 1.0;
@@ -852,24 +863,36 @@ __global__ __launch_bounds__(SolveCfg::NT) void k_solve_downdate(const TF* __res
 //
 // k_split_linv: one workgroup scales L^{-1} (MAXB x MAXB, row-major [n][k],
 // zero past nT) by the power of two 2^e that puts its largest magnitude
-// below 2^14 and writes the hi/lo fp16 halves and 2^e.
-__global__ __launch_bounds__(256) void k_split_linv(const double* __restrict__ Linv,
-                                                    const int32_t* nTptr, _Float16* __restrict__ Lh,
-                                                    _Float16* __restrict__ Ll, float* __restrict__ lsc) {
-  __shared__ double red[256];
+// below 2^14 and writes the hi/lo fp16 halves and 2^e; each thread keeps its
+// 16 entries in registers between the maximum and the split.
+__global__ __launch_bounds__(1024) void k_split_linv(const double* __restrict__ Linv,
+                                                     const int32_t* nTptr, _Float16* __restrict__ Lh,
+                                                     _Float16* __restrict__ Ll, float* __restrict__ lsc) {
+  static_assert(MAXB * MAXB == 1024 * 16, "16 entries per thread");
+  __shared__ double red[16];
   const int nt = *nTptr;
+  // thread t holds entries 16 t .. 16 t + 15 (one row segment) in registers
+  // for both the maximum and the split
+  const int e0 = threadIdx.x * 16, n = e0 / MAXB, k0 = e0 % MAXB;
+  double x[16];
   double m = 0.0;
-  for (int e = threadIdx.x; e < MAXB * MAXB; e += 256) {
-    const int n = e / MAXB, k = e % MAXB;
-    if (n < nt && k < nt) m = fmax(m, fabs(Linv[e]));
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const v2d v = *reinterpret_cast<const v2d*>(Linv + e0 + 2 * q);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = k0 + 2 * q + h;
+      x[2 * q + h] = (n < nt && k < nt) ? v[h] : 0.0;
+      m = fmax(m, fabs(x[2 * q + h]));
+    }
   }
-  red[threadIdx.x] = m;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, RPC_WAVE));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
-    __syncthreads();
-  }
-  const double mx = red[0];
+  double mx = 0.0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) mx = fmax(mx, red[w]);
   double sc = 1.0;
   if (mx > 0.0 && mx < 1e300) {
     int ex;
@@ -878,12 +901,18 @@ __global__ __launch_bounds__(256) void k_split_linv(const double* __restrict__ L
     q = q < -100 ? -100 : (q > 100 ? 100 : q);
     sc = ldexp(1.0, q);
   }
-  for (int e = threadIdx.x; e < MAXB * MAXB; e += 256) {
-    const int n = e / MAXB, k = e % MAXB;
-    const double x = (n < nt && k < nt) ? Linv[e] * sc : 0.0;
-    const _Float16 h = (_Float16)x;
-    Lh[e] = h;
-    Ll[e] = (_Float16)(x - (double)h);
+  v8h_t hi[2], lo[2];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const double xs = x[e] * sc;
+    const _Float16 h = (_Float16)xs;
+    hi[e / 8][e % 8] = h;
+    lo[e / 8][e % 8] = (_Float16)(xs - (double)h);
+  }
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    *reinterpret_cast<v8h_t*>(Lh + e0 + 8 * g) = hi[g];
+    *reinterpret_cast<v8h_t*>(Ll + e0 + 8 * g) = lo[g];
   }
   if (threadIdx.x == 0) lsc[0] = (float)sc;
 }
@@ -1224,7 +1253,7 @@ static void phase_select(FJob<T, TN, TF>& j, int i, hipStream_t st) {
                      o->tau, o->mode, (const T*)w.XS, dp, (const TN*)w.ns, (const TF*)w.FS, r,
                      j.k_out, w.nT, w.stop, j.pivots, w.Lc, w.Si, (T*)w.XSa, (TN*)w.nsa,
                      (TF*)w.FSa, j.status);
-  hipLaunchKernelGGL(k_tri_inv, dim3(MAXB), dim3(64), 0, st, (const double*)w.Lc, w.nT, w.Linv);
+  hipLaunchKernelGGL(k_tri_inv, dim3(MAXB), dim3(256), 0, st, (const double*)w.Lc, w.nT, w.Linv);
   prof::end(prof::ACCEPT, st);
 }
 
@@ -1324,7 +1353,7 @@ static void phase_solve(FJob<T, TN, TF>& j, int i, hipStream_t st) {
   // pivot block, and a split product's 2^-22 there dominates their error.
   constexpr bool split = std::is_same<T, __bf16>::value && std::is_same<TF, float>::value;
   if (split) {
-    hipLaunchKernelGGL(k_split_linv, dim3(1), dim3(256), 0, st, (const double*)w.Linv, w.nT, w.Lh,
+    hipLaunchKernelGGL(k_split_linv, dim3(1), dim3(1024), 0, st, (const double*)w.Linv, w.nT, w.Lh,
                        w.Ll, w.lsc);
     hipLaunchKernelGGL(k_solve_split, dim3((unsigned)((N + MAXB - 1) / MAXB)), dim3(512),
                        SolveSplit::bytes, st, (const float*)w.W, w.ldw, N, (const _Float16*)w.Lh,
