@@ -417,8 +417,7 @@ __global__ __launch_bounds__(1024) void k_accept_reject(
   __shared__ double dinv[MAXB];  // 1 / sqrt(H(i,i)) of accepted pivots, by position
   __shared__ int64_t props[MAXB];
   __shared__ double zs[MAXB];
-  __shared__ int nacc;
-  __shared__ int decide[2];  // by step parity: a slow wave may still read step i's flag
+  __shared__ int first[MAXB];  // first proposal of the block with the same point
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   if (*stop) {
@@ -428,54 +427,62 @@ __global__ __launch_bounds__(1024) void k_accept_reject(
   const int k = *kptr;
   for (int a = wave; a < bi; a += 16)
     for (int c = lane; c <= a; c += 64) H[tri(a, c)] = Hg[a * MAXB + c];
-  if (tid == 0) nacc = 0;
   if (tid < bi) {
     props[tid] = prop[tid];
     zs[tid] = (mode == RPC_SAMPLED) ? z[tid] : 0.0;
   }
   __syncthreads();
-  if (tid < bi) rho_loc[tid] = H[tri(tid, tid)];
-  __syncthreads();
-  for (int i = 0; i < bi; ++i) {
-    if (wave == 0) {
-      const int64_t pi = props[i];
-      const int na = nacc;
-      bool dup = false;
-      for (int a = lane; a < na; a += 64) dup |= (props[accl[a]] == pi);
-      dup = __any(dup);
-      if (lane == 0) {
-        const double hii = H[tri(i, i)];
-        bool ok;
-        if (mode == RPC_REPLAY) {
-          ok = hii > tau && !dup;
-          if (!ok) set_status(status, RPC_EBREAKDOWN);
-        } else if (mode == RPC_GREEDY) {
-          ok = hii > tau;  // b = 1: z * H(0,0) < H(0,0) holds for every z in [0, 1)
-        } else {
-          ok = !dup && hii > tau && zs[i] * rho_loc[i] < hii;
-        }
-        decide[i & 1] = ok ? 1 : 0;
-        if (ok) {
-          dinv[na] = 1.0 / sqrt(hii);
-          accl[na] = i;
-          nacc = na + 1;
-        }
+  if (tid < bi) {
+    rho_loc[tid] = H[tri(tid, tid)];
+    int f = tid;
+    for (int j = 0; j < tid; ++j)
+      if (props[j] == props[tid]) {
+        f = j;
+        break;
       }
+    first[tid] = f;
+  }
+  __syncthreads();
+  // Every thread takes each decision itself from the same values, so a step
+  // needs one barrier if it accepts (after its elimination) and none if it
+  // rejects (H is then unchanged).  A proposal repeats an accepted one iff a
+  // proposal of the block with the same point was accepted before it: each
+  // thread keeps the accepted points as a bit mask over first[] in registers.
+  static_assert(MAXB <= 128, "two 64-bit masks");
+  unsigned long long taken[2] = {0ull, 0ull};
+  int na = 0;
+  for (int i = 0; i < bi; ++i) {
+    const double hii = H[tri(i, i)];
+    const int fi = first[i];
+    const bool dup = (taken[fi >> 6] >> (fi & 63)) & 1ull;
+    bool ok;
+    if (mode == RPC_REPLAY) {
+      ok = hii > tau && !dup;
+      if (!ok && tid == 0) set_status(status, RPC_EBREAKDOWN);
+    } else if (mode == RPC_GREEDY) {
+      ok = hii > tau;  // b = 1: z * H(0,0) < H(0,0) holds for every z in [0, 1)
+    } else {
+      ok = !dup && hii > tau && zs[i] * rho_loc[i] < hii;
+    }
+    if (!ok) continue;
+    if (tid == 0) {
+      dinv[na] = 1.0 / sqrt(hii);
+      accl[na] = i;
+    }
+    taken[fi >> 6] |= 1ull << (fi & 63);
+    ++na;
+    // lower trailing triangle, 32 row groups x 32 column lanes
+    const double rh = 1.0 / hii;
+    const int ty = tid >> 5, tx = tid & 31;
+    for (int a = i + 1 + ty; a < bi; a += 32) {
+      const double hai = H[tri(a, i)] * rh;
+      const int ra = tri(a, 0);
+      for (int c = i + 1 + tx; c <= a; c += 32) H[ra + c] -= hai * H[tri(c, i)];
     }
     __syncthreads();
-    if (decide[i & 1]) {
-      // lower trailing triangle, 32 row groups x 32 column lanes
-      const double rh = 1.0 / H[tri(i, i)];
-      const int ty = tid >> 5, tx = tid & 31;
-      for (int a = i + 1 + ty; a < bi; a += 32) {
-        const double hai = H[tri(a, i)] * rh;
-        const int ra = tri(a, 0);
-        for (int c = i + 1 + tx; c <= a; c += 32) H[ra + c] -= hai * H[tri(c, i)];
-      }
-      __syncthreads();
-    }
   }
-  const int nt = nacc;
+  __syncthreads();
+  const int nt = na;
   // compact L(x, y) = H(accl[x], accl[y]) dinv[y] (x >= y), row-major MAXB x MAXB
   for (int x = wave; x < MAXB; x += 16) {
     const int ax = x < nt ? accl[x] : 0;
