@@ -119,6 +119,35 @@ def test_sampled_ragged_shapes(gpu):
     assert np.abs(F[:, :k] - ref["F"]).max() / np.abs(ref["F"]).max() < 1e-12
 
 
+@pytest.mark.parametrize("n,d,unfused", [(77, 1, False), (1337, 37, False), (1337, 37, True),
+                                         (2051, 70, False), (300, 130, True)])
+def test_split16_ragged_shapes(gpu, n, d, unfused):
+    """The split-fp16 distance form on shapes that leave partial tiles: N below
+    or not a multiple of the 128-row tile, d not a multiple of the 64-deep
+    split stage (a stage that is partly or wholly padding), r not a multiple
+    of b; fused and two-kernel paths, replaying the oracle's pivots, to the
+    split form's F bar 2e-4."""
+    torch, rp = gpu
+    rng = np.random.default_rng(n + d)
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    eps = median_sq_distance(X, seed=n)
+    r, b = min(60, n), 16
+    u = uniform_stream(2 * b * (-(-r // b)), seed=n)
+    ref = oracle.arpc(X, eps, r=r, b=b, mode="sampled", uniforms=u)
+    Xd = torch.from_numpy(X).cuda()
+    rep = torch.as_tensor(np.asarray(ref["S"], dtype=np.int64)).cuda()
+    out = rp.rpchol_factor(Xd, eps, r, b, mode="replay", replay=rep, gemm_dtype="split16",
+                           factor_dtype="f32", unfused=unfused)
+    assert rp.status_sync(out["status"]) == 0
+    k = int(out["k"].item())
+    assert k == ref["k"]
+    F = out["F"][:, :k].double().cpu().numpy()
+    err = np.abs(F - ref["F"]).max() / np.abs(ref["F"]).max()
+    print(f"split16 N={n} d={d} unfused={unfused}: F error {err:.3g}")
+    assert err < 2e-4
+    assert not out["F"][:, k:].any().item()
+
+
 def test_degenerate_all_equal_points(gpu):
     X = np.ones((300, 4), dtype=np.float32)
     u = uniform_stream(2 * 4 * 4, seed=1)
