@@ -233,15 +233,21 @@ def kernel_columns(rp, torch, Xd, eps, ud, w, d, steps):
 
 
 def factor_forms(rp, torch, Xd, eps, ud, w, reps=3):
-    """The factorisation alone (rpchol_factor, float32 factor) in its three
-    product forms: bf16 distances (the benchmark's), split-fp16 distances
-    (float32-grade at the fp16 MFMA rate) and float32 MFMA distances.  Each
-    form's F is compared with the float64 path replaying that form's pivots."""
+    """The factorisation alone (rpchol_factor) in its product forms: bf16
+    distances (the benchmark's), split-fp16 distances (float32-grade at the
+    fp16 MFMA rate) and float32 MFMA distances, with a float32 factor; bf16
+    distances with a float64 factor, stored in full and in the low-memory form
+    (only F(S, :) kept, earlier rounds' kernel columns evaluated again).  Each
+    form's F is compared with the float64 path replaying that form's pivots;
+    device_bytes = factor output + workspace."""
     res = {}
-    for gemm in ("bf16", "split16", "f32"):
+    forms = [("bf16", "bf16", "f32", False), ("split16", "split16", "f32", False),
+             ("f32", "f32", "f32", False), ("bf16_f64_factor", "bf16", "f64", False),
+             ("bf16_f64_low_memory", "bf16", "f64", True)]
+    for name, gemm, fdt, low in forms:
         def run():
             return rp.rpchol_factor(Xd, eps, w["r"], w["b"], uniforms=ud, gemm_dtype=gemm,
-                                    factor_dtype="f32")
+                                    factor_dtype=fdt, low_memory=low)
         out = run()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -251,12 +257,20 @@ def factor_forms(rp, torch, Xd, eps, ud, w, reps=3):
         dt = (time.perf_counter() - t0) / reps
         st = rp.status_sync(out["status"])
         k = int(out["k"].item())
-        ref = rp.rpchol_factor(Xd, eps, w["r"], w["b"], mode="replay", replay=out["pivots"][:k].clone(),
+        piv = out["pivots"][:k].clone()
+        ref = rp.rpchol_factor(Xd, eps, w["r"], w["b"], mode="replay", replay=piv,
                                gemm_dtype="f64", factor_dtype="f64")
         F64 = ref["F"][:, :k]
-        err = ((out["F"][:, :k].double() - F64).abs().max() / F64.abs().max()).item()
-        res[gemm] = {"ms": dt * 1e3, "k": k, "status": st, "F_rel_err_vs_fp64_replay": err}
-        del out, ref, F64
+        if low:  # the r x r factor rows F(S, :) against the same rows of the float64 factor
+            F64 = F64[piv]
+            Fk = out["F"][:k, :k]
+        else:
+            Fk = out["F"][:, :k]
+        err = ((Fk.double() - F64).abs().max() / F64.abs().max()).item()
+        res[name] = {"ms": dt * 1e3, "k": k, "status": st, "F_rel_err_vs_fp64_replay": err,
+                     "device_bytes": int(out["Fbuf"].numel() * out["Fbuf"].element_size()
+                                         + out["workspace"].numel())}
+        del out, ref, F64, Fk
     return res
 
 

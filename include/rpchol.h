@@ -123,9 +123,22 @@ typedef struct {
  *               rpc_batched_run); the factorisation then uses the two-kernel
  *               arithmetic of RPC_FACTOR_UNFUSED, so a job factorised alone
  *               with this bit equals the same job factorised in a group, bit
- *               for bit.  Other bits: RPC_EINVAL. */
+ *               for bit.
+ *               RPC_FACTOR_LOW_MEMORY: the low-memory form (the paper's
+ *               appendix on randomly pivoted Cholesky): the N x r factor is
+ *               never stored; F receives only F(S, :), the r x r lower
+ *               triangular factor rows of the pivots in pivot order (ldf >= r;
+ *               rows and columns >= k are zero), from which any row follows as
+ *               F(x, :) = K(x, X_S) F(S, :)^{-T}.  Each round evaluates again
+ *               the kernel columns of every earlier round in place of reading
+ *               F (round i makes i extra column passes), keeping the memory at
+ *               O(N (d + b) + r^2) beyond the points.  Needs factor_dtype F64;
+ *               not with RPC_FACTOR_SHARED_X.  Pivots, k, rho and
+ *               round_accepted are as in the full form (to rounding).
+ *               Other bits: RPC_EINVAL. */
 #define RPC_FACTOR_UNFUSED 1
 #define RPC_FACTOR_SHARED_X 2
+#define RPC_FACTOR_LOW_MEMORY 4
 typedef struct {
   int32_t r;
   int32_t b;

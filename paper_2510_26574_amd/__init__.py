@@ -175,13 +175,16 @@ def status_sync(status, stream=None):
 
 RPC_FACTOR_UNFUSED = 1
 RPC_FACTOR_SHARED_X = 2
+RPC_FACTOR_LOW_MEMORY = 4
 
 
 def rpchol_factor(X, eps, r, b, mode="sampled", uniforms=None, replay=None, gemm_dtype="f64",
-                  factor_dtype="f64", tau=0.0, unfused=False, shared_x=False, status=None, stream=None):
+                  factor_dtype="f64", tau=0.0, unfused=False, shared_x=False, low_memory=False,
+                  status=None, stream=None):
     """Algorithm 2 on the Gaussian kernel of the rows of X (N x d float32, CUDA).
 
-    Returns dict: F (N x r view, column-major storage), pivots (r int64),
+    Returns dict: F (N x r view, column-major storage; with low_memory the
+    r x r factor rows F(S, :) of the pivots in pivot order), pivots (r int64),
     rho (N float64), k (1 int32, device), status (1 int32, device).
     """
     torch = _torch()
@@ -189,7 +192,8 @@ def rpchol_factor(X, eps, r, b, mode="sampled", uniforms=None, replay=None, gemm
     N = X.shape[0]
     dev = X.device
     fdt = torch.float64 if factor_dtype == "f64" else torch.float32
-    ldf = _ld(N)
+    rows = r if low_memory else N
+    ldf = _ld(rows)
     Fbuf = torch.empty((r, ldf), dtype=fdt, device=dev)
     piv = torch.empty(r, dtype=torch.int64, device=dev)
     rho = torch.empty(N, dtype=torch.float64, device=dev)
@@ -199,7 +203,8 @@ def rpchol_factor(X, eps, r, b, mode="sampled", uniforms=None, replay=None, gemm
     nrounds = -(-(r if mode != "replay" else replay.numel()) // b)
     racc = torch.zeros(nrounds, dtype=torch.int32, device=dev)
     opts = rpc_factor_opts(int(r), int(b), MODES[mode], DTYPES[gemm_dtype], DTYPES[factor_dtype],
-                           (RPC_FACTOR_UNFUSED if unfused else 0) | (RPC_FACTOR_SHARED_X if shared_x else 0),
+                           (RPC_FACTOR_UNFUSED if unfused else 0) | (RPC_FACTOR_SHARED_X if shared_x else 0)
+                           | (RPC_FACTOR_LOW_MEMORY if low_memory else 0),
                            float(tau), 0, 0, 0, 0, racc.data_ptr())
     if mode == "sampled":
         assert uniforms is not None and uniforms.dtype == torch.float64 and uniforms.is_cuda
@@ -216,7 +221,7 @@ def rpchol_factor(X, eps, r, b, mode="sampled", uniforms=None, replay=None, gemm
     _check(lib.rpchol_factor(ctypes.byref(pts), ctypes.byref(opts), _ptr(Fbuf), ldf, _ptr(piv),
                              _ptr(rho), _ptr(k), _ptr(ws), nb.value, _ptr(st), _stream(torch, stream)),
            "rpchol_factor")
-    return {"F": Fbuf[:, :N].t(), "Fbuf": Fbuf, "ldf": ldf, "pivots": piv, "rho": rho, "k": k,
+    return {"F": Fbuf[:, :rows].t(), "Fbuf": Fbuf, "ldf": ldf, "pivots": piv, "rho": rho, "k": k,
             "status": st, "round_accepted": racc, "workspace": ws}
 
 

@@ -21,6 +21,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "dense.hpp"
 #include "profile.hpp"
 #include "split16.hpp"
 #include "tile_gemm.hpp"
@@ -406,8 +407,9 @@ template <typename T, typename TN, typename TF>
 __global__ __launch_bounds__(1024) void k_accept_reject(
     const double* __restrict__ Hg, int bi, const int64_t* __restrict__ prop,
     const double* __restrict__ z, double tau, int mode, const T* __restrict__ XS, int64_t dp,
-    const TN* __restrict__ ns, const TF* __restrict__ FS, int r, int32_t* kptr, int32_t* nTptr,
-    const int32_t* stop, int64_t* __restrict__ pivots, double* __restrict__ Lc,
+    const TN* __restrict__ ns, const TF* __restrict__ FS, int r, int32_t* kptr,
+    const int32_t* kfptr, int32_t* nTptr, const int32_t* stop, int64_t* __restrict__ pivots,
+    double* __restrict__ Lc,
     int64_t* __restrict__ Si, T* __restrict__ XSa, TN* __restrict__ nsa, TF* __restrict__ FSa,
     int32_t* status) {
   constexpr int PK = MAXB * (MAXB + 1) / 2;
@@ -424,7 +426,8 @@ __global__ __launch_bounds__(1024) void k_accept_reject(
     if (tid == 0) *nTptr = 0;
     return;
   }
-  const int k = *kptr;
+  const int k = *kptr;    // accepted pivots so far (position in `pivots`)
+  const int kf = *kfptr;  // leading columns of the proposal rows FS to carry into FSa
   for (int a = wave; a < bi; a += 16)
     for (int c = lane; c <= a; c += 64) H[tri(a, c)] = Hg[a * MAXB + c];
   if (tid < bi) {
@@ -493,7 +496,7 @@ __global__ __launch_bounds__(1024) void k_accept_reject(
   for (int a = wave; a < nt; a += 16) {
     const int64_t src = accl[a];
     for (int64_t c = lane; c < dp; c += 64) XSa[a * dp + c] = XS[src * dp + c];
-    for (int l = lane; l < k; l += 64) FSa[(int64_t)a * r + l] = FS[src * r + l];
+    for (int l = lane; l < kf; l += 64) FSa[(int64_t)a * r + l] = FS[src * r + l];
   }
   if (tid < nt) {
     nsa[tid] = ns[accl[tid]];
@@ -1221,15 +1224,15 @@ static int round_block(const rpc_factor_opts* o, int i) {
   return o->r - i * b < b ? o->r - i * b : b;
 }
 
-// Round i, part 1: proposals, the proposal block, Algorithm 3, L^{-1}.
+// Round i: the proposals (pivot draw, greedy argmax or replay list); returns
+// the accept-test uniforms of the round (sampled mode) or null.
 template <typename T, typename TN, typename TF>
-static void phase_select(FJob<T, TN, TF>& j, int i, hipStream_t st) {
+static const double* draw_proposals(FJob<T, TN, TF>& j, int i, hipStream_t st) {
   const rpc_factor_opts* o = j.o;
   FactorWs& w = j.w;
   const int64_t N = j.X.N;
-  const int r = o->r, b = o->b;
+  const int b = o->b;
   const int nb = (int)((N + CHUNK - 1) / CHUNK);
-  const int64_t dp = w.dp;
   const int bi = round_block(o, i);
   const double* z = nullptr;
   prof::begin(prof::PIVOT, st);
@@ -1249,6 +1252,19 @@ static void phase_select(FJob<T, TN, TF>& j, int i, hipStream_t st) {
                        w.prop, j.status, w.stop);
   }
   prof::end(prof::PIVOT, st);
+  return z;
+}
+
+// Round i, part 1: proposals, the proposal block, Algorithm 3, L^{-1}.
+template <typename T, typename TN, typename TF>
+static void phase_select(FJob<T, TN, TF>& j, int i, hipStream_t st) {
+  const rpc_factor_opts* o = j.o;
+  FactorWs& w = j.w;
+  const int64_t N = j.X.N;
+  const int r = o->r;
+  const int64_t dp = w.dp;
+  const int bi = round_block(o, i);
+  const double* z = draw_proposals(j, i, st);
   prof::begin(prof::ACCEPT, st);
   hipLaunchKernelGGL((k_gather<T, TN, TF>), dim3(bi), dim3(256), 0, st, (const T*)w.Xp,
                      (const TN*)w.xn, dp, (const TF*)j.F, j.ldf, r, w.prop, bi, j.k_out, w.stop,
@@ -1258,8 +1274,8 @@ static void phase_select(FJob<T, TN, TF>& j, int i, hipStream_t st) {
                      (const TF*)w.FS, r, bi, j.k_out, w.stop, j.X.eps, MAXB, w.H);
   hipLaunchKernelGGL((k_accept_reject<T, TN, TF>), dim3(1), dim3(1024), 0, st, w.H, bi, w.prop, z,
                      o->tau, o->mode, (const T*)w.XS, dp, (const TN*)w.ns, (const TF*)w.FS, r,
-                     j.k_out, w.nT, w.stop, j.pivots, w.Lc, w.Si, (T*)w.XSa, (TN*)w.nsa,
-                     (TF*)w.FSa, j.status);
+                     j.k_out, (const int32_t*)j.k_out, w.nT, w.stop, j.pivots, w.Lc, w.Si,
+                     (T*)w.XSa, (TN*)w.nsa, (TF*)w.FSa, j.status);
   hipLaunchKernelGGL(k_tri_inv, dim3(MAXB), dim3(256), 0, st, (const double*)w.Lc, w.nT, w.Linv);
   prof::end(prof::ACCEPT, st);
 }
@@ -1401,6 +1417,288 @@ static int run_factor(const rpc_points* X, const rpc_factor_opts* o, TF* F, int6
   }
   hipLaunchKernelGGL((k_zero_tail<TF>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, F, ldf,
                      N, o->r, k_out);
+  RPC_LAUNCH_CHECK();
+  return RPC_OK;
+}
+
+// ------------------------------------------------------------ low-memory form
+// The factorisation that keeps only the r x r factor F(S, :) instead of the
+// N x r factor (the low-memory variant of randomly pivoted Cholesky the
+// paper's appendix on it mentions): any row of F is
+// F(x, :) = K(x, X_S) F(S, :)^{-T}, so every use of F in a round is
+// recomputed from kernel columns.  F(S, :) and its inverse Minv are kept in
+// slot coordinates: round j's pivots occupy rows and columns SW j ..
+// SW j + nT_j - 1 (SW = b rounded up to 8; unused slots are zero), R = SW t.
+// Round i:
+//   proposal rows  FS = K(S', X_S) Minv^T                              (b x R)
+//   Schur update   F F(S_i, :)^T = K(:, X_S) Z with Z = Minv^T F(S_i, :)^T, so
+//                  W = K(:, S_i) - sum_{j<i} K(:, S_j) Z(slots of j, :): the
+//                  kernel columns of every earlier round are evaluated again
+//                  (round i makes i extra column passes);
+//   block solve    G = W L_i^{-T} updates rho; G is not kept;
+//   factor         F(S_i, :) = [F(S_i, :k) | L_i] and the rows of S_i in
+//                  Minv = [-L_i^{-1} F(S_i, :k) Minv_< | L_i^{-1}] (block
+//                  inverse of a lower triangular matrix).
+// Memory beyond the points: rho, two N x b column blocks and O(R^2).
+__global__ void k_fill_f64(double* __restrict__ p, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) p[e] = 0.0;
+}
+
+__global__ void k_lm_init(int32_t* pads, int t, int sw, int32_t* zero) {
+  for (int i = threadIdx.x; i < t; i += blockDim.x) pads[i] = sw * i;
+  if (threadIdx.x == 0) *zero = 0;
+}
+
+// KP[j][m] = exp(-|XS_j - XSall_m|^2 / eps) in float64 for proposal j < bi
+// and slot m < R; zero for slots of rounds not yet taken (>= rounds) or past
+// their round's accepted count.  16 x 16 pairs per workgroup, 64 coordinates
+// staged at a time.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lm_kp(const T* __restrict__ XS, const T* __restrict__ XSall,
+                                               int64_t dp, int bi, int R, int sw, int rounds,
+                                               const int32_t* __restrict__ round_nT, double eps,
+                                               double* __restrict__ KP) {
+  __shared__ double sa[16][65];
+  __shared__ double sb[16][65];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int m0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+  const int m = m0 + tx, j = j0 + ty;
+  auto valid = [&](int mm) {
+    const int jr = mm / sw, a = mm % sw;
+    return mm < R && jr < rounds && a < round_nT[jr];
+  };
+  double d2 = 0.0;
+  for (int64_t c0 = 0; c0 < dp; c0 += 64) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int rr = e / 64, cc = e % 64;
+      const int64_t c = c0 + cc;
+      sa[rr][cc] = (valid(m0 + rr) && c < dp) ? to_d(XSall[(int64_t)(m0 + rr) * dp + c]) : 0.0;
+      sb[rr][cc] = (j0 + rr < bi && c < dp) ? to_d(XS[(int64_t)(j0 + rr) * dp + c]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int cc = 0; cc < 64; ++cc) {
+      const double t = sa[tx][cc] - sb[ty][cc];
+      d2 += t * t;
+    }
+    __syncthreads();
+  }
+  if (m < R && j < bi) KP[(int64_t)j * R + m] = valid(m) ? exp(-d2 / eps) : 0.0;
+}
+
+// FSa rows a >= nT (not written by this round's Algorithm 3) set to zero.
+__global__ void k_lm_zero_rows(double* __restrict__ A, int R, const int32_t* nTptr) {
+  const int nt = *nTptr;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < (int64_t)MAXB * R;
+       e += (int64_t)gridDim.x * 256) {
+    const int a = (int)(e / R);
+    if (a >= nt) A[e] = 0.0;
+  }
+}
+
+// Slots SW i .. SW i + SW - 1 of F(S, :) and the diagonal block of Minv:
+// FSp(SW i + a, l) = F(S_i, :)(a, l) for l < SW i, L_i(a, l - SW i) after;
+// Minv(SW i + a, SW i + c) = L_i^{-1}(a, c); rows a >= nT are zero.  Both
+// column-major R x R.
+__global__ void k_lm_rows(double* __restrict__ FSp, double* __restrict__ Minv,
+                          const double* __restrict__ FSa, const double* __restrict__ Lc,
+                          const double* __restrict__ Linv, const int32_t* nTptr, int i, int sw,
+                          int R) {
+  const int nt = *nTptr;
+  const int s0 = sw * i;
+  const int64_t n = (int64_t)sw * (s0 + sw);
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    const int a = (int)(e % sw), l = (int)(e / sw);
+    double f = 0.0, v = 0.0;
+    if (a < nt) {
+      if (l < s0) {
+        f = FSa[(int64_t)a * R + l];
+      } else {
+        const int c = l - s0;
+        f = c <= a ? Lc[a * MAXB + c] : 0.0;
+        v = Linv[a * MAXB + c];
+      }
+    }
+    FSp[(s0 + a) + (int64_t)l * R] = f;
+    if (l >= s0) Minv[(s0 + a) + (int64_t)l * R] = v;
+  }
+}
+
+// Keep round i's accepted point rows, norms, count and offset.
+template <typename T, typename TN>
+__global__ void k_lm_save(const T* __restrict__ XSa, const TN* __restrict__ nsa, int64_t dp,
+                          const int32_t* nTptr, const int32_t* kptr, int sw, T* __restrict__ XSall,
+                          TN* __restrict__ nsall, int32_t* round_nT, int32_t* round_k, int i) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < (int64_t)sw * dp;
+       e += (int64_t)gridDim.x * 256)
+    XSall[e] = XSa[e];
+  if (blockIdx.x == 0) {
+    for (int a = threadIdx.x; a < sw; a += 256) nsall[a] = nsa[a];
+    if (threadIdx.x == 0) {
+      round_nT[i] = *nTptr;
+      round_k[i] = *kptr;
+    }
+  }
+}
+
+// F(p, q) = FSp(slot p, slot q) in compact pivot order (round j's slot a is
+// pivot round_k[j] + a); F is r x r column-major, cleared beforehand.
+__global__ void k_lm_compact(const double* __restrict__ FSp, int R, int sw,
+                             const int32_t* __restrict__ round_nT,
+                             const int32_t* __restrict__ round_k, int t, double* __restrict__ F,
+                             int64_t ldf) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < (int64_t)R * R;
+       e += (int64_t)gridDim.x * 256) {
+    const int pr = (int)(e % R), pc = (int)(e / R);
+    const int jr = pr / sw, a = pr % sw, jc = pc / sw, c = pc % sw;
+    if (jr >= t || jc >= t || a >= round_nT[jr] || c >= round_nT[jc]) continue;
+    F[(int64_t)(round_k[jr] + a) + (int64_t)(round_k[jc] + c) * ldf] = FSp[e];
+  }
+}
+
+__global__ void k_clear_square(double* __restrict__ F, int r, int64_t ldf) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < (int64_t)r * r;
+       e += (int64_t)gridDim.x * 256)
+    F[(e % r) + (e / r) * ldf] = 0.0;
+}
+
+struct LowMemWs {
+  double* Minv;
+  double* FSp;
+  double* Z;
+  double* KP;
+  double* Wt;
+  void* XSall;
+  void* nsall;
+  int32_t* round_nT;
+  int32_t* round_k;
+  int32_t* pads;
+  int32_t* zero;
+};
+
+static int lm_slot(const rpc_factor_opts* o) { return (int)align_up((size_t)o->b, 8); }
+
+template <typename T, typename TN>
+static size_t carve_lowmem(WsCursor& c, FactorWs& w, LowMemWs& l, int64_t N, int64_t d,
+                           const rpc_factor_opts* o) {
+  const int t = n_rounds(o), sw = lm_slot(o), R = sw * t;
+  carve<T, TN, double>(c, w, N, d, R);  // FS / FSa rows have R entries (slot coordinates)
+  l.Minv = c.take<double>((size_t)R * R);
+  l.FSp = c.take<double>((size_t)R * R);
+  l.Z = c.take<double>((size_t)R * MAXB);
+  l.KP = c.take<double>((size_t)MAXB * R);
+  l.Wt = c.take<double>((size_t)w.ldw * MAXB);
+  // + MAXB rows: the column kernel's direct loads read whole 128-row tiles of
+  // a round's block, which for the last rounds' blocks run past R
+  l.XSall = c.take<T>((size_t)(R + MAXB) * w.dp);
+  l.nsall = c.take<TN>((size_t)R);
+  l.round_nT = c.take<int32_t>((size_t)t);
+  l.round_k = c.take<int32_t>((size_t)t);
+  l.pads = c.take<int32_t>((size_t)t);
+  l.zero = c.take<int32_t>(1);
+  return c.used;
+}
+
+template <typename T, typename TN>
+static int run_factor_lowmem(const rpc_points* X, const rpc_factor_opts* o, double* F, int64_t ldf,
+                             int64_t* pivots, double* rho, int32_t* k_out, void* ws,
+                             size_t ws_bytes, int32_t* status, hipStream_t st) {
+  typedef typename FCfg<T, double>::K CfgK;
+  typedef typename FCfg<T, double>::S CfgS;
+  WsCursor cur{(char*)ws, 0, ws_bytes, true};
+  FJob<T, TN, double> j{*X, o, nullptr, 0, pivots, rho, k_out, status, FactorWs{}};
+  LowMemWs l;
+  carve_lowmem<T, TN>(cur, j.w, l, X->N, X->d, o);
+  if (!cur.ok) return RPC_EWORKSPACE;
+  FactorWs& w = j.w;
+  const int64_t N = X->N, dp = w.dp;
+  const int t = n_rounds(o), sw = lm_slot(o), R = sw * t;
+  auto clear = [&](double* p, int64_t n) {
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+  };
+  clear(l.Minv, (int64_t)R * R);
+  clear(l.FSp, (int64_t)R * R);
+  clear((double*)w.FS, (int64_t)MAXB * R);
+  clear((double*)w.FSa, (int64_t)MAXB * R);
+  hipLaunchKernelGGL(k_lm_init, dim3(1), dim3(256), 0, st, l.pads, t, sw, l.zero);
+  hipLaunchKernelGGL((k_prep<T, TN>), dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, X->X, N,
+                     X->d, X->ldx, dp, (T*)w.Xp, (TN*)w.xn, rho, status, nullptr);
+  hipLaunchKernelGGL(k_init_small, dim3(1), dim3(256), 0, st, pivots, o->r, k_out, w.nT, w.stop);
+  RPC_LAUNCH_CHECK();
+  constexpr size_t smC0 = DirectSmem<CfgK, cols_stages<T>(), true, true>::bytes;
+  constexpr size_t smC1 = ColStoreSmem<CfgK, double>::bytes;
+  constexpr size_t smC = smC0 > smC1 ? smC0 : smC1;
+  const size_t smS = DirectSmem<CfgS, kStages, false, true>::bytes;
+  const size_t smD = TileSmem<SolveCfg, false, true>::bytes;
+  const unsigned gm = (unsigned)((N + 127) / 128);
+  const unsigned gs = (unsigned)((N + SolveCfg::BM - 1) / SolveCfg::BM);
+  for (int i = 0; i < t; ++i) {
+    const int bi = round_block(o, i);
+    const double* z = draw_proposals(j, i, st);
+    prof::begin(prof::ACCEPT, st);
+    // proposal rows: points and norms gathered, F rows from the kernel
+    hipLaunchKernelGGL((k_gather<T, TN, double>), dim3(bi), dim3(256), 0, st, (const T*)w.Xp,
+                       (const TN*)w.xn, dp, (const double*)nullptr, (int64_t)0, R, w.prop, bi,
+                       (const int32_t*)l.zero, w.stop, (T*)w.XS, (TN*)w.ns, (double*)w.FS, N,
+                       status);
+    hipLaunchKernelGGL((k_lm_kp<T>), dim3((unsigned)((R + 15) / 16), (unsigned)((bi + 15) / 16)),
+                       dim3(256), 0, st, (const T*)w.XS, (const T*)l.XSall, dp, bi, R, sw, i,
+                       (const int32_t*)l.round_nT, X->eps, l.KP);
+    dense::gemm64<false, true>(st, R, bi, R, l.Minv, R, l.KP, R, (double*)w.FS, R, 1.0, 0.0);
+    const unsigned hb = (unsigned)((bi + 15) / 16);
+    hipLaunchKernelGGL((k_pivot_block<T, double>), dim3(hb, hb), dim3(256), 0, st, (const T*)w.XS,
+                       dp, (const double*)w.FS, R, bi, (const int32_t*)(l.pads + i), w.stop, X->eps,
+                       MAXB, w.H);
+    hipLaunchKernelGGL((k_accept_reject<T, TN, double>), dim3(1), dim3(1024), 0, st, w.H, bi,
+                       w.prop, z, o->tau, o->mode, (const T*)w.XS, dp, (const TN*)w.ns,
+                       (const double*)w.FS, R, k_out, (const int32_t*)(l.pads + i), w.nT, w.stop,
+                       pivots, w.Lc, w.Si, (T*)w.XSa, (TN*)w.nsa, (double*)w.FSa, status);
+    hipLaunchKernelGGL(k_lm_zero_rows, dim3((unsigned)((MAXB * R + 255) / 256)), dim3(256), 0, st,
+                       (double*)w.FSa, R, (const int32_t*)w.nT);
+    hipLaunchKernelGGL(k_tri_inv, dim3(MAXB), dim3(256), 0, st, (const double*)w.Lc, w.nT, w.Linv);
+    prof::end(prof::ACCEPT, st);
+    // W = K(:, S_i) - sum_{j<i} K(:, S_j) Z(slots of j, :)
+    prof::begin(prof::KERNEL_COLS, st);
+    dense::gemm64<true, true>(st, R, MAXB, R, l.Minv, R, (const double*)w.FSa, R, l.Z, R, 1.0, 0.0);
+    hipLaunchKernelGGL((k_kernel_cols<T, TN, double, CfgK>), dim3(gm, 1), dim3(CfgK::NT), smC, st,
+                       (const T*)w.Xp, (const TN*)w.xn, N, dp, (const T*)w.XSa, (const TN*)w.nsa,
+                       w.nT, X->eps, (double*)w.W, w.ldw);
+    for (int jj = 0; jj < i; ++jj) {
+      hipLaunchKernelGGL((k_kernel_cols<T, TN, double, CfgK>), dim3(gm, 1), dim3(CfgK::NT), smC,
+                         st, (const T*)w.Xp, (const TN*)w.xn, N, dp,
+                         (const T*)l.XSall + (int64_t)sw * jj * dp, (const TN*)l.nsall + sw * jj,
+                         (const int32_t*)(l.round_nT + jj), X->eps, l.Wt, w.ldw);
+      hipLaunchKernelGGL((k_schur<double, CfgS>), dim3(gm, 1), dim3(CfgS::NT), smS, st,
+                         (const double*)l.Wt, w.ldw, N, (const double*)(l.Z + sw * jj), R,
+                         (const int32_t*)(l.round_nT + jj), w.nT, (double*)w.W, w.ldw);
+    }
+    prof::end(prof::KERNEL_COLS, st);
+    // rho -= rownorms(W L_i^{-T})^2 (the block of F itself goes to scratch)
+    prof::begin(prof::SOLVE, st);
+    hipLaunchKernelGGL((k_solve_downdate<double>), dim3(gs), dim3(SolveCfg::NT), smD, st,
+                       (const double*)w.W, w.ldw, N, w.Linv, (const int32_t*)l.zero, w.nT, l.Wt,
+                       w.ldw, rho);
+    // F(S_i, :), Minv's rows of S_i
+    hipLaunchKernelGGL(k_lm_rows, dim3((unsigned)(((int64_t)sw * sw * (i + 1) + 255) / 256)),
+                       dim3(256), 0, st, l.FSp, l.Minv, (const double*)w.FSa, (const double*)w.Lc,
+                       (const double*)w.Linv, (const int32_t*)w.nT, i, sw, R);
+    if (i > 0)
+      dense::gemm64<true, false>(st, sw, (int64_t)sw * i, MAXB, w.Linv, MAXB, l.Z, R,
+                                 l.Minv + (int64_t)sw * i, R, -1.0, 0.0);
+    hipLaunchKernelGGL((k_lm_save<T, TN>), dim3((unsigned)((sw * dp + 255) / 256)), dim3(256), 0, st,
+                       (const T*)w.XSa, (const TN*)w.nsa, dp, (const int32_t*)w.nT,
+                       (const int32_t*)k_out, sw, (T*)l.XSall + (int64_t)sw * i * dp,
+                       (TN*)l.nsall + sw * i, l.round_nT, l.round_k, i);
+    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(MAXB), 0, st, w.Si, k_out, w.nT, rho,
+                       o->round_accepted, i);
+    prof::end(prof::SOLVE, st);
+    RPC_LAUNCH_CHECK();
+  }
+  const unsigned gc = (unsigned)(((int64_t)R * R + 255) / 256 < 4096 ? ((int64_t)R * R + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_clear_square, dim3(gc), dim3(256), 0, st, F, o->r, ldf);
+  hipLaunchKernelGGL(k_lm_compact, dim3(gc), dim3(256), 0, st, (const double*)l.FSp, R, sw,
+                     (const int32_t*)l.round_nT, (const int32_t*)l.round_k, t, F, ldf);
   RPC_LAUNCH_CHECK();
   return RPC_OK;
 }
@@ -1560,7 +1858,11 @@ static int check_factor_args(const rpc_points* X, const rpc_factor_opts* o) {
     if (!o->replay || o->n_replay < 1 || o->n_replay > o->r) return RPC_EINVAL;
   }
   if (!(o->tau >= 0.0)) return RPC_EINVAL;
-  if (o->flags & ~(RPC_FACTOR_UNFUSED | RPC_FACTOR_SHARED_X)) return RPC_EINVAL;
+  if (o->flags & ~(RPC_FACTOR_UNFUSED | RPC_FACTOR_SHARED_X | RPC_FACTOR_LOW_MEMORY))
+    return RPC_EINVAL;
+  if ((o->flags & RPC_FACTOR_LOW_MEMORY) &&
+      (o->factor_dtype != RPC_F64 || (o->flags & RPC_FACTOR_SHARED_X)))
+    return RPC_EINVAL;
   if (X->N > (int64_t)1 << 23) return RPC_EINVAL;  // keeps sum(rho_q) < 2^63
   return RPC_OK;
 }
@@ -1590,7 +1892,12 @@ extern "C" int rpchol_factor_workspace_size(const rpc_points* X, const rpc_facto
     typedef typename std::remove_pointer<decltype(tf)>::type TF;
     WsCursor c{nullptr, 0, 0, true};
     FactorWs w;
-    *bytes = carve<T, TN, TF>(c, w, X->N, X->d, o->r);
+    if (o->flags & RPC_FACTOR_LOW_MEMORY) {
+      LowMemWs l;
+      *bytes = carve_lowmem<T, TN>(c, w, l, X->N, X->d, o);
+    } else {
+      *bytes = carve<T, TN, TF>(c, w, X->N, X->d, o->r);
+    }
     return (int)RPC_OK;
   });
 }
@@ -1600,12 +1907,19 @@ extern "C" int rpchol_factor(const rpc_points* X, const rpc_factor_opts* o, void
                              size_t ws_bytes, int32_t* status, rpc_stream_t stream) {
   int rc = check_factor_args(X, o);
   if (rc) return rc;
-  if (!F || !pivots || !rho || !k_out || !status || ldf < X->N || ldf % 8 != 0) return RPC_EINVAL;
+  const bool lowmem = (o->flags & RPC_FACTOR_LOW_MEMORY) != 0;
+  if (!F || !pivots || !rho || !k_out || !status || ldf < (lowmem ? o->r : X->N) || ldf % 8 != 0)
+    return RPC_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   return dispatch(o, [&](auto* t, auto* tn, auto* tf) {
     typedef typename std::remove_pointer<decltype(t)>::type T;
     typedef typename std::remove_pointer<decltype(tn)>::type TN;
     typedef typename std::remove_pointer<decltype(tf)>::type TF;
+    if constexpr (std::is_same<TF, double>::value) {
+      if (lowmem)
+        return run_factor_lowmem<T, TN>(X, o, (double*)F, ldf, pivots, rho, k_out, ws, ws_bytes,
+                                        status, st);
+    }
     return run_factor<T, TN, TF>(X, o, (TF*)F, ldf, pivots, rho, k_out, ws, ws_bytes, status, st);
   });
 }
@@ -1626,6 +1940,7 @@ int check_group_args(const rpc_points* X, const double* eps, const rpc_factor_op
     const rpc_factor_opts* o = opts[g];
     if (!(o->flags & RPC_FACTOR_SHARED_X)) return RPC_EINVAL;
     if (o->mode == RPC_REPLAY || o->gemm_dtype == RPC_F32_SPLIT16) return RPC_EINVAL;
+    if (o->flags & RPC_FACTOR_LOW_MEMORY) return RPC_EINVAL;
     if (o->r != a->r || o->b != a->b || o->mode != a->mode || o->gemm_dtype != a->gemm_dtype ||
         o->factor_dtype != a->factor_dtype || o->tau != a->tau || o->flags != a->flags)
       return RPC_EINVAL;

@@ -56,7 +56,7 @@ def test_host_side_validation(lib):
         dict(n_uniforms=10),   # too few uniforms
         dict(gemm_dtype=7),
         dict(factor_dtype=2),  # bf16 storage of F is not offered
-        dict(flags=4),         # unknown option bit
+        dict(flags=8),         # unknown option bit
         dict(gemm_dtype=3),    # split-fp16 distances need a float32 factor
     ]
     for kw in bad:
@@ -87,6 +87,27 @@ def test_host_side_validation(lib):
     o.flags = rp.RPC_FACTOR_SHARED_X  # not offered for a group on shared points
     assert lib.rpchol_factor_group_workspace_size(ctypes.byref(pts), ctypes.byref(o), 2,
                                                   ctypes.byref(nb)) == rp.RPC_EINVAL
+    # low-memory form: float64 factor only, not on shared points; its workspace
+    # holds two column blocks instead of the N x r factor
+    o = rp.rpc_factor_opts(8, 2, rp.MODES["sampled"], rp.DTYPES["bf16"], rp.DTYPES["f64"],
+                           rp.RPC_FACTOR_LOW_MEMORY, 0.0, 0x2000, 64, 0, 0, 0)
+    assert lib.rpchol_factor_workspace_size(ctypes.byref(pts), ctypes.byref(o), ctypes.byref(nb)) == 0
+    o.factor_dtype = rp.DTYPES["f32"]
+    assert lib.rpchol_factor_workspace_size(ctypes.byref(pts), ctypes.byref(o), ctypes.byref(nb)) == rp.RPC_EINVAL
+    o.factor_dtype = rp.DTYPES["f64"]
+    o.flags = rp.RPC_FACTOR_LOW_MEMORY | rp.RPC_FACTOR_SHARED_X
+    assert lib.rpchol_factor_workspace_size(ctypes.byref(pts), ctypes.byref(o), ctypes.byref(nb)) == rp.RPC_EINVAL
+    big = rp.rpc_points(1_000_000, 512, 512, 0x1000, 1.0)
+    full = rp.rpc_factor_opts(1024, 128, rp.MODES["sampled"], rp.DTYPES["bf16"], rp.DTYPES["f64"], 0,
+                              0.0, 0x2000, 2048, 0, 0, 0)
+    low = rp.rpc_factor_opts(1024, 128, rp.MODES["sampled"], rp.DTYPES["bf16"], rp.DTYPES["f64"],
+                             rp.RPC_FACTOR_LOW_MEMORY, 0.0, 0x2000, 2048, 0, 0, 0)
+    nf, nl = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.rpchol_factor_workspace_size(ctypes.byref(big), ctypes.byref(full), ctypes.byref(nf)) == 0
+    assert lib.rpchol_factor_workspace_size(ctypes.byref(big), ctypes.byref(low), ctypes.byref(nl)) == 0
+    # full form: workspace + the caller's N x r float64 factor (8.2 GB); low-memory
+    # form: workspace + an r x r factor
+    assert nl.value + 1024 * 1024 * 8 < nf.value + 1_000_000 * 1024 * 8 - 4 * 10**9
     # group of factorisations on shared points: sizes and option checks (host side only)
     og = rp.rpc_factor_opts(8, 2, rp.MODES["sampled"], 0, 0, rp.RPC_FACTOR_SHARED_X, 0.0, 0x2000, 64, 0, 0, 0)
     n1 = ctypes.c_size_t(0)
