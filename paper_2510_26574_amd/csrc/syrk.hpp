@@ -128,6 +128,19 @@ struct SyrkLoader {
 };
 
 // grid.x = 8 * ceil(groups / 8) * n_upper, groups = nz * nch (z-major).
+// Group g of a Gram launch -> (Gram z, row chunk ch).  Workgroups are
+// dealt to the 8 XCDs in turn, so groups g and g + 8 run on the same XCD one
+// after the other; the nz Grams of one row chunk are placed there, and the
+// second reads the chunk's F panels while the first has them in that XCD's
+// L2.  g covers group_slots(nz, nch) groups; false for the padding ones.
+__device__ inline bool group_decode(int g, int nz, int nch, int& z, int& ch) {
+  const int blk = g / (8 * nz), w = g % (8 * nz);
+  z = w / 8;
+  ch = blk * 8 + w % 8;
+  return ch < nch;
+}
+__host__ __device__ inline int group_slots(int nz, int nch) { return 8 * nz * ((nch + 7) / 8); }
+
 template <typename T, typename TF>
 __global__ __launch_bounds__(NTH, 2) void k_syrk_partial(const TF* __restrict__ A, int64_t lda,
                                                          int64_t N, int r, const T* __restrict__ s0,
@@ -145,13 +158,12 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_partial(const TF* __restrict__ 
   __shared__ __attribute__((aligned(16))) T Bs[2][TILE * LDK];
   const int nt = n_tiles(r);
   const int nu = n_upper(nt);
-  const int groups = nz * nch;
   const int xcd = blockIdx.x % 8;
   const int slot = blockIdx.x / 8;
   const int g = (slot / nu) * 8 + xcd;
-  if (g >= groups) return;
+  int z, ch;
+  if (g >= group_slots(nz, nch) || !group_decode(g, nz, nch, z, ch)) return;
   const int tile = slot % nu;
-  const int z = g / nch, ch = g % nch;
   int ti, tj;
   upper_decode(tile, nt, ti, tj);
   // columns >= k are zero: tiles entirely beyond k are skipped (the reduce
@@ -363,20 +375,19 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_split_partial(
   __shared__ __attribute__((aligned(16))) _Float16 Bl[2][TILE * LDK];
   const int nt = n_tiles(r);
   const int nu = n_upper(nt);
-  const int groups = nz * nch;
   const int xcd = blockIdx.x % 8;
   const int slot = blockIdx.x / 8;
   const int g = (slot / nu) * 8 + xcd;
-  if (g >= groups) return;
+  int z, ch;
+  if (g >= group_slots(nz, nch) || !group_decode(g, nz, nch, z, ch)) return;
   const int tile = slot % nu;
-  const int z = g / nch, ch = g % nch;
   int ti, tj;
   upper_decode(tile, nt, ti, tj);
   const int kk = kptr ? *kptr : r;
   if (tj * TILE >= kk) return;
   const bool diag = ti == tj;
   const float* s = z ? s1 : s0;
-  const float scale = scl[g];
+  const float scale = scl[z * nch + ch];
   double* out = (z ? part1 : part0) + ((int64_t)ch * nu + tile) * TILE * TILE;
   const int64_t n0 = (int64_t)ch * chunk;
   const int64_t n1 = n0 + chunk < N ? n0 + chunk : N;
@@ -565,8 +576,7 @@ inline void gram2_partial(hipStream_t st, const TF* A, int64_t lda, int64_t N, i
   int64_t chunk;
   plan(N, nch, chunk, sizeof(T) == 4);
   const int nu = n_upper(n_tiles(r));
-  const int groups = nz * nch;
-  const unsigned blocks = (unsigned)(8 * ((groups + 7) / 8) * nu);
+  const unsigned blocks = (unsigned)(group_slots(nz, nch) * nu);
   hipLaunchKernelGGL((k_syrk_partial<T, TF>), dim3(blocks), dim3(NTH), 0, st, A, lda, N, r, s0, s1, nz,
                      chunk, nch, part0, part1, kptr);
 }
@@ -582,7 +592,7 @@ inline void gram2_partial_split(hipStream_t st, const float* A, int64_t lda, int
   const int nu = n_upper(n_tiles(r));
   const int groups = nz * nch;
   hipLaunchKernelGGL(k_split_scales, dim3(groups), dim3(256), 0, st, s0, s1, N, chunk, nch, scl);
-  const unsigned blocks = (unsigned)(8 * ((groups + 7) / 8) * nu);
+  const unsigned blocks = (unsigned)(group_slots(nz, nch) * nu);
   hipLaunchKernelGGL(k_syrk_split_partial, dim3(blocks), dim3(NTH), 0, st, A, lda, N, r, s0, s1,
                      (const float*)scl, nz, chunk, nch, part0, part1, kptr);
 }
