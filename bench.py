@@ -229,7 +229,7 @@ def kernel_columns(rp, torch, Xd, eps, ud, w, d, steps):
             "frac_mfma_peak": tf / PEAK["bf16"], "ai_flop_per_byte": ai, "ceiling_tflops": ceil_tf,
             "frac_ceiling": tf / ceil_tf, "frac_hbm_peak": byts / sec / 1e9 / PEAK["hbm"],
             "algorithmic_bytes_per_launch": byts / max(n, 1),
-            "traffic": pmc_traffic("k_kernel_cols")}
+            "traffic": pmc_traffic("k_kernel_colsIDF16bff")}
 
 
 def factor_forms(rp, torch, Xd, eps, ud, w, reps=3):
