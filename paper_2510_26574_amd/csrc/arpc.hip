@@ -345,13 +345,21 @@ __global__ __launch_bounds__(256) void k_gather(const T* __restrict__ Xp, const 
   if (threadIdx.x == 0) ns[j] = xn[s];
 }
 
-// H[i][j] = exp(-sum_l (x_i - x_j)^2 / eps) - sum_l FS[i][l] FS[j][l], float64.
-// Grid (ceil(bi/16), ceil(bi/16)); thread (ty, tx) owns pair (i0 + ty, j0 + tx).
+// H[i][j] = exp(-sum_c (x_i - x_j)^2 / eps) - sum_l FS[i][l] FS[j][l], float64,
+// split over the joint index range (dp coordinates, then k factor columns)
+// in slices of PB_CH so that many workgroups share a block whose k reaches
+// thousands: workgroup (tile of 16 x 16 pairs, slice z) writes the slice's
+// two partial sums; k_pivot_block_finish adds the slices in order (the same
+// order on every run) and forms H.
+constexpr int PB_CH = 256;
+static int pb_slices(int64_t dp, int r) { return (int)((dp + r + PB_CH - 1) / PB_CH); }
+
 template <typename T, typename TF>
-__global__ __launch_bounds__(256) void k_pivot_block(const T* __restrict__ XS, int64_t dp,
-                                                     const TF* __restrict__ FS, int r, int bi,
-                                                     const int32_t* kptr, const int32_t* stop,
-                                                     double eps, int ldh, double* __restrict__ H) {
+__global__ __launch_bounds__(256) void k_pivot_block_part(const T* __restrict__ XS, int64_t dp,
+                                                          const TF* __restrict__ FS, int r, int bi,
+                                                          const int32_t* kptr, const int32_t* stop,
+                                                          double* __restrict__ pd2,
+                                                          double* __restrict__ pff) {
   if (*stop) return;
   __shared__ double si_[16][65];
   __shared__ double sj_[16][65];
@@ -359,35 +367,70 @@ __global__ __launch_bounds__(256) void k_pivot_block(const T* __restrict__ XS, i
   const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
   const int i = i0 + ty, j = j0 + tx;
   const int k = *kptr;
+  const int64_t e0 = (int64_t)blockIdx.z * PB_CH, e1 = e0 + PB_CH;
   double d2 = 0.0, ff = 0.0;
-  for (int64_t c0 = 0; c0 < dp; c0 += 64) {
+  const int64_t cend = e1 < dp ? e1 : dp;
+  for (int64_t c0 = e0; c0 < cend; c0 += 64) {
     for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-      int rr = e / 64, cc = e % 64;
-      int64_t c = c0 + cc;
-      si_[rr][cc] = (i0 + rr < bi && c < dp) ? to_d(XS[(int64_t)(i0 + rr) * dp + c]) : 0.0;
-      sj_[rr][cc] = (j0 + rr < bi && c < dp) ? to_d(XS[(int64_t)(j0 + rr) * dp + c]) : 0.0;
+      const int rr = e / 64, cc = e % 64;
+      const int64_t c = c0 + cc;
+      si_[rr][cc] = (i0 + rr < bi && c < cend) ? to_d(XS[(int64_t)(i0 + rr) * dp + c]) : 0.0;
+      sj_[rr][cc] = (j0 + rr < bi && c < cend) ? to_d(XS[(int64_t)(j0 + rr) * dp + c]) : 0.0;
     }
     __syncthreads();
 #pragma unroll 8
     for (int cc = 0; cc < 64; ++cc) {
-      double t = si_[ty][cc] - sj_[tx][cc];
+      const double t = si_[ty][cc] - sj_[tx][cc];
       d2 += t * t;
     }
     __syncthreads();
   }
-  for (int l0 = 0; l0 < k; l0 += 64) {
+  const int64_t lb = (e0 > dp ? e0 : dp) - dp, le = (e1 < dp + k ? e1 : dp + k) - dp;
+  for (int64_t l0 = lb; l0 < le; l0 += 64) {
     for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-      int rr = e / 64, cc = e % 64;
-      int l = l0 + cc;
-      si_[rr][cc] = (i0 + rr < bi && l < k) ? to_d(FS[(int64_t)(i0 + rr) * r + l]) : 0.0;
-      sj_[rr][cc] = (j0 + rr < bi && l < k) ? to_d(FS[(int64_t)(j0 + rr) * r + l]) : 0.0;
+      const int rr = e / 64, cc = e % 64;
+      const int64_t l = l0 + cc;
+      si_[rr][cc] = (i0 + rr < bi && l < le) ? to_d(FS[(int64_t)(i0 + rr) * r + l]) : 0.0;
+      sj_[rr][cc] = (j0 + rr < bi && l < le) ? to_d(FS[(int64_t)(j0 + rr) * r + l]) : 0.0;
     }
     __syncthreads();
 #pragma unroll 8
     for (int cc = 0; cc < 64; ++cc) ff += si_[ty][cc] * sj_[tx][cc];
     __syncthreads();
   }
-  if (i < bi && j < bi) H[i * ldh + j] = exp(-d2 / eps) - ff;
+  if (i < bi && j < bi) {
+    const int64_t o = ((int64_t)blockIdx.z * MAXB + i) * MAXB + j;
+    pd2[o] = d2;
+    pff[o] = ff;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pivot_block_finish(const double* __restrict__ pd2,
+                                                            const double* __restrict__ pff, int ks,
+                                                            int bi, const int32_t* stop, double eps,
+                                                            int ldh, double* __restrict__ H) {
+  if (*stop) return;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int i = e / MAXB, j = e % MAXB;
+  if (i >= bi || j >= bi) return;
+  double d2 = 0.0, ff = 0.0;
+  for (int z = 0; z < ks; ++z) {
+    d2 += pd2[((int64_t)z * MAXB + i) * MAXB + j];
+    ff += pff[((int64_t)z * MAXB + i) * MAXB + j];
+  }
+  H[i * ldh + j] = exp(-d2 / eps) - ff;
+}
+
+template <typename T, typename TF>
+static void launch_pivot_block(const T* XS, int64_t dp, const TF* FS, int r, int bi,
+                               const int32_t* kptr, const int32_t* stop, double eps, double* pd2,
+                               double* pff, double* H, hipStream_t st) {
+  const unsigned hb = (unsigned)((bi + 15) / 16);
+  const int ks = pb_slices(dp, r);
+  hipLaunchKernelGGL((k_pivot_block_part<T, TF>), dim3(hb, hb, (unsigned)ks), dim3(256), 0, st, XS,
+                     dp, FS, r, bi, kptr, stop, pd2, pff);
+  hipLaunchKernelGGL(k_pivot_block_finish, dim3(MAXB * MAXB / 256), dim3(256), 0, st,
+                     (const double*)pd2, (const double*)pff, ks, bi, stop, eps, MAXB, H);
 }
 
 // ------------------------------------------------------------ Algorithm 3
@@ -1128,6 +1171,8 @@ struct FactorWs {
   void* ns;
   void* FS;
   double* H;
+  double* pd2;  // slice partial sums of the proposal block
+  double* pff;
   double* Lc;
   double* Linv;
   _Float16* Lh;  // split-fp16 halves of L^{-1} and their power-of-two scale
@@ -1169,6 +1214,8 @@ static void carve_job(WsCursor& c, FactorWs& w, int64_t N, int64_t d, int r) {
   w.ns = c.take<TN>(MAXB);
   w.FS = c.take<TF>((size_t)MAXB * r);
   w.H = c.take<double>((size_t)MAXB * MAXB);
+  w.pd2 = c.take<double>((size_t)pb_slices(w.dp, r) * MAXB * MAXB);
+  w.pff = c.take<double>((size_t)pb_slices(w.dp, r) * MAXB * MAXB);
   w.Lc = c.take<double>((size_t)MAXB * MAXB);
   w.Linv = c.take<double>((size_t)MAXB * MAXB);
   w.Lh = c.take<_Float16>((size_t)MAXB * MAXB);
@@ -1269,9 +1316,8 @@ static void phase_select(FJob<T, TN, TF>& j, int i, hipStream_t st) {
   hipLaunchKernelGGL((k_gather<T, TN, TF>), dim3(bi), dim3(256), 0, st, (const T*)w.Xp,
                      (const TN*)w.xn, dp, (const TF*)j.F, j.ldf, r, w.prop, bi, j.k_out, w.stop,
                      (T*)w.XS, (TN*)w.ns, (TF*)w.FS, N, j.status);
-  const unsigned hb = (unsigned)((bi + 15) / 16);
-  hipLaunchKernelGGL((k_pivot_block<T, TF>), dim3(hb, hb), dim3(256), 0, st, (const T*)w.XS, dp,
-                     (const TF*)w.FS, r, bi, j.k_out, w.stop, j.X.eps, MAXB, w.H);
+  launch_pivot_block<T, TF>((const T*)w.XS, dp, (const TF*)w.FS, r, bi, j.k_out, w.stop, j.X.eps,
+                            w.pd2, w.pff, w.H, st);
   hipLaunchKernelGGL((k_accept_reject<T, TN, TF>), dim3(1), dim3(1024), 0, st, w.H, bi, w.prop, z,
                      o->tau, o->mode, (const T*)w.XS, dp, (const TN*)w.ns, (const TF*)w.FS, r,
                      j.k_out, (const int32_t*)j.k_out, w.nT, w.stop, j.pivots, w.Lc, w.Si,
@@ -1646,10 +1692,9 @@ static int run_factor_lowmem(const rpc_points* X, const rpc_factor_opts* o, doub
                        dim3(256), 0, st, (const T*)w.XS, (const T*)l.XSall, dp, bi, R, sw, i,
                        (const int32_t*)l.round_nT, X->eps, l.KP);
     dense::gemm64<false, true>(st, R, bi, R, l.Minv, R, l.KP, R, (double*)w.FS, R, 1.0, 0.0);
-    const unsigned hb = (unsigned)((bi + 15) / 16);
-    hipLaunchKernelGGL((k_pivot_block<T, double>), dim3(hb, hb), dim3(256), 0, st, (const T*)w.XS,
-                       dp, (const double*)w.FS, R, bi, (const int32_t*)(l.pads + i), w.stop, X->eps,
-                       MAXB, w.H);
+    launch_pivot_block<T, double>((const T*)w.XS, dp, (const double*)w.FS, R, bi,
+                                  (const int32_t*)(l.pads + i), w.stop, X->eps, w.pd2, w.pff, w.H,
+                                  st);
     hipLaunchKernelGGL((k_accept_reject<T, TN, double>), dim3(1), dim3(1024), 0, st, w.H, bi,
                        w.prop, z, o->tau, o->mode, (const T*)w.XS, dp, (const TN*)w.ns,
                        (const double*)w.FS, R, k_out, (const int32_t*)(l.pads + i), w.nT, w.stop,
