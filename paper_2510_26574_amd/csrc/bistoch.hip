@@ -511,6 +511,7 @@ struct EigWs {
   int64_t* pi;
   double* Ut;
   int32_t* conv;
+  int32_t* cskip;  // per block step of the r x r Cholesky: nothing left inside k
   double* delta;
   double* sk;
   double* skq;  // split-K partials of the r x p block product
@@ -553,6 +554,7 @@ static size_t carve_eig(WsCursor& c, EigWs& w, int64_t N, int r, int nev, bool f
   w.pi = c.take<int64_t>((size_t)nbu * nev);
   w.Ut = fix_const ? c.take<double>((size_t)align_up((size_t)N, 8) * nev) : nullptr;
   w.conv = c.take<int32_t>(1);
+  w.cskip = c.take<int32_t>((size_t)(r + dense::NB - 1) / dense::NB);
   w.delta = c.take<double>(1);
   w.sk = c.take<double>((size_t)dense::SPLITK_MAX * p * p);
   w.skq = c.take<double>((size_t)dense::SPLITK_MAX * r * p);
@@ -627,7 +629,7 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   RPC_LAUNCH_CHECK();
 
   // ---- Cholesky QR in Gram space: S G_B S = L' L'^T, R = L'^T S^{-1}
-  dense::cholesky(st, w.Gs, r, r, status);
+  dense::cholesky(st, w.Gs, r, r, status, k, w.cskip);
   // M = R C R^T = L'^T (S^{-1} C S^{-1}) L'
   dense::gemm64<false, true>(st, r, r, r, w.Cs, r, w.Gs, r, w.T1, r, 1.0, 0.0);
   dense::gemm64<true, true>(st, r, r, r, w.Gs, r, w.T1, r, w.M, r, 1.0, 0.0);

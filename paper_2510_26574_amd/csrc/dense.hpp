@@ -164,12 +164,23 @@ __device__ inline void chol_panel_lds(double* a, int n, int lda_s, int32_t* stat
   }
 }
 
-// Factor the NB x NB diagonal block starting at (j0, j0) of A (n x n, ld).
+// Active order of a matrix whose rows and columns from *kptr on are those of
+// the identity (no coupling): its Cholesky factor is the identity there too.
+__device__ inline int active_n(int n, const int32_t* kptr) {
+  if (!kptr) return n;
+  const int k = *kptr;
+  return k < n ? (k > 0 ? k : 0) : n;
+}
+
+// Factor the NB x NB diagonal block starting at (j0, j0) of A (n x n, ld);
+// only its part inside the active order.
 __global__ __launch_bounds__(256) void k_chol_diag(double* A, int64_t ld, int n, int j0,
-                                                   int32_t* status) {
+                                                   int32_t* status, const int32_t* kptr) {
   constexpr int LDS = NB + 1;  // odd stride: column walks do not pile onto one bank
   __shared__ double a[NB * LDS];
   __shared__ double piv[NB];
+  n = active_n(n, kptr);
+  if (j0 >= n) return;
   const int nb = n - j0 < NB ? n - j0 : NB;
   for (int e = threadIdx.x; e < nb * nb; e += 256) {
     int i = e % nb, c = e / nb;
@@ -183,9 +194,12 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* A, int64_t ld, int n,
 }
 
 // Panel: rows i >= j0 + NB of block column j0 solve x L_jj^T = a (forward
-// substitution along the row), one thread per row.
-__global__ __launch_bounds__(256) void k_chol_panel(double* A, int64_t ld, int n, int j0) {
+// substitution along the row), one thread per row, within the active order.
+__global__ __launch_bounds__(256) void k_chol_panel(double* A, int64_t ld, int n, int j0,
+                                                    const int32_t* kptr) {
   __shared__ double L[NB * NB];
+  n = active_n(n, kptr);
+  if (j0 >= n) return;
   const int nb = n - j0 < NB ? n - j0 : NB;
   for (int e = threadIdx.x; e < nb * nb; e += 256) {
     int i = e % nb, c = e / nb;
@@ -210,17 +224,31 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* A, int64_t ld, int n
     if (c < nb) A[row + (int64_t)(j0 + c) * ld] = x[c];
 }
 
+// skip[b] = 1 when block step b has no trailing rows inside the active order.
+__global__ void k_chol_skips(int n, const int32_t* kptr, int nblk, int32_t* skip) {
+  const int ne = active_n(n, kptr);
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) skip[b] = (b + 1) * NB >= ne ? 1 : 0;
+}
+
 // Blocked right-looking Cholesky A = L L^T (lower, column-major), in place.
-inline void cholesky(hipStream_t st, double* A, int64_t ld, int n, int32_t* status) {
+// kptr (optional, device): rows and columns from *kptr on are those of the
+// identity; the block steps past it return at once (skip holds one int per
+// block step).
+inline void cholesky(hipStream_t st, double* A, int64_t ld, int n, int32_t* status,
+                     const int32_t* kptr = nullptr, int32_t* skip = nullptr) {
+  const int nblk = (n + NB - 1) / NB;
+  if (kptr && skip)
+    hipLaunchKernelGGL(k_chol_skips, dim3(1), dim3(256), 0, st, n, kptr, nblk, skip);
   for (int j0 = 0; j0 < n; j0 += NB) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, A, ld, n, j0, status);
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, A, ld, n, j0, status, kptr);
     const int rest = n - j0 - NB;
     if (rest > 0) {
-      hipLaunchKernelGGL(k_chol_panel, dim3((rest + 255) / 256), dim3(256), 0, st, A, ld, n, j0);
+      hipLaunchKernelGGL(k_chol_panel, dim3((rest + 255) / 256), dim3(256), 0, st, A, ld, n, j0,
+                         kptr);
       // trailing A[j0+NB:, j0+NB:] -= P P^T, P = A[j0+NB:, j0:j0+NB]
       const double* P = A + (j0 + NB) + (int64_t)j0 * ld;
       gemm64<false, false>(st, rest, rest, NB, P, ld, P, ld, A + (j0 + NB) + (int64_t)(j0 + NB) * ld,
-                           ld, -1.0, 1.0);
+                           ld, -1.0, 1.0, (kptr && skip) ? skip + j0 / NB : nullptr);
     }
   }
   hipLaunchKernelGGL(k_zero_upper, dim3((unsigned)(((int64_t)n * n + 255) / 256)), dim3(256), 0, st,
