@@ -148,6 +148,24 @@ def test_split16_ragged_shapes(gpu, n, d, unfused):
     assert not out["F"][:, k:].any().item()
 
 
+def test_sampled_large_rank_f64(gpu):
+    """Ranks in the hundreds: the proposal block's factor product spans several
+    slices of the split proposal-block kernel (coordinates and factor columns
+    in one index range), many rounds of b = 64; pivots identical to the
+    oracle's, F within the float64 bar."""
+    X = torus_points(3000, seed=41)
+    eps = median_sq_distance(X, seed=41) / 16.0  # narrow kernel: slow spectral decay, many pivots
+    r, b = 600, 64
+    u = uniform_stream(2 * b * (-(-r // b)), seed=41)
+    ref = oracle.arpc(X, eps, r=r, b=b, mode="sampled", uniforms=u)
+    out, k, F, piv, rho = _run_factor(gpu, X, eps, r, b, "sampled", u=u)
+    assert ref["k"] > 300
+    assert k == ref["k"] and list(piv[:k]) == list(ref["S"])
+    err = np.abs(F[:, :k] - ref["F"]).max() / np.abs(ref["F"]).max()
+    print(f"k = {k}: F error {err:.3g}")
+    assert err < 1e-12
+
+
 def test_degenerate_all_equal_points(gpu):
     X = np.ones((300, 4), dtype=np.float32)
     u = uniform_stream(2 * 4 * 4, seed=1)
