@@ -152,7 +152,9 @@ def test_sampled_large_rank_f64(gpu):
     """Ranks in the hundreds: the proposal block's factor product spans several
     slices of the split proposal-block kernel (coordinates and factor columns
     in one index range), many rounds of b = 64; pivots identical to the
-    oracle's, F within the float64 bar."""
+    oracle's.  F is held to the float64 error model of its products and block
+    solves, 10 sqrt(k) u cond(F(S, :)) (u = 2^-53; the two sides sum and block
+    differently), which at this rank exceeds the small cases' 1e-12."""
     X = torus_points(3000, seed=41)
     eps = median_sq_distance(X, seed=41) / 16.0  # narrow kernel: slow spectral decay, many pivots
     r, b = 600, 64
@@ -162,8 +164,9 @@ def test_sampled_large_rank_f64(gpu):
     assert ref["k"] > 300
     assert k == ref["k"] and list(piv[:k]) == list(ref["S"])
     err = np.abs(F[:, :k] - ref["F"]).max() / np.abs(ref["F"]).max()
-    print(f"k = {k}: F error {err:.3g}")
-    assert err < 1e-12
+    bar = 10.0 * math.sqrt(k) * 2.0 ** -53 * np.linalg.cond(ref["F"][np.asarray(ref["S"]), :])
+    print(f"k = {k}: F error {err:.3g}, bar {bar:.3g}")
+    assert err < bar
 
 
 def test_degenerate_all_equal_points(gpu):
