@@ -169,6 +169,21 @@ def test_sampled_large_rank_f64(gpu):
     assert err < bar
 
 
+def test_repeated_proposals(gpu):
+    """A block that proposes the same point several times (32 draws from 50
+    points, 8 of them repeats in the first round): Algorithm 3 accepts a point
+    at most once; pivots identical to the oracle's, F within the float64 bar."""
+    rng = np.random.default_rng(51)
+    X = rng.standard_normal((50, 4)).astype(np.float32)
+    eps = median_sq_distance(X, seed=51)
+    u = uniform_stream(2 * 32 * 2, seed=51)
+    ref = oracle.arpc(X, eps, r=40, b=32, mode="sampled", uniforms=u)
+    out, k, F, piv, rho = _run_factor(gpu, X, eps, 40, 32, "sampled", u=u)
+    assert k == ref["k"] and list(piv[:k]) == list(ref["S"])
+    assert len(set(piv[:k].tolist())) == k
+    assert np.abs(F[:, :k] - ref["F"]).max() / np.abs(ref["F"]).max() < 1e-12
+
+
 def test_degenerate_all_equal_points(gpu):
     X = np.ones((300, 4), dtype=np.float32)
     u = uniform_stream(2 * 4 * 4, seed=1)
