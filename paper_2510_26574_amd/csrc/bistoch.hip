@@ -558,7 +558,7 @@ static size_t carve_eig(WsCursor& c, EigWs& w, int64_t N, int r, int nev, bool f
   w.delta = c.take<double>(1);
   w.sk = c.take<double>((size_t)dense::SPLITK_MAX * p * p);
   w.skq = c.take<double>((size_t)dense::SPLITK_MAX * r * p);
-  w.gsc = c.take<float>(64);
+  w.gsc = c.take<float>(2 * syrk::MAX_CHUNKS);
   return c.used;
 }
 

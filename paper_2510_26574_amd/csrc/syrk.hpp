@@ -504,38 +504,58 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_split_partial(
       }
 }
 
-// G[i + j r] = sum over chunks of the partial tile entry (min(i,j), max(i,j)).
+// G[i + j r] = sum over chunks of the partial tile entry (min(i,j), max(i,j)):
+// workgroups run over the upper tiles (blockIdx.y) and each thread sums two
+// adjacent entries of its tile over the chunks (16-byte loads, chunks in
+// order, eight in flight), then writes them and their mirror images.  Inside a
+// diagonal tile only the upper entry is used for both, so G is exactly
+// symmetric; entries with an index >= k are zero.
 __global__ __launch_bounds__(256) void k_syrk_reduce(const double* __restrict__ part, int nch, int r,
                                                      double* __restrict__ G, const int32_t* kptr) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)r * r) return;
-  const int i = (int)(e % r), j = (int)(e / r);
-  const int kk = kptr ? *kptr : r;
-  if (i >= kk || j >= kk) {
-    G[e] = 0.0;
-    return;
-  }
   const int nt = n_tiles(r), nu = n_upper(nt);
-  // both (i, j) and (j, i) read the upper-triangle entry, also inside a
-  // diagonal tile (whose two mirror entries were summed separately), so G is
-  // exactly symmetric
-  int a = i, b = j;
-  if (i > j) {
-    a = j;
-    b = i;
+  const int u = blockIdx.y;
+  int ti, tj;
+  upper_decode(u, nt, ti, tj);
+  const int e = (blockIdx.x * 256 + threadIdx.x) * 2;  // entries e, e + 1: rows a, a + 1 of column b
+  if (e >= TILE * TILE) return;
+  const int a = e % TILE, b = e / TILE;
+  const int kk = kptr ? *kptr : r;
+  double s0 = 0.0, s1 = 0.0;
+  if (tj * TILE < kk) {  // tiles wholly past k were not computed
+    const double* p = part + (int64_t)u * TILE * TILE + e;
+    const int64_t step = (int64_t)nu * TILE * TILE;
+#pragma unroll 8
+    for (int c = 0; c < nch; ++c) {
+      const v2d v = *reinterpret_cast<const v2d*>(p + c * step);
+      s0 += v[0];
+      s1 += v[1];
+    }
   }
-  const int t = upper_index(a / TILE, b / TILE, nt);
-  const int64_t off = (int64_t)t * TILE * TILE + (a % TILE) + (int64_t)(b % TILE) * TILE;
-  double acc = 0.0;
-  for (int c = 0; c < nch; ++c) acc += part[(int64_t)c * nu * TILE * TILE + off];
-  G[e] = acc;
+  const int j = tj * TILE + b;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int i = ti * TILE + a + h;
+    if (i >= r || j >= r) continue;
+    if (ti == tj && a + h > b) continue;  // the mirror of an upper entry of this tile
+    const double v = (i < kk && j < kk) ? (h ? s1 : s0) : 0.0;
+    G[i + (int64_t)j * r] = v;
+    G[j + (int64_t)i * r] = v;
+  }
 }
 
 // Row chunking: about 32 chunks of whole 256-row flush runs (both types).
-inline void plan(int64_t N, int& nch, int64_t& chunk, bool f32) {
-  (void)f32;
-  int64_t want = (N + 255) / 256;
-  int c = (int)(want < 32 ? want : 32);
+// Row chunks of the Gram partial products: about 4096 workgroups per Gram
+// (chunks x upper tiles), at least 256 rows per chunk, at most MAX_CHUNKS
+// chunks; the partial buffers then hold about 4096 tiles of 128 x 128 doubles
+// per Gram.  Many short workgroups keep the ones that share a chunk's panels
+// close together in time, so more of the panel re-reads hit L2.
+constexpr int MAX_CHUNKS = 128;
+inline void plan(int64_t N, int r, int& nch, int64_t& chunk) {
+  const int nu = n_upper(n_tiles(r));
+  int64_t want = (4096 + nu - 1) / nu;
+  const int64_t rows_cap = (N + 255) / 256;
+  if (want > rows_cap) want = rows_cap;
+  int c = (int)(want < MAX_CHUNKS ? want : MAX_CHUNKS);
   if (c < 1) c = 1;
   chunk = (int64_t)align_up((size_t)((N + c - 1) / c), 256);
   nch = (int)((N + chunk - 1) / chunk);
@@ -544,15 +564,20 @@ inline void plan(int64_t N, int& nch, int64_t& chunk, bool f32) {
 inline size_t part_elems(int64_t N, int r, bool f32) {
   int nch;
   int64_t chunk;
-  plan(N, nch, chunk, f32);
+  plan(N, r, nch, chunk);
   const int nu = n_upper(n_tiles(r));
   return (size_t)nch * nu * TILE * TILE;
 }
 
-// Partial-buffer size that serves both product types (and any rank <= r).
+// Partial-buffer size that serves any rank <= r (the chunk count depends on
+// the tile count, so the largest product of the two is taken).
 inline size_t part_elems_any(int64_t N, int r) {
-  const size_t a = part_elems(N, r, true), b = part_elems(N, r, false);
-  return a > b ? a : b;
+  size_t m = 0;
+  for (int t = 1; t <= n_tiles(r); ++t) {
+    const size_t e = part_elems(N, t * TILE < r ? t * TILE : r, true);
+    m = e > m ? e : m;
+  }
+  return m;
 }
 
 // part0/part1 each hold part_cap doubles, enough when gram2_fits holds
@@ -562,7 +587,7 @@ template <typename T>
 inline bool gram2_fits(int64_t N, int r, size_t part_cap) {
   int nch;
   int64_t chunk;
-  plan(N, nch, chunk, sizeof(T) == 4);
+  plan(N, r, nch, chunk);
   return (size_t)nch * n_upper(n_tiles(r)) * TILE * TILE <= part_cap;
 }
 
@@ -574,7 +599,7 @@ inline void gram2_partial(hipStream_t st, const TF* A, int64_t lda, int64_t N, i
                           const int32_t* kptr = nullptr) {
   int nch;
   int64_t chunk;
-  plan(N, nch, chunk, sizeof(T) == 4);
+  plan(N, r, nch, chunk);
   const int nu = n_upper(n_tiles(r));
   const unsigned blocks = (unsigned)(group_slots(nz, nch) * nu);
   hipLaunchKernelGGL((k_syrk_partial<T, TF>), dim3(blocks), dim3(NTH), 0, st, A, lda, N, r, s0, s1, nz,
@@ -582,13 +607,13 @@ inline void gram2_partial(hipStream_t st, const TF* A, int64_t lda, int64_t N, i
 }
 
 // Split-fp16 form of gram2_partial for float32 operands and scales; scl
-// holds at least nz * nch floats (nch <= 32).
+// holds at least nz * nch floats (nch <= MAX_CHUNKS).
 inline void gram2_partial_split(hipStream_t st, const float* A, int64_t lda, int64_t N, int r,
                                 int nz, const float* s0, const float* s1, float* scl,
                                 double* part0, double* part1, const int32_t* kptr = nullptr) {
   int nch;
   int64_t chunk;
-  plan(N, nch, chunk, true);
+  plan(N, r, nch, chunk);
   const int nu = n_upper(n_tiles(r));
   const int groups = nz * nch;
   hipLaunchKernelGGL(k_split_scales, dim3(groups), dim3(256), 0, st, s0, s1, N, chunk, nch, scl);
@@ -603,10 +628,10 @@ inline void gram2_reduce(hipStream_t st, int64_t N, int r, int nz, const double*
                          const int32_t* kptr = nullptr) {
   int nch;
   int64_t chunk;
-  plan(N, nch, chunk, sizeof(T) == 4);
-  const unsigned gr = (unsigned)(((int64_t)r * r + 255) / 256);
-  hipLaunchKernelGGL(k_syrk_reduce, dim3(gr), dim3(256), 0, st, part0, nch, r, G0, kptr);
-  if (nz == 2) hipLaunchKernelGGL(k_syrk_reduce, dim3(gr), dim3(256), 0, st, part1, nch, r, G1, kptr);
+  plan(N, r, nch, chunk);
+  const dim3 gr(TILE * TILE / 512, (unsigned)n_upper(n_tiles(r)));
+  hipLaunchKernelGGL(k_syrk_reduce, gr, dim3(256), 0, st, part0, nch, r, G0, kptr);
+  if (nz == 2) hipLaunchKernelGGL(k_syrk_reduce, gr, dim3(256), 0, st, part1, nch, r, G1, kptr);
 }
 
 }  // namespace
