@@ -166,7 +166,7 @@ def roofline(w, d, res, prof, steps, prec):
 
 # (profile class, Gram arithmetic) -> kernel the class brackets in the mixed
 # form, as named by rocprofv3
-KERNEL_NAMES = {("gram", "split16"): "k_syrk_split_partial", ("gram", "f32"): "k_syrk_partial<float, float>",
+KERNEL_NAMES = {("gram", "split16"): "k_syrk_split_pair_partial", ("gram", "f32"): "k_syrk_partial<float, float>",
                 ("kernel_cols", "split16"): "k_cols_schurIDF16b", ("kernel_cols", "f32"): "k_cols_schurIDF16b"}
 
 

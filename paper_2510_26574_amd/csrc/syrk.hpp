@@ -504,6 +504,220 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_split_partial(
       }
 }
 
+// Both Grams of one row chunk (nz = 2) from a single pass over its panels:
+// each workgroup loads the float32 panels of its tile once and stages the
+// split of s_0 A and of s_1 A, so the panel reads per MFMA are half those of
+// k_syrk_split_partial.  The two accumulator sets fit the register budget
+// because the runs are joined in float32 rather than float64: a float32 run
+// covers 256 rows (as above) and a float32 second-level sum joins the runs of
+// the chunk, at most PAIR_RUNS of them (the launcher takes this kernel only
+// for such chunks), before the float64 partial tile is written.  Stages are
+// 32 rows deep, which fits two stage buffers of the eight hi/lo operand tiles
+// in the 160 KB of LDS.  Four waves take each Gram, a 64 x 64 quarter of the
+// tile apiece: LDS bandwidth bounds this kernel, and a 64 x 64 wave tile reads
+// a third fewer fragment bytes per MFMA than the 64 x 32 one.
+constexpr int PAIR_BK = 32;
+constexpr int PAIR_LDK = PAIR_BK + 8;  // 80-byte pitch: the 16 rows of a fragment read
+                                       // fall on distinct groups of four banks
+constexpr int PAIR_RUNS = 64;          // most 256-row runs in one chunk
+
+struct PairLoader {  // 128 columns x 32 rows of float32, two 4-row vectors per thread
+  static constexpr int VPC = PAIR_BK / 4;
+  static constexpr int PER = TILE * VPC / NTH;
+  static_assert(NTH % VPC == 0, "every vector of a thread covers the same rows");
+  v4f buf[PER];
+  __device__ inline void load(const float* __restrict__ A, int64_t lda, int r, int c0,
+                              int64_t n0, int64_t n1, int tid) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int vid = tid + p * NTH;
+      const int col = vid / VPC;
+      const int64_t n = n0 + (vid % VPC) * 4;
+      const int gc = c0 + col;
+      if (gc < r && n + 4 <= n1) {
+        buf[p] = *reinterpret_cast<const v4f*>(A + (int64_t)gc * lda + n);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          buf[p][e] = (gc < r && n + e < n1) ? A[(int64_t)gc * lda + n + e] : 0.0f;
+      }
+    }
+  }
+  // hi = fp16(x s), lo = fp16(x s - hi), with s the row scale times the chunk's 2^e
+  __device__ inline void store(_Float16* __restrict__ hi, _Float16* __restrict__ lo,
+                               const float (&ss)[4], int tid) const {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int vid = tid + p * NTH;
+      const int col = vid / VPC;
+      const int kv = (vid % VPC) * 4;
+      v4h h, l;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float x = buf[p][e];
+        const _Float16 xh = (_Float16)(x * ss[e]);
+        h[e] = xh;
+        l[e] = (_Float16)__builtin_fmaf(x, ss[e], -(float)xh);
+      }
+      *reinterpret_cast<v4h*>(hi + col * PAIR_LDK + kv) = h;
+      *reinterpret_cast<v4h*>(lo + col * PAIR_LDK + kv) = l;
+    }
+  }
+};
+
+// Row scales of the 4 rows n .. n + 3 a thread stages (zero past n1).
+__device__ inline void pair_row_scales(const float* __restrict__ s, int64_t n, int64_t n1,
+                                       float (&out)[4]) {
+  if (n + 4 <= n1) {
+    const v4f v = *reinterpret_cast<const v4f*>(s + n);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[e] = v[e];
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[e] = n + e < n1 ? s[n + e] : 0.0f;
+  }
+}
+
+// grid.x = 8 * ceil(nch / 8) * n_upper: chunk ch's tiles on XCD ch % 8.
+// s0 and s1 are both required; scl as for k_syrk_split_partial with nz = 2.
+__global__ __launch_bounds__(NTH, 2) void k_syrk_split_pair_partial(
+    const float* __restrict__ A, int64_t lda, int64_t N, int r, const float* __restrict__ s0,
+    const float* __restrict__ s1, const float* __restrict__ scl, int64_t chunk, int nch,
+    double* __restrict__ part0, double* __restrict__ part1, const int32_t* kptr) {
+  constexpr int BK = PAIR_BK;
+  constexpr int LDK = PAIR_LDK;
+  constexpr int TS = TILE * LDK;
+  // [stage buffer][z][A hi, A lo, B hi, B lo]
+  __shared__ __attribute__((aligned(16))) _Float16 lds[2][2][4][TS];
+  const int nt = n_tiles(r);
+  const int nu = n_upper(nt);
+  const int xcd = blockIdx.x % 8;
+  const int slot = blockIdx.x / 8;
+  const int ch = (slot / nu) * 8 + xcd;
+  if (ch >= nch) return;
+  const int tile = slot % nu;
+  int ti, tj;
+  upper_decode(tile, nt, ti, tj);
+  const int kk = kptr ? *kptr : r;
+  if (tj * TILE >= kk) return;
+  const bool diag = ti == tj;
+  const float scale[2] = {scl[ch], scl[nch + ch]};
+  double* out0 = part0 + ((int64_t)ch * nu + tile) * TILE * TILE;
+  double* out1 = part1 + ((int64_t)ch * nu + tile) * TILE * TILE;
+  const int64_t n0 = (int64_t)ch * chunk;
+  const int64_t n1 = n0 + chunk < N ? n0 + chunk : N;
+
+  // waves 0-3 compute G_0's tile, waves 4-7 G_1's, each a 64 x 64 quarter
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wz = wave >> 2, wm = wave & 1, wn = (wave >> 1) & 1;
+  const int64_t nrow = (tid % PairLoader::VPC) * 4;  // this thread's rows within a stage
+  constexpr int PM = 4, PN = 4;                     // 16 x 16 blocks per wave
+  v4f acc[PM][PN], acc2[PM][PN];
+#pragma unroll
+  for (int i = 0; i < PM; ++i)
+#pragma unroll
+    for (int j = 0; j < PN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        acc[i][j][e] = 0.0f;
+        acc2[i][j][e] = 0.0f;
+      }
+  // register ring of two stages, as in k_syrk_split_partial
+  PairLoader la0, lb0, la1, lb1;
+  float w0[2][4], w1[2][4];  // row scales: w[z][e] = s_z at the rows of ring set 0 / 1
+  auto stage = [&](const PairLoader& la, const PairLoader& lb, const float (&w)[2][4], int b)
+                   __attribute__((always_inline)) {
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+      float ss[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ss[e] = w[z][e] * scale[z];
+      la.store(lds[b][z][0], lds[b][z][1], ss, tid);
+      if (!diag) lb.store(lds[b][z][2], lds[b][z][3], ss, tid);
+    }
+  };
+  auto compute = [&](int b) __attribute__((always_inline)) {
+    const _Float16* ah_s = lds[b][wz][0];
+    const _Float16* al_s = lds[b][wz][1];
+    const _Float16* bh_s = diag ? lds[b][wz][0] : lds[b][wz][2];
+    const _Float16* bl_s = diag ? lds[b][wz][1] : lds[b][wz][3];
+    // lane group lane / 16 takes k = 8 (lane / 16) .. + 7 of the 32-row stage
+    v8h bh[PN], bl[PN];
+#pragma unroll
+    for (int j = 0; j < PN; ++j) {
+      const int o = (wn * 64 + j * 16 + (lane & 15)) * LDK + 8 * (lane >> 4);
+      bh[j] = *reinterpret_cast<const v8h*>(bh_s + o);
+      bl[j] = *reinterpret_cast<const v8h*>(bl_s + o);
+    }
+#pragma unroll
+    for (int i = 0; i < PM; ++i) {
+      const int o = (wm * 64 + i * 16 + (lane & 15)) * LDK + 8 * (lane >> 4);
+      const v8h ah = *reinterpret_cast<const v8h*>(ah_s + o);
+      const v8h al = *reinterpret_cast<const v8h*>(al_s + o);
+#pragma unroll
+      for (int j = 0; j < PN; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  };
+  int rows = 0;
+  auto flush = [&]() __attribute__((always_inline)) {
+    rows += BK;
+    if (rows < FLUSH_ROWS) return;
+    rows = 0;
+#pragma unroll
+    for (int i = 0; i < PM; ++i)
+#pragma unroll
+      for (int j = 0; j < PN; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          acc2[i][j][e] += acc[i][j][e];
+          acc[i][j][e] = 0.0f;
+        }
+  };
+  const int nst = (int)((n1 - n0 + BK - 1) / BK);
+  auto fetch = [&](PairLoader& la, PairLoader& lb, float (&w)[2][4], int q)
+                   __attribute__((always_inline)) {
+    const int64_t p0 = n0 + (int64_t)q * BK;
+    la.load(A, lda, r, ti * TILE, p0, n1, tid);
+    if (!diag) lb.load(A, lda, r, tj * TILE, p0, n1, tid);
+    pair_row_scales(s0, p0 + nrow, n1, w[0]);
+    pair_row_scales(s1, p0 + nrow, n1, w[1]);
+  };
+  fetch(la0, lb0, w0, 0);
+  if (nst > 1) fetch(la1, lb1, w1, 1);
+  stage(la0, lb0, w0, 0);
+  __syncthreads();
+  for (int q = 0; q < nst; q += 2) {
+    if (q + 2 < nst) fetch(la0, lb0, w0, q + 2);
+    compute(0);
+    if (q + 1 < nst) stage(la1, lb1, w1, 1);
+    flush();
+    __syncthreads();
+    if (q + 1 >= nst) break;
+    if (q + 3 < nst) fetch(la1, lb1, w1, q + 3);
+    compute(1);
+    if (q + 2 < nst) stage(la0, lb0, w0, 0);
+    flush();
+    __syncthreads();
+  }
+  const double unscale = 1.0 / ((double)scale[wz] * (double)scale[wz]);
+  double* o = wz ? out1 : out0;
+#pragma unroll
+  for (int i = 0; i < PM; ++i)
+#pragma unroll
+    for (int j = 0; j < PN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double v = ((double)acc2[i][j][e] + (double)acc[i][j][e]) * unscale;
+        const int row = wm * 64 + i * 16 + 4 * (lane >> 4) + e;
+        const int col = wn * 64 + j * 16 + (lane & 15);
+        o[row + col * TILE] = v;
+      }
+}
+
 // G[i + j r] = sum over chunks of the partial tile entry (min(i,j), max(i,j)):
 // workgroups run over the upper tiles (blockIdx.y) and each thread sums two
 // adjacent entries of its tile over the chunks (16-byte loads, chunks in
@@ -543,7 +757,6 @@ __global__ __launch_bounds__(256) void k_syrk_reduce(const double* __restrict__ 
   }
 }
 
-// Row chunking: about 32 chunks of whole 256-row flush runs (both types).
 // Row chunks of the Gram partial products: about 4096 workgroups per Gram
 // (chunks x upper tiles), at least 256 rows per chunk, at most MAX_CHUNKS
 // chunks; the partial buffers then hold about 4096 tiles of 128 x 128 doubles
@@ -617,6 +830,12 @@ inline void gram2_partial_split(hipStream_t st, const float* A, int64_t lda, int
   const int nu = n_upper(n_tiles(r));
   const int groups = nz * nch;
   hipLaunchKernelGGL(k_split_scales, dim3(groups), dim3(256), 0, st, s0, s1, N, chunk, nch, scl);
+  if (nz == 2 && s0 && s1 && chunk <= (int64_t)PAIR_RUNS * FLUSH_ROWS) {
+    const unsigned blocks = (unsigned)(8 * ((nch + 7) / 8) * nu);
+    hipLaunchKernelGGL(k_syrk_split_pair_partial, dim3(blocks), dim3(NTH), 0, st, A, lda, N, r,
+                       s0, s1, (const float*)scl, chunk, nch, part0, part1, kptr);
+    return;
+  }
   const unsigned blocks = (unsigned)(group_slots(nz, nch) * nu);
   hipLaunchKernelGGL(k_syrk_split_partial, dim3(blocks), dim3(NTH), 0, st, A, lda, N, r, s0, s1,
                      (const float*)scl, nz, chunk, nch, part0, part1, kptr);

@@ -24,7 +24,7 @@ def test_profile_traffic_lines():
                 found[m.group(1)] = int(m.group(2))
                 for src in m.group(4).split(","):
                     assert os.path.exists(os.path.join(ROOT, src)), src
-    for kernel in ("k_syrk_split_partial", "k_cols_schurIDF16b", "k_kernel_colsIDF16bff"):
+    for kernel in ("k_syrk_split_pair_partial", "k_cols_schurIDF16b", "k_kernel_colsIDF16bff"):
         assert kernel in found and found[kernel] > 10**8, kernel
 
 

@@ -315,6 +315,36 @@ def test_float32_grams_many_chunks(gpu, gram, ltol, atol):
     assert ae < atol
 
 
+@pytest.mark.parametrize("N", [1_500_000, 2_200_000])
+def test_split16_grams_long_chunks(gpu, N):
+    """Split-fp16 Grams over long row chunks (r = 128, one column tile): at
+    N = 1.5e6 a chunk holds 46 runs of 256 rows (both Grams from one pass over
+    F, runs joined in float32), at N = 2.2e6 it holds 68 (more than 64: one
+    pass per Gram with float64 joins).  Torus points, float32 factor; the
+    eigenvalues match those of the float64-Gram form of the same factor to the
+    split form's bar (4 x the float32 one, as above)."""
+    torch, rp = gpu
+    r, b, nev = 128, 64, 16
+    X = torus_points(N, seed=8)
+    eps = median_sq_distance(X, seed=8) / 64  # a narrow kernel: all 128 columns taken
+    u = uniform_stream(2 * b * (r // b), seed=8)
+    out = rp.rpchol_factor(torch.from_numpy(X).cuda(), eps, r, b, mode="sampled", gemm_dtype="f32",
+                           factor_dtype="f32", uniforms=torch.from_numpy(u).cuda())
+    assert rp.status_sync(out["status"]) == 0
+    k = int(out["k"].item())
+    deg = rp.bistoch_degrees(out["F"], out["k"])
+    assert rp.status_sync(deg["status"]) == 0
+    lam = {}
+    for gram in ("f64", "split16"):
+        e = rp.bistoch_eig(out["F"], out["k"], deg["d"], deg["q"], nev, gram_dtype=gram)
+        assert rp.status_sync(e["status"]) == 0
+        lam[gram] = e["lam"].cpu().numpy()
+    le = np.abs(lam["split16"] / lam["f64"] - 1).max()
+    print(f"N={N}, k={k}: eigenvalue error {le:.3g}")
+    assert np.min(np.abs(lam["f64"] - 1.0)) < 1e-6
+    assert le < 4e-6
+
+
 def test_split16_rejects_float64_factor(gpu):
     torch, rp = gpu
     X, eps = _torus_case(seed=5)
