@@ -91,7 +91,8 @@ __global__ void k_reduce_cols(const double* __restrict__ part, int nch, int r, d
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= r) return;
   double s = 0.0;
-  for (int c = 0; c < nch; ++c) s += part[(int64_t)c * r + col];
+#pragma unroll 8
+  for (int c = 0; c < nch; ++c) s += part[(int64_t)c * r + col];  // in order, 8 loads in flight
   out[col] = s;
 }
 
