@@ -451,6 +451,43 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ A, i
   }
 }
 
+// v from another lane of the same DPP row (CTRL: a DPP control code with
+// every lane's source inside its row), as two 32-bit moves.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const unsigned long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffull), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// v of lane S of this lane's aligned group of 8: lane S & 3 of each quad by a
+// quad permutation, then the other quad's copy by the half-row mirror.
+template <int S>
+__device__ inline double bcast8(double v) {
+  constexpr int K = S & 3;
+  const double v1 = dpp_f64<K | (K << 2) | (K << 4) | (K << 6)>(v);
+  const double v2 = dpp_f64<0x141>(v1);
+  return ((int)(threadIdx.x & 7) >> 2) == (S >> 2) ? v1 : v2;
+}
+
+// One step i = 8 m + S of the right-looking solve in k_chol_small's inverse.
+template <int S>
+__device__ inline void step8(double (&xr)[JMAX / 8], int m, int sub, int p, int j,
+                             const double* __restrict__ a, const double* __restrict__ rdg) {
+  constexpr int LDS = JMAX + 1;
+  const int i = 8 * m + S;
+  const double xv = bcast8<S>(xr[m] * rdg[i]);
+  if (sub == S) xr[m] = xv;
+#pragma unroll
+  for (int m2 = 0; m2 < JMAX / 8; ++m2) {
+    if (m2 < m) continue;
+    const int r = sub + 8 * m2;
+    const double l = a[r + i * LDS];  // r, i < JMAX: inside the array
+    xr[m2] = (r > i && r < p) ? xr[m2] - l * xv : xr[m2];
+  }
+}
+
 // One-workgroup Cholesky G = R^T R of a p x p SPD matrix (p <= JMAX); writes
 // R (upper, column-major, ldr; zero below the diagonal).  With `equil` the
 // factorisation runs on the equilibrated S G S, s_i = 1/sqrt(G_ii), and
@@ -485,22 +522,39 @@ __global__ __launch_bounds__(1024) void k_chol_small(const double* __restrict__ 
     }
     return;
   }
-  // X = L^{-1} by forward substitution, one column per group of 8 lanes
-  // (partial dot products over every 8th index, joined by xor shuffles; all
-  // 8 lanes hold the sum and store the same value).  Then
-  // R^{-1} = S L^{-T} = S X^T (upper).
+  // X = L^{-1}, one column j per group of 8 lanes, right-looking: lane sub
+  // keeps rows r = sub + 8 m of x in registers; step i (unrolled, so i is a
+  // constant) takes x_i = b_i / L(i, i) in its owner lane, broadcasts it to
+  // the group (two DPP moves) and subtracts L(r, i) x_i from the rows r > i.
+  // The steps are straight-line code and their L loads do not depend on
+  // earlier steps, so only the broadcast and one fma per step are serial.
+  // Steps i < j see x_i = 0.  Then R^{-1} = S L^{-T} = S X^T.
+  __shared__ double rdg[JMAX];
+  if (tid < p) rdg[tid] = 1.0 / a[tid + tid * LDS];
+  __syncthreads();
+  constexpr int MR = JMAX / 8;
   const int g = tid >> 3, sub = tid & 7;
   if (g < p) {
     const int j = g;
-    double* x = xi + j * LDS;
-    x[j] = 1.0 / a[j + j * LDS];
-    for (int i = j + 1; i < p; ++i) {
-      double t = 0.0;
-      for (int q = j + sub; q < i; q += 8) t += a[i + q * LDS] * x[q];
-      t += __shfl_xor(t, 1, 64);
-      t += __shfl_xor(t, 2, 64);
-      t += __shfl_xor(t, 4, 64);
-      x[i] = -t / a[i + i * LDS];
+    double xr[MR];
+#pragma unroll
+    for (int m = 0; m < MR; ++m) xr[m] = (sub + 8 * m == j) ? 1.0 : 0.0;
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+      // steps i >= p (possible for p < JMAX) only touch rows >= p, never stored
+      step8<0>(xr, m, sub, p, j, a, rdg);
+      step8<1>(xr, m, sub, p, j, a, rdg);
+      step8<2>(xr, m, sub, p, j, a, rdg);
+      step8<3>(xr, m, sub, p, j, a, rdg);
+      step8<4>(xr, m, sub, p, j, a, rdg);
+      step8<5>(xr, m, sub, p, j, a, rdg);
+      step8<6>(xr, m, sub, p, j, a, rdg);
+      step8<7>(xr, m, sub, p, j, a, rdg);
+    }
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+      const int r = sub + 8 * m;
+      if (r < p) xi[r + j * LDS] = xr[m];
     }
   }
   __syncthreads();
