@@ -117,28 +117,36 @@ __device__ inline void chol_panel_lds(double* a, int n, int lda_s, int32_t* stat
         P0[q] = (q < jw && i0 < n) ? a[i0 + (j0 + q) * lda_s] : 0.0;
         P1[q] = (q < jw && i1 < n) ? a[i1 + (j0 + q) * lda_s] : 0.0;
       }
+      // one column of the panel: pivot, scale, update the panel's later
+      // columns; a full panel (jw == W) runs without per-column branches so
+      // the columns' independent updates can interleave
+      bool bad = false;
+      auto column = [&](int jj, int cw) __attribute__((always_inline)) {
+        double p = bcast_lane(P0[jj], jj);  // diagonal (j0 + jj, j0 + jj)
+        bad |= !(p > 0.0);
+        p = p > 0.0 ? p : 1.0;
+        const double rd = rsqrt(p), d = p * rd;
+        // column jj: rows below the diagonal scaled, the diagonal set to d
+        P0[jj] = lane > jj ? P0[jj] * rd : (lane == jj ? d : P0[jj]);
+        P1[jj] = P1[jj] * rd;
 #pragma unroll
-      for (int jj = 0; jj < W; ++jj) {
-        if (jj < jw) {
-          double p = bcast_lane(P0[jj], jj);  // diagonal (j0 + jj, j0 + jj)
-          if (!(p > 0.0)) {
-            if (lane == 0) set_status(status, RPC_EBREAKDOWN);
-            p = 1.0;
-          }
-          const double d = sqrt(p), rd = 1.0 / d;
-          // column jj: rows below the diagonal scaled, the diagonal set to d
-          P0[jj] = lane > jj ? P0[jj] * rd : (lane == jj ? d : P0[jj]);
-          P1[jj] = P1[jj] * rd;
-#pragma unroll
-          for (int c2 = jj + 1; c2 < W; ++c2) {
-            if (c2 < jw) {
-              const double f = bcast_lane(P0[jj], c2);  // L(j0 + c2, j0 + jj)
-              if (lane >= c2) P0[c2] -= P0[jj] * f;
-              P1[c2] -= P1[jj] * f;
-            }
+        for (int c2 = jj + 1; c2 < W; ++c2) {
+          if (c2 < cw) {
+            const double f = bcast_lane(P0[jj], c2);  // L(j0 + c2, j0 + jj)
+            P0[c2] = lane >= c2 ? P0[c2] - P0[jj] * f : P0[c2];
+            P1[c2] -= P1[jj] * f;
           }
         }
+      };
+      if (jw == W) {
+#pragma unroll
+        for (int jj = 0; jj < W; ++jj) column(jj, W);
+      } else {
+#pragma unroll
+        for (int jj = 0; jj < W; ++jj)
+          if (jj < jw) column(jj, jw);
       }
+      if (bad && lane == 0) set_status(status, RPC_EBREAKDOWN);
 #pragma unroll
       for (int q = 0; q < W; ++q) {
         if (q < jw && i0 < n && lane >= q) a[i0 + (j0 + q) * lda_s] = P0[q];
