@@ -206,6 +206,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* A, int64_t ld, int n,
 __global__ __launch_bounds__(256) void k_chol_panel(double* A, int64_t ld, int n, int j0,
                                                     const int32_t* kptr) {
   __shared__ double L[NB * NB];
+  __shared__ double rdg[NB];  // 1 / L(c, c), taken once
   n = active_n(n, kptr);
   if (j0 >= n) return;
   const int nb = n - j0 < NB ? n - j0 : NB;
@@ -213,19 +214,29 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* A, int64_t ld, int n
     int i = e % nb, c = e / nb;
     L[i + c * NB] = A[(j0 + i) + (int64_t)(j0 + c) * ld];
   }
+  if ((int)threadIdx.x < nb) {
+    const int c = threadIdx.x;
+    rdg[c] = 1.0 / A[(j0 + c) + (int64_t)(j0 + c) * ld];
+  }
   __syncthreads();
   const int64_t row = (int64_t)j0 + nb + blockIdx.x * 256 + threadIdx.x;
   if (row >= n) return;
   double x[NB];
 #pragma unroll
   for (int c = 0; c < NB; ++c) x[c] = c < nb ? A[row + (int64_t)(j0 + c) * ld] : 0.0;
+  // forward substitution x L^T = a; a full block runs without per-column branches
+  auto column = [&](int c) __attribute__((always_inline)) {
+    double s = x[c];
+    for (int l = 0; l < c; ++l) s -= x[l] * L[c + l * NB];
+    x[c] = s * rdg[c];
+  };
+  if (nb == NB) {
 #pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    if (c < nb) {
-      double s = x[c];
-      for (int l = 0; l < c; ++l) s -= x[l] * L[c + l * NB];
-      x[c] = s / L[c + c * NB];
-    }
+    for (int c = 0; c < NB; ++c) column(c);
+  } else {
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (c < nb) column(c);
   }
 #pragma unroll
   for (int c = 0; c < NB; ++c)
@@ -404,7 +415,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ A, i
         if (apq != 0.0 && fabs(apq) > 1e-300) {
           const double tau = (aqq - app) / (2.0 * apq);
           const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
+          c = rsqrt(1.0 + t * t);
           s = t * c;
         }
         cs[tid] = c;
