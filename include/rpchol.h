@@ -157,7 +157,14 @@ typedef struct {
 /* Options of bistoch_eig (Algorithm 1 after the factorisation).
  *  nev        number of leading eigenpairs returned (1 <= nev <= r).
  *  gamma      regulariser added to the entries (i, i), i < k, of D~^{-1} F
- *             before the QR (the paper's stabilised QR); default 0.
+ *             before the QR (the stabilised QR of the "Numerical experiments"
+ *             section); default 0.  The decomposition is then that of
+ *             B' C B'^T with B' = D~^{-1} F + gamma E_k (E_k: ones at (i, i),
+ *             i < k): G_B gains gamma (B_k + B_k^T) + gamma^2 I_k and U rows
+ *             i < k gain gamma (R^{-1} V)[i, :], so U stays orthonormal; the
+ *             eigenvalues carry a floor of order gamma^2 (the paper's 1e-8
+ *             floor).  ext_E satisfies U = B' ext_E, so the extension of a
+ *             training row i < k differs from U[i, :] by gamma ext_E[i, :].
  *  fix_const  if nonzero, U(:, 0) is set to 1/sqrt(N) and U re-orthonormalised
  *             by a QR with positive diag(R) (Algorithm 1, optional lines).
  *  gram_dtype F64, F32 or F32_SPLIT16: arithmetic of the two N-long Gram
@@ -233,7 +240,8 @@ int bistoch_degrees(const void* F, int32_t f_dtype, int64_t N, int64_t ldf, int3
                     rpc_stream_t stream);
 
 /* ---- Algorithm 1: factored EVD ----------------------------------------
- * With B = D~^{-1} F (+ gamma on its leading diagonal) and C = F^T Q~^{-1} F:
+ * With B = D~^{-1} F (+ gamma on its leading diagonal, see rpc_eig_opts) and
+ * C = F^T Q~^{-1} F:
  * G_B = B^T B = R^T R (Cholesky QR, R upper triangular with positive
  * diagonal, so Q = B R^{-1} is never formed), M = R C R^T, M = V Lambda V^T,
  * U = B R^{-1} V(:, :nev).  Outputs: U (N x nev, column-major, u_dtype;

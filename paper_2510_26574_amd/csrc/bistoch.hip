@@ -152,8 +152,11 @@ __global__ __launch_bounds__(256) void k_gram_finish(double* __restrict__ GB, do
     GB[e] = g;
     C[e] = c;
   } else {
-    const double si = 1.0 / sqrt(GB[i + (int64_t)i * r]);
-    const double sj = 1.0 / sqrt(GB[j + (int64_t)j * r]);
+    // a diagonal entry <= 0 (singular G_B) keeps scale 1, so the Cholesky
+    // meets a pivot <= 0, reports RPC_EBREAKDOWN and stays finite
+    const double gi = GB[i + (int64_t)i * r], gj = GB[j + (int64_t)j * r];
+    const double si = gi > 0.0 ? 1.0 / sqrt(gi) : 1.0;
+    const double sj = gj > 0.0 ? 1.0 / sqrt(gj) : 1.0;
     Gs[e] = GB[e] * si * sj;
     Cs[e] = C[e] / (si * sj);
     if (i == j) s[i] = si;
@@ -377,6 +380,21 @@ __global__ __launch_bounds__(512, 4) void k_form_u_split(const float* __restrict
         }
       }
     }
+}
+
+// The regularised QR factors B' = D~^{-1} F + gamma E_k (E_k: ones at (i, i),
+// i < k), so U = B' R^{-1} V = D~^{-1} F Z + gamma E_k Z with Z = R^{-1} V: rows
+// i < k of U gain gamma Z[i, :].
+template <typename TU>
+__global__ void k_gamma_rows(TU* __restrict__ U, int64_t ldu, int64_t N,
+                             const double* __restrict__ Z, int r, int nev,
+                             const int32_t* __restrict__ kptr, double gamma) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * nev) return;
+  const int i = (int)(e % r), j = (int)(e / r);
+  if (i >= *kptr || i >= N) return;
+  TU* u = U + i + (int64_t)j * ldu;
+  *u = (TU)(to_d(*u) + gamma * Z[e]);
 }
 
 // out[0] = 2^e with max |x| 2^e < 2^14 (1 when x is all zero), one workgroup.
@@ -734,6 +752,9 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   if (!split_u)
     hipLaunchKernelGGL((k_form_u<TG, TF, TU>), gu, dim3(CfgU::NT), smU, st, F, ldf, N, r,
                        (const TG*)Zt, nev, (const double*)w.sd, U, ldu, k);
+  if (o->gamma != 0.0)
+    hipLaunchKernelGGL((k_gamma_rows<TU>), dim3(nblk((int64_t)r * nev)), dim3(256), 0, st, U, ldu, N,
+                       (const double*)w.Z, r, nev, k, o->gamma);
   RPC_LAUNCH_CHECK();
 
   if (o->fix_const) {

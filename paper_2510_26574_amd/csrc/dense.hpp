@@ -451,13 +451,16 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ A, i
       __syncthreads();
     }
   }
-  // sort the p real eigenvalues in decreasing order (selection by rank)
+  // sort the p real eigenvalues in decreasing order (selection by rank; a
+  // NaN ranks as -inf, so the ranks always form a permutation)
   __shared__ int order[JMAX];
   if (tid < p) {
-    const double x = a[tid + tid * n];
+    const double x0 = a[tid + tid * n];
+    const double x = x0 == x0 ? x0 : -INFINITY;
     int rank = 0;
     for (int j = 0; j < p; ++j) {
-      const double y = a[j + j * n];
+      const double y0 = a[j + j * n];
+      const double y = y0 == y0 ? y0 : -INFINITY;
       if (y > x || (y == x && j < tid)) ++rank;
     }
     order[rank] = tid;

@@ -506,3 +506,34 @@ def test_symmetric_normalization_subspace_path(gpu):
     assert np.abs(lam / res["lam"] - 1).max() < 1e-10
     m = _gap_index(res["lam_all"], nev)
     assert _angle(eig["U"].cpu().numpy()[:, :m], res["U"][:, :m]) < 1e-8
+
+
+@pytest.mark.parametrize("gamma", [1e-6, 1e-3])
+@pytest.mark.parametrize("r,b,nev", [(64, 8, 16), (160, 32, 24)])
+def test_eig_gamma_regularised_qr(gpu, gamma, r, b, nev):
+    """The regularised QR of the "Numerical experiments" section: gamma on the
+    entries (i, i), i < k, of D~^{-1} F.  Float64 path against the oracle on
+    the same pivots (bars of the float64 form), U orthonormal, and the
+    extension identity U = B' E with B' the regularised matrix; r = 64 takes
+    the Jacobi eigensolver, r = 160 the subspace iteration."""
+    torch, rp = gpu
+    X, eps = _torus_case(seed=31)
+    u = uniform_stream(2 * b * (-(-r // b)), seed=31)
+    ref = oracle.arpc(X, eps, r=r, b=b, mode="sampled", uniforms=u)
+    out, k, F, piv, rho = _run_factor(gpu, X, eps, r, b, "sampled", u=u)
+    assert k == ref["k"] and list(piv[:k]) == list(ref["S"])
+    deg = rp.bistoch_degrees(out["F"], out["k"])
+    eig = rp.bistoch_eig(out["F"], out["k"], deg["d"], deg["q"], nev, gamma=gamma)
+    assert rp.status_sync(eig["status"]) == 0
+    res = oracle.bistoch_eig(ref["F"], nev, gamma=gamma)
+    lam = eig["lam"].cpu().numpy()
+    U = eig["U"].cpu().numpy()
+    assert np.abs(lam / res["lam"] - 1).max() < 1e-10
+    m = _gap_index(res["lam_all"], nev)
+    assert _angle(U[:, :m], res["U"][:, :m]) < 1e-8
+    assert np.abs(U.T @ U - np.eye(nev)).max() < 1e-10
+    d = deg["d"].cpu().numpy()
+    Bp = F[:, :k] / d[:, None]
+    Bp[np.arange(k), np.arange(k)] += gamma
+    E = eig["E"].cpu().numpy()[:k]
+    assert np.abs(Bp @ E - U).max() < 1e-8

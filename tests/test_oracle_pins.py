@@ -395,7 +395,13 @@ def test_nystrom_extension_reproduces_training_rows():
 
 def test_degree_assert_raises():
     F = np.array([[1.0, 0.0], [-3.0, 0.1], [0.5, 0.2]])
-    with pytest.raises(DegreeError):
+    with pytest.raises(DegreeError, match="D~"):
+        bistoch_degrees(F)
+    # d~ = (2.375, 2.4375, 3.3125, 3.75, 1.25, 0.5) > 0 by hand, but
+    # q~[0] = F[0] . F^T (1/d~) = -0.065 < 0: the second assert fires
+    F = np.array([[0.5, 1.0], [0.0, 0.75], [-0.5, 0.75], [-0.75, 0.75], [-0.25, 0.25], [-0.75, -0.25]])
+    assert np.allclose(F @ (F.T @ np.ones(6)), [2.375, 2.4375, 3.3125, 3.75, 1.25, 0.5])
+    with pytest.raises(DegreeError, match="Q~"):
         bistoch_degrees(F)
 
 
@@ -437,3 +443,31 @@ def test_error_bounds_lemma12_lemma14_thm7():
         ) * tr_err
         lhs = np.abs(np.linalg.eigvalsh(P - Pt)).sum()
         assert lhs <= bound
+
+
+@pytest.mark.parametrize("gamma", [1e-6, 1e-3, 0.1])
+def test_gamma_regularised_qr_matches_dense(gamma):
+    """The regularised QR of the "Numerical experiments" section (gamma added
+    to the entries (i, i), i < k, of D~^{-1} F): the oracle's eigenpairs equal
+    those of the dense N x N matrix B' C B'^T with B' = D~^{-1} F + gamma E_k
+    formed explicitly, its U is orthonormal, and U = B' E (the extension
+    identity, which for gamma > 0 holds with B' and not with D~^{-1} F)."""
+    X, eps, out = _factor(n=500, r=48, b=8, seed=9)
+    F = out["F"]
+    N, k = F.shape
+    nev = 10
+    res = bistoch_eig(F, nev, gamma=gamma)
+    c, d, q = bistoch_degrees(F)
+    Bp = F / d[:, None]
+    Bp[np.arange(k), np.arange(k)] += gamma
+    C = F.T @ (F / q[:, None])
+    lam, V = np.linalg.eigh(Bp @ C @ Bp.T)
+    lam, V = lam[::-1], V[:, ::-1]
+    assert np.max(np.abs(res["lam"] - lam[:nev]) / np.abs(lam[:nev])) < 1e-10
+    m = max(i for i in range(1, nev + 1) if i == nev or lam[i - 1] / lam[i] - 1 > 1e-3)
+    assert _angles(res["U"][:, :m], V[:, :m]) < 1e-8
+    assert np.max(np.abs(res["U"].T @ res["U"] - np.eye(nev))) < 1e-12
+    assert np.max(np.abs(Bp @ res["E"] - res["U"])) < 1e-10
+    # the regulariser moves the spectrum: without it the eigenvalues differ
+    if gamma >= 1e-3:
+        assert np.max(np.abs(bistoch_eig(F, nev)["lam"] - res["lam"])) > 1e-6
