@@ -239,6 +239,22 @@ int bistoch_degrees(const void* F, int32_t f_dtype, int64_t N, int64_t ldf, int3
                     void* workspace, size_t workspace_bytes, int32_t* dev_status,
                     rpc_stream_t stream);
 
+/* ---- bistoch_degrees for callers that cannot allocate ------------------
+ * For code that may not call hipMalloc or pass a workspace (work under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same computation and results as bistoch_degrees, bit for bit, with the
+ * scratch taken from a library-owned static device array of about 9 MiB
+ * (each GPU the library runs on holds one copy until the process ends).
+ * Limits: N <= 1048576 and r <= 1024; larger sizes return RPC_EWORKSPACE
+ * without launching anything.  `stream` must belong to the current device
+ * (RPC_EINVAL otherwise).  Every call on a GPU shares that GPU's array, so
+ * calls that overlap in time on one GPU (different streams, or host
+ * threads) race and give undefined results; calls in one stream are
+ * ordered and safe.  Allocates no device or host memory. */
+int bistoch_degrees_noalloc(const void* F, int32_t f_dtype, int64_t N, int64_t ldf, int32_t r,
+                            const int32_t* k, double* c, double* d_tilde, double* q_tilde,
+                            int32_t* dev_status, rpc_stream_t stream);
+
 /* ---- Algorithm 1: factored EVD ----------------------------------------
  * With B = D~^{-1} F (+ gamma on its leading diagonal, see rpc_eig_opts) and
  * C = F^T Q~^{-1} F:

@@ -67,6 +67,7 @@ _SIGS = {
     "rpchol_factor": [_VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP, _SZ, _VP, _VP],
     "bistoch_degrees_workspace_size": [_I64, _I32, _VP],
     "bistoch_degrees": [_VP, _I32, _I64, _I64, _I32, _VP, _VP, _VP, _VP, _VP, _SZ, _VP, _VP],
+    "bistoch_degrees_noalloc": [_VP, _I32, _I64, _I64, _I32, _VP, _VP, _VP, _VP, _VP, _VP],
     "bistoch_eig_workspace_size": [_I64, _I32, _VP, _VP],
     "bistoch_eig": [_VP, _I32, _I64, _I64, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _I64, _VP, _VP,
                     _VP, _SZ, _VP, _VP],
@@ -309,6 +310,16 @@ def bistoch_degrees(F, k, status=None, stream=None):
     _check(lib.bistoch_degrees(_ptr(F), code, N, ldf, r, _ptr(k), _ptr(c), _ptr(d), _ptr(q), _ptr(ws),
                                nb.value, _ptr(st), _stream(torch, stream)), "bistoch_degrees")
     return {"c": c, "d": d, "q": q, "status": st}
+
+
+def bistoch_degrees_noalloc(F, k, c, d, q, status, stream=None):
+    """bistoch_degrees into caller-given c (r), d, q (N) float64 buffers, with
+    the library's static scratch instead of a workspace (no allocation)."""
+    torch = _torch()
+    code, N, ldf, r = _factor_args(F)
+    _check(load_library().bistoch_degrees_noalloc(_ptr(F), code, N, ldf, r, _ptr(k), _ptr(c), _ptr(d),
+                                                  _ptr(q), _ptr(status), _stream(torch, stream)),
+           "bistoch_degrees_noalloc")
 
 
 def bistoch_eig(F, k, d, q, nev, gamma=0.0, fix_const=False, gram_dtype="f64", u_dtype="f64",

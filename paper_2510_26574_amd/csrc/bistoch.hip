@@ -15,6 +15,7 @@
 // host synchronisation is needed.
 #include <math.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "common.hpp"
@@ -871,6 +872,63 @@ extern "C" int bistoch_degrees(const void* F, int32_t fdt, int64_t N, int64_t ld
   if (fdt == RPC_F32)
     return run_degrees<float>((const float*)F, N, ldf, r, k, c, dt, qt, ws, ws_bytes, status, st);
   return RPC_EINVAL;
+}
+
+// ---- bistoch_degrees with library-owned scratch (no workspace argument)
+// The partial column sums, 1/d~ and w live in one file-scope device array,
+// sized for N <= 2^20 and r <= 1024: 128 chunks x 1024 partial sums, 2^20
+// reciprocals and 1024 weights, each block rounded up to 256 bytes.
+namespace {
+constexpr int64_t NOALLOC_MAX_N = int64_t(1) << 20;
+constexpr int NOALLOC_MAX_R = 1024;
+constexpr size_t NOALLOC_BYTES = size_t(128) * 1024 * 8 + (size_t(1) << 20) * 8 + 1024 * 8 + 3 * 256;
+constexpr int NOALLOC_MAX_DEV = 64;
+}  // namespace
+
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEV] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (each device holds its own copy of the array).
+int scratch_ptr_current(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEV) return RPC_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return RPC_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return RPC_OK;
+}
+}  // namespace
+
+extern "C" int bistoch_degrees_noalloc(const void* F, int32_t fdt, int64_t N, int64_t ldf, int32_t r,
+                                       const int32_t* k, double* c, double* dt, double* qt,
+                                       int32_t* status, rpc_stream_t stream) {
+  if (!F || !k || !c || !dt || !qt || !status || N < 1 || r < 1 || r > N || ldf < N) return RPC_EINVAL;
+  if (fdt != RPC_F64 && fdt != RPC_F32) return RPC_EINVAL;
+  if (N > NOALLOC_MAX_N || r > NOALLOC_MAX_R || degrees_ws(N, r) > NOALLOC_BYTES) return RPC_EWORKSPACE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int dev = 0;
+  RPC_HIP_CHECK(hipGetDevice(&dev));
+  if (st) {
+    int sdev = -1;
+    RPC_HIP_CHECK(hipStreamGetDevice(st, &sdev));
+    if (sdev != dev) return RPC_EINVAL;
+  }
+  void* ws = nullptr;
+  const int rc = scratch_ptr_current(&ws);
+  if (rc != RPC_OK) return rc;
+  // every scratch entry the kernels read is written earlier in the same call,
+  // so nothing needs clearing
+  if (fdt == RPC_F64)
+    return run_degrees<double>((const double*)F, N, ldf, r, k, c, dt, qt, ws, NOALLOC_BYTES, status, st);
+  return run_degrees<float>((const float*)F, N, ldf, r, k, c, dt, qt, ws, NOALLOC_BYTES, status, st);
 }
 
 extern "C" int bistoch_eig_workspace_size(int64_t N, int32_t r, const rpc_eig_opts* o, size_t* bytes) {

@@ -132,6 +132,19 @@ def test_host_side_validation(lib):
         assert rc == rp.RPC_EINVAL
 
 
+def test_noalloc_degrees_host_checks(lib):
+    """The no-allocation degrees call refuses sizes beyond its static scratch
+    (N > 2^20 or r > 1024) before touching a device, and bad arguments."""
+    import paper_2510_26574_amd as rp
+
+    fake = ctypes.c_void_p(0x1000)
+    for N, r, rc in [(1_048_577, 8, rp.RPC_EWORKSPACE), (2_000_000, 1025, rp.RPC_EWORKSPACE),
+                     (100, 101, rp.RPC_EINVAL), (100, 8, rp.RPC_EINVAL)]:
+        fdt = 0 if N != 100 or r != 8 else 7  # the last case: unknown dtype
+        assert lib.bistoch_degrees_noalloc(fake, fdt, N, N + 8, r, fake, fake, fake, fake, fake,
+                                           None) == rc
+
+
 def test_surrogate_and_batched_host_checks(lib):
     import paper_2510_26574_amd as rp
 
