@@ -66,9 +66,10 @@ typedef enum {
 
 /* RPC_F32_SPLIT16: float32 data whose products run on the fp16 MFMA pipe,
  * each operand split as hi = fp16(x) plus lo = fp16(x - hi) and each product
- * taken as hi hi + hi lo + lo hi (float32-grade, about 2^-22 relative per
- * product); accepted as gemm_dtype and as gram_dtype, in both cases with a
- * float32 factor. */
+ * taken as hi hi + hi lo + lo hi (about 2^-22 relative per product: 22 of
+ * float32's 24 significand bits, so a form of its own between bf16 and
+ * float32, not float32-grade); accepted as gemm_dtype and as gram_dtype, in
+ * both cases with a float32 factor. */
 typedef enum { RPC_F64 = 0, RPC_F32 = 1, RPC_BF16 = 2, RPC_F32_SPLIT16 = 3 } rpc_dtype;
 
 typedef enum {
@@ -97,7 +98,8 @@ typedef struct {
  *               accumulation), or F32_SPLIT16 (float32 points, the inner
  *               products as split fp16 pairs after scaling both operands by
  *               one power of two chosen from max |x| (exact): float32-grade
- *               columns at the fp16 MFMA rate; the Schur update is split
+ *               columns at the fp16 MFMA rate, with about 22 of float32's
+ *               24 significand bits per product; the Schur update is split
  *               likewise, the pivot-block solve stays float64; needs
  *               factor_dtype F32).
  *               The pivot block H uses the same points in float64.
@@ -135,10 +137,17 @@ typedef struct {
  *               O(N (d + b) + r^2) beyond the points.  Needs factor_dtype F64;
  *               not with RPC_FACTOR_SHARED_X.  Pivots, k, rho and
  *               round_accepted are as in the full form (to rounding).
+ *               RPC_FACTOR_SPLIT_SOLVE: the pivot-block solve G = W L^{-T}
+ *               runs on the fp16 MFMA pipe as split hi/lo pairs (about 2^-22
+ *               per product) instead of in float64; only with BF16 products
+ *               and a float32 factor, not with RPC_FACTOR_LOW_MEMORY.  Without
+ *               it the solve is float64 in every form, as the method's
+ *               precision form asks.
  *               Other bits: RPC_EINVAL. */
 #define RPC_FACTOR_UNFUSED 1
 #define RPC_FACTOR_SHARED_X 2
 #define RPC_FACTOR_LOW_MEMORY 4
+#define RPC_FACTOR_SPLIT_SOLVE 8
 typedef struct {
   int32_t r;
   int32_t b;

@@ -177,11 +177,12 @@ def status_sync(status, stream=None):
 RPC_FACTOR_UNFUSED = 1
 RPC_FACTOR_SHARED_X = 2
 RPC_FACTOR_LOW_MEMORY = 4
+RPC_FACTOR_SPLIT_SOLVE = 8
 
 
 def rpchol_factor(X, eps, r, b, mode="sampled", uniforms=None, replay=None, gemm_dtype="f64",
                   factor_dtype="f64", tau=0.0, unfused=False, shared_x=False, low_memory=False,
-                  status=None, stream=None):
+                  split_solve=False, status=None, stream=None):
     """Algorithm 2 on the Gaussian kernel of the rows of X (N x d float32, CUDA).
 
     Returns dict: F (N x r view, column-major storage; with low_memory the
@@ -205,7 +206,8 @@ def rpchol_factor(X, eps, r, b, mode="sampled", uniforms=None, replay=None, gemm
     racc = torch.zeros(nrounds, dtype=torch.int32, device=dev)
     opts = rpc_factor_opts(int(r), int(b), MODES[mode], DTYPES[gemm_dtype], DTYPES[factor_dtype],
                            (RPC_FACTOR_UNFUSED if unfused else 0) | (RPC_FACTOR_SHARED_X if shared_x else 0)
-                           | (RPC_FACTOR_LOW_MEMORY if low_memory else 0),
+                           | (RPC_FACTOR_LOW_MEMORY if low_memory else 0)
+                           | (RPC_FACTOR_SPLIT_SOLVE if split_solve else 0),
                            float(tau), 0, 0, 0, 0, racc.data_ptr())
     if mode == "sampled":
         assert uniforms is not None and uniforms.dtype == torch.float64 and uniforms.is_cuda

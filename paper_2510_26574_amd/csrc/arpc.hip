@@ -1416,12 +1416,13 @@ static void phase_solve(FJob<T, TN, TF>& j, int i, hipStream_t st) {
   FactorWs& w = j.w;
   const size_t smD = TileSmem<CfgD, false, true>::bytes;
   prof::begin(prof::SOLVE, st);
-  // mixed form: the solve on the fp16 pipe as split pairs.  The float32-grade
-  // forms (float32 and split-fp16 distances) keep the float64 solve: it
-  // multiplies the columns' rounding errors by up to the condition of the
-  // pivot block, and a split product's 2^-22 there dominates their error.
-  constexpr bool split = std::is_same<T, __bf16>::value && std::is_same<TF, float>::value;
-  if (split) {
+  // The solve is float64 (MFMA) in every form by default.  Only on request
+  // (RPC_FACTOR_SPLIT_SOLVE, bf16 products with a float32 factor) does it run
+  // on the fp16 pipe as split pairs: the solve multiplies the columns'
+  // rounding errors by up to the condition of the pivot block, and a split
+  // product's 2^-22 adds to that.
+  constexpr bool can_split = std::is_same<T, __bf16>::value && std::is_same<TF, float>::value;
+  if (can_split && (j.o->flags & RPC_FACTOR_SPLIT_SOLVE)) {
     hipLaunchKernelGGL(k_split_linv, dim3(1), dim3(1024), 0, st, (const double*)w.Linv, w.nT, w.Lh,
                        w.Ll, w.lsc);
     hipLaunchKernelGGL(k_solve_split, dim3((unsigned)((N + MAXB - 1) / MAXB)), dim3(512),
@@ -1903,7 +1904,11 @@ static int check_factor_args(const rpc_points* X, const rpc_factor_opts* o) {
     if (!o->replay || o->n_replay < 1 || o->n_replay > o->r) return RPC_EINVAL;
   }
   if (!(o->tau >= 0.0)) return RPC_EINVAL;
-  if (o->flags & ~(RPC_FACTOR_UNFUSED | RPC_FACTOR_SHARED_X | RPC_FACTOR_LOW_MEMORY))
+  if (o->flags &
+      ~(RPC_FACTOR_UNFUSED | RPC_FACTOR_SHARED_X | RPC_FACTOR_LOW_MEMORY | RPC_FACTOR_SPLIT_SOLVE))
+    return RPC_EINVAL;
+  if ((o->flags & RPC_FACTOR_SPLIT_SOLVE) &&
+      (o->gemm_dtype != RPC_BF16 || o->factor_dtype != RPC_F32 || (o->flags & RPC_FACTOR_LOW_MEMORY)))
     return RPC_EINVAL;
   if ((o->flags & RPC_FACTOR_LOW_MEMORY) &&
       (o->factor_dtype != RPC_F64 || (o->flags & RPC_FACTOR_SHARED_X)))

@@ -56,7 +56,8 @@ def test_host_side_validation(lib):
         dict(n_uniforms=10),   # too few uniforms
         dict(gemm_dtype=7),
         dict(factor_dtype=2),  # bf16 storage of F is not offered
-        dict(flags=8),         # unknown option bit
+        dict(flags=16),        # unknown option bit
+        dict(flags=8),         # split solve: bf16 products with a float32 factor only
         dict(gemm_dtype=3),    # split-fp16 distances need a float32 factor
     ]
     for kw in bad:
