@@ -68,20 +68,20 @@ def make_inputs(w):
     return X, eps, u
 
 
-def run_path(rp, torch, Xd, eps, ud, w, prec, replay=None):
+def run_path(rp, torch, Xd, eps, ud, w, prec, replay=None, split_solve=False):
     gemm, fac, gram = prec
     mode = "replay" if replay is not None else "sampled"
     out = rp.rpchol_factor(Xd, eps, w["r"], w["b"], mode=mode, uniforms=ud if replay is None else None,
-                           replay=replay, gemm_dtype=gemm, factor_dtype=fac)
+                           replay=replay, gemm_dtype=gemm, factor_dtype=fac, split_solve=split_solve)
     deg = rp.bistoch_degrees(out["F"], out["k"], status=out["status"])
     eig = rp.bistoch_eig(out["F"], out["k"], deg["d"], deg["q"], w["nev"], gram_dtype=gram,
                          status=out["status"])
     return out, deg, eig
 
 
-def timed(rp, torch, Xd, eps, ud, w, prec, steps, warmup, profile=False):
+def timed(rp, torch, Xd, eps, ud, w, prec, steps, warmup, profile=False, split_solve=False):
     for _ in range(warmup):
-        res = run_path(rp, torch, Xd, eps, ud, w, prec)
+        res = run_path(rp, torch, Xd, eps, ud, w, prec, split_solve=split_solve)
         st = rp.status_sync(res[0]["status"])
         if st != 0:
             raise RuntimeError(f"device status {rp.STATUS_NAMES.get(st, st)} for {prec}")
@@ -91,7 +91,7 @@ def timed(rp, torch, Xd, eps, ud, w, prec, steps, warmup, profile=False):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        res = run_path(rp, torch, Xd, eps, ud, w, prec)
+        res = run_path(rp, torch, Xd, eps, ud, w, prec, split_solve=split_solve)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     prof = None
@@ -105,39 +105,45 @@ def timed(rp, torch, Xd, eps, ud, w, prec, steps, warmup, profile=False):
 
 
 def roofline(w, d, res, prof, steps, prec):
-    """Per-class achieved rates; pick the class with the largest time."""
-    N, r = w["N"], w["r"]
+    """Per-class achieved rates on the method's own work (flops of the
+    products the algorithm defines, bytes it must move), each class against
+    the peak of the pipe its kernel runs on; the roofline line reports the
+    class with the largest time.  Split-fp16 products (three fp16 MFMA
+    products per float32 product) are counted once, at the method's flops,
+    so their fraction of the fp16 pipe cannot exceed 1/3: that ceiling is
+    reported beside them as `emulation_ceiling_frac`."""
+    N = w["N"]
     nT = res[0]["round_accepted"].cpu().numpy().astype(np.int64)
     kb = np.concatenate([[0], np.cumsum(nT)[:-1]])
     k = int(nT.sum())
+    nev = w["nev"]
     dp = -(-d // 32) * 32
-    gsz = {"bf16": 2, "f32": 4, "f64": 8}
+    gsz = {"bf16": 2, "f32": 4, "f64": 8, "split16": 4}
     xs, fs = gsz[prec[0]], gsz[prec[1]]
     rounds = len(nT)
-    # the columns kernel of the benchmark runs fused with the Schur update
-    # (W = K(X, X_S) - F F_S^T written once): its work is the distance product
-    # (2 N dp per column), the Schur product (2 N kb per column; three fp16
-    # products each when the distance product is bf16, which puts both on the
-    # 2.5 PFLOP/s pipe) and its bytes X per round, the F panel, W once
-    split = prec[0] == "bf16" and prec[1] == "f32"
+    mixed = prec[0] == "bf16" and prec[1] == "f32"  # Schur update as split fp16 pairs
+    split_gram = prec[2] == "split16"
     schur_fl = float(np.sum(2.0 * N * kb * nT))
-    schur_by = float(np.sum(N * kb * fs))
     work = {
-        # flops, bytes, bound-dtype
-        "kernel_cols": (2.0 * N * dp * k + schur_fl * (3 if split else 1),
-                        rounds * N * dp * xs + schur_by + N * k * fs, prec[0]),
-        "schur": (float(np.sum(2.0 * N * kb * nT)), float(np.sum(N * kb * fs + 2 * N * nT * fs)), prec[1]),
-        # the mixed form's solve runs as split fp16 pairs (three products each)
-        "solve_downdate": (float(np.sum(1.0 * N * nT * nT)) * (3 if split else 1),
-                           float(np.sum(2 * N * nT * fs + 16 * N)), "f16" if split else "f64"),
-        # both Grams over the k nonzero columns (symmetric: k (k + 1) / 2 dot products each);
-        # the split-fp16 form takes three fp16 products per float32 product
-        "gram": (2.0 * N * k * (k + 1) * (3 if prec[2] == "split16" else 1), 2.0 * N * k * fs,
-                 "f16" if prec[2] == "split16" else prec[2]),
+        # name: (flops, bytes, pipe, split-fp16 products inside)
+        # fused kernel columns + Schur update: distance product 2 N dp per
+        # column, Schur product 2 N k_i per column; X once per round, the F
+        # panel once, W written once
+        "kernel_cols": (2.0 * N * dp * k + schur_fl, rounds * N * dp * xs + float(np.sum(N * kb * fs))
+                        + N * k * fs, prec[0], mixed),
+        "schur": (schur_fl, float(np.sum(N * kb * fs + 2 * N * nT * fs)), prec[1], False),
+        # G = W L^{-T}: N nT^2 flops per round (L^{-1} lower triangular); W read, F written, rho
+        "solve_downdate": (float(np.sum(1.0 * N * nT * nT)), float(np.sum(2 * N * nT * fs + 16 * N)),
+                           "f64", False),
+        "degrees": (7.0 * N * k, 4.0 * N * k * fs + 5 * 8.0 * N, "f64", False),
+        # both Grams, symmetric (k (k + 1) / 2 dot products of length N each), one pass over F
+        "gram": (2.0 * N * k * (k + 1), 1.0 * N * k * fs, "f16" if split_gram else prec[2], split_gram),
+        "form_u": (2.0 * N * k * nev, 1.0 * N * k * fs + 8.0 * N * nev, "f16" if split_gram else prec[2],
+                   split_gram),
     }
     out = {}
-    for name, (fl, by, dt) in work.items():
-        ms, n = prof[name]
+    for name, (fl, by, dt, split) in work.items():
+        ms, n = prof.get(name, (0.0, 0))
         if n == 0 or ms <= 0:
             continue
         sec = ms / 1e3 / steps
@@ -147,10 +153,12 @@ def roofline(w, d, res, prof, steps, prec):
         ridge = PEAK[dt] * 1e12 / (PEAK["hbm"] * 1e9)
         bound = "mfma" if ai >= ridge else "hbm"
         out[name] = {
-            "ms_per_step": ms / steps, "launches_per_step": n / steps, "tflops": tf, "gbs": gbs,
-            "ai_flop_per_byte": ai, "bound": bound,
+            "ms_per_step": ms / steps, "launches_per_step": n / steps, "method_flops": fl,
+            "algorithmic_bytes": by, "tflops": tf, "gbs": gbs, "ai_flop_per_byte": ai, "bound": bound,
             "frac_mfma_peak": tf / PEAK[dt], "frac_hbm_peak": gbs / PEAK["hbm"], "mfma_dtype": dt,
         }
+        if split:
+            out[name]["emulation_ceiling_frac"] = 1.0 / 3.0
     dom = max(out, key=lambda x: out[x]["ms_per_step"])
     o = out[dom]
     nl = o["launches_per_step"]
@@ -160,7 +168,11 @@ def roofline(w, d, res, prof, steps, prec):
         ach, peak, unit = o["gbs"], PEAK["hbm"], "GB/s"
     line = {"bound": o["bound"], "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
             "traffic": pmc_traffic(KERNEL_NAMES.get((dom, prec[2]))), "kernel": dom,
-            "avg_launch_ms": o["ms_per_step"] / nl}
+            "avg_launch_ms": o["ms_per_step"] / nl,
+            "algorithmic_bytes_per_launch": o["algorithmic_bytes"] / nl,
+            "method_flops_per_launch": o["method_flops"] / nl}
+    if "emulation_ceiling_frac" in o:
+        line["emulation_ceiling_frac"] = o["emulation_ceiling_frac"]
     return line, out
 
 
@@ -234,8 +246,8 @@ def kernel_columns(rp, torch, Xd, eps, ud, w, d, steps):
 
 def factor_forms(rp, torch, Xd, eps, ud, w, reps=3):
     """The factorisation alone (rpchol_factor) in its product forms: bf16
-    distances (the benchmark's), split-fp16 distances (float32-grade at the
-    fp16 MFMA rate) and float32 MFMA distances, with a float32 factor; bf16
+    distances (the benchmark's), split-fp16 distances (22 of float32's 24
+    bits per product, at the fp16 MFMA rate) and float32 MFMA distances, with a float32 factor; bf16
     distances with a float64 factor, stored in full and in the low-memory form
     (only F(S, :) kept, earlier rounds' kernel columns evaluated again).  Each
     form's F is compared with the float64 path replaying that form's pivots;
@@ -275,28 +287,38 @@ def factor_forms(rp, torch, Xd, eps, ud, w, reps=3):
 
 
 def cpu_baseline(X, eps, w, n_sample):
-    """The float64 oracle timed on a leading-row sample, scaled linearly in N."""
+    """The float64 oracle on a seeded uniform sample of the workload's rows
+    (same r, b, nev, eps and uniforms), timed on the host's cores twice: with
+    the BLAS pool at every core it offers, and at one thread.  The reported
+    value scales the all-core time to the full N by the method's cost, linear
+    in N at fixed r (a model estimate, labelled as such)."""
     import oracle
     from synth import uniform_stream
+    from threadpoolctl import threadpool_info, threadpool_limits
 
-    try:
-        from threadpoolctl import threadpool_info
-
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        cores = os.cpu_count()
-    Xs = X[:n_sample]
+    cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    rows = np.sort(np.random.default_rng(4242).choice(X.shape[0], n_sample, replace=False))
+    Xs = X[rows]
     t = -(-w["r"] // w["b"])
     u = uniform_stream(2 * w["b"] * t, seed=w["seed"])
-    t0 = time.perf_counter()
-    ref = oracle.arpc(Xs, eps, r=w["r"], b=w["b"], mode="sampled", uniforms=u)
-    oracle.bistoch_eig(ref["F"], w["nev"])
-    dt = time.perf_counter() - t0
+
+    def run():
+        t0 = time.perf_counter()
+        ref = oracle.arpc(Xs, eps, r=w["r"], b=w["b"], mode="sampled", uniforms=u)
+        oracle.bistoch_eig(ref["F"], w["nev"])
+        return time.perf_counter() - t0, ref["k"]
+
+    dt, k = run()
+    with threadpool_limits(limits=1):
+        dt1, _ = run()
     scale = w["N"] / n_sample
     return {
         "value": dt * scale, "unit": "s", "cores": int(cores), "kind": "oracle",
-        "sample": f"first {n_sample} of {w['N']} rows, same r/b/nev/eps/uniforms; measured {dt:.1f}s, "
-                  f"scaled x{scale:.1f} (cost linear in N)",
+        "sample": f"{n_sample} uniformly drawn rows (seed 4242) of the {w['N']} with the workload's "
+                  f"r/b/nev/eps/uniforms (k = {k} accepted); measured {dt:.1f} s on {cores} threads and "
+                  f"{dt1:.1f} s on 1; value = the {cores}-thread time x {scale:.1f} (model estimate, cost "
+                  f"linear in N at fixed r)",
+        "measured_s": dt, "measured_s_1thread": dt1, "sample_rows": n_sample, "sample_k": int(k),
     }
 
 
@@ -653,7 +675,7 @@ def main():
     ap.add_argument("--workload", default="ks1m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=8192)
+    ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--form", default="headline", choices=["headline", "surrogate", "batched", "paper"],
@@ -699,6 +721,9 @@ def main():
     t_mixed, res_m, prof = timed(rp, torch, Xd, eps, ud, w, mixed, args.steps, args.warmup, profile=True)
     log(f"[bench] mixed {t_mixed * 1e3:.2f} ms/step")
     roof, per_kernel = roofline(w, X.shape[1], res_m, prof, args.steps, mixed)
+    log("[bench] mixed path with the split-fp16 pivot-block solve")
+    t_split_solve, _, _ = timed(rp, torch, Xd, eps, ud, w, mixed, args.steps, args.warmup, split_solve=True)
+    log(f"[bench] mixed, split solve {t_split_solve * 1e3:.2f} ms/step")
     t_plain = None
     prof_p = None
     if not args.no_plain:
@@ -723,11 +748,15 @@ def main():
         "config": {
             "workload": f"KS delay embedding N={w['N']} d={X.shape[1]} r={w['r']} b={w['b']} nev={w['nev']}"
                         if w["kind"] == "ks" else f"torus N={w['N']} r={w['r']} b={w['b']} nev={w['nev']}",
-            "precision": "bf16 products, fp32 factor/Schur tiles, "
-                         + ("fp32 Grams as split fp16 pairs" if args.gram == "split16" else "fp32 Gram tiles")
-                         + ", fp64 pivots/solves/eig",
+            "precision": "bf16 distance products (fp32 accumulation, fp32 norms of the rounded points); "
+                         "fp32 factor with the Schur update as split-fp16 pairs; fp64 pivot selection, "
+                         "pivot block, Algorithm 3, triangular solve (fp64 MFMA) and residual diagonal; "
+                         + ("Grams and U as split-fp16 pairs (22-bit products) with fp64 chunk sums"
+                            if args.gram == "split16" else "fp32 Gram tiles with fp64 chunk sums")
+                         + "; fp64 r x r stages and eigensolver",
             "eps": eps,
         },
+        "mixed_split_solve_s": t_split_solve,
         "plain_fp64_s": t_plain,
         "speedup_vs_plain_fp64": (t_plain / t_mixed) if t_plain else None,
         "roofline": roof,

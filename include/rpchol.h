@@ -97,9 +97,9 @@ typedef struct {
  *               is the exact Gaussian kernel of the rounded points up to fp32
  *               accumulation), or F32_SPLIT16 (float32 points, the inner
  *               products as split fp16 pairs after scaling both operands by
- *               one power of two chosen from max |x| (exact): float32-grade
- *               columns at the fp16 MFMA rate, with about 22 of float32's
- *               24 significand bits per product; the Schur update is split
+ *               one power of two chosen from max |x| (exact): columns at
+ *               the fp16 MFMA rate with about 22 of float32's 24
+ *               significand bits per product; the Schur update is split
  *               likewise, the pivot-block solve stays float64; needs
  *               factor_dtype F32).
  *               The pivot block H uses the same points in float64.
@@ -115,6 +115,11 @@ typedef struct {
  *  round_accepted  optional device int32 array of ceil(r / b) entries (or
  *               ceil(n_replay / b) in replay mode) receiving the number of
  *               pivots accepted in each round; may be NULL.
+ *  round_trace  optional device double array of as many entries receiving
+ *               after each round the relative trace error
+ *               tr(K - F F^T) / tr(K) = sum(rho) / N of the factor so far
+ *               (the error Algorithm 2 reduces round by round; Theorem 1
+ *               bounds its expectation); may be NULL.
  *  flags        RPC_FACTOR_UNFUSED: evaluate the kernel columns and the Schur
  *               update W -= F F_S^T in two kernels (W written, then read
  *               back) instead of one fused kernel where both products share
@@ -161,6 +166,7 @@ typedef struct {
   const int64_t* replay;
   int64_t n_replay;
   int32_t* round_accepted;
+  double* round_trace;
 } rpc_factor_opts;
 
 /* Options of bistoch_eig (Algorithm 1 after the factorisation).

@@ -47,7 +47,7 @@ class rpc_factor_opts(ctypes.Structure):
                 ("flags", ctypes.c_int32), ("tau", ctypes.c_double),
                 ("uniforms", ctypes.c_void_p), ("n_uniforms", ctypes.c_int64),
                 ("replay", ctypes.c_void_p), ("n_replay", ctypes.c_int64),
-                ("round_accepted", ctypes.c_void_p)]
+                ("round_accepted", ctypes.c_void_p), ("round_trace", ctypes.c_void_p)]
 
 
 NORMALIZATIONS = {"bistochastic": 0, "symmetric": 1}
@@ -204,11 +204,12 @@ def rpchol_factor(X, eps, r, b, mode="sampled", uniforms=None, replay=None, gemm
     pts = _points(X, eps)
     nrounds = -(-(r if mode != "replay" else replay.numel()) // b)
     racc = torch.zeros(nrounds, dtype=torch.int32, device=dev)
+    rtrace = torch.zeros(nrounds, dtype=torch.float64, device=dev)
     opts = rpc_factor_opts(int(r), int(b), MODES[mode], DTYPES[gemm_dtype], DTYPES[factor_dtype],
                            (RPC_FACTOR_UNFUSED if unfused else 0) | (RPC_FACTOR_SHARED_X if shared_x else 0)
                            | (RPC_FACTOR_LOW_MEMORY if low_memory else 0)
                            | (RPC_FACTOR_SPLIT_SOLVE if split_solve else 0),
-                           float(tau), 0, 0, 0, 0, racc.data_ptr())
+                           float(tau), 0, 0, 0, 0, racc.data_ptr(), rtrace.data_ptr())
     if mode == "sampled":
         assert uniforms is not None and uniforms.dtype == torch.float64 and uniforms.is_cuda
         opts.uniforms = uniforms.data_ptr()
@@ -225,7 +226,7 @@ def rpchol_factor(X, eps, r, b, mode="sampled", uniforms=None, replay=None, gemm
                              _ptr(rho), _ptr(k), _ptr(ws), nb.value, _ptr(st), _stream(torch, stream)),
            "rpchol_factor")
     return {"F": Fbuf[:, :rows].t(), "Fbuf": Fbuf, "ldf": ldf, "pivots": piv, "rho": rho, "k": k,
-            "status": st, "round_accepted": racc, "workspace": ws}
+            "status": st, "round_accepted": racc, "round_trace": rtrace, "workspace": ws}
 
 
 def rpchol_factor_group(X, eps_list, r, b, uniforms_list, gemm_dtype="f32", factor_dtype="f32", tau=0.0,

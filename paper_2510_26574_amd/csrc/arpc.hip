@@ -761,7 +761,8 @@ __global__ __launch_bounds__(CfgK::NT, SPLIT ? 4 : 1) void k_cols_schur(const T*
 }
 
 // ------------------------------------------------------------ split-fp16 distance product
-// The float32-grade form of the kernel columns: the points stay float32 and
+// The split-fp16 form of the kernel columns (22 of float32's 24 significand
+// bits per product, a form of its own below float32): the points stay float32 and
 // the inner products <x, s> run on the fp16 MFMA pipe as split pairs (three
 // products, unit roundoff 2^-22), both operands scaled by one power of two
 // s_X chosen from max |x| (so that |x s_X| < 2^15; exact).  xmax is that
@@ -1144,6 +1145,44 @@ __global__ void k_round_end(const int64_t* __restrict__ Si, int32_t* kptr, const
   }
 }
 
+// Trace error after a round, sum(rho) / N (the relative trace error
+// tr(K - F F^T) / tr(K), tr(K) = N for the Gaussian kernel): float64 partial
+// sums over CHUNK entries, then one workgroup adds them in a fixed order.
+__global__ __launch_bounds__(256) void k_trace_partial(const double* __restrict__ rho, int64_t N,
+                                                       double* __restrict__ part) {
+  __shared__ double ws[4];
+  const int64_t base = (int64_t)blockIdx.x * CHUNK;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < CHUNK; e += 256) {
+    const int64_t i = base + e;
+    if (i < N) s += rho[i];
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+__global__ __launch_bounds__(256) void k_trace_finish(const double* __restrict__ part, int nb,
+                                                      int64_t N, double* __restrict__ out) {
+  __shared__ double ws[4];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < nb; j += 256) s += part[j];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = ((ws[0] + ws[1]) + (ws[2] + ws[3])) / (double)N;
+}
+
+static void launch_round_trace(const double* rho, int64_t N, double* tpart, double* round_trace,
+                               int round, hipStream_t st) {
+  if (!round_trace) return;
+  const int nb = (int)((N + CHUNK - 1) / CHUNK);
+  hipLaunchKernelGGL(k_trace_partial, dim3((unsigned)nb), dim3(256), 0, st, rho, N, tpart);
+  hipLaunchKernelGGL(k_trace_finish, dim3(1), dim3(256), 0, st, (const double*)tpart, nb, N,
+                     round_trace + round);
+}
+
 // Zero F columns k .. r-1 (unused budget).
 template <typename TF>
 __global__ __launch_bounds__(256) void k_zero_tail(TF* __restrict__ F, int64_t ldf, int64_t N, int r,
@@ -1185,6 +1224,7 @@ struct FactorWs {
   int32_t* nT;
   int32_t* stop;
   unsigned long long* tot;
+  double* tpart;   // partial sums of the per-round trace error
   unsigned* xmax;  // max |x| of the points (split-fp16 distance form)
   int64_t ldw;
   int64_t dp;
@@ -1228,6 +1268,7 @@ static void carve_job(WsCursor& c, FactorWs& w, int64_t N, int64_t d, int r) {
   w.nT = c.take<int32_t>(1);
   w.stop = c.take<int32_t>(1);
   w.tot = c.take<unsigned long long>(1);
+  w.tpart = c.take<double>((size_t)nb);
 }
 
 template <typename T, typename TN, typename TF>
@@ -1436,6 +1477,7 @@ static void phase_solve(FJob<T, TN, TF>& j, int i, hipStream_t st) {
   }
   hipLaunchKernelGGL(k_round_end, dim3(1), dim3(MAXB), 0, st, w.Si, j.k_out, w.nT, j.rho,
                      j.o->round_accepted, i);
+  launch_round_trace(j.rho, N, w.tpart, j.o->round_trace, i, st);
   prof::end(prof::SOLVE, st);
 }
 
@@ -1738,6 +1780,7 @@ static int run_factor_lowmem(const rpc_points* X, const rpc_factor_opts* o, doub
                        (TN*)l.nsall + sw * i, l.round_nT, l.round_k, i);
     hipLaunchKernelGGL(k_round_end, dim3(1), dim3(MAXB), 0, st, w.Si, k_out, w.nT, rho,
                        o->round_accepted, i);
+    launch_round_trace(rho, N, w.tpart, o->round_trace, i, st);
     prof::end(prof::SOLVE, st);
     RPC_LAUNCH_CHECK();
   }

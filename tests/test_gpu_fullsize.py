@@ -162,7 +162,7 @@ def test_degrees_and_eigenpairs(run):
 
 
 def test_split16_distance_form(run):
-    """The float32-grade form (float32 points, split-fp16 distance and Schur
+    """The split-fp16 form (float32 points, split-fp16 distance and Schur
     products) at full size: round 0 against the oracle on the float32 points
     (the proposal block and Algorithm 3 in float64 on both sides), and F at
     sampled rows, after round 0 and whole against the closed form

@@ -103,6 +103,10 @@ def test_sampled_c1_pivots_and_factor(gpu, b):
     assert np.abs(F[:, :k] - ref["F"]).max() / scale < 1e-12
     assert np.abs(rho - ref["rho"]).max() < 1e-12
     assert np.all(rho[ref["S"]] == 0)
+    # per-round trace error sum(rho) / N after each round
+    tr = out["round_trace"].cpu().numpy()
+    assert len(tr) == len(ref["trace_err"])
+    assert np.abs(tr - np.asarray(ref["trace_err"])).max() < 1e-12
 
 
 def test_sampled_ragged_shapes(gpu):
