@@ -300,6 +300,178 @@ __global__ void k_eye_k(double* __restrict__ C, int r, const int32_t* kptr) {
 
 __global__ void k_set_int(int32_t* p, int32_t v) { *p = v; }
 
+// ---- spectral-projector restart of the subspace iteration
+// When the subspace iteration has not met its residual test (eigenvalues
+// clustered around the edge of the block, so the block converges slowly),
+// the top part of the spectrum is split off exactly: X = sign(A) by the
+// Newton-Schulz iteration X <- (3 X - X^3) / 2 on A = (M - sigma I) / s, with
+// sigma in the widest gap of the current Ritz values theta_{nev-1} ..
+// theta_{p-1} and s a bound on |M - sigma I| (the iteration converges for
+// every eigenvalue of A in (-sqrt 3, sqrt 3) other than 0; a small one grows
+// by 3/2 per step until it nears +-1, then the convergence is quadratic).
+// Each iterate is formed on the tiles on and below the diagonal and mirrored,
+// so it is exactly symmetric.  P = (I + X) / 2 projects onto the eigenvectors
+// above sigma, so
+// M' = (M - eps I) P + eps I keeps those eigenpairs and maps every other
+// eigenvalue to eps = 1e-3 theta_{j-1} below sigma; four block products on M'
+// then converge at the ratio eps / lambda, and the final Rayleigh-Ritz step
+// and residual test use
+// M itself.  Every kernel returns at once when `conv` is set (the usual case),
+// and the Newton-Schulz steps once X^2 = I to 1e-10 (trace deficit).
+constexpr int NS_MAX = 56;
+constexpr int NS_TILES = 128;  // 64-wide diagonal tiles of an r x r product, r <= 8192
+
+// fbp: [0] sigma, [1] 1 / s, [3] eps
+__global__ void k_fb_setup(const double* __restrict__ theta, int p, int nev,
+                           const double* __restrict__ delta, const int32_t* conv,
+                           double* __restrict__ fbp, int32_t* nsdone, int32_t* nsfinal,
+                           int32_t nsfinal0) {
+  if (*conv || threadIdx.x != 0) return;
+  int js = nev;
+  double best = -1.0;
+  for (int j = nev; j < p; ++j) {
+    const double g = theta[j - 1] - theta[j];
+    if (g > best) {
+      best = g;
+      js = j;
+    }
+  }
+  const double sg = 0.5 * (theta[js - 1] + theta[js]);
+  // the eigenvalues of M lie in [*delta, lambda_max]: M is the PSD inner
+  // matrix plus the accumulated diagonal shift *delta, and the top Ritz value
+  // theta_0 <= lambda_max is converged (the residual test failed lower down)
+  double c = fmax(theta[0] - sg, sg - *delta);
+  c = c > 0.0 ? c : 1.0;
+  fbp[0] = sg;
+  fbp[1] = 1.0 / (1.25 * c);
+  fbp[2] = 0.0;
+  fbp[3] = 1e-3 * fabs(theta[js - 1]);
+  *nsdone = 0;
+  *nsfinal = nsfinal0;
+}
+
+// X0 = (M - sigma I) / s, symmetrised; Mc = M.
+__global__ void k_fb_x0(const double* __restrict__ M, int r, const double* __restrict__ fbp,
+                        double* __restrict__ X0, double* __restrict__ Mc, const int32_t* conv) {
+  if (*conv) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * r) return;
+  const int i = (int)(e % r), j = (int)(e / r);
+  const double m = M[e];
+  Mc[e] = m;
+  X0[e] = (0.5 * (m + M[j + (int64_t)i * r]) - (i == j ? fbp[0] : 0.0)) * fbp[1];
+}
+
+// T = X X (tiles on and below the diagonal, mirrored) with the trace deficit
+// sum_i (1 - T_ii) of each diagonal tile in pd[bx].
+__global__ __launch_bounds__(256) void k_ns_sq(int r, const double* __restrict__ X,
+                                               double* __restrict__ T, double* __restrict__ pd,
+                                               const int32_t* conv, const int32_t* nsdone) {
+  if (*conv || *nsdone || blockIdx.x < blockIdx.y) return;
+  typedef TileCfg<double, 64, 64, 16, 2, 2> Cfg;
+  __shared__ double smem[TileSmem<Cfg, false, false>::bytes / sizeof(double)];
+  __shared__ double red[4];
+  const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM, n0 = (int64_t)blockIdx.y * Cfg::BN;
+  // T(m, n) = sum_k X(m, k) X(n, k) (X symmetric)
+  GOperand<double, false> a{X, r, r, r, nullptr, (r % 2) == 0};
+  GOperand<double, false> b{X, r, r, r, nullptr, (r % 2) == 0};
+  TileAcc<Cfg> acc;
+  acc.zero();
+  tile_mainloop<Cfg>(acc, a, b, m0, n0, 0, r, smem);
+  double dsum = 0.0;
+  for_each_acc<Cfg>(acc, [&](int row, int col, double v) {
+    const int64_t m = m0 + row, n = n0 + col;
+    if (m < r && n < r && m >= n) {
+      T[m + n * r] = v;
+      T[n + m * r] = v;
+      if (m == n) dsum += 1.0 - v;
+    }
+  });
+  if (blockIdx.x != blockIdx.y) return;
+  dsum = wave_sum(dsum);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dsum;
+  __syncthreads();
+  if (threadIdx.x == 0) pd[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Xn = (3 X - X T) / 2, unless the deficit of T = X^2 is below 1e-10: then X
+// is the sign and the iteration stops (nsdone, nsfinal = the buffer of X).
+__global__ __launch_bounds__(256) void k_ns_upd(int r, const double* __restrict__ X,
+                                                const double* __restrict__ T,
+                                                double* __restrict__ Xn,
+                                                const double* __restrict__ pd, int nt, int cur,
+                                                const int32_t* conv, int32_t* nsdone,
+                                                int32_t* nsfinal) {
+  if (*conv || *nsdone || blockIdx.x < blockIdx.y) return;
+  __shared__ double dfc;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int t = 0; t < nt; ++t) s += pd[t];
+    dfc = s;
+  }
+  __syncthreads();
+  if (dfc <= 1e-10) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {  // a lower tile: runs
+      *nsdone = 1;
+      *nsfinal = cur;
+    }
+    return;
+  }
+  typedef TileCfg<double, 64, 64, 16, 2, 2> Cfg;
+  __shared__ double smem[TileSmem<Cfg, false, false>::bytes / sizeof(double)];
+  const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM, n0 = (int64_t)blockIdx.y * Cfg::BN;
+  GOperand<double, false> a{X, r, r, r, nullptr, (r % 2) == 0};
+  GOperand<double, false> b{T, r, r, r, nullptr, (r % 2) == 0};  // T symmetric: T(n, k) = T(k, n)
+  TileAcc<Cfg> acc;
+  acc.zero();
+  tile_mainloop<Cfg>(acc, a, b, m0, n0, 0, r, smem);
+  for_each_acc<Cfg>(acc, [&](int row, int col, double v) {
+    const int64_t m = m0 + row, n = n0 + col;
+    if (m < r && n < r && m >= n) {
+      const double x = 1.5 * X[m + n * r] - 0.5 * v;
+      Xn[m + n * r] = x;
+      Xn[n + m * r] = x;
+    }
+  });
+}
+
+// T = (Mc - eps I) (I + X) / 2 + eps I, X the final Newton-Schulz iterate.
+__global__ __launch_bounds__(256) void k_fb_mprime(int r, const double* __restrict__ Mc,
+                                                   const double* __restrict__ X0,
+                                                   const double* __restrict__ X1,
+                                                   const int32_t* nsfinal,
+                                                   const double* __restrict__ fbp,
+                                                   double* __restrict__ T, const int32_t* conv) {
+  if (*conv) return;
+  typedef TileCfg<double, 64, 64, 16, 2, 2> Cfg;
+  __shared__ double smem[TileSmem<Cfg, false, false>::bytes / sizeof(double)];
+  const double* X = *nsfinal ? X1 : X0;
+  const double eps = fbp[3];
+  const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM, n0 = (int64_t)blockIdx.y * Cfg::BN;
+  GOperand<double, false> a{Mc, r, r, r, nullptr, (r % 2) == 0};
+  GOperand<double, false> b{X, r, r, r, nullptr, (r % 2) == 0};  // X symmetric
+  TileAcc<Cfg> acc;
+  acc.zero();
+  tile_mainloop<Cfg>(acc, a, b, m0, n0, 0, r, smem);
+  for_each_acc<Cfg>(acc, [&](int row, int col, double v) {
+    const int64_t m = m0 + row, n = n0 + col;
+    if (m < r && n < r) {
+      const int64_t e = m + n * r;
+      T[e] = 0.5 * (v - eps * X[e] + Mc[e]) + (m == n ? 0.5 * eps : 0.0);
+    }
+  });
+}
+
+// M = (T + T^T) / 2
+__global__ void k_sym(const double* __restrict__ T, int r, double* __restrict__ M,
+                      const int32_t* conv) {
+  if (*conv) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * r) return;
+  const int i = (int)(e % r), j = (int)(e / r);
+  M[e] = 0.5 * (T[e] + T[j + (int64_t)i * r]);
+}
+
 __global__ void k_flag_noconv(const int32_t* conv, int32_t* status) {
   if (!*conv) set_status(status, RPC_ENOCONV);
 }
@@ -536,6 +708,9 @@ struct EigWs {
   double* sk;
   double* skq;  // split-K partials of the r x p block product
   float* gsc;   // per-chunk power-of-two scales of the split-fp16 Grams
+  // spectral-projector restart (subspace iteration only)
+  double *Xa, *Xb, *Mc, *Tn, *fbp, *pd;
+  int32_t *nsdone, *nsfinal;
   size_t part_cap;
   int p;
 };
@@ -579,6 +754,15 @@ static size_t carve_eig(WsCursor& c, EigWs& w, int64_t N, int r, int nev, bool f
   w.sk = c.take<double>((size_t)dense::SPLITK_MAX * p * p);
   w.skq = c.take<double>((size_t)dense::SPLITK_MAX * r * p);
   w.gsc = c.take<float>(2 * syrk::MAX_CHUNKS);
+  const bool sub = r > dense::JMAX;
+  w.Xa = sub ? c.take<double>((size_t)r * r) : nullptr;
+  w.Xb = sub ? c.take<double>((size_t)r * r) : nullptr;
+  w.Mc = sub ? c.take<double>((size_t)r * r) : nullptr;
+  w.Tn = sub ? c.take<double>((size_t)r * r) : nullptr;
+  w.fbp = c.take<double>(8);
+  w.pd = c.take<double>(2 * NS_TILES);
+  w.nsdone = c.take<int32_t>(1);
+  w.nsfinal = c.take<int32_t>(1);
   return c.used;
 }
 
@@ -692,9 +876,8 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
       }
     };
     products(12);
-    const int max_rr = 4;
-    for (int it = 0; it < max_rr; ++it) {
-      if (it > 0) products(6);
+    // Rayleigh-Ritz on the block and the residual test (sets conv)
+    auto rayleigh_ritz = [&]() {
       dense::gemm64_splitk<false, true>(st, r, p, r, w.M, r, w.Q, r, w.Y, r, 1.0, 0.0, w.skq, w.conv);
       dense::gemm64_splitk<true, true>(st, p, p, r, w.Q, r, w.Y, r, w.H, p, 1.0, 0.0, w.sk, w.conv);
       hipLaunchKernelGGL(dense::k_jacobi, dim3(1), dim3(1024), 0, st, (const double*)w.H,
@@ -707,10 +890,42 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
                          (const int32_t*)w.conv);
       hipLaunchKernelGGL(k_ritz_check, dim3(1), dim3(1024), 0, st, (const double*)w.T1,
                          (const double*)w.Q, (const double*)w.theta, r, nev, 1e-10, w.conv);
+    };
+    const int max_rr = 4;
+    for (int it = 0; it < max_rr; ++it) {
+      if (it > 0) products(6);
+      rayleigh_ritz();
       if (it == 0)
         hipLaunchKernelGGL(k_shift_down, dim3(1), dim3(1024), 0, st, w.M, r, (const double*)w.theta,
                            p, w.delta, (const int32_t*)w.conv);
     }
+    // not converged: spectral-projector restart (every launch below returns
+    // at once when conv is set)
+    const unsigned grr2 = nblk((int64_t)r * r);
+    const dim3 gt((unsigned)((r + 63) / 64), (unsigned)((r + 63) / 64));
+    hipLaunchKernelGGL(k_fb_setup, dim3(1), dim3(64), 0, st, (const double*)w.theta, p, nev,
+                       (const double*)w.delta, (const int32_t*)w.conv, w.fbp, w.nsdone, w.nsfinal,
+                       (int32_t)(NS_MAX % 2));
+    hipLaunchKernelGGL(k_fb_x0, dim3(grr2), dim3(256), 0, st, (const double*)w.M, r,
+                       (const double*)w.fbp, w.Xa, w.Mc, (const int32_t*)w.conv);
+    double* xbuf[2] = {w.Xa, w.Xb};
+    for (int i = 0; i < NS_MAX; ++i) {
+      double* pdi = w.pd + (i % 2) * NS_TILES;
+      hipLaunchKernelGGL(k_ns_sq, gt, dim3(256), 0, st, r, (const double*)xbuf[i % 2], w.Tn, pdi,
+                         (const int32_t*)w.conv, (const int32_t*)w.nsdone);
+      hipLaunchKernelGGL(k_ns_upd, gt, dim3(256), 0, st, r, (const double*)xbuf[i % 2],
+                         (const double*)w.Tn, xbuf[(i + 1) % 2], (const double*)pdi, (int)gt.x, i % 2,
+                         (const int32_t*)w.conv, w.nsdone, w.nsfinal);
+    }
+    hipLaunchKernelGGL(k_fb_mprime, gt, dim3(256), 0, st, r, (const double*)w.Mc, (const double*)w.Xa,
+                       (const double*)w.Xb, (const int32_t*)w.nsfinal, (const double*)w.fbp, w.Tn,
+                       (const int32_t*)w.conv);
+    hipLaunchKernelGGL(k_sym, dim3(grr2), dim3(256), 0, st, (const double*)w.Tn, r, w.M,
+                       (const int32_t*)w.conv);
+    products(4);
+    hipLaunchKernelGGL(k_copy_cols, dim3(grr2), dim3(256), 0, st, (const double*)w.Mc, (int64_t)r,
+                       w.M, (int64_t)r, r, r, (const int32_t*)w.conv);
+    rayleigh_ritz();
     hipLaunchKernelGGL(k_unshift, dim3(1), dim3(128), 0, st, w.theta, p, (const double*)w.delta);
     hipLaunchKernelGGL(k_flag_noconv, dim3(1), dim3(1), 0, st, (const int32_t*)w.conv, status);
     hipLaunchKernelGGL(k_copy_cols, dim3(nblk((int64_t)r * nev)), dim3(256), 0, st,
