@@ -470,22 +470,28 @@ def bench_surrogate(args, rp, torch):
     print(json.dumps(line), flush=True)
 
 
-PAPER_VSA = dict(n_time=512, J=64, eps=32.0, r=4096, b=64, nev=64, seed=0, trace_err=0.0891, tau=1e-6)
+PAPER_VSA = dict(n_time=512, J=64, eps=32.0, r=4096, b=64, nev=64, seed=0, trace_err=0.0891, tau=1e-6,
+                 gamma=1e-7)
 
 
 def bench_paper(args, rp, torch):
     """The paper's own workload: vector-valued delay embedding of a KS
     trajectory (512 times x 64 grid points = 32 768 product states in R^64),
-    ARPC with r = 4096, b = 64 in float32, then Algorithm 1 (top 64).  The
-    paper reports a trace error of 8.91% on its own trajectory and random
-    draws (one A100, float32); that figure is quoted as context.
+    ARPC with r = 4096, b = 64 in float32, then Algorithm 1 (top 64) with the
+    regularised QR (gamma on the leading diagonal of D~^{-1} F; the paper does
+    not give its gamma.  Here gamma = 1e-7: the regulariser moves lambda_1 by
+    about 3 gamma, so lambda_1 = 1 to 1e-6, and lifts the floor of the
+    eigenvalues; gamma = 1e-4 puts that floor near the paper's 1e-8 but moves
+    lambda_1 by 6e-4).  The paper reports a trace error of 8.91% on its
+    own trajectory and random draws (one A100, float32); that figure is quoted
+    as context.
 
-    Two readings of the bandwidth are run.  With exp(-|.|^2 / eps), eps = 32
-    (the value the section states) the trace error lands near the paper's
-    figure and is the timed line; eps J = 2048 (the kernel as printed) makes
-    the kernel numerically low rank on this trajectory (trace error ~1e-7),
-    which float32 cannot resolve, so it runs in float64 and is reported with
-    its status.  Prints one JSON line."""
+    The timed line is the kernel as printed, exp(-|.|^2 / (eps J)) with
+    eps = 32 and J = 64, in float32 as the paper ran it (and in float64
+    beside it); on this trajectory that kernel is numerically low rank (trace
+    error about 1e-7 at r = 4096).  The reading exp(-|.|^2 / eps), whose
+    trace error lands near the paper's figure, is reported too.  Prints one
+    JSON line."""
     from synth import uniform_stream, vsa_points
 
     c = PAPER_VSA
@@ -497,14 +503,14 @@ def bench_paper(args, rp, torch):
     u = uniform_stream(2 * b * (-(-r // b)), seed=c["seed"])
     Xd, ud = torch.from_numpy(X).cuda(), torch.from_numpy(u).cuda()
 
-    def one(eps_run, prec, tau):
+    def one(eps_run, prec, tau, gamma):
         g, f, gr = prec
 
         def run():
             out = rp.rpchol_factor(Xd, eps_run, r, b, uniforms=ud, gemm_dtype=g, factor_dtype=f, tau=tau)
             deg = rp.bistoch_degrees(out["F"], out["k"], status=out["status"])
             eig = rp.bistoch_eig(out["F"], out["k"], deg["d"], deg["q"], c["nev"], gram_dtype=gr,
-                                 status=out["status"])
+                                 gamma=gamma, status=out["status"])
             return out, deg, eig
         for _ in range(args.warmup):
             run()
@@ -516,23 +522,27 @@ def bench_paper(args, rp, torch):
         dt = (time.perf_counter() - t) / args.steps
         st = rp.status_sync(out["status"])
         lam = eig["lam"].cpu().numpy()
+        tr = out["round_trace"].cpu().numpy()
         return {"eps": eps_run, "precision": {"gemm": g, "factor": f, "gram": gr}, "tau": tau,
-                "seconds": dt, "status": rp.STATUS_NAMES.get(st, st),
+                "gamma": gamma, "seconds": dt, "status": rp.STATUS_NAMES.get(st, st),
                 "accepted_pivots": int(out["k"].item()),
                 "trace_error": float(out["rho"].sum().item() / N),
+                "trace_error_by_round": [float(x) for x in tr[:: max(1, len(tr) // 8)]],
                 "lam_head": [float(x) for x in lam[:6]], "lam_64": float(lam[-1])}
 
     # float32 factor storage: proposals whose updated pivot falls to the
     # float32 noise floor are rejected (tau = 1e-6 max diag K, diag K = 1)
-    main = one(c["eps"], ("f32", "f32", "f32"), c["tau"])
-    low_rank = one(c["eps"] * c["J"], ("f64", "f64", "f64"), 0.0)
+    printed = one(c["eps"] * c["J"], ("f32", "f32", "f32"), c["tau"], c["gamma"])
+    printed64 = one(c["eps"] * c["J"], ("f64", "f64", "f64"), 0.0, c["gamma"])
+    eps_only = one(c["eps"], ("f32", "f32", "f32"), c["tau"], c["gamma"])
     line = {
         "metric": "paper workload (vector-valued KS delay embedding): seconds and trace error",
-        "form": "paper", "value": main["seconds"], "unit": "s", "higher_is_better": False, "n_gpus": 1,
+        "form": "paper", "value": printed["seconds"], "unit": "s", "higher_is_better": False, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"VSA KS N*M={N} d=J={d} r={r} b={b} nev={c['nev']}"},
-        "kernel_eps": main,
-        "kernel_eps_times_J": low_rank,
+        "config": {"workload": f"VSA KS N*M={N} d=J={d} r={r} b={b} nev={c['nev']} gamma={c['gamma']}"},
+        "kernel_eps_times_J": printed,
+        "kernel_eps_times_J_float64": printed64,
+        "kernel_eps": eps_only,
         "paper_trace_error_context": {"value": c["trace_err"], "hardware": "1x NVIDIA A100 40 GiB, fp32",
                                       "note": "the authors' trajectory, random draws and regularised QR"},
     }

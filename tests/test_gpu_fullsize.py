@@ -210,7 +210,12 @@ def test_algorithm1_matches_oracle_on_device_factor(run):
     device's eigenpairs of the same factor are compared with it, both for the
     benchmark's split-fp16 Grams (bars EIG, ANG) and for float64 Grams
     (eigenvalues 1e-6, angles 1e-4).  A missed or misplaced top eigenpair
-    fails here, where residual and orthonormality checks alone would not."""
+    fails here, where residual and orthonormality checks alone would not.
+    Subspaces are compared up to the last relative eigengap of at least 1e-2
+    in the top 64: by Davis-Kahan the angle of a block is its perturbation
+    over the gap at its edge, and the KS spectrum has near-degenerate pairs
+    (translation symmetry) whose 1e-3 gaps would make the angle measure the
+    gap rather than the arithmetic."""
     import paper_2510_26574_amd as rp
 
     torch = run["torch"]
@@ -221,18 +226,22 @@ def test_algorithm1_matches_oracle_on_device_factor(run):
     del F64
     lam_o, U_o = res["lam"], res["U"]
     m = NEV
-    for j in range(NEV - 1, 0, -1):
-        if res["lam_all"][j - 1] / res["lam_all"][j] - 1 > 1e-3:
+    for j in range(NEV, 0, -1):
+        if res["lam_all"][j - 1] / res["lam_all"][j] - 1 > 1e-2:
             m = j
             break
     e64 = rp.bistoch_eig(out["F"], out["k"], deg["d"], deg["q"], NEV, gram_dtype="f64")
     assert rp.status_sync(e64["status"]) == 0
+    errs = []
     for name, eig, ltol, atol in [("split16", run["eig"], EIG, ANG), ("f64", e64, 1e-6, 1e-4)]:
         lam = eig["lam"].cpu().numpy()
         le = float(np.abs(lam / lam_o - 1).max())
         Ug = eig["U"].double().cpu().numpy()
-        s = np.linalg.svd(U_o[:, :m].T @ Ug[:, :m], compute_uv=False)
-        ae = float(np.arccos(np.clip(s.min(), -1.0, 1.0)))
+        Qg, _ = np.linalg.qr(Ug[:, :m])
+        sine = np.linalg.norm(Qg - U_o[:, :m] @ (U_o[:, :m].T @ Qg), 2)
+        ae = float(np.arcsin(min(sine, 1.0)))
         print(f"Algorithm 1 ({name} Grams) vs oracle on the device factor (k = {k}): eigenvalues {le:.3g}, "
-              f"angle {ae:.3g} over {m}")
+              f"angle {ae:.3g} over {m} (gap {res['lam_all'][m - 1] / res['lam_all'][m] - 1:.3g})")
+        errs.append((le, ltol, ae, atol))
+    for le, ltol, ae, atol in errs:
         assert le <= ltol and ae <= atol
