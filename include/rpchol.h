@@ -194,7 +194,7 @@ typedef struct {
  *             eigenpair is (1, D~^{1/2} 1 / |D~^{1/2} 1|).  fix_const is not
  *             defined for it (RPC_EINVAL); ext_E is then R^T V Lambda^{-1}, the
  *             matrix of the extension f(y)^T E / sqrt(c^T f(y)), which
- *             nystrom_extend (built for P~) does not apply. */
+ *             nystrom_extend_symmetric applies. */
 typedef enum {
   RPC_BISTOCHASTIC = 0, /* P~ = D~^{-1} K~ Q~^{-1} K~ D~^{-1} (Algorithm 1) */
   RPC_SYMMETRIC = 1     /* L~ = D~^{-1/2} K~ D~^{-1/2} (symmetric normalisation) */
@@ -298,6 +298,20 @@ int nystrom_extend(const rpc_points* Y, const rpc_points* X, const int64_t* pivo
                    const double* c, const double* ext_E, int32_t nev, double* Phi, int64_t ldphi,
                    void* workspace, size_t workspace_bytes, int32_t* dev_status,
                    rpc_stream_t stream);
+
+/* ---- Nystrom extension for the symmetric normalisation -----------------
+ * The eigenvectors of L~ = D~^{-1/2} K~ D~^{-1/2} (bistoch_eig with
+ * normalization RPC_SYMMETRIC) at new points, from L~ U = U Lambda and the
+ * Nystrom extension of the section "Nystrom method connection":
+ * Phi(y, :) = f(y)^T E / sqrt(d~(y)), f(y) = F(S, :)^{-1} k(X_S, y),
+ * d~(y) = c^T f(y), E = R^T V Lambda^{-1} (the ext_E of that call).  At a
+ * training point it reproduces the row of U.  Arguments, layouts, workspace
+ * (nystrom_extend_workspace_size) and errors as nystrom_extend. */
+int nystrom_extend_symmetric(const rpc_points* Y, const rpc_points* X, const int64_t* pivots,
+                             const int32_t* k, const void* F, int32_t f_dtype, int64_t ldf,
+                             int32_t r, const double* c, const double* ext_E, int32_t nev,
+                             double* Phi, int64_t ldphi, void* workspace, size_t workspace_bytes,
+                             int32_t* dev_status, rpc_stream_t stream);
 
 /* ---- Batched form: many independent decompositions ----------------------
  * A job is one full decomposition of its own points (rpchol_factor, then

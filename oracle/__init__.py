@@ -30,6 +30,7 @@ from .bistoch import (
     dense_bistochastic,
     dense_symmetric,
     symmetric_eig,
+    symmetric_extend,
 )
 
 __all__ = [
@@ -48,5 +49,6 @@ __all__ = [
     "dense_bistochastic",
     "dense_symmetric",
     "symmetric_eig",
+    "symmetric_extend",
     "surrogate",
 ]

@@ -148,18 +148,34 @@ def dense_symmetric(K):
 
 
 def symmetric_eig(F, nev):
-    """Symmetric normalisation route: L~ = (D~^{-1/2} F)(D~^{-1/2} F)^T, EVD via
-    QR of D~^{-1/2} F and EVD of R R^T (B = D~^{-1/2} F, C = I)."""
+    """Symmetric normalisation route (Section "Symmetric normalization"):
+    L~ = (D~^{-1/2} F)(D~^{-1/2} F)^T, EVD via QR of B = D~^{-1/2} F and EVD of
+    R R^T (the general route with C = I).  E = R^T V Lambda^{-1} (k x nev,
+    signed like U) is the extension matrix: from L~ U = U Lambda and
+    B^T U = R^T V, U = B E, so a new point y with f(y) = F(S, :)^{-1} k(X_S, y)
+    and d~(y) = c^T f(y) gets the values f(y)^T E / sqrt(d~(y))."""
     F = np.asarray(F, dtype=np.float64)
-    d = F @ (F.T @ np.ones(F.shape[0]))
+    c = F.T @ np.ones(F.shape[0])
+    d = F @ c
     if not np.all(d > 0):
         raise DegreeError("diag(D~) > 0 failed")
     B = F / np.sqrt(d)[:, None]
     Q, R = np.linalg.qr(B, mode="reduced")
     lam, V = np.linalg.eigh(R @ R.T)
     lam, V = lam[::-1], V[:, ::-1]
-    return {"U": sign_normalize(Q @ V[:, :nev]), "lam": lam[:nev].copy(), "lam_all": lam.copy(),
-            "d": d}
+    U = sign_normalize(Q @ V[:, :nev])
+    Vn = V[:, :nev] * np.sign(np.sum(U * (Q @ V[:, :nev]), axis=0))[None, :]
+    E = R.T @ Vn / lam[None, :nev]
+    return {"U": U, "lam": lam[:nev].copy(), "lam_all": lam.copy(), "d": d, "c": c, "E": E}
+
+
+def symmetric_extend(Y, X, S, F, c, E, eps):
+    """Extension of the eigenvectors of L~ to new points Y (rows):
+    f(y) = F(S, :)^{-1} k(X_S, y), value = (f(y)^T E) / sqrt(c^T f(y))."""
+    S = np.asarray(S, dtype=np.int64)
+    Kys = gaussian_kernel(X[S], Y, eps)
+    f = sla.solve_triangular(np.asarray(F, dtype=np.float64)[S, :], Kys, lower=True)
+    return (f.T @ E) / np.sqrt(f.T @ c)[:, None]
 
 
 def gaussian_dense(X, eps):

@@ -74,6 +74,8 @@ _SIGS = {
     "nystrom_extend_workspace_size": [_I64, _I64, _I32, _I32, _VP],
     "nystrom_extend": [_VP, _VP, _VP, _VP, _VP, _I32, _I64, _I32, _VP, _VP, _I32, _VP, _I64, _VP,
                        _SZ, _VP, _VP],
+    "nystrom_extend_symmetric": [_VP, _VP, _VP, _VP, _VP, _I32, _I64, _I32, _VP, _VP, _I32, _VP, _I64,
+                                 _VP, _SZ, _VP, _VP],
     "surrogate_layout": [_VP, _VP],
     "surrogate_init_uniforms": [_VP, _VP],
     "surrogate_init": [_VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP],
@@ -352,8 +354,10 @@ def bistoch_eig(F, k, d, q, nev, gamma=0.0, fix_const=False, gram_dtype="f64", u
     return {"U": Ubuf[:, :N].t(), "lam": lam, "E": E.t(), "status": st, "workspace": ws}
 
 
-def nystrom_extend(Y, X, eps, pivots, k, F, c, E, status=None, stream=None):
-    """Extended eigenvector values at the rows of Y (M x d float32). Returns Phi (M x nev)."""
+def nystrom_extend(Y, X, eps, pivots, k, F, c, E, status=None, stream=None, symmetric=False):
+    """Extended eigenvector values at the rows of Y (M x d float32). Returns Phi
+    (M x nev).  symmetric=True extends the eigenvectors of L~ (bistoch_eig with
+    normalization="symmetric") through nystrom_extend_symmetric."""
     torch = _torch()
     lib = load_library()
     code, N, ldf, r = _factor_args(F)
@@ -368,9 +372,10 @@ def nystrom_extend(Y, X, eps, pivots, k, F, c, E, status=None, stream=None):
     _check(lib.nystrom_extend_workspace_size(M, Y.shape[1], r, nev, ctypes.byref(nb)),
            "nystrom_extend_workspace_size")
     ws = _workspace(torch, nb.value, dev)
-    _check(lib.nystrom_extend(ctypes.byref(py), ctypes.byref(px), _ptr(pivots), _ptr(k), _ptr(F), code,
-                              ldf, r, _ptr(c), _ptr(E), nev, _ptr(Phib), M, _ptr(ws), nb.value, _ptr(st),
-                              _stream(torch, stream)), "nystrom_extend")
+    fn = lib.nystrom_extend_symmetric if symmetric else lib.nystrom_extend
+    _check(fn(ctypes.byref(py), ctypes.byref(px), _ptr(pivots), _ptr(k), _ptr(F), code,
+              ldf, r, _ptr(c), _ptr(E), nev, _ptr(Phib), M, _ptr(ws), nb.value, _ptr(st),
+              _stream(torch, stream)), "nystrom_extend")
     return {"Phi": Phib.t(), "status": st}
 
 

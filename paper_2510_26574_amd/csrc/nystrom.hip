@@ -1,9 +1,12 @@
 // nystrom_extend: out-of-sample values of the eigenvectors of P~ (the
 // extension formula of the paper's "Nystrom method connection" section,
-// applied to the bistochastic approximation), on gfx950.
+// applied to the bistochastic approximation), on gfx950;
+// nystrom_extend_symmetric: the same for L~ = D~^{-1/2} K~ D~^{-1/2} (the
+// symmetric normalisation).
 //
 // For a new point y:  f(y) = F(S, :)^{-1} k(X_S, y),  d~(y) = c^T f(y),
-// phi(y) = f(y)^T E / d~(y),  E = C R^T V Lambda^{-1} (from bistoch_eig).
+// phi(y) = f(y)^T E / d~(y),  E = C R^T V Lambda^{-1} (from bistoch_eig), or
+// phi(y) = f(y)^T E / sqrt(d~(y)),  E = R^T V Lambda^{-1} (symmetric).
 // F(S, :) is lower triangular in pivot order, so the two triangular solves
 // are folded once into E' = F(S, :)^{-T} [c | E]; each block of new points
 // then costs one MFMA distance product with an exp epilogue and one product
@@ -111,13 +114,15 @@ __global__ __launch_bounds__(256) void k_cross_kernel(const double* __restrict__
   });
 }
 
+// Phi(i, j) = P(i, j + 1) / P(i, 0) (bistochastic) or / sqrt(P(i, 0)) (symmetric)
 __global__ void k_divide(const double* __restrict__ P, int64_t ldp, int64_t m, int nev,
-                         double* __restrict__ Phi, int64_t ldphi) {
+                         double* __restrict__ Phi, int64_t ldphi, int sym) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= m * nev) return;
   const int64_t i = e % m;
   const int j = (int)(e / m);
-  Phi[i + j * ldphi] = P[i + (int64_t)(j + 1) * ldp] / P[i];
+  const double dy = P[i];
+  Phi[i + j * ldphi] = P[i + (int64_t)(j + 1) * ldp] / (sym ? sqrt(dy) : dy);
 }
 
 struct NysWs {
@@ -143,7 +148,7 @@ template <typename TF>
 static int run_nys(const rpc_points* Y, const rpc_points* X, const int64_t* piv, const int32_t* k,
                    const TF* F, int64_t ldf, int r, const double* c, const double* E, int nev,
                    double* Phi, int64_t ldphi, void* ws, size_t ws_bytes, int32_t* status,
-                   hipStream_t st) {
+                   hipStream_t st, int sym) {
   WsCursor cur{(char*)ws, 0, ws_bytes, true};
   NysWs w;
   carve_nys(cur, w, Y->N, Y->d, r, nev);
@@ -164,7 +169,7 @@ static int run_nys(const rpc_points* Y, const rpc_points* X, const int64_t* piv,
                        (const double*)w.XS, (const double*)w.xsn, r, X->eps, w.K, m);
     dense::gemm64<false, true>(st, m, nev + 1, r, w.K, m, w.B0, r, w.P, m, 1.0, 0.0);
     hipLaunchKernelGGL(k_divide, dim3((unsigned)((m * nev + 255) / 256)), dim3(256), 0, st,
-                       (const double*)w.P, m, m, nev, Phi + m0, ldphi);
+                       (const double*)w.P, m, m, nev, Phi + m0, ldphi, sym);
     RPC_LAUNCH_CHECK();
   }
   prof::end(prof::NYSTROM, st);
@@ -182,11 +187,10 @@ extern "C" int nystrom_extend_workspace_size(int64_t M, int64_t d, int32_t r, in
   return RPC_OK;
 }
 
-extern "C" int nystrom_extend(const rpc_points* Y, const rpc_points* X, const int64_t* pivots,
-                              const int32_t* k, const void* F, int32_t fdt, int64_t ldf, int32_t r,
-                              const double* c, const double* E, int32_t nev, double* Phi,
-                              int64_t ldphi, void* ws, size_t ws_bytes, int32_t* status,
-                              rpc_stream_t stream) {
+static int nystrom_any(const rpc_points* Y, const rpc_points* X, const int64_t* pivots,
+                       const int32_t* k, const void* F, int32_t fdt, int64_t ldf, int32_t r,
+                       const double* c, const double* E, int32_t nev, double* Phi, int64_t ldphi,
+                       void* ws, size_t ws_bytes, int32_t* status, rpc_stream_t stream, int sym) {
   if (!Y || !X || !Y->X || !X->X || !pivots || !k || !F || !c || !E || !Phi || !status)
     return RPC_EINVAL;
   if (Y->N < 1 || Y->d != X->d || Y->ldx < Y->d || X->ldx < X->d || !(X->eps > 0.0)) return RPC_EINVAL;
@@ -194,11 +198,30 @@ extern "C" int nystrom_extend(const rpc_points* Y, const rpc_points* X, const in
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (fdt == RPC_F64)
     return run_nys<double>(Y, X, pivots, k, (const double*)F, ldf, r, c, E, nev, Phi, ldphi, ws,
-                           ws_bytes, status, st);
+                           ws_bytes, status, st, sym);
   if (fdt == RPC_F32)
     return run_nys<float>(Y, X, pivots, k, (const float*)F, ldf, r, c, E, nev, Phi, ldphi, ws,
-                          ws_bytes, status, st);
+                          ws_bytes, status, st, sym);
   return RPC_EINVAL;
+}
+
+extern "C" int nystrom_extend(const rpc_points* Y, const rpc_points* X, const int64_t* pivots,
+                              const int32_t* k, const void* F, int32_t fdt, int64_t ldf, int32_t r,
+                              const double* c, const double* E, int32_t nev, double* Phi,
+                              int64_t ldphi, void* ws, size_t ws_bytes, int32_t* status,
+                              rpc_stream_t stream) {
+  return nystrom_any(Y, X, pivots, k, F, fdt, ldf, r, c, E, nev, Phi, ldphi, ws, ws_bytes, status,
+                     stream, 0);
+}
+
+extern "C" int nystrom_extend_symmetric(const rpc_points* Y, const rpc_points* X,
+                                        const int64_t* pivots, const int32_t* k, const void* F,
+                                        int32_t fdt, int64_t ldf, int32_t r, const double* c,
+                                        const double* E, int32_t nev, double* Phi, int64_t ldphi,
+                                        void* ws, size_t ws_bytes, int32_t* status,
+                                        rpc_stream_t stream) {
+  return nystrom_any(Y, X, pivots, k, F, fdt, ldf, r, c, E, nev, Phi, ldphi, ws, ws_bytes, status,
+                     stream, 1);
 }
 
 extern "C" int rpc_status_sync(const int32_t* dev_status, rpc_stream_t stream) {

@@ -512,6 +512,35 @@ def test_symmetric_normalization_subspace_path(gpu):
     assert _angle(eig["U"].cpu().numpy()[:, :m], res["U"][:, :m]) < 1e-8
 
 
+def test_symmetric_extension(gpu):
+    """nystrom_extend_symmetric: the eigenvectors of L~ at new points against
+    the oracle's symmetric extension f(y)^T E / sqrt(c^T f(y)), and at
+    training points the rows of U."""
+    torch, rp = gpu
+    X, eps = _torus_case(seed=8)
+    nev = 10
+    ref, out, deg, eig, res = _sym_case(gpu, X, eps, 64, 8, nev, seed=33)
+    Y = torus_points(700, seed=101)
+    rows = np.array([0, 5, 999, 1999, int(ref["S"][3])])
+    Yall = np.concatenate([Y, X[rows]])
+    ph = rp.nystrom_extend(torch.from_numpy(Yall).cuda(), torch.from_numpy(X).cuda(), eps, out["pivots"],
+                           out["k"], out["F"], deg["c"], eig["E"], symmetric=True)
+    assert rp.status_sync(ph["status"]) == 0
+    P = ph["Phi"].cpu().numpy()
+    # the oracle's extension with its own E, up to the last clear eigenvalue
+    # gap, rotated by O = U_oracle^T U_gpu (eigenvectors of a degenerate
+    # eigenvalue, e.g. the torus's symmetric pairs, are unique only up to an
+    # orthogonal map of their block, and so is the extension)
+    Po = oracle.symmetric_extend(Yall, X, ref["S"], ref["F"], res["c"], res["E"], eps)
+    m = _gap_index(res["lam_all"], nev)
+    O = res["U"][:, :m].T @ eig["U"].cpu().numpy()[:, :m]
+    err = np.abs(P[:, :m] - Po[:, :m] @ O).max() / np.abs(Po[:, :m]).max()
+    Ut = eig["U"].cpu().numpy()[rows]
+    terr = np.abs(P[len(Y):] - Ut).max() / np.abs(Ut).max()
+    print(f"symmetric extension: error {err:.3g} (new points), {terr:.3g} (training rows)")
+    assert err < 1e-9 and terr < 1e-9
+
+
 @pytest.mark.parametrize("gamma", [1e-6, 1e-3])
 @pytest.mark.parametrize("r,b,nev", [(64, 8, 16), (160, 32, 24)])
 def test_eig_gamma_regularised_qr(gpu, gamma, r, b, nev):

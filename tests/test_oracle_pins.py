@@ -471,3 +471,99 @@ def test_gamma_regularised_qr_matches_dense(gamma):
     # the regulariser moves the spectrum: without it the eigenvalues differ
     if gamma >= 1e-3:
         assert np.max(np.abs(bistoch_eig(F, nev)["lam"] - res["lam"])) > 1e-6
+
+
+# ------------------------------------------- symmetric normalisation pins
+
+
+def test_symmetric_extension_reproduces_training_rows():
+    """Extension of L~'s eigenvectors (f(y)^T E / sqrt(d~(y))) evaluated at
+    training points = rows of U; at a new point it is the dense formula
+    d~(y)^{-1/2} k~(y, X) D~^{-1/2} U Lambda^{-1} with k~(y, X) = f(y)^T F^T."""
+    from oracle.bistoch import symmetric_extend
+
+    X, eps, out = _factor(n=400, r=48, b=6, seed=12)
+    F, S = out["F"], out["S"]
+    res = symmetric_eig(F, 8)
+    rows = np.array([0, 9, 200, 399, int(S[5])])
+    phi = symmetric_extend(X[rows], X, S, F, res["c"], res["E"], eps)
+    assert np.max(np.abs(phi - res["U"][rows])) < 1e-8
+    Y = torus_points(30, seed=77)
+    f = sla.solve_triangular(F[S, :], gaussian_kernel(X[S], Y, eps), lower=True)  # k x M
+    kt = f.T @ F.T  # k~(y, X)
+    dy = kt.sum(axis=1)
+    dense = (kt / np.sqrt(dy)[:, None]) @ (res["U"] / np.sqrt(res["d"])[:, None]) / res["lam"][None, :]
+    assert np.max(np.abs(symmetric_extend(Y, X, S, F, res["c"], res["E"], eps) - dense)) < 1e-9
+
+
+def _sym_bound(dmin, delta, N, trK, err):
+    """Theorem 3's bound on the trace norm of L - L~."""
+    return (1.0 / dmin + math.sqrt(N) / delta ** 2 * trK + N / (4.0 * delta ** 3) * trK * err) * err
+
+
+def test_theorem3_and_remark4_symmetric_bounds():
+    """Theorem 3: |L - L~|_* <= [1/d_min + sqrt(N) tr K / delta^2 + N tr K
+    tr(K - K~) / (4 delta^3)] tr(K - K~) for every realisation; Remark 4: with
+    the exact degrees D in place of D~, L - L~_D is PSD with trace norm at most
+    tr(K - K~) / d_min.  The oracle's symmetric eigenvalues satisfy Mirsky's
+    sum |lambda_i(L) - lambda_i(L~)| <= |L - L~|_*."""
+    X, eps = _torus(220, seed=13)
+    K = gaussian_kernel(X, X, eps)
+    N = K.shape[0]
+    L, d = dense_symmetric(K)
+    lamL = np.sort(np.linalg.eigvalsh(L))[::-1]
+    trK = np.trace(K)
+    for r, b in [(12, 4), (30, 6), (60, 10)]:
+        out = arpc(X, eps, r=r, b=b, mode="sampled", uniforms=uniform_stream(2 * b * (-(-r // b)), seed=r + 5))
+        F = out["F"]
+        Kt = F @ F.T
+        err = trK - np.trace(Kt)
+        Lt, dt = dense_symmetric(Kt)
+        assert np.all(dt > 0)
+        tn = np.abs(np.linalg.eigvalsh(L - Lt)).sum()
+        assert tn <= _sym_bound(d.min(), min(d.min(), dt.min()), N, trK, err)
+        sD = 1.0 / np.sqrt(d)
+        LD = Kt * sD[:, None] * sD[None, :]
+        ev = np.linalg.eigvalsh(L - LD)
+        assert ev.min() >= -1e-12 and ev.sum() <= err / d.min() * (1 + 1e-12)
+        lo = np.zeros(N)
+        lo[:out["k"]] = symmetric_eig(F, 1)["lam_all"]
+        assert np.abs(lamL - np.sort(lo)[::-1]).sum() <= tn * (1 + 1e-9)
+
+
+def test_corollary5_probability_bound():
+    """Corollary 5 for RPC: with zeta from Theorem 1 (r' = 10, e = 1/2, r set
+    by its rank condition) and 1 < t < d_min / (sqrt(N) zeta), with
+    probability at least 1 - 1/t both d~_min > d_min - sqrt(N) t zeta and
+    |L - L~|_* < [1/d_min + sqrt(N) tr K / a_t^2 + N tr K t zeta / (4 a_t^3)]
+    t zeta, a_t = d_min - sqrt(N) t zeta.  Checked as a frequency over 60
+    seeds against 1 - 1/t less three binomial standard deviations."""
+    X, eps = _torus(200, seed=3)
+    eps = 4.0 * eps  # a wide kernel: fast spectral decay, so the corollary applies
+    K = gaussian_kernel(X, X, eps)
+    N = K.shape[0]
+    L, d = dense_symmetric(K)
+    lam = np.sort(np.linalg.eigvalsh(K))[::-1]
+    trK = np.trace(K)
+    rp, e = 10, 0.5
+    tail = lam[rp:].sum()
+    r = int(math.ceil(rp / e + rp * math.log(trK / (e * tail))))
+    zeta = (1 + e) * tail
+    dmin = d.min()
+    tmax = dmin / (math.sqrt(N) * zeta)
+    assert tmax > 4
+    seeds = 60
+    hits = {2.0: 0, 4.0: 0}
+    for s in range(seeds):
+        out = arpc(X, eps, r=r, b=1, mode="sampled", uniforms=uniform_stream(2 * r, seed=900 + s))
+        Kt = out["F"] @ out["F"].T
+        Lt, dt = dense_symmetric(Kt)
+        tn = np.abs(np.linalg.eigvalsh(L - Lt)).sum()
+        for t in hits:
+            a = dmin - math.sqrt(N) * t * zeta
+            bound = (1 / dmin + math.sqrt(N) * trK / a ** 2 + N * trK * t * zeta / (4 * a ** 3)) * t * zeta
+            if dt.min() > a and tn < bound:
+                hits[t] += 1
+    for t, h in hits.items():
+        p = 1 - 1 / t
+        assert h / seeds >= p - 3 * math.sqrt(p * (1 - p) / seeds)
