@@ -908,6 +908,134 @@ __global__ __launch_bounds__(SolveCfg::NT) void k_solve_downdate(const TF* __res
   }
 }
 
+// ------------------------------------------------------------ persistent float64 solve
+// The same G = W L^{-T} (float64 MFMA), F(:, k + j) = G(:, j) and
+// rho -= rownorms(G)^2 as k_solve_downdate, organised for N >> 128: one
+// workgroup per CU stages L^{-1} (128 x 128, lower triangular, zero past nT)
+// in LDS once; then each wave walks 16-row blocks on its own (no workgroup
+// barrier after the staging, so the waves drift apart and one wave's loads
+// overlap another's MFMAs).  A block's W entries go straight from global
+// memory into the MFMA A operand (lane l: row l % 16, k-slot l / 16), in
+// chunks of four k-steps with the next chunk in flight; MFMA steps wholly
+// above the diagonal of L^{-1} and column tiles at or past nT are skipped.
+// A row's norm is summed over its 16 lanes by xor shuffles in a fixed order
+// (deterministic).
+constexpr int SP_LDK = MAXB + 1;  // odd stride: a fragment's 16 rows on distinct banks
+constexpr int SP_NT = 1024;
+
+template <typename TF>
+__global__ __launch_bounds__(SP_NT) void k_solve_persist(const TF* __restrict__ W, int64_t ldw,
+                                                         int64_t N, const double* __restrict__ Linv,
+                                                         const int32_t* kptr, const int32_t* nTptr,
+                                                         TF* __restrict__ F, int64_t ldf,
+                                                         double* __restrict__ rho) {
+  constexpr int NJ = MAXB / 16, CH = 4;
+  const int nt = *nTptr;
+  if (nt == 0) return;
+  const int k = *kptr;
+  __shared__ double Ls[MAXB * SP_LDK];
+  for (int e = threadIdx.x; e < MAXB * MAXB; e += SP_NT) Ls[(e / MAXB) * SP_LDK + e % MAXB] = Linv[e];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, kq = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int nks = (nt + 3) / 4, nch = (nks + CH - 1) / CH;
+  // k-steps each column tile needs: L^{-1}(n, k) = 0 for k > n
+  int lim[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int l = 16 * j >= nt ? 0 : 4 * (j + 1);
+    lim[j] = l < nks ? l : nks;
+  }
+  const int64_t step = 4 * ldw;
+  const int64_t nrb = (N + 15) / 16;
+  for (int64_t rb = (int64_t)blockIdx.x * (SP_NT / 64) + wave; rb < nrb;
+       rb += (int64_t)gridDim.x * (SP_NT / 64)) {
+    const int64_t m = rb * 16 + (lane & 15);
+    const bool rok = m < N;
+    // W holds MAXB columns: with the row clamped every address is valid
+    const TF* wp = W + (rok ? m : N - 1) + (int64_t)kq * ldw;
+    auto load = [&](TF (&buf)[CH], int ch) __attribute__((always_inline)) {
+      const TF* pc = wp + (int64_t)(ch * CH) * step;
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        const TF v = pc[q * step];
+        buf[q] = (rok && 4 * (ch * CH + q) + kq < nt) ? v : (TF)0;
+      }
+    };
+    v4d acc[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+    auto compute = [&](const TF (&buf)[CH], int ch) __attribute__((always_inline)) {
+      double av[CH];
+#pragma unroll
+      for (int q = 0; q < CH; ++q) av[q] = (double)buf[q];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        if (ch * CH >= lim[j]) continue;
+        const double* lrow = Ls + (16 * j + (lane & 15)) * SP_LDK + kq;
+        double b[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+          const int sq = ch * CH + q;
+          b[q] = sq < lim[j] ? lrow[4 * sq] : 0.0;  // past the tile's limit: zero step
+        }
+#pragma unroll
+        for (int q = 0; q < CH; ++q) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], b[q], acc[j], 0, 0, 0);
+      }
+    };
+    TF a0[CH], a1[CH];
+    load(a0, 0);
+    for (int ch = 0; ch < nch; ch += 2) {
+      if (ch + 1 < nch) load(a1, ch + 1);
+      compute(a0, ch);
+      if (ch + 1 >= nch) break;
+      if (ch + 2 < nch) load(a0, ch + 2);
+      compute(a1, ch + 1);
+    }
+    // F columns (element e of lane l: row l / 16 + 4 e, column 16 j + l % 16)
+    // and the squared row norms of G
+    double s2[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int col = 16 * j + (lane & 15);
+      if (16 * j >= nt) break;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double g = col < nt ? acc[j][e] : 0.0;
+        s2[e] += g * g;
+        const int64_t row = rb * 16 + kq + 4 * e;
+        if (col < nt && row < N) F[row + (int64_t)(k + col) * ldf] = (TF)g;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      double v = s2[e];
+      v += __shfl_xor(v, 1, 64);
+      v += __shfl_xor(v, 2, 64);
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 8, 64);
+      const int64_t row = rb * 16 + kq + 4 * e;
+      if ((lane & 15) == 0 && row < N) {
+        const double r2 = rho[row] - v;
+        rho[row] = r2 > 0.0 ? r2 : 0.0;
+      }
+    }
+  }
+}
+
+static int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+      n = 256;
+    cus[dev] = n;
+  }
+  return cus[dev];
+}
+
 // ------------------------------------------------------------ split-fp16 solve
 // Mixed form (bf16 distance product, float32 factor): G = W L^{-T} on the
 // fp16 MFMA pipe as split pairs (three products per float32 product).  W
@@ -1471,9 +1599,14 @@ static void phase_solve(FJob<T, TN, TF>& j, int i, hipStream_t st) {
                        (const _Float16*)w.Ll, (const float*)w.lsc, j.k_out, w.nT, (float*)j.F,
                        j.ldf, j.rho);
   } else {
-    hipLaunchKernelGGL((k_solve_downdate<TF>), dim3((unsigned)((N + CfgD::BM - 1) / CfgD::BM)),
-                       dim3(CfgD::NT), smD, st, (const TF*)w.W, w.ldw, N, w.Linv, j.k_out, w.nT,
-                       j.F, j.ldf, j.rho);
+    const int64_t nrb = (N + 15) / 16;
+    const int64_t cus = device_cus();
+    const int64_t need = (nrb + SP_NT / 64 - 1) / (SP_NT / 64);
+    const unsigned grid = (unsigned)(need < cus ? need : cus);
+    hipLaunchKernelGGL((k_solve_persist<TF>), dim3(grid), dim3(SP_NT), 0, st,
+                       (const TF*)w.W, w.ldw, N, (const double*)w.Linv, (const int32_t*)j.k_out,
+                       (const int32_t*)w.nT, j.F, j.ldf, j.rho);
+    (void)smD;
   }
   hipLaunchKernelGGL(k_round_end, dim3(1), dim3(MAXB), 0, st, w.Si, j.k_out, w.nT, j.rho,
                      j.o->round_accepted, i);
