@@ -200,13 +200,25 @@ typedef enum {
   RPC_SYMMETRIC = 1     /* L~ = D~^{-1/2} K~ D~^{-1/2} (symmetric normalisation) */
 } rpc_normalization;
 
+/* QR of B in Algorithm 1 (the paper suggests CGS2 or Cholesky QR2):
+ *  RPC_QR_CHOLQR   Cholesky QR in Gram space: G_B = B^T B = R^T R (column
+ *                  equilibrated), Q = B R^{-1} never formed (default; one
+ *                  N-long Gram product, exact to the Gram's rounding times
+ *                  cond(B)^2).
+ *  RPC_QR_CHOLQR2  Cholesky QR2: Q1 = B R1^{-1} is formed in float64 (N x r
+ *                  workspace), its Gram G2 = Q1^T Q1 = R2^T R2 factored
+ *                  again, R = R2 R1, U = Q1 R2^{-1} V: orthogonality to
+ *                  rounding for B with cond(B) up to about u^{-1/2}, at the
+ *                  cost of one N x r x r product and one more Gram. */
+typedef enum { RPC_QR_CHOLQR = 0, RPC_QR_CHOLQR2 = 1 } rpc_qr_mode;
+
 typedef struct {
   int32_t nev;
   int32_t fix_const;
   int32_t gram_dtype;
   int32_t u_dtype;
   int32_t normalization; /* rpc_normalization */
-  int32_t reserved_;     /* must be 0 */
+  int32_t qr_mode;       /* rpc_qr_mode */
   double gamma;
 } rpc_eig_opts;
 

@@ -56,7 +56,7 @@ NORMALIZATIONS = {"bistochastic": 0, "symmetric": 1}
 class rpc_eig_opts(ctypes.Structure):
     _fields_ = [("nev", ctypes.c_int32), ("fix_const", ctypes.c_int32),
                 ("gram_dtype", ctypes.c_int32), ("u_dtype", ctypes.c_int32),
-                ("normalization", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+                ("normalization", ctypes.c_int32), ("qr_mode", ctypes.c_int32),
                 ("gamma", ctypes.c_double)]
 
 
@@ -327,8 +327,11 @@ def bistoch_degrees_noalloc(F, k, c, d, q, status, stream=None):
            "bistoch_degrees_noalloc")
 
 
+QR_MODES = {"cholqr": 0, "cholqr2": 1}
+
+
 def bistoch_eig(F, k, d, q, nev, gamma=0.0, fix_const=False, gram_dtype="f64", u_dtype="f64",
-                normalization="bistochastic", status=None, stream=None):
+                normalization="bistochastic", qr_mode="cholqr", status=None, stream=None):
     """Top-nev eigenpairs of P~ (Algorithm 1), or of L~ = D~^{-1/2} K~ D~^{-1/2}
     with normalization="symmetric" (q may then be None).  Returns U (N x nev
     view), lam, E."""
@@ -343,7 +346,7 @@ def bistoch_eig(F, k, d, q, nev, gamma=0.0, fix_const=False, gram_dtype="f64", u
     E = torch.empty((nev, r), dtype=torch.float64, device=dev)
     st = status if status is not None else torch.zeros(1, dtype=torch.int32, device=dev)
     opts = rpc_eig_opts(int(nev), 1 if fix_const else 0, DTYPES[gram_dtype], DTYPES[u_dtype],
-                        NORMALIZATIONS[normalization], 0, float(gamma))
+                        NORMALIZATIONS[normalization], QR_MODES[qr_mode], float(gamma))
     nb = ctypes.c_size_t(0)
     _check(lib.bistoch_eig_workspace_size(N, r, ctypes.byref(opts), ctypes.byref(nb)),
            "bistoch_eig_workspace_size")

@@ -289,13 +289,23 @@ __global__ void k_rsqrt(const double* __restrict__ x, double* __restrict__ y, in
   if (i < n) y[i] = 1.0 / sqrt(x[i]);
 }
 
-// C = I on the leading k x k block, zero elsewhere (symmetric normalisation).
+// C = I on the leading k x k block, zero elsewhere (symmetric normalisation);
+// the whole identity when kptr is null.
 __global__ void k_eye_k(double* __restrict__ C, int r, const int32_t* kptr) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)r * r) return;
   const int i = (int)(e % r), j = (int)(e / r);
-  const int k = *kptr;
+  const int k = kptr ? *kptr : r;
   C[e] = (i == j && i < k) ? 1.0 : 0.0;
+}
+
+// G = I on every row and column >= k (unused budget), as for G_B.
+__global__ void k_pad_eye(double* __restrict__ G, int r, const int32_t* kptr) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * r) return;
+  const int i = (int)(e % r), j = (int)(e / r);
+  const int k = *kptr;
+  if (i >= k || j >= k) G[e] = (i == j) ? 1.0 : 0.0;
 }
 
 __global__ void k_set_int(int32_t* p, int32_t v) { *p = v; }
@@ -708,6 +718,9 @@ struct EigWs {
   double* sk;
   double* skq;  // split-K partials of the r x p block product
   float* gsc;   // per-chunk power-of-two scales of the split-fp16 Grams
+  // Cholesky QR2: Q1 = B R1^{-1} (N x r), G2 = Q1^T Q1 = L2 L2^T, R1^{-1}
+  double *Q1, *G2, *R1i, *sk2;
+  int64_t ldq;
   // spectral-projector restart (subspace iteration only)
   double *Xa, *Xb, *Mc, *Tn, *fbp, *pd;
   int32_t *nsdone, *nsfinal;
@@ -715,7 +728,8 @@ struct EigWs {
   int p;
 };
 
-static size_t carve_eig(WsCursor& c, EigWs& w, int64_t N, int r, int nev, bool fix_const) {
+static size_t carve_eig(WsCursor& c, EigWs& w, int64_t N, int r, int nev, bool fix_const,
+                        bool cholqr2) {
   w.p = r <= dense::JMAX ? r : dense::JMAX;
   const int p = w.p;
   const int nbu = (int)((N + 4095) / 4096);
@@ -754,6 +768,11 @@ static size_t carve_eig(WsCursor& c, EigWs& w, int64_t N, int r, int nev, bool f
   w.sk = c.take<double>((size_t)dense::SPLITK_MAX * p * p);
   w.skq = c.take<double>((size_t)dense::SPLITK_MAX * r * p);
   w.gsc = c.take<float>(2 * syrk::MAX_CHUNKS);
+  w.ldq = (int64_t)align_up((size_t)N, 8);
+  w.Q1 = cholqr2 ? c.take<double>((size_t)w.ldq * r) : nullptr;
+  w.G2 = cholqr2 ? c.take<double>((size_t)r * r) : nullptr;
+  w.R1i = cholqr2 ? c.take<double>((size_t)r * r) : nullptr;
+  w.sk2 = cholqr2 ? c.take<double>((size_t)dense::SPLITK_MAX * dense::NB * r) : nullptr;
   const bool sub = r > dense::JMAX;
   w.Xa = sub ? c.take<double>((size_t)r * r) : nullptr;
   w.Xb = sub ? c.take<double>((size_t)r * r) : nullptr;
@@ -788,11 +807,13 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   const int nev = o->nev;
   WsCursor cur{(char*)ws, 0, ws_bytes, true};
   EigWs w;
-  carve_eig(cur, w, N, r, nev, o->fix_const != 0);
+  const bool qr2 = o->qr_mode == RPC_QR_CHOLQR2;
+  carve_eig(cur, w, N, r, nev, o->fix_const != 0, qr2);
   if (!cur.ok) return RPC_EWORKSPACE;
   const int p = w.p;
   if (!syrk::gram2_fits<TG>(N, r, w.part_cap) ||
-      (o->fix_const && !syrk::gram2_fits<double>(N, nev, w.part_cap)))
+      (o->fix_const && !syrk::gram2_fits<double>(N, nev, w.part_cap)) ||
+      (qr2 && !syrk::gram2_fits<double>(N, r, w.part_cap)))
     return RPC_EWORKSPACE;
   const int sym = o->normalization == RPC_SYMMETRIC;
   prof::begin(prof::SMALL, st);
@@ -838,6 +859,33 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   dense::gemm64<false, true>(st, r, r, r, w.Cs, r, w.Gs, r, w.T1, r, 1.0, 0.0);
   dense::gemm64<true, true>(st, r, r, r, w.Gs, r, w.T1, r, w.M, r, 1.0, 0.0);
   RPC_LAUNCH_CHECK();
+  if (qr2) {
+    // Cholesky QR2: Q1 = B R1^{-1} formed explicitly (float64), its Gram
+    // G2 = Q1^T Q1 = L2 L2^T, and R = R2 R1 with R2 = L2^T, so that
+    // M = R C R^T = L2^T (R1 C R1^T) L2 and U = Q1 R2^{-1} V.
+    // R1^{-1} = S L'^{-T}
+    hipLaunchKernelGGL(k_eye_k, dim3(grr), dim3(256), 0, st, w.R1i, r, (const int32_t*)nullptr);
+    dense::trsm_lt(st, w.Gs, r, r, w.R1i, r, r, w.sk2);
+    hipLaunchKernelGGL(k_scale_rows, dim3(grr), dim3(256), 0, st, w.R1i, (int64_t)r, r, r,
+                       (const double*)w.s, 0);
+    typedef FormUCfg<double> CfgQ;
+    size_t smQ = TileSmem<CfgQ, false, true>::bytes;
+    if (ColStoreSmem<CfgQ, double>::bytes > smQ) smQ = ColStoreSmem<CfgQ, double>::bytes;
+    const dim3 gq((unsigned)((N + CfgQ::BM - 1) / CfgQ::BM), (unsigned)((r + CfgQ::BN - 1) / CfgQ::BN));
+    hipLaunchKernelGGL((k_form_u<double, TF, double>), gq, dim3(CfgQ::NT), smQ, st, F, ldf, N, r,
+                       (const double*)w.R1i, r, (const double*)w.sd, w.Q1, w.ldq, k);
+    if (o->gamma != 0.0)
+      hipLaunchKernelGGL((k_gamma_rows<double>), dim3(grr), dim3(256), 0, st, w.Q1, w.ldq, N,
+                         (const double*)w.R1i, r, r, k, o->gamma);
+    syrk::gram2_partial<double, double>(st, (const double*)w.Q1, w.ldq, N, r, 1, (const double*)nullptr,
+                                        (const double*)nullptr, w.part, w.part1, k);
+    syrk::gram2_reduce<double>(st, N, r, 1, w.part, w.part1, w.G2, nullptr, k);
+    hipLaunchKernelGGL(k_pad_eye, dim3(grr), dim3(256), 0, st, w.G2, r, k);
+    dense::cholesky(st, w.G2, r, r, status, k, w.cskip);
+    dense::gemm64<false, true>(st, r, r, r, w.M, r, w.G2, r, w.T1, r, 1.0, 0.0);
+    dense::gemm64<true, true>(st, r, r, r, w.G2, r, w.T1, r, w.M, r, 1.0, 0.0);
+    RPC_LAUNCH_CHECK();
+  }
 
   // ---- top-nev eigenpairs of M
   prof::end(prof::SMALL, st);
@@ -939,11 +987,16 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   prof::end(prof::EIG, st);
   prof::begin(prof::FORM_U, st);
   // ---- Z = R^{-1} V = S L'^{-T} V ;  U = D~^{-1} F Z
+  // (Cholesky QR2: Z = R2^{-1} V = L2^{-T} V, U = Q1 Z)
   hipLaunchKernelGGL(k_copy_cols, dim3(nblk((int64_t)r * nev)), dim3(256), 0, st,
                      (const double*)w.V, (int64_t)r, w.Z, (int64_t)r, r, nev, (const int32_t*)nullptr);
-  dense::trsm_lt(st, w.Gs, r, r, w.Z, r, nev, w.sk);  // w.sk holds >= SPLITK_MAX NB nev doubles
-  hipLaunchKernelGGL(k_scale_rows, dim3(nblk((int64_t)r * nev)), dim3(256), 0, st, w.Z, (int64_t)r,
-                     r, nev, (const double*)w.s, 0);
+  if (qr2) {
+    dense::trsm_lt(st, w.G2, r, r, w.Z, r, nev, w.sk);
+  } else {
+    dense::trsm_lt(st, w.Gs, r, r, w.Z, r, nev, w.sk);  // w.sk holds >= SPLITK_MAX NB nev doubles
+    hipLaunchKernelGGL(k_scale_rows, dim3(nblk((int64_t)r * nev)), dim3(256), 0, st, w.Z, (int64_t)r,
+                       r, nev, (const double*)w.s, 0);
+  }
   typedef FormUCfg<TG> CfgU;
   const dim3 gu((unsigned)((N + CfgU::BM - 1) / CfgU::BM), (unsigned)((nev + CfgU::BN - 1) / CfgU::BN));
   size_t smU = TileSmem<CfgU, false, true>::bytes;
@@ -953,8 +1006,16 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   hipLaunchKernelGGL((k_cvt<TG>), dim3(nblk((int64_t)r * nev)), dim3(256), 0, st, (const double*)w.Z,
                      Zt, (int64_t)r * nev);
   bool split_u = false;
+  if (qr2) {
+    typedef FormUCfg<double> CfgQ;
+    size_t smQ = TileSmem<CfgQ, false, true>::bytes;
+    if (ColStoreSmem<CfgQ, TU>::bytes > smQ) smQ = ColStoreSmem<CfgQ, TU>::bytes;
+    const dim3 gq((unsigned)((N + CfgQ::BM - 1) / CfgQ::BM), (unsigned)((nev + CfgQ::BN - 1) / CfgQ::BN));
+    hipLaunchKernelGGL((k_form_u<double, double, TU>), gq, dim3(CfgQ::NT), smQ, st, (const double*)w.Q1,
+                       w.ldq, N, r, (const double*)w.Z, nev, (const double*)nullptr, U, ldu, k);
+  }
   if constexpr (std::is_same<TG, float>::value && std::is_same<TF, float>::value) {
-    if (o->gram_dtype == RPC_F32_SPLIT16) {
+    if (!qr2 && o->gram_dtype == RPC_F32_SPLIT16) {
       // the split-fp16 form forms U on the fp16 pipe as well
       split_u = true;
       hipLaunchKernelGGL(k_pow2_scale, dim3(1), dim3(1024), 0, st, (const float*)Zt,
@@ -965,10 +1026,10 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
                          (const double*)w.sd, U, ldu, k);
     }
   }
-  if (!split_u)
+  if (!split_u && !qr2)
     hipLaunchKernelGGL((k_form_u<TG, TF, TU>), gu, dim3(CfgU::NT), smU, st, F, ldf, N, r,
                        (const TG*)Zt, nev, (const double*)w.sd, U, ldu, k);
-  if (o->gamma != 0.0)
+  if (o->gamma != 0.0 && !qr2)
     hipLaunchKernelGGL((k_gamma_rows<TU>), dim3(nblk((int64_t)r * nev)), dim3(256), 0, st, U, ldu, N,
                        (const double*)w.Z, r, nev, k, o->gamma);
   RPC_LAUNCH_CHECK();
@@ -1004,7 +1065,13 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   RPC_LAUNCH_CHECK();
 
   // ---- extension matrix E = C R^T V Lambda^{-1} (signed like U); R^T = S^{-1} L'
-  dense::gemm64<false, true>(st, r, nev, r, w.Gs, r, w.V, r, w.T2, r, 1.0, 0.0);
+  // (Cholesky QR2: R^T V = S^{-1} L' (L2 V))
+  const double* Vr = w.V;
+  if (qr2) {
+    dense::gemm64<false, true>(st, r, nev, r, w.G2, r, w.V, r, w.Z, r, 1.0, 0.0);
+    Vr = w.Z;
+  }
+  dense::gemm64<false, true>(st, r, nev, r, w.Gs, r, Vr, r, w.T2, r, 1.0, 0.0);
   hipLaunchKernelGGL(k_scale_rows, dim3(nblk((int64_t)r * nev)), dim3(256), 0, st, w.T2, (int64_t)r,
                      r, nev, (const double*)w.s, 1);
   dense::gemm64<false, true>(st, r, nev, r, w.C, r, w.T2, r, ext_E, r, 1.0, 0.0);
@@ -1064,7 +1131,7 @@ static int check_eig_opts(int64_t N, int r, const rpc_eig_opts* o) {
   if (!(o->gamma >= 0.0)) return RPC_EINVAL;
   if (o->normalization != RPC_BISTOCHASTIC && o->normalization != RPC_SYMMETRIC) return RPC_EINVAL;
   if (o->normalization == RPC_SYMMETRIC && o->fix_const) return RPC_EINVAL;
-  if (o->reserved_ != 0) return RPC_EINVAL;
+  if (o->qr_mode != RPC_QR_CHOLQR && o->qr_mode != RPC_QR_CHOLQR2) return RPC_EINVAL;
   return RPC_OK;
 }
 
@@ -1152,7 +1219,7 @@ extern "C" int bistoch_eig_workspace_size(int64_t N, int32_t r, const rpc_eig_op
   if (!bytes) return RPC_EINVAL;
   WsCursor c{nullptr, 0, 0, true};
   EigWs w;
-  *bytes = carve_eig(c, w, N, r, o->nev, o->fix_const != 0);
+  *bytes = carve_eig(c, w, N, r, o->nev, o->fix_const != 0, o->qr_mode == RPC_QR_CHOLQR2);
   return RPC_OK;
 }
 

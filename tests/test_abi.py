@@ -73,7 +73,7 @@ def test_host_side_validation(lib):
     assert lib.bistoch_eig_workspace_size(1000, 64, ctypes.byref(eo), ctypes.byref(nb)) == 0
     eo = rp.rpc_eig_opts(16, 0, rp.DTYPES["split16"], 1, 0, 0, 0.0)  # split-fp16 Gram
     assert lib.bistoch_eig_workspace_size(1000, 64, ctypes.byref(eo), ctypes.byref(nb)) == 0
-    for bad in (dict(normalization=2), dict(normalization=1, fix_const=1), dict(reserved_=1),
+    for bad in (dict(normalization=2), dict(normalization=1, fix_const=1), dict(qr_mode=2),
                 dict(gram_dtype=4), dict(u_dtype=rp.DTYPES["split16"])):
         eo = rp.rpc_eig_opts(16, 0, 0, 0, 0, 0, 0.0)
         for kk, v in bad.items():

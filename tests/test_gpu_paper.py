@@ -59,11 +59,11 @@ def test_pivots_and_factor(case):
     assert np.abs(tr / np.asarray(ref["trace_err"]) - 1).max() < 1e-6
 
 
-@pytest.mark.parametrize("gamma", [1e-7, 0.0])
-def test_regularised_eigenpairs(case, gamma):
+@pytest.mark.parametrize("gamma,qr", [(1e-7, "cholqr"), (0.0, "cholqr"), (0.0, "cholqr2")])
+def test_regularised_eigenpairs(case, gamma, qr):
     rp, out, deg = case["rp"], case["out"], case["deg"]
     res = oracle.bistoch_eig(case["ref"]["F"], NEV, gamma=gamma)
-    eig = rp.bistoch_eig(out["F"], out["k"], deg["d"], deg["q"], NEV, gamma=gamma)
+    eig = rp.bistoch_eig(out["F"], out["k"], deg["d"], deg["q"], NEV, gamma=gamma, qr_mode=qr)
     st = rp.status_sync(eig["status"])
     assert st == 0, rp.STATUS_NAMES.get(st, st)
     lam = eig["lam"].cpu().numpy()
@@ -77,7 +77,7 @@ def test_regularised_eigenpairs(case, gamma):
     Qg, _ = np.linalg.qr(U[:, :m])
     Qo, _ = np.linalg.qr(res["U"][:, :m])
     ae = float(np.arcsin(min(np.linalg.norm(Qg - Qo @ (Qo.T @ Qg), 2), 1.0)))
-    print(f"paper form, gamma {gamma:g}: lambda_1 - 1 = {lam[0] - 1:.3g}, lambda_{NEV} = {lam[-1]:.3g}, "
+    print(f"paper form, gamma {gamma:g}, {qr}: lambda_1 - 1 = {lam[0] - 1:.3g}, lambda_{NEV} = {lam[-1]:.3g}, "
           f"eigenvalue error {le:.3g}, angle {ae:.3g} over {m}")
     assert le < 1e-6 and ae < 1e-4
     assert abs(lam[0] - 1) < 1e-6

@@ -603,3 +603,34 @@ def test_eig_clustered_spectrum(gpu, N, k, nev, kind):
     print(f"clustered: lam[1] / lam[{nev}] = {res['lam'][1] / res['lam'][-1]:.3g}, eigenvalue error "
           f"{le:.3g}, angle {ae:.3g} over {m}")
     assert le < 1e-10 and ae < 1e-8
+
+
+@pytest.mark.parametrize("r,b,nev,gamma,norm", [(64, 8, 16, 0.0, "bistochastic"), (160, 32, 24, 0.0, "bistochastic"),
+                                                (160, 32, 24, 1e-3, "bistochastic"),
+                                                (64, 8, 12, 0.0, "symmetric")])
+def test_eig_cholqr2(gpu, r, b, nev, gamma, norm):
+    """Cholesky QR2 (Q1 = B R1^{-1} formed, its Gram factored again, R = R2
+    R1): eigenpairs against the oracle's Householder QR route to the float64
+    bars, U orthonormal, and the extension identity U = B' E."""
+    torch, rp = gpu
+    X, eps = _torus_case(seed=17)
+    u = uniform_stream(2 * b * (-(-r // b)), seed=17)
+    ref = oracle.arpc(X, eps, r=r, b=b, mode="sampled", uniforms=u)
+    out, k, F, piv, rho = _run_factor(gpu, X, eps, r, b, "sampled", u=u)
+    deg = rp.bistoch_degrees(out["F"], out["k"])
+    eig = rp.bistoch_eig(out["F"], out["k"], deg["d"], deg["q"], nev, gamma=gamma, normalization=norm,
+                         qr_mode="cholqr2")
+    assert rp.status_sync(eig["status"]) == 0
+    res = (oracle.bistoch_eig(ref["F"], nev, gamma=gamma) if norm == "bistochastic"
+           else oracle.symmetric_eig(ref["F"], nev))
+    lam = eig["lam"].cpu().numpy()
+    U = eig["U"].cpu().numpy()
+    m = _gap_index(res["lam_all"], nev)
+    le, ae = np.abs(lam / res["lam"] - 1).max(), _angle(U[:, :m], res["U"][:, :m])
+    orth = np.abs(U.T @ U - np.eye(nev)).max()
+    print(f"cholqr2 r={r} gamma={gamma} {norm}: eigenvalues {le:.3g}, angle {ae:.3g}, orthonormality {orth:.3g}")
+    assert le < 1e-10 and ae < 1e-8 and orth < 1e-12
+    d = deg["d"].cpu().numpy()
+    Bp = F[:, :k] / (d if norm == "bistochastic" else np.sqrt(d))[:, None]
+    Bp[np.arange(k), np.arange(k)] += gamma
+    assert np.abs(Bp @ eig["E"].cpu().numpy()[:k] - U).max() < 1e-8
