@@ -90,6 +90,23 @@ __device__ inline double to_d(T x) { return (double)x; }
 template <>
 __device__ inline double to_d<__bf16>(__bf16 x) { return (double)(float)x; }
 
+// Split of two float32 values into fp16 pairs: hi = fp16(v) (round to
+// nearest, one packed conversion for both), lo = fp16(v - hi) by one
+// mixed-precision fma per value (v - hi is exact in float32, so hi + lo
+// carries v to 22 bits).  Returns the two hi halves packed in *hb (v0 in bits
+// 15:0) and the two lo halves in *lb.  The caller scales v into fp16 range.
+typedef _Float16 v2h_t __attribute__((ext_vector_type(2)));
+__device__ inline void split_pair_f16(float v0, float v1, uint32_t& hb, uint32_t& lb) {
+  v2h_t hp;
+  hp[0] = (_Float16)v0;
+  hp[1] = (_Float16)v1;
+  hb = __builtin_bit_cast(uint32_t, hp);
+  // mixlo writes bits 15:0 and mixhi bits 31:16 of the same register
+  asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(lb) : "v"(v0), "v"(hb));
+  asm("v_fma_mixhi_f16 %0, %1, 1.0, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+      : "+v"(lb) : "v"(v1), "v"(hb));
+}
+
 // Broadcast lane `src` (wave-uniform) of a double held in a VGPR pair.
 __device__ inline double bcast_lane(double v, int src) {
   const unsigned long long u = __double_as_longlong(v);

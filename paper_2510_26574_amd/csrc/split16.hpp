@@ -39,13 +39,14 @@ typedef _Float16 v8h_t __attribute__((ext_vector_type(8)));
 
 __device__ inline void split8(const float (&x)[8], v8h_t& hi, v8h_t& lo,
                               float sc = SchurSplit::SC) {
+  // x sc is exact (sc a power of two); hi = fp16(x sc), lo = fp16(x sc - hi)
+  uint32_t hw[4], lw[4];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    // hi = fp16(x sc); lo = fp16(x sc - hi), the remainder formed exactly by the fma
-    const _Float16 h = (_Float16)(x[e] * sc);
-    hi[e] = h;
-    lo[e] = (_Float16)__builtin_fmaf(x[e], sc, -(float)h);
-  }
+  for (int e = 0; e < 8; e += 2) split_pair_f16(x[e] * sc, x[e + 1] * sc, hw[e >> 1], lw[e >> 1]);
+  typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+  const v4u h4 = {hw[0], hw[1], hw[2], hw[3]}, l4 = {lw[0], lw[1], lw[2], lw[3]};
+  hi = __builtin_bit_cast(v8h_t, h4);
+  lo = __builtin_bit_cast(v8h_t, l4);
 }
 
 // Register ring of two stages: the global reads of stage s + 2 are issued

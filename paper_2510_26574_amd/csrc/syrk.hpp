@@ -347,17 +347,13 @@ struct SplitLoader {
       const int vid = tid + p * NTH;
       const int col = vid / VPC;
       const int kv = (vid % VPC) * 4;
-      v4h h, l;
+      // v = x s rounded to float32, split into fp16 hi and lo
+      uint32_t hw[2], lw[2];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        // hi = fp16(x s); lo = fp16(x s - hi) with the remainder formed exactly by the fma
-        const float x = ld.buf[p][e];
-        const _Float16 xh = (_Float16)(x * ss[e]);
-        h[e] = xh;
-        l[e] = (_Float16)__builtin_fmaf(x, ss[e], -(float)xh);
-      }
-      *reinterpret_cast<v4h*>(hi + col * SPLIT_LDK + kv) = h;
-      *reinterpret_cast<v4h*>(lo + col * SPLIT_LDK + kv) = l;
+      for (int e = 0; e < 4; e += 2)
+        split_pair_f16(ld.buf[p][e] * ss[e], ld.buf[p][e + 1] * ss[e + 1], hw[e >> 1], lw[e >> 1]);
+      *reinterpret_cast<uint2*>(hi + col * SPLIT_LDK + kv) = make_uint2(hw[0], hw[1]);
+      *reinterpret_cast<uint2*>(lo + col * SPLIT_LDK + kv) = make_uint2(lw[0], lw[1]);
     }
   }
 };
@@ -543,7 +539,7 @@ struct PairLoader {  // 128 columns x 32 rows of float32, two 4-row vectors per 
       }
     }
   }
-  // hi = fp16(x s), lo = fp16(x s - hi), with s the row scale times the chunk's 2^e
+  // v = x s rounded to float32 (s the row scale times the chunk's 2^e), hi = fp16(v), lo = fp16(v - hi)
   __device__ inline void store(_Float16* __restrict__ hi, _Float16* __restrict__ lo,
                                const float (&ss)[4], int tid) const {
 #pragma unroll
@@ -551,16 +547,13 @@ struct PairLoader {  // 128 columns x 32 rows of float32, two 4-row vectors per 
       const int vid = tid + p * NTH;
       const int col = vid / VPC;
       const int kv = (vid % VPC) * 4;
-      v4h h, l;
+      // v = x s rounded to float32, split into fp16 hi and lo
+      uint32_t hw[2], lw[2];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float x = buf[p][e];
-        const _Float16 xh = (_Float16)(x * ss[e]);
-        h[e] = xh;
-        l[e] = (_Float16)__builtin_fmaf(x, ss[e], -(float)xh);
-      }
-      *reinterpret_cast<v4h*>(hi + col * PAIR_LDK + kv) = h;
-      *reinterpret_cast<v4h*>(lo + col * PAIR_LDK + kv) = l;
+      for (int e = 0; e < 4; e += 2)
+        split_pair_f16(buf[p][e] * ss[e], buf[p][e + 1] * ss[e + 1], hw[e >> 1], lw[e >> 1]);
+      *reinterpret_cast<uint2*>(hi + col * PAIR_LDK + kv) = make_uint2(hw[0], hw[1]);
+      *reinterpret_cast<uint2*>(lo + col * PAIR_LDK + kv) = make_uint2(lw[0], lw[1]);
     }
   }
 };
