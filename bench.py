@@ -286,6 +286,50 @@ def factor_forms(rp, torch, Xd, eps, ud, w, reps=3):
     return res
 
 
+def low_memory_pipeline(rp, torch, Xd, eps, ud, w):
+    """The whole method in the low-memory form: rpchol_factor with
+    low_memory=True (bf16 distance products, float64 F(S, :) only) and
+    bistoch_lowmem (Algorithm 1 over factor rows recomputed in blocks of
+    65536).  Timed once after a warm-up; device_bytes = F(S, :) + both
+    workspaces + c, d~, q~, U.  Eigenvalues and the top subspace are compared
+    with the plain float64 path (float64 products, full factor,
+    bistoch_degrees + bistoch_eig) replaying the same pivots; the difference
+    is that of the bf16 distance products inside the factorisation."""
+    def run():
+        fac = rp.rpchol_factor(Xd, eps, w["r"], w["b"], uniforms=ud, gemm_dtype="bf16",
+                               factor_dtype="f64", low_memory=True)
+        res = rp.bistoch_lowmem(Xd, eps, fac["pivots"], fac["k"], fac["F"], w["nev"],
+                                status=fac["status"])
+        return fac, res
+    fac, res = run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fac, res = run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = rp.status_sync(res["status"])
+    k = int(fac["k"].item())
+    piv = fac["pivots"][:k].clone()
+    ref = rp.rpchol_factor(Xd, eps, w["r"], w["b"], mode="replay", replay=piv, gemm_dtype="f64",
+                           factor_dtype="f64")
+    deg = rp.bistoch_degrees(ref["F"], ref["k"], status=ref["status"])
+    eig = rp.bistoch_eig(ref["F"], ref["k"], deg["d"], deg["q"], w["nev"], status=ref["status"])
+    st_ref = rp.status_sync(ref["status"])
+    lam, lam_f = res["lam"].cpu().numpy(), eig["lam"].cpu().numpy()
+    Qa, _ = np.linalg.qr(res["U"].cpu().numpy())
+    Qb, _ = np.linalg.qr(eig["U"].cpu().numpy())
+    ang = float(np.linalg.norm(Qb - Qa @ (Qa.T @ Qb), 2))
+    nbytes = (fac["Fbuf"].numel() * 8 + fac["workspace"].numel() + res["workspace"].numel()
+              + (res["c"].numel() + res["d"].numel() + res["q"].numel()) * 8
+              + res["U"].numel() * 8)
+    full_F = ref["Fbuf"].numel() * 8
+    del ref, deg, eig
+    return {"ms": dt * 1e3, "k": k, "status": st, "status_full_replay": st_ref,
+            "device_bytes": int(nbytes), "full_factor_bytes": int(full_F),
+            "lam_rel_err_vs_plain_fp64_replay": float(np.abs(lam / lam_f - 1).max()),
+            "principal_angle_vs_plain_fp64_replay_rad": ang}
+
+
 def cpu_baseline(X, eps, w, n_sample):
     """The float64 oracle on a seeded uniform sample of the workload's rows
     (same r, b, nev, eps and uniforms), timed on the host's cores twice: with
@@ -745,6 +789,9 @@ def main():
     kcols = kernel_columns(rp, torch, Xd, eps, ud, w, X.shape[1], args.steps)
     log("[bench] factorisation product forms")
     forms = factor_forms(rp, torch, Xd, eps, ud, w)
+    log("[bench] low-memory pipeline (factor + Algorithm 1)")
+    lowmem = low_memory_pipeline(rp, torch, Xd, eps, ud, w)
+    log(f"[bench] low-memory pipeline {lowmem['ms']:.1f} ms")
     log("[bench] parity check")
     par = parity(rp, torch, Xd, eps, w, res_m)
     cpu = None
@@ -772,6 +819,7 @@ def main():
         "roofline": roof,
         "kernel_columns_bf16": kcols,
         "factor_forms": forms,
+        "low_memory_pipeline": lowmem,
         "cpu_baseline": cpu,
         "kernels_mixed": per_kernel,
         "kernels_plain_fp64": per_kernel_p if t_plain else None,

@@ -325,6 +325,46 @@ int nystrom_extend_symmetric(const rpc_points* Y, const rpc_points* X, const int
                              double* Phi, int64_t ldphi, void* workspace, size_t workspace_bytes,
                              int32_t* dev_status, rpc_stream_t stream);
 
+/* ---- Algorithm 1 from the low-memory factor ------------------------------
+ * The whole of Algorithm 1 (bistoch_degrees then bistoch_eig) for a factor
+ * from rpchol_factor with RPC_FACTOR_LOW_MEMORY, which keeps only
+ * FS = F(S, :) (r x r float64, row i = pivot i, leading dimension ldfs >= r;
+ * entries with an index >= k are ignored).  The N x r factor is never
+ * stored: F F^T interpolates K on the pivots, so every row follows from the
+ * points as F(x, :) = K(x, X_S) FS^{-T} (the appendix on randomly pivoted
+ * Cholesky and its low-memory remark), and each pass over the factor
+ * recomputes it block by block, block_rows rows at a time (0: 65536; else a
+ * multiple of 8192, at least r unless N is smaller): an MFMA distance
+ * product with an exp epilogue and a product with FS^{-T}.  Five passes:
+ * c; d~ and w; q~; the two Grams; U.  Memory O(N (d + nev) + r^2 +
+ * block_rows (r + d)) beyond the points.  Float64 throughout.  X is the
+ * points and bandwidth of the factorisation; pivots and k as it returned.
+ * Options as bistoch_eig with gram_dtype RPC_F64 and qr_mode RPC_QR_CHOLQR
+ * (the second pass of Cholesky QR2 needs Q1 = B R1^{-1}, an N x r matrix):
+ * others give RPC_EINVAL.  Outputs as bistoch_degrees (c, d_tilde, q_tilde;
+ * q_tilde may be NULL with the symmetric normalisation) and bistoch_eig (U,
+ * lambda, ext_E); device-side failures as those two calls report them. */
+int bistoch_lowmem_workspace_size(const rpc_points* X, int32_t r, const rpc_eig_opts* opts,
+                                  int64_t block_rows, size_t* bytes);
+int bistoch_lowmem(const rpc_points* X, const int64_t* pivots, const int32_t* k, const double* FS,
+                   int64_t ldfs, int32_t r, const rpc_eig_opts* opts, int64_t block_rows,
+                   double* c, double* d_tilde, double* q_tilde, void* U, int64_t ldu,
+                   double* lambda, double* ext_E, void* workspace, size_t workspace_bytes,
+                   int32_t* dev_status, rpc_stream_t stream);
+
+/* ---- Nystrom extension from the low-memory factor -------------------------
+ * nystrom_extend (normalization RPC_BISTOCHASTIC) or nystrom_extend_symmetric
+ * (RPC_SYMMETRIC) with F(S, :) given directly as FS (r x r float64, row i =
+ * pivot i, ldfs >= r), as rpchol_factor returns it with
+ * RPC_FACTOR_LOW_MEMORY; c and ext_E from bistoch_lowmem.  Workspace
+ * nystrom_extend_workspace_size; other arguments and errors as
+ * nystrom_extend. */
+int nystrom_extend_lowmem(const rpc_points* Y, const rpc_points* X, const int64_t* pivots,
+                          const int32_t* k, const double* FS, int64_t ldfs, int32_t r,
+                          const double* c, const double* ext_E, int32_t nev, int32_t normalization,
+                          double* Phi, int64_t ldphi, void* workspace, size_t workspace_bytes,
+                          int32_t* dev_status, rpc_stream_t stream);
+
 /* ---- Batched form: many independent decompositions ----------------------
  * A job is one full decomposition of its own points (rpchol_factor, then
  * bistoch_degrees, then bistoch_eig, exactly as the three calls made one

@@ -104,6 +104,11 @@ _SIGS = {
     "rpchol_factor_group_workspace_size": [_VP, _VP, _I32, _VP],
     "rpchol_factor_group": [_VP, _VP, _VP, _I32, _VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, _SZ,
                             _VP],
+    "bistoch_lowmem_workspace_size": [_VP, _I32, _VP, _I64, _VP],
+    "bistoch_lowmem": [_VP, _VP, _VP, _VP, _I64, _I32, _VP, _I64, _VP, _VP, _VP, _VP, _I64, _VP, _VP,
+                       _VP, _SZ, _VP, _VP],
+    "nystrom_extend_lowmem": [_VP, _VP, _VP, _VP, _VP, _I64, _I32, _VP, _VP, _I32, _I32, _VP, _I64,
+                              _VP, _SZ, _VP, _VP],
     "rpc_status_sync": [_VP, _VP],
     "rpc_version": [],
     "rpc_profile_enable": [ctypes.c_int],
@@ -379,6 +384,69 @@ def nystrom_extend(Y, X, eps, pivots, k, F, c, E, status=None, stream=None, symm
     _check(fn(ctypes.byref(py), ctypes.byref(px), _ptr(pivots), _ptr(k), _ptr(F), code,
               ldf, r, _ptr(c), _ptr(E), nev, _ptr(Phib), M, _ptr(ws), nb.value, _ptr(st),
               _stream(torch, stream)), "nystrom_extend")
+    return {"Phi": Phib.t(), "status": st}
+
+
+def bistoch_lowmem(X, eps, pivots, k, FS, nev, gamma=0.0, fix_const=False, u_dtype="f64",
+                   normalization="bistochastic", block_rows=0, status=None, stream=None):
+    """Algorithm 1 from the low-memory factor: FS = F(S, :) (r x r, the F of
+    rpchol_factor(..., low_memory=True)), the points X (N x d float32) and
+    the pivots; factor rows recomputed block by block.  Returns c, d, q, U,
+    lam, E as bistoch_degrees and bistoch_eig."""
+    torch = _torch()
+    lib = load_library()
+    N = X.shape[0]
+    r = FS.shape[1]
+    assert FS.dtype == torch.float64 and FS.stride(0) == 1, "FS must be column-major float64"
+    ldfs = FS.stride(1) if r > 1 else _ld(r)
+    dev = X.device
+    udt = torch.float64 if u_dtype == "f64" else torch.float32
+    ldu = _ld(N)
+    c = torch.empty(r, dtype=torch.float64, device=dev)
+    d = torch.empty(N, dtype=torch.float64, device=dev)
+    q = torch.empty(N, dtype=torch.float64, device=dev)
+    Ubuf = torch.empty((nev, ldu), dtype=udt, device=dev)
+    lam = torch.empty(nev, dtype=torch.float64, device=dev)
+    E = torch.empty((nev, r), dtype=torch.float64, device=dev)
+    st = status if status is not None else torch.zeros(1, dtype=torch.int32, device=dev)
+    opts = rpc_eig_opts(int(nev), 1 if fix_const else 0, DTYPES["f64"], DTYPES[u_dtype],
+                        NORMALIZATIONS[normalization], QR_MODES["cholqr"], float(gamma))
+    pts = _points(X, eps)
+    nb = ctypes.c_size_t(0)
+    _check(lib.bistoch_lowmem_workspace_size(ctypes.byref(pts), r, ctypes.byref(opts), int(block_rows),
+                                             ctypes.byref(nb)), "bistoch_lowmem_workspace_size")
+    ws = _workspace(torch, nb.value, dev)
+    _check(lib.bistoch_lowmem(ctypes.byref(pts), _ptr(pivots), _ptr(k), _ptr(FS), ldfs, r,
+                              ctypes.byref(opts), int(block_rows), _ptr(c), _ptr(d), _ptr(q),
+                              _ptr(Ubuf), ldu, _ptr(lam), _ptr(E), _ptr(ws), nb.value, _ptr(st),
+                              _stream(torch, stream)), "bistoch_lowmem")
+    return {"c": c, "d": d, "q": q, "U": Ubuf[:, :N].t(), "lam": lam, "E": E.t(), "status": st,
+            "workspace": ws}
+
+
+def nystrom_extend_lowmem(Y, X, eps, pivots, k, FS, c, E, symmetric=False, status=None, stream=None):
+    """nystrom_extend with F(S, :) given directly (the low-memory factor)."""
+    torch = _torch()
+    lib = load_library()
+    r = FS.shape[1]
+    assert FS.dtype == torch.float64 and FS.stride(0) == 1
+    ldfs = FS.stride(1) if r > 1 else _ld(r)
+    nev = E.shape[1]
+    assert E.stride(0) == 1 and E.stride(1) == r, "E must be r x nev column-major"
+    M = Y.shape[0]
+    dev = Y.device
+    Phib = torch.empty((nev, M), dtype=torch.float64, device=dev)
+    st = status if status is not None else torch.zeros(1, dtype=torch.int32, device=dev)
+    py, px = _points(Y, eps), _points(X, eps)
+    nb = ctypes.c_size_t(0)
+    _check(lib.nystrom_extend_workspace_size(M, Y.shape[1], r, nev, ctypes.byref(nb)),
+           "nystrom_extend_workspace_size")
+    ws = _workspace(torch, nb.value, dev)
+    _check(lib.nystrom_extend_lowmem(ctypes.byref(py), ctypes.byref(px), _ptr(pivots), _ptr(k),
+                                     _ptr(FS), ldfs, r, _ptr(c), _ptr(E), nev,
+                                     NORMALIZATIONS["symmetric" if symmetric else "bistochastic"],
+                                     _ptr(Phib), M, _ptr(ws), nb.value, _ptr(st),
+                                     _stream(torch, stream)), "nystrom_extend_lowmem")
     return {"Phi": Phib.t(), "status": st}
 
 

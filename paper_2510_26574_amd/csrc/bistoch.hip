@@ -20,6 +20,7 @@
 
 #include "common.hpp"
 #include "dense.hpp"
+#include "kernel_rows.hpp"
 #include "profile.hpp"
 #include "split16.hpp"
 #include "syrk.hpp"
@@ -728,8 +729,10 @@ struct EigWs {
   int p;
 };
 
+// gram_rows: rows of the factor one Gram launch covers (N, or the block
+// rows of the low-memory form), which sizes the chunk partial buffers.
 static size_t carve_eig(WsCursor& c, EigWs& w, int64_t N, int r, int nev, bool fix_const,
-                        bool cholqr2) {
+                        bool cholqr2, int64_t gram_rows = 0) {
   w.p = r <= dense::JMAX ? r : dense::JMAX;
   const int p = w.p;
   const int nbu = (int)((N + 4095) / 4096);
@@ -737,7 +740,7 @@ static size_t carve_eig(WsCursor& c, EigWs& w, int64_t N, int r, int nev, bool f
   w.sq = c.take<double>(N);
   w.ssd = c.take<double>(N);
   w.ssq = c.take<double>(N);
-  w.part_cap = syrk::part_elems_any(N, r);
+  w.part_cap = syrk::part_elems_any(gram_rows > 0 && gram_rows < N ? gram_rows : N, r);
   w.part = c.take<double>(w.part_cap);
   w.part1 = c.take<double>(w.part_cap);
   w.GB = c.take<double>((size_t)r * r);
@@ -787,6 +790,79 @@ static size_t carve_eig(WsCursor& c, EigWs& w, int64_t N, int r, int nev, bool f
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// ---- low-memory form: rows of the factor recomputed from the points
+// The low-memory factorisation keeps only L = F(S, :) (r x r, lower
+// triangular in pivot order).  Since F F^T interpolates K on the pivots,
+// every row of the factor follows from the points as
+//   F(x, :) = K(x, X_S) L^{-T},
+// so a block of rows costs one MFMA distance product with an exp epilogue
+// (k_cross_kernel) and one product with T = L^{-T}, computed once per call
+// (rows and columns >= k of T are zero, so are the recomputed columns >= k).
+// Everything is float64.
+
+// T[i, j] = 0 for i >= k or j >= k
+__global__ void k_zero_beyond_k(double* __restrict__ T, int r, const int32_t* kptr) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * r) return;
+  const int k = *kptr;
+  const int i = (int)(e % r), j = (int)(e / r);
+  if (i >= k || j >= k) T[e] = 0.0;
+}
+
+// A += B (first: A = B) over n entries, for two pairs at once (b1 may be null)
+__global__ void k_accum2(double* __restrict__ a0, const double* __restrict__ b0,
+                         double* __restrict__ a1, const double* __restrict__ b1, int64_t n,
+                         int first) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  a0[e] = first ? b0[e] : a0[e] + b0[e];
+  if (b1) a1[e] = first ? b1[e] : a1[e] + b1[e];
+}
+
+constexpr int64_t LM_BLOCK = 65536;  // default rows per recomputed block
+
+struct LmRows {
+  const rpc_points* X;
+  const int64_t* piv;
+  const int32_t* k;
+  const double* FSlm;
+  int64_t ldfs;
+  int r;
+  int64_t dp, blk;
+  int32_t* status;
+  double *XS, *xsn, *FS, *T, *Yp, *yn, *Kb, *Fb;
+
+  static void carve(WsCursor& c, LmRows& l, int64_t N, int64_t d, int r, int64_t blk) {
+    l.dp = (int64_t)align_up((size_t)d, 16);
+    l.blk = blk < N ? blk : N;
+    l.XS = c.take<double>((size_t)r * l.dp);
+    l.xsn = c.take<double>(r);
+    l.FS = c.take<double>((size_t)r * r);
+    l.T = c.take<double>((size_t)r * r);
+    l.Yp = c.take<double>((size_t)l.blk * l.dp);
+    l.yn = c.take<double>(l.blk);
+    l.Kb = c.take<double>((size_t)l.blk * r);
+    l.Fb = c.take<double>((size_t)l.blk * r);
+  }
+  // pivot points, L with the identity beyond k, and T = L^{-T} zeroed beyond k
+  void setup(hipStream_t st) const {
+    hipLaunchKernelGGL((k_gather_pivots<double>), dim3(r), dim3(256), 0, st, X->X, X->ldx, X->d, dp,
+                       piv, k, FSlm, ldfs, r, XS, xsn, FS, 1);
+    hipLaunchKernelGGL(k_fill_identity, dim3(nblk((int64_t)r * r)), dim3(256), 0, st, T, r, r);
+    dense::trsm_lt(st, FS, r, r, T, r, r);
+    hipLaunchKernelGGL(k_zero_beyond_k, dim3(nblk((int64_t)r * r)), dim3(256), 0, st, T, r, k);
+  }
+  // Fb (m x r, leading dimension m) = rows m0 .. m0 + m - 1 of the factor
+  void rows(hipStream_t st, int64_t m0, int64_t m) const {
+    hipLaunchKernelGGL(k_prep_rows64, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st,
+                       X->X + m0 * X->ldx, X->ldx, m, X->d, dp, Yp, yn, status);
+    hipLaunchKernelGGL(k_cross_kernel, dim3((unsigned)((m + 63) / 64), (unsigned)((r + 63) / 64)),
+                       dim3(256), 0, st, (const double*)Yp, (const double*)yn, m, dp,
+                       (const double*)XS, (const double*)xsn, r, X->eps, Kb, m);
+    dense::gemm64<false, true>(st, m, r, r, Kb, m, T, r, Fb, m, 1.0, 0.0);
+  }
+};
+
 // Orthonormalise the r x p block Y into Q by Cholesky QR (Gram, one-workgroup
 // Cholesky, row-parallel triangular solve).
 static void chol_qr(hipStream_t st, const double* Y, double* Q, int r, int p, EigWs& w,
@@ -799,19 +875,24 @@ static void chol_qr(hipStream_t st, const double* Y, double* Q, int r, int p, Ei
   dense::gemm64<false, true>(st, r, p, p, Y, r, w.Rinv, p, Q, r, 1.0, 0.0, skip);
 }
 
+// lm: the low-memory form (F unused; TG = TF = double; CholQR only): the
+// Grams and U are formed block by block from recomputed rows.  Its
+// workspace follows the caller's LmRows carve.
 template <typename TG, typename TF, typename TU>
 static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
                    const double* dt, const double* qt, const rpc_eig_opts* o, TU* U, int64_t ldu,
                    double* lambda, double* ext_E, void* ws, size_t ws_bytes, int32_t* status,
-                   hipStream_t st) {
+                   hipStream_t st, const LmRows* lm = nullptr) {
   const int nev = o->nev;
   WsCursor cur{(char*)ws, 0, ws_bytes, true};
   EigWs w;
   const bool qr2 = o->qr_mode == RPC_QR_CHOLQR2;
-  carve_eig(cur, w, N, r, nev, o->fix_const != 0, qr2);
+  carve_eig(cur, w, N, r, nev, o->fix_const != 0, qr2, lm ? lm->blk : 0);
   if (!cur.ok) return RPC_EWORKSPACE;
+  if (lm && (qr2 || !std::is_same<TG, double>::value || !std::is_same<TF, double>::value))
+    return RPC_EINVAL;
   const int p = w.p;
-  if (!syrk::gram2_fits<TG>(N, r, w.part_cap) ||
+  if (!syrk::gram2_fits<TG>(lm ? lm->blk : N, r, w.part_cap) ||
       (o->fix_const && !syrk::gram2_fits<double>(N, nev, w.part_cap)) ||
       (qr2 && !syrk::gram2_fits<double>(N, r, w.part_cap)))
     return RPC_EWORKSPACE;
@@ -830,7 +911,22 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   // C = (Q~^{-1/2} F)^T (Q~^{-1/2} F) (bistochastic) or C = I (symmetric)
   const int nz = sym ? 1 : 2;
   prof::begin(prof::GRAM, st);
-  if constexpr (std::is_same<TG, float>::value && std::is_same<TF, float>::value) {
+  if (lm) {
+    // block by block: partial products of the recomputed rows, reduced into
+    // Gs / Cs (free until the equilibration) and added into G_B / C
+    int first = 1;
+    for (int64_t m0 = 0; m0 < N; m0 += lm->blk, first = 0) {
+      const int64_t m = N - m0 < lm->blk ? N - m0 : lm->blk;
+      lm->rows(st, m0, m);
+      syrk::gram2_partial<double, double>(st, lm->Fb, m, m, r, nz, (const double*)w.ssd + m0,
+                                          sym ? nullptr : (const double*)w.ssq + m0, w.part, w.part1,
+                                          k);
+      syrk::gram2_reduce<double>(st, m, r, nz, w.part, w.part1, w.Gs, w.Cs, k);
+      hipLaunchKernelGGL(k_accum2, dim3(nblk((int64_t)r * r)), dim3(256), 0, st, w.GB,
+                         (const double*)w.Gs, w.C, sym ? (const double*)nullptr : (const double*)w.Cs,
+                         (int64_t)r * r, first);
+    }
+  } else if constexpr (std::is_same<TG, float>::value && std::is_same<TF, float>::value) {
     if (o->gram_dtype == RPC_F32_SPLIT16)
       syrk::gram2_partial_split(st, F, ldf, N, r, nz, (const float*)w.ssd, (const float*)w.ssq,
                                 w.gsc, w.part, w.part1, k);
@@ -845,10 +941,19 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   const unsigned grr = nblk((int64_t)r * r);
   RPC_LAUNCH_CHECK();
   prof::begin(prof::SMALL, st);
-  syrk::gram2_reduce<TG>(st, N, r, nz, w.part, w.part1, w.GB, w.C, k);
+  if (!lm) syrk::gram2_reduce<TG>(st, N, r, nz, w.part, w.part1, w.GB, w.C, k);
   if (sym) hipLaunchKernelGGL(k_eye_k, dim3(grr), dim3(256), 0, st, w.C, r, k);
+  // the regularised QR reads rows 0 .. k-1 of F (recomputed in the low-memory form)
+  const TF* Fg = F;
+  int64_t ldg = ldf;
+  if (lm && o->gamma != 0.0) {
+    const int64_t m = N < lm->blk ? N : lm->blk;
+    lm->rows(st, 0, m);
+    Fg = reinterpret_cast<const TF*>(lm->Fb);
+    ldg = m;
+  }
   hipLaunchKernelGGL((k_gram_finish<TF>), dim3(grr), dim3(256), 0, st, w.GB, w.C, w.Gs, w.Cs, w.s,
-                     r, k, F, ldf, N, (const double*)w.sd, o->gamma, 0);
+                     r, k, Fg, ldg, N, (const double*)w.sd, o->gamma, 0);
   hipLaunchKernelGGL((k_gram_finish<TF>), dim3(grr), dim3(256), 0, st, w.GB, w.C, w.Gs, w.Cs, w.s,
                      r, k, F, ldf, N, (const double*)w.sd, o->gamma, 1);
   RPC_LAUNCH_CHECK();
@@ -1026,9 +1131,19 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
                          (const double*)w.sd, U, ldu, k);
     }
   }
-  if (!split_u && !qr2)
+  if (lm) {
+    for (int64_t m0 = 0; m0 < N; m0 += lm->blk) {
+      const int64_t m = N - m0 < lm->blk ? N - m0 : lm->blk;
+      lm->rows(st, m0, m);
+      const dim3 gm((unsigned)((m + CfgU::BM - 1) / CfgU::BM), gu.y);
+      hipLaunchKernelGGL((k_form_u<TG, double, TU>), gm, dim3(CfgU::NT), smU, st,
+                         (const double*)lm->Fb, m, m, r, (const TG*)Zt, nev,
+                         (const double*)w.sd + m0, U + m0, ldu, k);
+    }
+  } else if (!split_u && !qr2) {
     hipLaunchKernelGGL((k_form_u<TG, TF, TU>), gu, dim3(CfgU::NT), smU, st, F, ldf, N, r,
                        (const TG*)Zt, nev, (const double*)w.sd, U, ldu, k);
+  }
   if (o->gamma != 0.0 && !qr2)
     hipLaunchKernelGGL((k_gamma_rows<TU>), dim3(nblk((int64_t)r * nev)), dim3(256), 0, st, U, ldu, N,
                        (const double*)w.Z, r, nev, k, o->gamma);
@@ -1106,6 +1221,47 @@ static int run_degrees(const TF* F, int64_t N, int64_t ldf, int r, const int32_t
                      r, wv);
   hipLaunchKernelGGL((k_rowdot<TF>), dim3(nblk(N)), dim3(256), sh, st, F, ldf, N, r, k,
                      (const double*)wv, qt, (double*)nullptr, (int32_t)RPC_EQDEGREE, status);
+  prof::end(prof::DEGREES, st);
+  RPC_LAUNCH_CHECK();
+  return RPC_OK;
+}
+
+// The degree passes of Algorithm 1 over recomputed rows: pass 1 c = F^T 1;
+// pass 2 d~ = F c (asserted > 0) and w = F^T (1/d~); pass 3 q~ = F w
+// (asserted > 0).  Blocks start at multiples of COLCHUNK, so the partial
+// column sums of block b land at chunk m0 / COLCHUNK of one buffer and are
+// reduced in the same order as in run_degrees.
+static int run_degrees_lm(const LmRows& lm, int64_t N, int r, const int32_t* k, double* c,
+                          double* dt, double* qt, double* part, double* inv, double* wv,
+                          int32_t* status, hipStream_t st) {
+  const int nch = (int)((N + COLCHUNK - 1) / COLCHUNK);
+  const size_t sh = (size_t)r * sizeof(double);
+  prof::begin(prof::DEGREES, st);
+  for (int pass = 0; pass < 3; ++pass) {
+    for (int64_t m0 = 0; m0 < N; m0 += lm.blk) {
+      const int64_t m = N - m0 < lm.blk ? N - m0 : lm.blk;
+      lm.rows(st, m0, m);
+      const dim3 gc((unsigned)((m + COLCHUNK - 1) / COLCHUNK), (unsigned)((r + 15) / 16));
+      double* pb = part + (m0 / COLCHUNK) * r;
+      if (pass == 0) {
+        hipLaunchKernelGGL((k_coldot_partial<double>), gc, dim3(1024), 0, st, (const double*)lm.Fb, m,
+                           m, r, k, (const double*)nullptr, pb);
+      } else if (pass == 1) {
+        hipLaunchKernelGGL((k_rowdot<double>), dim3(nblk(m)), dim3(256), sh, st, (const double*)lm.Fb,
+                           m, m, r, k, (const double*)c, dt + m0, inv + m0, (int32_t)RPC_EDEGREE,
+                           status);
+        hipLaunchKernelGGL((k_coldot_partial<double>), gc, dim3(1024), 0, st, (const double*)lm.Fb, m,
+                           m, r, k, (const double*)inv + m0, pb);
+      } else {
+        hipLaunchKernelGGL((k_rowdot<double>), dim3(nblk(m)), dim3(256), sh, st, (const double*)lm.Fb,
+                           m, m, r, k, (const double*)wv, qt + m0, (double*)nullptr,
+                           (int32_t)RPC_EQDEGREE, status);
+      }
+    }
+    if (pass < 2)
+      hipLaunchKernelGGL(k_reduce_cols, dim3((r + 255) / 256), dim3(256), 0, st, (const double*)part,
+                         nch, r, pass == 0 ? c : wv);
+  }
   prof::end(prof::DEGREES, st);
   RPC_LAUNCH_CHECK();
   return RPC_OK;
@@ -1211,6 +1367,89 @@ extern "C" int bistoch_degrees_noalloc(const void* F, int32_t fdt, int64_t N, in
   if (fdt == RPC_F64)
     return run_degrees<double>((const double*)F, N, ldf, r, k, c, dt, qt, ws, NOALLOC_BYTES, status, st);
   return run_degrees<float>((const float*)F, N, ldf, r, k, c, dt, qt, ws, NOALLOC_BYTES, status, st);
+}
+
+// ---- Algorithm 1 from the low-memory factor
+namespace {
+struct LmLayout {
+  LmRows rows;
+  double *part, *inv, *wv;
+  size_t eig_off;  // start of run_eig's workspace (256-aligned)
+};
+int64_t lm_block_rows(int64_t block_rows) { return block_rows > 0 ? block_rows : LM_BLOCK; }
+size_t carve_lm(WsCursor& c, LmLayout& l, int64_t N, int64_t d, int r, int64_t blk) {
+  LmRows::carve(c, l.rows, N, d, r, blk);
+  const int nch = (int)((N + COLCHUNK - 1) / COLCHUNK);
+  l.part = c.take<double>((size_t)nch * r);
+  l.inv = c.take<double>((size_t)N);
+  l.wv = c.take<double>((size_t)r);
+  l.eig_off = align_up(c.used, 256);
+  return l.eig_off;
+}
+int check_lm_args(const rpc_points* X, int r, const rpc_eig_opts* o, int64_t block_rows) {
+  if (!X || !X->X || X->N < 1 || X->d < 1 || X->ldx < X->d || !(X->eps > 0.0)) return RPC_EINVAL;
+  int rc = check_eig_opts(X->N, r, o);
+  if (rc) return rc;
+  if (o->gram_dtype != RPC_F64 || o->qr_mode != RPC_QR_CHOLQR) return RPC_EINVAL;
+  if (block_rows < 0 || block_rows % COLCHUNK != 0) return RPC_EINVAL;
+  if (block_rows > 0 && block_rows < r && block_rows < X->N) return RPC_EINVAL;
+  return RPC_OK;
+}
+}  // namespace
+
+extern "C" int bistoch_lowmem_workspace_size(const rpc_points* X, int32_t r, const rpc_eig_opts* o,
+                                             int64_t block_rows, size_t* bytes) {
+  int rc = check_lm_args(X, r, o, block_rows);
+  if (rc) return rc;
+  if (!bytes) return RPC_EINVAL;
+  const int64_t blk = lm_block_rows(block_rows);
+  WsCursor c{nullptr, 0, 0, true};
+  LmLayout l;
+  carve_lm(c, l, X->N, X->d, r, blk);
+  WsCursor e{nullptr, 0, 0, true};
+  EigWs w;
+  carve_eig(e, w, X->N, r, o->nev, o->fix_const != 0, false, blk < X->N ? blk : X->N);
+  *bytes = l.eig_off + e.used;
+  return RPC_OK;
+}
+
+extern "C" int bistoch_lowmem(const rpc_points* X, const int64_t* pivots, const int32_t* k,
+                              const double* FS, int64_t ldfs, int32_t r, const rpc_eig_opts* o,
+                              int64_t block_rows, double* c, double* dt, double* qt, void* U,
+                              int64_t ldu, double* lambda, double* ext_E, void* ws, size_t ws_bytes,
+                              int32_t* status, rpc_stream_t stream) {
+  int rc = check_lm_args(X, r, o, block_rows);
+  if (rc) return rc;
+  const int64_t N = X->N;
+  if (!pivots || !k || !FS || !c || !dt || !U || !lambda || !ext_E || !status) return RPC_EINVAL;
+  if (!qt && o->normalization != RPC_SYMMETRIC) return RPC_EINVAL;
+  if (ldfs < r || ldu < N || ldu % 8 != 0) return RPC_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int64_t blk = lm_block_rows(block_rows);
+  WsCursor cur{(char*)ws, 0, ws_bytes, true};
+  LmLayout l;
+  carve_lm(cur, l, N, X->d, r, blk);
+  if (!cur.ok || ws_bytes < l.eig_off) return RPC_EWORKSPACE;
+  l.rows.X = X;
+  l.rows.piv = pivots;
+  l.rows.k = k;
+  l.rows.FSlm = FS;
+  l.rows.ldfs = ldfs;
+  l.rows.r = r;
+  l.rows.status = status;
+  l.rows.setup(st);
+  RPC_LAUNCH_CHECK();
+  // the symmetric normalisation needs only d~; q~ is formed all the same
+  double* qv = qt ? qt : l.inv;
+  rc = run_degrees_lm(l.rows, N, r, k, c, dt, qv, l.part, l.inv, l.wv, status, st);
+  if (rc) return rc;
+  void* ews = (char*)ws + l.eig_off;
+  const size_t ebytes = ws_bytes - l.eig_off;
+  if (o->u_dtype == RPC_F64)
+    return run_eig<double, double, double>(nullptr, N, N, r, k, dt, qt, o, (double*)U, ldu, lambda,
+                                           ext_E, ews, ebytes, status, st, &l.rows);
+  return run_eig<double, double, float>(nullptr, N, N, r, k, dt, qt, o, (float*)U, ldu, lambda, ext_E,
+                                        ews, ebytes, status, st, &l.rows);
 }
 
 extern "C" int bistoch_eig_workspace_size(int64_t N, int32_t r, const rpc_eig_opts* o, size_t* bytes) {

@@ -16,46 +16,12 @@
 #include "common.hpp"
 #include "dense.hpp"
 #include "profile.hpp"
+#include "kernel_rows.hpp"
 #include "tile_gemm.hpp"
 
 namespace {
 
 constexpr int64_t MCH = 65536;  // new points per block
-
-// XS[i][:] = X[piv[i]][:] (i < k; zero rows beyond), xsn[i] = |XS[i]|^2;
-// FS (r x r column-major) = F(S, :) on the leading k x k block, identity beyond.
-template <typename TF>
-__global__ __launch_bounds__(256) void k_gather_pivots(const float* __restrict__ X, int64_t ldx,
-                                                       int64_t d, int64_t dp,
-                                                       const int64_t* __restrict__ piv,
-                                                       const int32_t* kptr,
-                                                       const TF* __restrict__ F, int64_t ldf,
-                                                       int r, double* __restrict__ XS,
-                                                       double* __restrict__ xsn,
-                                                       double* __restrict__ FS) {
-  const int i = blockIdx.x;
-  const int k = *kptr;
-  __shared__ double red[4];
-  double s = 0.0;
-  const int64_t p = i < k ? piv[i] : -1;
-  for (int64_t c = threadIdx.x; c < dp; c += 256) {
-    const double v = (p >= 0 && c < d) ? (double)X[p * ldx + c] : 0.0;
-    XS[(int64_t)i * dp + c] = v;
-    s += v * v;
-  }
-  s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) xsn[i] = red[0] + red[1] + red[2] + red[3];
-  for (int j = threadIdx.x; j < r; j += 256) {
-    double v;
-    if (i < k && j < k)
-      v = to_d(F[p + (int64_t)j * ldf]);
-    else
-      v = (i == j) ? 1.0 : 0.0;
-    FS[i + (int64_t)j * r] = v;
-  }
-}
 
 // rhs = [c | E] (r x (nev+1), column-major), rows >= k zero.
 __global__ void k_rhs(const double* __restrict__ c, const double* __restrict__ E, int r, int nev,
@@ -67,51 +33,6 @@ __global__ void k_rhs(const double* __restrict__ c, const double* __restrict__ E
   double v = 0.0;
   if (i < k) v = j == 0 ? c[i] : E[i + (int64_t)(j - 1) * r];
   B0[e] = v;
-}
-
-__global__ __launch_bounds__(256) void k_prep_rows64(const float* __restrict__ Y, int64_t ldy,
-                                                     int64_t m, int64_t d, int64_t dp,
-                                                     double* __restrict__ Yp,
-                                                     double* __restrict__ yn, int32_t* status) {
-  const int lane = threadIdx.x & 63;
-  const int64_t n = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (n >= m) return;
-  double s = 0.0;
-  bool bad = false;
-  for (int64_t j = lane; j < dp; j += 64) {
-    const float v = j < d ? Y[n * ldy + j] : 0.0f;
-    if (!isfinite(v)) bad = true;
-    Yp[n * dp + j] = (double)v;
-    s += (double)v * (double)v;
-  }
-  s = wave_sum(s);
-  if (__any(bad) && lane == 0) set_status(status, RPC_ENONFINITE);
-  if (lane == 0) yn[n] = s;
-}
-
-// Kys[m][i] = exp(-max(0, yn + xsn - 2 <y, x_i>) / eps), column-major m x r.
-__global__ __launch_bounds__(256) void k_cross_kernel(const double* __restrict__ Yp,
-                                                      const double* __restrict__ yn, int64_t m,
-                                                      int64_t dp, const double* __restrict__ XS,
-                                                      const double* __restrict__ xsn, int r,
-                                                      double eps, double* __restrict__ K,
-                                                      int64_t ldk) {
-  typedef TileCfg<double, 64, 64, 16, 2, 2> Cfg;
-  __shared__ double smem[TileSmem<Cfg, true, true>::bytes / sizeof(double)];
-  const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM, n0 = (int64_t)blockIdx.y * Cfg::BN;
-  GOperand<double, true> A{Yp, dp, m, dp, nullptr, true};
-  GOperand<double, true> B{XS, dp, r, dp, nullptr, true};
-  TileAcc<Cfg> acc;
-  acc.zero();
-  tile_mainloop<Cfg>(acc, A, B, m0, n0, 0, dp, smem);
-  for_each_acc<Cfg>(acc, [&](int row, int col, double v) {
-    const int64_t i = m0 + row, j = n0 + col;
-    if (i < m && j < r) {
-      double d2 = yn[i] + xsn[j] - 2.0 * v;
-      d2 = d2 > 0.0 ? d2 : 0.0;
-      K[i + j * ldk] = exp(-d2 / eps);
-    }
-  });
 }
 
 // Phi(i, j) = P(i, j + 1) / P(i, 0) (bistochastic) or / sqrt(P(i, 0)) (symmetric)
@@ -148,14 +69,14 @@ template <typename TF>
 static int run_nys(const rpc_points* Y, const rpc_points* X, const int64_t* piv, const int32_t* k,
                    const TF* F, int64_t ldf, int r, const double* c, const double* E, int nev,
                    double* Phi, int64_t ldphi, void* ws, size_t ws_bytes, int32_t* status,
-                   hipStream_t st, int sym) {
+                   hipStream_t st, int sym, int pivot_rows) {
   WsCursor cur{(char*)ws, 0, ws_bytes, true};
   NysWs w;
   carve_nys(cur, w, Y->N, Y->d, r, nev);
   if (!cur.ok) return RPC_EWORKSPACE;
   prof::begin(prof::NYSTROM, st);
   hipLaunchKernelGGL((k_gather_pivots<TF>), dim3(r), dim3(256), 0, st, X->X, X->ldx, X->d, w.dp, piv,
-                     k, F, ldf, r, w.XS, w.xsn, w.FS);
+                     k, F, ldf, r, w.XS, w.xsn, w.FS, pivot_rows);
   hipLaunchKernelGGL(k_rhs, dim3((unsigned)(((int64_t)r * (nev + 1) + 255) / 256)), dim3(256), 0, st,
                      c, E, r, nev, k, w.B0);
   dense::trsm_lt(st, w.FS, r, r, w.B0, r, nev + 1);
@@ -190,18 +111,20 @@ extern "C" int nystrom_extend_workspace_size(int64_t M, int64_t d, int32_t r, in
 static int nystrom_any(const rpc_points* Y, const rpc_points* X, const int64_t* pivots,
                        const int32_t* k, const void* F, int32_t fdt, int64_t ldf, int32_t r,
                        const double* c, const double* E, int32_t nev, double* Phi, int64_t ldphi,
-                       void* ws, size_t ws_bytes, int32_t* status, rpc_stream_t stream, int sym) {
+                       void* ws, size_t ws_bytes, int32_t* status, rpc_stream_t stream, int sym,
+                       int pivot_rows = 0) {
   if (!Y || !X || !Y->X || !X->X || !pivots || !k || !F || !c || !E || !Phi || !status)
     return RPC_EINVAL;
   if (Y->N < 1 || Y->d != X->d || Y->ldx < Y->d || X->ldx < X->d || !(X->eps > 0.0)) return RPC_EINVAL;
-  if (r < 1 || r > X->N || nev < 1 || nev > r || ldf < X->N || ldphi < Y->N) return RPC_EINVAL;
+  if (r < 1 || r > X->N || nev < 1 || nev > r || ldf < (pivot_rows ? r : X->N) || ldphi < Y->N)
+    return RPC_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (fdt == RPC_F64)
     return run_nys<double>(Y, X, pivots, k, (const double*)F, ldf, r, c, E, nev, Phi, ldphi, ws,
-                           ws_bytes, status, st, sym);
-  if (fdt == RPC_F32)
+                           ws_bytes, status, st, sym, pivot_rows);
+  if (fdt == RPC_F32 && !pivot_rows)
     return run_nys<float>(Y, X, pivots, k, (const float*)F, ldf, r, c, E, nev, Phi, ldphi, ws,
-                          ws_bytes, status, st, sym);
+                          ws_bytes, status, st, sym, 0);
   return RPC_EINVAL;
 }
 
@@ -222,6 +145,17 @@ extern "C" int nystrom_extend_symmetric(const rpc_points* Y, const rpc_points* X
                                         rpc_stream_t stream) {
   return nystrom_any(Y, X, pivots, k, F, fdt, ldf, r, c, E, nev, Phi, ldphi, ws, ws_bytes, status,
                      stream, 1);
+}
+
+extern "C" int nystrom_extend_lowmem(const rpc_points* Y, const rpc_points* X,
+                                     const int64_t* pivots, const int32_t* k, const double* FS,
+                                     int64_t ldfs, int32_t r, const double* c, const double* E,
+                                     int32_t nev, int32_t normalization, double* Phi, int64_t ldphi,
+                                     void* ws, size_t ws_bytes, int32_t* status,
+                                     rpc_stream_t stream) {
+  if (normalization != RPC_BISTOCHASTIC && normalization != RPC_SYMMETRIC) return RPC_EINVAL;
+  return nystrom_any(Y, X, pivots, k, FS, RPC_F64, ldfs, r, c, E, nev, Phi, ldphi, ws, ws_bytes,
+                     status, stream, normalization == RPC_SYMMETRIC, 1);
 }
 
 extern "C" int rpc_status_sync(const int32_t* dev_status, rpc_stream_t stream) {

@@ -161,3 +161,33 @@ def test_surrogate_and_batched_host_checks(lib):
     assert lib.surrogate_train_workspace_size(ctypes.byref(sh), 4096, 65, ctypes.byref(nb)) == rp.RPC_EINVAL
     assert lib.surrogate_extend_workspace_size(ctypes.byref(sh), 1000, 512, 1024, 32, ctypes.byref(nb)) == rp.RPC_EINVAL
     assert lib.rpc_batched_workspace_size(None, 0, 4, ctypes.byref(nb)) == rp.RPC_EINVAL
+
+
+def test_lowmem_alg1_host_checks(lib):
+    """bistoch_lowmem accepts float64 Grams with Cholesky QR and block sizes
+    that are multiples of 8192 (at least r), and nothing else."""
+    import paper_2510_26574_amd as rp
+
+    pts = rp.rpc_points(100000, 16, 16, 0x1000, 1.0)
+    nb = ctypes.c_size_t(0)
+
+    def size(r=256, nev=16, gram="f64", qr="cholqr", block=0, gamma=0.0):
+        o = rp.rpc_eig_opts(nev, 0, rp.DTYPES[gram], rp.DTYPES["f64"], 0, rp.QR_MODES[qr], gamma)
+        return lib.bistoch_lowmem_workspace_size(ctypes.byref(pts), r, ctypes.byref(o), block,
+                                                 ctypes.byref(nb))
+
+    assert size() == 0 and nb.value > 0
+    small = nb.value
+    assert size(block=8192) == 0 and nb.value < small  # smaller blocks, smaller workspace
+    for bad in [dict(gram="f32"), dict(qr="cholqr2"), dict(block=1000), dict(block=-8192),
+                dict(r=9000, block=8192), dict(nev=300), dict(gamma=-1.0)]:
+        assert size(**bad) == rp.RPC_EINVAL, bad
+    o = rp.rpc_eig_opts(16, 0, rp.DTYPES["f64"], rp.DTYPES["f64"], 0, 0, 0.0)
+    fake = ctypes.c_void_p(0x1000)
+    # null outputs and ldu below N are rejected before any launch
+    assert lib.bistoch_lowmem(ctypes.byref(pts), fake, fake, fake, 256, 256, ctypes.byref(o), 0, fake,
+                              fake, fake, None, 100008, fake, fake, fake, 1 << 30, fake,
+                              None) == rp.RPC_EINVAL
+    assert lib.bistoch_lowmem(ctypes.byref(pts), fake, fake, fake, 256, 256, ctypes.byref(o), 0, fake,
+                              fake, fake, fake, 99992, fake, fake, fake, 1 << 30, fake,
+                              None) == rp.RPC_EINVAL

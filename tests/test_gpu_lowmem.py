@@ -121,3 +121,106 @@ def test_lowmem_rows_reproduce_full_factor(gpu):
     ef = _rel(Frows, full["F"][rows][:, :k].cpu().numpy())
     print(f"rebuilt rows error {ef:.3g}")
     assert ef < 1e-12
+
+
+# ---- Algorithm 1 from the low-memory factor (bistoch_lowmem) --------------
+# Rows of the factor are recomputed block by block as K(x, X_S) F(S, :)^{-T}
+# in every pass; the results are those of Algorithm 1 on the full factor.
+# Bars (float64): c, d~, q~ and the eigenvalues 1e-10 relative, the
+# top-nev subspace 1e-8 rad, as the full form's float64 parity (the product
+# with the explicit F(S, :)^{-T} adds rounding of order u cond(F(S, :)),
+# far below them at these sizes).
+
+
+def _angle(U, V):
+    Qu, _ = np.linalg.qr(U)
+    Qv, _ = np.linalg.qr(V)
+    return float(np.linalg.norm(Qv - Qu @ (Qu.T @ Qv), 2))
+
+
+def _alg1_lowmem(gpu, X, eps, out, nev, block_rows, **kw):
+    torch, rp = gpu
+    Xd = torch.from_numpy(X).cuda()
+    res = rp.bistoch_lowmem(Xd, eps, out["pivots"], out["k"], out["F"], nev, block_rows=block_rows,
+                            **kw)
+    st = rp.status_sync(res["status"])
+    assert st == 0, rp.STATUS_NAMES.get(st, st)
+    return res
+
+
+@pytest.mark.parametrize("case", ["torus_blocks", "ks_gamma", "symmetric"])
+def test_lowmem_alg1_matches_oracle(gpu, case):
+    if case == "torus_blocks":  # three blocks of 8192 rows, the last ragged
+        X = torus_points(20000, seed=31)
+        r, b, nev, kw = 96, 16, 16, {}
+    elif case == "ks_gamma":
+        X = ks_points(9000, q=4, seed=32)
+        r, b, nev, kw = 128, 32, 24, {"gamma": 1e-3}
+    else:
+        X = torus_points(9000, seed=33)
+        r, b, nev, kw = 80, 16, 12, {"normalization": "symmetric"}
+    eps = median_sq_distance(X, seed=31)
+    u = uniform_stream(2 * b * (-(-r // b)), seed=31)
+    ref = oracle.arpc(X, eps, r=r, b=b, mode="sampled", uniforms=u)
+    out, k = _lowmem(gpu, X, eps, r, b, "sampled", u=u)
+    assert k == ref["k"] and list(out["pivots"][:k].cpu().numpy()) == list(ref["S"])
+    res = _alg1_lowmem(gpu, X, eps, out, nev, 8192, **kw)
+    F = ref["F"]
+    c_o, d_o, q_o = oracle.bistoch_degrees(F)
+    if case == "symmetric":
+        orc = oracle.symmetric_eig(F, nev)
+    else:
+        orc = oracle.bistoch_eig(F, nev, gamma=kw.get("gamma", 0.0))
+    ec = _rel(res["c"].cpu().numpy()[:k], c_o)
+    ed = _rel(res["d"].cpu().numpy(), d_o)
+    eq = _rel(res["q"].cpu().numpy(), q_o)
+    lam = res["lam"].cpu().numpy()
+    el = float(np.abs(lam / orc["lam"] - 1).max())
+    ang = _angle(res["U"].cpu().numpy(), orc["U"])
+    print(f"{case}: k = {k}; c {ec:.2g}, d {ed:.2g}, q {eq:.2g}, lambda {el:.2g}, angle {ang:.2g}")
+    assert ec < 1e-10 and ed < 1e-10 and eq < 1e-10
+    assert el < 1e-10 and ang < 1e-8
+    # unit columns, each signed so its largest-magnitude entry is positive
+    U = res["U"].cpu().numpy()
+    assert np.abs(np.linalg.norm(U, axis=0) - 1).max() < 1e-10
+    assert (U[np.abs(U).argmax(axis=0), np.arange(nev)] > 0).all()
+
+
+def test_lowmem_alg1_equals_full_form_and_extends(gpu):
+    """On the same pivots the low-memory Algorithm 1 equals bistoch_degrees +
+    bistoch_eig on the full float64 factor, and its Nystrom extension from
+    F(S, :) reproduces U at training rows and matches the full form's at new
+    points."""
+    torch, rp = gpu
+    X = ks_points(17000, q=8, seed=34)
+    eps = median_sq_distance(X, seed=34)
+    r, b, nev = 160, 32, 20
+    u = uniform_stream(2 * b * (r // b), seed=34)
+    out, k = _lowmem(gpu, X, eps, r, b, "sampled", u=u)
+    full = rp.rpchol_factor(torch.from_numpy(X).cuda(), eps, r, b, uniforms=torch.from_numpy(u).cuda(),
+                            factor_dtype="f64")
+    assert rp.status_sync(full["status"]) == 0 and int(full["k"].item()) == k
+    deg = rp.bistoch_degrees(full["F"], full["k"])
+    eig = rp.bistoch_eig(full["F"], full["k"], deg["d"], deg["q"], nev)
+    assert rp.status_sync(eig["status"]) == 0
+    res = _alg1_lowmem(gpu, X, eps, out, nev, 16384)
+    assert _rel(res["d"].cpu().numpy(), deg["d"].cpu().numpy()) < 1e-10
+    assert _rel(res["q"].cpu().numpy(), deg["q"].cpu().numpy()) < 1e-10
+    lam, lam_f = res["lam"].cpu().numpy(), eig["lam"].cpu().numpy()
+    assert np.abs(lam / lam_f - 1).max() < 1e-10
+    assert _angle(res["U"].cpu().numpy(), eig["U"].cpu().numpy()) < 1e-8
+    # extension: training rows reproduce U; new points agree with the full form
+    Xd = torch.from_numpy(X).cuda()
+    rows = np.arange(0, X.shape[0], 97)
+    ext = rp.nystrom_extend_lowmem(Xd[torch.from_numpy(rows).cuda()].contiguous(), Xd, eps,
+                                   out["pivots"], out["k"], out["F"], res["c"], res["E"])
+    assert rp.status_sync(ext["status"]) == 0
+    Phi = ext["Phi"].cpu().numpy()
+    U = res["U"].cpu().numpy()
+    assert np.abs(Phi - U[rows]).max() < 1e-9 * np.abs(U).max()
+    Y = torch.from_numpy(ks_points(500, q=8, seed=35)).cuda()
+    e_lm = rp.nystrom_extend_lowmem(Y, Xd, eps, out["pivots"], out["k"], out["F"], res["c"], res["E"])
+    e_full = rp.nystrom_extend(Y, Xd, eps, full["pivots"], full["k"], full["F"], deg["c"], eig["E"])
+    assert rp.status_sync(e_full["status"]) == 0 and rp.status_sync(e_lm["status"]) == 0
+    A, B = e_lm["Phi"].cpu().numpy(), e_full["Phi"].cpu().numpy()
+    assert np.abs(A - B).max() < 1e-8 * np.abs(B).max()
