@@ -244,6 +244,50 @@ def kernel_columns(rp, torch, Xd, eps, ud, w, d, steps):
             "traffic": pmc_traffic("k_kernel_colsIDF16bff")}
 
 
+GROUP_BW = (0.25, 0.5, 1.0, 2.0, 4.0, 8.0, 16.0, 32.0)
+
+
+def kernel_columns_group(rp, torch, Xd, eps, w, d):
+    """Kernel columns of eight bandwidths of the same points in one launch per
+    round (rpchol_factor_group; bf16 products, float32 factors): each tile of
+    X is read from HBM once per round for the eight jobs, so one X pass feeds
+    up to 8 n_T columns.  Flops 2 N d n_T per job and round; bytes: the bf16
+    points once per round plus every job's fp32 columns written.  Each job's
+    uniforms come from its own seed."""
+    from synth import uniform_stream
+
+    eps_list = [m * eps for m in GROUP_BW]
+    t = -(-w["r"] // w["b"])
+    us = [torch.from_numpy(uniform_stream(2 * w["b"] * t, seed=100 + g)).cuda()
+          for g in range(len(eps_list))]
+    for _ in range(2):
+        rp.profile_enable(True)
+        rp.profile_reset()
+        outs = rp.rpchol_factor_group(Xd, eps_list, w["r"], w["b"], us, gemm_dtype="bf16",
+                                      factor_dtype="f32")
+        torch.cuda.synchronize()
+        prof = rp.profile_read()
+        rp.profile_enable(False)
+    N = w["N"]
+    dp = -(-d // 32) * 32
+    nT = np.stack([o["round_accepted"].cpu().numpy().astype(np.float64) for o in outs])
+    sts = [rp.status_sync(o["status"]) for o in outs]
+    ms, n = prof["kernel_cols"]
+    flops = float(np.sum(2.0 * N * d * nT))
+    byts = float(t * N * dp * 2.0 + np.sum(N * nT * 4.0))
+    sec = ms / 1e3
+    ai = flops / byts
+    ceil_tf = min(PEAK["bf16"], ai * PEAK["hbm"] / 1e3)
+    tf = flops / sec / 1e12
+    del outs
+    return {"bandwidths": [float(m) for m in GROUP_BW], "ms_total": ms, "launches": n,
+            "columns_per_x_pass_max": int(len(eps_list) * w["b"]),
+            "k": [int(x) for x in nT.sum(axis=1)], "status": sts,
+            "tflops": tf, "gbs": byts / sec / 1e9, "frac_mfma_peak": tf / PEAK["bf16"],
+            "ai_flop_per_byte": ai, "ceiling_tflops": ceil_tf, "frac_ceiling": tf / ceil_tf,
+            "frac_hbm_peak": byts / sec / 1e9 / PEAK["hbm"]}
+
+
 def factor_forms(rp, torch, Xd, eps, ud, w, reps=3):
     """The factorisation alone (rpchol_factor) in its product forms: bf16
     distances (the benchmark's), split-fp16 distances (22 of float32's 24
@@ -287,16 +331,15 @@ def factor_forms(rp, torch, Xd, eps, ud, w, reps=3):
 
 
 def low_memory_pipeline(rp, torch, Xd, eps, ud, w):
-    """The whole method in the low-memory form: rpchol_factor with
-    low_memory=True (bf16 distance products, float64 F(S, :) only) and
-    bistoch_lowmem (Algorithm 1 over factor rows recomputed in blocks of
-    65536).  Timed once after a warm-up; device_bytes = F(S, :) + both
-    workspaces + c, d~, q~, U.  Eigenvalues and the top subspace are compared
-    with the plain float64 path (float64 products, full factor,
-    bistoch_degrees + bistoch_eig) replaying the same pivots; the difference
-    is that of the bf16 distance products inside the factorisation."""
+    """The plain float64 method in the low-memory form: rpchol_factor with
+    low_memory=True (float64 products, only F(S, :) kept) and bistoch_lowmem
+    (Algorithm 1 over factor rows recomputed in blocks of 65536).  Timed once
+    after a warm-up; device_bytes = F(S, :) + both workspaces + c, d~, q~, U,
+    against full_factor_bytes for the N x r float64 factor alone.
+    Eigenvalues and the top subspace are compared with the plain float64 path
+    (full factor, bistoch_degrees + bistoch_eig) replaying the same pivots."""
     def run():
-        fac = rp.rpchol_factor(Xd, eps, w["r"], w["b"], uniforms=ud, gemm_dtype="bf16",
+        fac = rp.rpchol_factor(Xd, eps, w["r"], w["b"], uniforms=ud, gemm_dtype="f64",
                                factor_dtype="f64", low_memory=True)
         res = rp.bistoch_lowmem(Xd, eps, fac["pivots"], fac["k"], fac["F"], w["nev"],
                                 status=fac["status"])
@@ -442,12 +485,12 @@ def bench_surrogate(args, rp, torch):
     losses = torch.zeros(epochs * spe, dtype=torch.float64, device="cuda")
     log(f"[surrogate] training {epochs} epochs x {spe} steps (batch {B})")
     # one untimed step on a copy-free warm-up is not possible without changing
-    # the weights, so the timing includes the first launch of each kernel
+    # the weights, so the timing includes the first launch of each kernel and
+    # the capture of the epoch graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for e in range(epochs):
-        sur.train_epoch(Xd, mean, rstd, perms[e], U, B, tscale=scale, lr=SUR["lr"],
-                        loss=losses[e * spe:(e + 1) * spe])
+    # every epoch replays one captured graph of the epoch's launches
+    sur.train_epochs(Xd, mean, rstd, perms, U, B, tscale=scale, lr=SUR["lr"], loss=losses)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     lc = losses.cpu().numpy()
@@ -787,6 +830,8 @@ def main():
         roof_p, per_kernel_p = roofline(w, X.shape[1], res_p, prof_p, args.steps, plain)
     log("[bench] kernel columns alone (unfused path)")
     kcols = kernel_columns(rp, torch, Xd, eps, ud, w, X.shape[1], args.steps)
+    log("[bench] kernel columns of eight bandwidths per X pass (group)")
+    kgroup = kernel_columns_group(rp, torch, Xd, eps, w, X.shape[1])
     log("[bench] factorisation product forms")
     forms = factor_forms(rp, torch, Xd, eps, ud, w)
     log("[bench] low-memory pipeline (factor + Algorithm 1)")
@@ -818,6 +863,7 @@ def main():
         "speedup_vs_plain_fp64": (t_plain / t_mixed) if t_plain else None,
         "roofline": roof,
         "kernel_columns_bf16": kcols,
+        "kernel_columns_bf16_group8": kgroup,
         "factor_forms": forms,
         "low_memory_pipeline": lowmem,
         "cpu_baseline": cpu,

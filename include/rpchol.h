@@ -24,8 +24,15 @@
  *     a caller-provided workspace whose size the *_workspace_size call
  *     returns.  Workspaces may not be shared by calls that overlap in time.
  *   - Every call is stream-ordered and asynchronous on `stream` (0 = the
- *     null stream).  The return value reports host-side argument checks and
- *     launch errors only.
+ *     null stream), with one exception: for r > 96, bistoch_eig and
+ *     bistoch_lowmem read the small eigensolver's convergence flag back to
+ *     the host after each of its Rayleigh-Ritz steps (one synchronisation of
+ *     `stream` each, usually one in all), and issue its retries and fallback
+ *     only when needed; while the stream is being captured into a graph, or
+ *     inside the batched form, they issue those launches unconditionally
+ *     (each returns at once after convergence) and never synchronise.  The
+ *     return value reports host-side argument checks and launch errors
+ *     only.
  *   - Failures found on the device (a degree <= 0, a Cholesky breakdown,
  *     non-finite input) are written to the device int32 *dev_status, which
  *     the caller clears to 0 before the call and reads after a sync
@@ -33,7 +40,8 @@
  *     written wins.
  *   - The accepted pivot count k lives in device memory (int32) so that no
  *     call needs a host synchronisation; columns of F at index >= k are 0.
- *   - Layouts: X is row-major N x d (float32, leading dimension ldx >= d).
+ *   - Layouts: X is row-major N x d (float32, float64 or bf16, leading
+ *     dimension ldx >= d).
  *     F is column-major N x r with leading dimension ldf >= N, ldf a
  *     multiple of 8.  U is column-major N x nev (leading dimension ldu >= N,
  *     a multiple of 8).  Phi is column-major M x nev (ldphi >= M).
@@ -78,14 +86,19 @@ typedef enum {
   RPC_REPLAY = 2   /* the ordered pivots in `replay` are taken, all accepted */
 } rpc_mode;
 
-/* Points: N rows of dimension d, row-major float32, and the bandwidth eps of
- * k(x, y) = exp(-|x - y|^2 / eps). */
+/* Points: N rows of dimension d, row-major, and the bandwidth eps of
+ * k(x, y) = exp(-|x - y|^2 / eps).  dtype is the element type of X:
+ * RPC_F32, RPC_F64 or RPC_BF16 (others: RPC_EINVAL).  The float64 arithmetic
+ * of the method sees the stored values exactly; bf16 distance products of
+ * float64 points round them through float32.  The learned-surrogate calls
+ * take RPC_F32 points only. */
 typedef struct {
   int64_t N;
   int64_t d;
   int64_t ldx;
-  const float* X; /* device */
+  const void* X; /* device, ldx elements per row */
   double eps;
+  int32_t dtype; /* rpc_dtype of X */
 } rpc_points;
 
 /* Options of rpchol_factor (Algorithm 2).
@@ -415,6 +428,12 @@ int rpc_batched_graph_create(const rpc_job* jobs, int32_t n_jobs, int32_t n_stre
 int rpc_batched_graph_launch(rpc_graph graph, rpc_stream_t stream);
 int rpc_batched_graph_destroy(rpc_graph graph);
 
+/* Any rpc_graph (batched jobs or surrogate training epochs): launch on
+ * `stream` (stream-ordered; the graph's work runs after what precedes it on
+ * the stream), or destroy (the handle is invalid afterwards). */
+int rpc_graph_launch(rpc_graph graph, rpc_stream_t stream);
+int rpc_graph_destroy(rpc_graph graph);
+
 /* Block-size autotuning: runs the job once untimed and `reps` times timed
  * (HIP events on `stream`, synchronising) for each candidate block size b
  * (the job's own b is ignored), writes the mean milliseconds to ms[i] (if
@@ -520,6 +539,27 @@ int surrogate_train_epoch(const sur_shape* shape, const sur_train_opts* opts, co
                           float* adam_m, float* adam_v, uint16_t* wbf16, double* loss,
                           void* workspace, size_t workspace_bytes, int32_t* dev_status,
                           rpc_stream_t stream);
+
+/* One training epoch captured as a graph: the launches of
+ * surrogate_train_epoch (ceil(n_idx / batch) AdamW steps over consecutive
+ * slices of idx) recorded once; each rpc_graph_launch runs one more epoch on
+ * the current contents of every buffer named here (rewrite idx in place with
+ * the next epoch's permutation between launches).  The AdamW step number is
+ * read from and advanced in device memory: step_counter (int64) holds the
+ * number of steps taken so far in this phase and grows by one per step, so
+ * every launch continues the bias correction where the last one stopped;
+ * o->step is ignored.  Replays equal surrogate_train_epoch calls bit for bit.
+ * stream must not be the null stream and profiling must be off (RPC_EINVAL);
+ * other arguments as surrogate_train_epoch.  For callers whose training is
+ * launch-bound (one step is about ten small launches). */
+int surrogate_train_graph_create(const sur_shape* shape, const sur_train_opts* opts,
+                                 const float* X, int64_t ldx, int64_t N, const double* mean,
+                                 const double* rstd, const int64_t* idx, int64_t n_idx,
+                                 int64_t batch, const void* T, int32_t t_dtype, int64_t ldt,
+                                 double tscale, float* params, float* adam_m, float* adam_v,
+                                 uint16_t* wbf16, double* loss, int64_t* step_counter,
+                                 void* workspace, size_t workspace_bytes, int32_t* dev_status,
+                                 rpc_stream_t stream, rpc_graph* graph);
 
 /* Forward pass over the M rows of Y (float32 row-major, ldy >= d): Phi (M x
  * n_out float32, column-major, ldphi >= M) and, if non-NULL, res (M float32,

@@ -38,7 +38,11 @@ class RpcError(RuntimeError):
 
 class rpc_points(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("d", ctypes.c_int64), ("ldx", ctypes.c_int64),
-                ("X", ctypes.c_void_p), ("eps", ctypes.c_double)]
+                ("X", ctypes.c_void_p), ("eps", ctypes.c_double), ("dtype", ctypes.c_int32)]
+
+    def __init__(self, N=0, d=0, ldx=0, X=0, eps=0.0, dtype=1):
+        # dtype defaults to RPC_F32, the points' usual storage
+        super().__init__(N, d, ldx, X, eps, dtype)
 
 
 class rpc_factor_opts(ctypes.Structure):
@@ -109,6 +113,11 @@ _SIGS = {
                        _VP, _SZ, _VP, _VP],
     "nystrom_extend_lowmem": [_VP, _VP, _VP, _VP, _VP, _I64, _I32, _VP, _VP, _I32, _I32, _VP, _I64,
                               _VP, _SZ, _VP, _VP],
+    "surrogate_train_graph_create": [_VP, _VP, _VP, _I64, _I64, _VP, _VP, _VP, _I64, _I64, _VP, _I32,
+                                     _I64, ctypes.c_double, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ,
+                                     _VP, _VP, _VP],
+    "rpc_graph_launch": [_VP, _VP],
+    "rpc_graph_destroy": [_VP],
     "rpc_status_sync": [_VP, _VP],
     "rpc_version": [],
     "rpc_profile_enable": [ctypes.c_int],
@@ -161,9 +170,15 @@ def _ld(n):
     return (n + 7) // 8 * 8
 
 
+_POINT_DTYPES = {"torch.float32": 1, "torch.float64": 0, "torch.bfloat16": 2}
+
+
 def _points(X, eps):
-    assert X.dtype.__str__() == "torch.float32" and X.is_cuda and X.dim() == 2 and X.stride(1) == 1
-    return rpc_points(X.shape[0], X.shape[1], X.stride(0), X.data_ptr(), float(eps))
+    """rpc_points of a row-major CUDA tensor (float32, float64 or bfloat16)."""
+    code = _POINT_DTYPES.get(str(X.dtype))
+    assert code is not None, f"points must be float32, float64 or bfloat16, not {X.dtype}"
+    assert X.is_cuda and X.dim() == 2 and X.stride(1) == 1
+    return rpc_points(X.shape[0], X.shape[1], X.stride(0), X.data_ptr(), float(eps), code)
 
 
 def _workspace(torch, nbytes, device):
@@ -729,6 +744,61 @@ class Surrogate:
                                          _ptr(self.wbf16), _ptr(loss), _ptr(ws), nb.value, _ptr(st),
                                          _stream(torch, stream)), "surrogate_train_epoch")
         self.steps[phase] += nsteps
+        return st
+
+    def train_epochs(self, X, mean, rstd, perms, T, batch, tscale=1.0, phase=0, lr=1e-3,
+                     betas=(0.9, 0.999), eps=1e-8, weight_decay=0.01, splits=0, loss=None,
+                     status=None, stream=None):
+        """len(perms) epochs, each ceil(N / batch) AdamW steps over the slices of
+        perms[e] (E x n int64, CUDA), from one captured epoch graph replayed per
+        epoch (the permutation is copied into the graph's index buffer first).
+        Equal bit for bit to calling train_epoch once per epoch.  loss (optional,
+        float64, E * steps) receives every step's loss."""
+        torch = _torch()
+        lib = load_library()
+        E, n = perms.shape
+        nsteps = -(-n // batch)
+        assert perms.dtype == torch.int64 and X.dtype == torch.float32 and X.stride(1) == 1
+        if phase == 0:
+            assert T.dim() == 2 and T.stride(0) == 1, "phase-0 targets must be column-major N x n_out"
+            ldt = T.stride(1) if T.shape[1] > 1 else T.shape[0]
+        else:
+            assert T.dim() == 1
+            ldt = T.shape[0]
+        if loss is not None:
+            assert loss.dtype == torch.float64 and loss.numel() >= E * nsteps
+        tcode = DTYPES["f64"] if T.dtype == torch.float64 else DTYPES["f32"]
+        opts = sur_train_opts(float(lr), float(betas[0]), float(betas[1]), float(eps),
+                              float(weight_decay), 1, int(phase), int(splits))
+        nb = ctypes.c_size_t(0)
+        _check(lib.surrogate_train_workspace_size(ctypes.byref(self.shape), min(batch, n), int(splits),
+                                                  ctypes.byref(nb)), "surrogate_train_workspace_size")
+        dev = X.device
+        ws = self._wsbuf("train", nb.value, dev)
+        st = status if status is not None else torch.zeros(1, dtype=torch.int32, device=dev)
+        idx = torch.empty(n, dtype=torch.int64, device=dev)
+        lbuf = torch.zeros(nsteps, dtype=torch.float64, device=dev) if loss is not None else None
+        counter = torch.full((1,), int(self.steps[phase]), dtype=torch.int64, device=dev)
+        s = stream if stream is not None else torch.cuda.Stream(device=dev)
+        s.wait_stream(torch.cuda.current_stream(dev))
+        graph = ctypes.c_void_p(0)
+        _check(lib.surrogate_train_graph_create(
+            ctypes.byref(self.shape), ctypes.byref(opts), _ptr(X), X.stride(0), X.shape[0], _ptr(mean),
+            _ptr(rstd), _ptr(idx), n, int(batch), _ptr(T), tcode, ldt, float(tscale), _ptr(self.params),
+            _ptr(self.m), _ptr(self.v), _ptr(self.wbf16), _ptr(lbuf), _ptr(counter), _ptr(ws), nb.value,
+            _ptr(st), ctypes.c_void_p(s.cuda_stream), ctypes.byref(graph)), "surrogate_train_graph_create")
+        try:
+            with torch.cuda.stream(s):
+                for e in range(E):
+                    idx.copy_(perms[e])
+                    _check(lib.rpc_graph_launch(graph, ctypes.c_void_p(s.cuda_stream)), "rpc_graph_launch")
+                    if loss is not None:
+                        loss[e * nsteps:(e + 1) * nsteps].copy_(lbuf)
+            torch.cuda.current_stream(dev).wait_stream(s)
+            s.synchronize()
+        finally:
+            lib.rpc_graph_destroy(graph)
+        self.steps[phase] += E * nsteps
         return st
 
     def infer(self, Y, mean, rstd, with_res=True, status=None, stream=None):

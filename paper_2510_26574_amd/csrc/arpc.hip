@@ -51,8 +51,11 @@ struct RoundState {
 // pivots = -1 and the counters.  xmax (optional, cleared beforehand): the
 // largest finite |x| over all points, as float bits (non-negative floats
 // order like their bit patterns).
-template <typename T, typename TN>
-__global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, int64_t N, int64_t d,
+// TX: element type of the points (float, double or bf16); every value is
+// taken to double exactly and converted to T from there (bf16 copies of
+// float64 points round through float32).
+template <typename T, typename TN, typename TX>
+__global__ __launch_bounds__(256) void k_prep(const TX* __restrict__ X, int64_t N, int64_t d,
                                               int64_t ldx, int64_t dp, T* __restrict__ Xp,
                                               TN* __restrict__ xn, double* __restrict__ rho,
                                               int32_t* status, unsigned* xmax) {
@@ -62,10 +65,21 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, int64
   double s = 0.0;
   float amax = 0.0f;
   bool bad = false;
-  // rows without padding, 8-float aligned: each lane converts 8 consecutive
-  // columns per pass with two 16-byte loads and one vector store
-  const bool vec = d == dp && (ldx % 8) == 0 && (((uintptr_t)X) & 31) == 0;
-  if (vec) {
+  // float32 rows without padding, 8-float aligned: each lane converts 8
+  // consecutive columns per pass with two 16-byte loads and one vector store
+  const bool vec = std::is_same<TX, float>::value && d == dp && (ldx % 8) == 0 &&
+                   (((uintptr_t)X) & 31) == 0;
+  if constexpr (!std::is_same<TX, float>::value) {
+    for (int64_t j = lane; j < dp; j += 64) {
+      const double v = j < d ? ld_point(X, n * ldx + j) : 0.0;
+      if (!isfinite(v)) bad = true;
+      else amax = fmaxf(amax, (float)fabs(v));
+      T c = cvtd<T>(v);
+      Xp[n * dp + j] = c;
+      const double cd = to_d(c);
+      s += cd * cd;
+    }
+  } else if (vec) {
     typedef T tv __attribute__((ext_vector_type(8)));
     for (int64_t j0 = (int64_t)lane * 8; j0 < dp; j0 += 512) {
       const v4f u0 = *reinterpret_cast<const v4f*>(X + n * ldx + j0);
@@ -106,6 +120,19 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, int64
     xn[n] = (TN)s;
     rho[n] = 1.0;
   }
+}
+
+// k_prep over the points of X (its dtype picks the loader)
+template <typename T, typename TN>
+static void launch_prep(const rpc_points* X, int64_t dp, T* Xp, TN* xn, double* rho,
+                        int32_t* status, unsigned* xmax, hipStream_t st) {
+  const dim3 g((unsigned)((X->N + 3) / 4));
+  with_points_type(X->dtype, [&](auto* tx) {
+    typedef typename std::remove_const<typename std::remove_pointer<decltype(tx)>::type>::type TX;
+    hipLaunchKernelGGL((k_prep<T, TN, TX>), g, dim3(256), 0, st, (const TX*)X->X, X->N, X->d,
+                       X->ldx, dp, Xp, xn, rho, status, xmax);
+    return (int)RPC_OK;
+  });
 }
 
 __global__ void k_clear_u32(unsigned* p) { *p = 0u; }
@@ -1625,9 +1652,7 @@ static int run_factor(const rpc_points* X, const rpc_factor_opts* o, TF* F, int6
   const int64_t N = X->N;
   const bool split = o->gemm_dtype == RPC_F32_SPLIT16;
   if (split) hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(1), 0, st, j.w.xmax);
-  hipLaunchKernelGGL((k_prep<T, TN>), dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, X->X, N,
-                     X->d, X->ldx, j.w.dp, (T*)j.w.Xp, (TN*)j.w.xn, rho, status,
-                     split ? j.w.xmax : nullptr);
+  launch_prep<T, TN>(X, j.w.dp, (T*)j.w.Xp, (TN*)j.w.xn, rho, status, split ? j.w.xmax : nullptr, st);
   hipLaunchKernelGGL(k_init_small, dim3(1), dim3(256), 0, st, pivots, o->r, k_out, j.w.nT, j.w.stop);
   RPC_LAUNCH_CHECK();
   const int t = n_rounds(o);
@@ -1844,8 +1869,7 @@ static int run_factor_lowmem(const rpc_points* X, const rpc_factor_opts* o, doub
   clear((double*)w.FS, (int64_t)MAXB * R);
   clear((double*)w.FSa, (int64_t)MAXB * R);
   hipLaunchKernelGGL(k_lm_init, dim3(1), dim3(256), 0, st, l.pads, t, sw, l.zero);
-  hipLaunchKernelGGL((k_prep<T, TN>), dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, X->X, N,
-                     X->d, X->ldx, dp, (T*)w.Xp, (TN*)w.xn, rho, status, nullptr);
+  launch_prep<T, TN>(X, dp, (T*)w.Xp, (TN*)w.xn, rho, status, nullptr, st);
   hipLaunchKernelGGL(k_init_small, dim3(1), dim3(256), 0, st, pivots, o->r, k_out, w.nT, w.stop);
   RPC_LAUNCH_CHECK();
   constexpr size_t smC0 = DirectSmem<CfgK, cols_stages<T>(), true, true>::bytes;
@@ -2017,8 +2041,7 @@ static int run_factor_group(const rpc_points* X, const double* eps, const rpc_fa
   const int64_t N = X->N;
   const int64_t dp = shared.dp;
   // the points are converted once; every job starts from rho = 1
-  hipLaunchKernelGGL((k_prep<T, TN>), dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, X->X, N,
-                     X->d, X->ldx, dp, (T*)shared.Xp, (TN*)shared.xn, rho[0], status[0], nullptr);
+  launch_prep<T, TN>(X, dp, (T*)shared.Xp, (TN*)shared.xn, rho[0], status[0], nullptr, st);
   for (int g = 0; g < G; ++g) {
     if (g > 0) {
       hipLaunchKernelGGL(k_fill_rho, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, rho[g], N);
@@ -2062,6 +2085,7 @@ static int run_factor_group(const rpc_points* X, const double* eps, const rpc_fa
 
 static int check_factor_args(const rpc_points* X, const rpc_factor_opts* o) {
   if (!X || !o || !X->X) return RPC_EINVAL;
+  if (X->dtype != RPC_F32 && X->dtype != RPC_F64 && X->dtype != RPC_BF16) return RPC_EINVAL;
   if (X->N < 1 || X->d < 1 || X->ldx < X->d || !(X->eps > 0.0)) return RPC_EINVAL;
   if (o->r < 1 || o->r > X->N || o->b < 1 || o->b > MAXB) return RPC_EINVAL;
   if (o->mode == RPC_GREEDY && o->b != 1) return RPC_EINVAL;

@@ -187,7 +187,14 @@ int issue_job(const rpc_job* j, void* ws, size_t wsb, hipStream_t s) {
 }
 
 // Fork onto the pool streams, issue every job, join back into `origin`.
+// Keeps bistoch_eig from blocking the issuing thread while jobs are issued.
+struct NoHostGate {
+  NoHostGate() { rpc_internal::set_host_gate_off(true); }
+  ~NoHostGate() { rpc_internal::set_host_gate_off(false); }
+};
+
 int issue_all(const rpc_job* jobs, int n, int ns, void* ws, size_t wsb, hipStream_t origin) {
+  NoHostGate no_gate;
   if (!jobs || n < 1 || ns < 1 || ns > MAX_STREAMS) return RPC_EINVAL;
   for (int i = 0; i < n; ++i)
     if (!jobs[i].dev_status) return RPC_EINVAL;
@@ -236,11 +243,6 @@ int issue_all(const rpc_job* jobs, int n, int ns, void* ws, size_t wsb, hipStrea
 
 }  // namespace
 
-struct rpc_graph_s {
-  hipGraph_t graph;
-  hipGraphExec_t exec;
-};
-
 extern "C" {
 
 int rpc_job_workspace_size(const rpc_job* job, size_t* bytes) {
@@ -288,19 +290,23 @@ int rpc_batched_graph_create(const rpc_job* jobs, int32_t n_jobs, int32_t n_stre
   return RPC_OK;
 }
 
-int rpc_batched_graph_launch(rpc_graph g, rpc_stream_t stream) {
+int rpc_graph_launch(rpc_graph g, rpc_stream_t stream) {
   if (!g) return RPC_EINVAL;
   RPC_HIP_CHECK(hipGraphLaunch(g->exec, reinterpret_cast<hipStream_t>(stream)));
   return RPC_OK;
 }
 
-int rpc_batched_graph_destroy(rpc_graph g) {
+int rpc_graph_destroy(rpc_graph g) {
   if (!g) return RPC_EINVAL;
   hipGraphExecDestroy(g->exec);
   hipGraphDestroy(g->graph);
   delete g;
   return RPC_OK;
 }
+
+int rpc_batched_graph_launch(rpc_graph g, rpc_stream_t stream) { return rpc_graph_launch(g, stream); }
+
+int rpc_batched_graph_destroy(rpc_graph g) { return rpc_graph_destroy(g); }
 
 int rpc_autotune_block(const rpc_job* job, const int32_t* candidates, int32_t n_candidates,
                        int32_t reps, void* workspace, size_t workspace_bytes, rpc_stream_t stream,

@@ -846,22 +846,41 @@ struct LmRows {
   }
   // pivot points, L with the identity beyond k, and T = L^{-T} zeroed beyond k
   void setup(hipStream_t st) const {
-    hipLaunchKernelGGL((k_gather_pivots<double>), dim3(r), dim3(256), 0, st, X->X, X->ldx, X->d, dp,
-                       piv, k, FSlm, ldfs, r, XS, xsn, FS, 1);
+    with_points_type(X->dtype, [&](auto* tx) {
+      typedef typename std::remove_const<typename std::remove_pointer<decltype(tx)>::type>::type TX;
+      hipLaunchKernelGGL((k_gather_pivots<double, TX>), dim3(r), dim3(256), 0, st, (const TX*)X->X,
+                         X->ldx, X->d, dp, piv, k, FSlm, ldfs, r, XS, xsn, FS, 1);
+      return (int)RPC_OK;
+    });
     hipLaunchKernelGGL(k_fill_identity, dim3(nblk((int64_t)r * r)), dim3(256), 0, st, T, r, r);
     dense::trsm_lt(st, FS, r, r, T, r, r);
     hipLaunchKernelGGL(k_zero_beyond_k, dim3(nblk((int64_t)r * r)), dim3(256), 0, st, T, r, k);
   }
   // Fb (m x r, leading dimension m) = rows m0 .. m0 + m - 1 of the factor
   void rows(hipStream_t st, int64_t m0, int64_t m) const {
-    hipLaunchKernelGGL(k_prep_rows64, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st,
-                       X->X + m0 * X->ldx, X->ldx, m, X->d, dp, Yp, yn, status);
+    with_points_type(X->dtype, [&](auto* tx) {
+      typedef typename std::remove_const<typename std::remove_pointer<decltype(tx)>::type>::type TX;
+      hipLaunchKernelGGL((k_prep_rows64<TX>), dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st,
+                         (const TX*)X->X + m0 * X->ldx, X->ldx, m, X->d, dp, Yp, yn, status);
+      return (int)RPC_OK;
+    });
     hipLaunchKernelGGL(k_cross_kernel, dim3((unsigned)((m + 63) / 64), (unsigned)((r + 63) / 64)),
                        dim3(256), 0, st, (const double*)Yp, (const double*)yn, m, dp,
                        (const double*)XS, (const double*)xsn, r, X->eps, Kb, m);
     dense::gemm64<false, true>(st, m, r, r, Kb, m, T, r, Fb, m, 1.0, 0.0);
   }
 };
+
+// Whether the eigensolver may synchronise `st` to read its convergence flag:
+// not while the stream is being captured into a graph, and not while the
+// batched form issues jobs (it must never block its issuing thread).
+thread_local int t_host_gate_off = 0;
+static bool host_gate_allowed(hipStream_t st) {
+  if (t_host_gate_off) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
+  return cs == hipStreamCaptureStatusNone;
+}
 
 // Orthonormalise the r x p block Y into Q by Cholesky QR (Gram, one-workgroup
 // Cholesky, row-parallel triangular solve).
@@ -1044,17 +1063,32 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
       hipLaunchKernelGGL(k_ritz_check, dim3(1), dim3(1024), 0, st, (const double*)w.T1,
                          (const double*)w.Q, (const double*)w.theta, r, nev, 1e-10, w.conv);
     };
+    // Outside stream capture and the batched form, the convergence flag is
+    // read back to the host after each Rayleigh-Ritz step (one stream
+    // synchronisation each), so the retries and the restart below are issued
+    // only when needed; otherwise they are issued unconditionally and every
+    // launch returns at once once `conv` is set.
+    const bool gate = host_gate_allowed(st);
+    auto converged = [&]() -> bool {
+      int32_t h = 0;
+      if (hipMemcpyAsync(&h, w.conv, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return false;
+      if (hipStreamSynchronize(st) != hipSuccess) return false;
+      return h != 0;
+    };
+    bool conv_host = false;
     const int max_rr = 4;
-    for (int it = 0; it < max_rr; ++it) {
+    for (int it = 0; it < max_rr && !conv_host; ++it) {
       if (it > 0) products(6);
       rayleigh_ritz();
       if (it == 0)
         hipLaunchKernelGGL(k_shift_down, dim3(1), dim3(1024), 0, st, w.M, r, (const double*)w.theta,
                            p, w.delta, (const int32_t*)w.conv);
+      if (gate) conv_host = converged();
     }
     // not converged: spectral-projector restart (every launch below returns
     // at once when conv is set)
     const unsigned grr2 = nblk((int64_t)r * r);
+    if (!conv_host) {
     const dim3 gt((unsigned)((r + 63) / 64), (unsigned)((r + 63) / 64));
     hipLaunchKernelGGL(k_fb_setup, dim3(1), dim3(64), 0, st, (const double*)w.theta, p, nev,
                        (const double*)w.delta, (const int32_t*)w.conv, w.fbp, w.nsdone, w.nsfinal,
@@ -1079,6 +1113,7 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
     hipLaunchKernelGGL(k_copy_cols, dim3(grr2), dim3(256), 0, st, (const double*)w.Mc, (int64_t)r,
                        w.M, (int64_t)r, r, r, (const int32_t*)w.conv);
     rayleigh_ritz();
+    }
     hipLaunchKernelGGL(k_unshift, dim3(1), dim3(128), 0, st, w.theta, p, (const double*)w.delta);
     hipLaunchKernelGGL(k_flag_noconv, dim3(1), dim3(1), 0, st, (const int32_t*)w.conv, status);
     hipLaunchKernelGGL(k_copy_cols, dim3(nblk((int64_t)r * nev)), dim3(256), 0, st,
@@ -1388,6 +1423,7 @@ size_t carve_lm(WsCursor& c, LmLayout& l, int64_t N, int64_t d, int r, int64_t b
 }
 int check_lm_args(const rpc_points* X, int r, const rpc_eig_opts* o, int64_t block_rows) {
   if (!X || !X->X || X->N < 1 || X->d < 1 || X->ldx < X->d || !(X->eps > 0.0)) return RPC_EINVAL;
+  if (X->dtype != RPC_F32 && X->dtype != RPC_F64 && X->dtype != RPC_BF16) return RPC_EINVAL;
   int rc = check_eig_opts(X->N, r, o);
   if (rc) return rc;
   if (o->gram_dtype != RPC_F64 || o->qr_mode != RPC_QR_CHOLQR) return RPC_EINVAL;
@@ -1490,3 +1526,7 @@ extern "C" int bistoch_eig(const void* F, int32_t fdt, int64_t N, int64_t ldf, i
   }
 #undef RPC_EIG_CALL
 }
+
+namespace rpc_internal {
+void set_host_gate_off(bool off) { t_host_gate_off = off ? 1 : 0; }
+}  // namespace rpc_internal

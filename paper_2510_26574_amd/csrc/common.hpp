@@ -90,6 +90,12 @@ __device__ inline double to_d(T x) { return (double)x; }
 template <>
 __device__ inline double to_d<__bf16>(__bf16 x) { return (double)(float)x; }
 
+// element i of a points row of element type TX, as float64 (exact)
+template <typename TX>
+__device__ inline double ld_point(const TX* __restrict__ p, int64_t i) {
+  return to_d(p[i]);
+}
+
 // Split of two float32 values into fp16 pairs: hi = fp16(v) (round to
 // nearest, one packed conversion for both), lo = fp16(v - hi) by one
 // mixed-precision fma per value (v - hi is exact in float32, so hi + lo
@@ -158,6 +164,30 @@ struct WsCursor {
     return reinterpret_cast<T*>(base + off);
   }
 };
+
+// Calls f((TX*)nullptr) with TX the element type of points of rpc_dtype
+// `dt` (float, double or __bf16); RPC_EINVAL for any other type.
+template <typename Fn>
+inline int with_points_type(int32_t dt, Fn&& f) {
+  if (dt == RPC_F32) return f((const float*)nullptr);
+  if (dt == RPC_F64) return f((const double*)nullptr);
+  if (dt == RPC_BF16) return f((const __bf16*)nullptr);
+  return RPC_EINVAL;
+}
+
+// A captured and instantiated HIP graph (rpc_graph of the C-ABI).
+struct rpc_graph_s {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+namespace rpc_internal {
+// The batched form issues many jobs from one host thread and must never block
+// it: while set on the calling thread, bistoch_eig issues the fallback
+// launches of its eigensolver unconditionally instead of reading the
+// convergence flag back to the host.
+void set_host_gate_off(bool off);
+}  // namespace rpc_internal
 
 #define RPC_HIP_CHECK(expr)                    \
   do {                                         \

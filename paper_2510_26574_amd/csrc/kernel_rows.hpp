@@ -14,8 +14,8 @@ namespace {
 // FS (r x r column-major) = F(S, :) on the leading k x k block, identity beyond.
 // F is the N x r factor (row of pivot i at piv[i]) or, with `pivot_rows`, the
 // r x r F(S, :) of the low-memory form (row of pivot i at i).
-template <typename TF>
-__global__ __launch_bounds__(256) void k_gather_pivots(const float* __restrict__ X, int64_t ldx,
+template <typename TF, typename TX>
+__global__ __launch_bounds__(256) void k_gather_pivots(const TX* __restrict__ X, int64_t ldx,
                                                        int64_t d, int64_t dp,
                                                        const int64_t* __restrict__ piv,
                                                        const int32_t* kptr,
@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void k_gather_pivots(const float* __restrict__
   double s = 0.0;
   const int64_t p = i < k ? piv[i] : -1;
   for (int64_t c = threadIdx.x; c < dp; c += 256) {
-    const double v = (p >= 0 && c < d) ? (double)X[p * ldx + c] : 0.0;
+    const double v = (p >= 0 && c < d) ? ld_point(X, p * ldx + c) : 0.0;
     XS[(int64_t)i * dp + c] = v;
     s += v * v;
   }
@@ -48,7 +48,8 @@ __global__ __launch_bounds__(256) void k_gather_pivots(const float* __restrict__
   }
 }
 
-__global__ __launch_bounds__(256) void k_prep_rows64(const float* __restrict__ Y, int64_t ldy,
+template <typename TX>
+__global__ __launch_bounds__(256) void k_prep_rows64(const TX* __restrict__ Y, int64_t ldy,
                                                      int64_t m, int64_t d, int64_t dp,
                                                      double* __restrict__ Yp,
                                                      double* __restrict__ yn, int32_t* status) {
@@ -58,10 +59,10 @@ __global__ __launch_bounds__(256) void k_prep_rows64(const float* __restrict__ Y
   double s = 0.0;
   bool bad = false;
   for (int64_t j = lane; j < dp; j += 64) {
-    const float v = j < d ? Y[n * ldy + j] : 0.0f;
+    const double v = j < d ? ld_point(Y, n * ldy + j) : 0.0;
     if (!isfinite(v)) bad = true;
-    Yp[n * dp + j] = (double)v;
-    s += (double)v * (double)v;
+    Yp[n * dp + j] = v;
+    s += v * v;
   }
   s = wave_sum(s);
   if (__any(bad) && lane == 0) set_status(status, RPC_ENONFINITE);

@@ -13,6 +13,8 @@
 // with E'.  Everything is float64.
 #include <math.h>
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "dense.hpp"
 #include "profile.hpp"
@@ -75,16 +77,24 @@ static int run_nys(const rpc_points* Y, const rpc_points* X, const int64_t* piv,
   carve_nys(cur, w, Y->N, Y->d, r, nev);
   if (!cur.ok) return RPC_EWORKSPACE;
   prof::begin(prof::NYSTROM, st);
-  hipLaunchKernelGGL((k_gather_pivots<TF>), dim3(r), dim3(256), 0, st, X->X, X->ldx, X->d, w.dp, piv,
-                     k, F, ldf, r, w.XS, w.xsn, w.FS, pivot_rows);
+  with_points_type(X->dtype, [&](auto* tx) {
+    typedef typename std::remove_const<typename std::remove_pointer<decltype(tx)>::type>::type TX;
+    hipLaunchKernelGGL((k_gather_pivots<TF, TX>), dim3(r), dim3(256), 0, st, (const TX*)X->X, X->ldx,
+                       X->d, w.dp, piv, k, F, ldf, r, w.XS, w.xsn, w.FS, pivot_rows);
+    return (int)RPC_OK;
+  });
   hipLaunchKernelGGL(k_rhs, dim3((unsigned)(((int64_t)r * (nev + 1) + 255) / 256)), dim3(256), 0, st,
                      c, E, r, nev, k, w.B0);
   dense::trsm_lt(st, w.FS, r, r, w.B0, r, nev + 1);
   RPC_LAUNCH_CHECK();
   for (int64_t m0 = 0; m0 < Y->N; m0 += w.mch) {
     const int64_t m = Y->N - m0 < w.mch ? Y->N - m0 : w.mch;
-    hipLaunchKernelGGL(k_prep_rows64, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st,
-                       Y->X + m0 * Y->ldx, Y->ldx, m, Y->d, w.dp, w.Yp, w.yn, status);
+    with_points_type(Y->dtype, [&](auto* ty) {
+      typedef typename std::remove_const<typename std::remove_pointer<decltype(ty)>::type>::type TY;
+      hipLaunchKernelGGL((k_prep_rows64<TY>), dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st,
+                         (const TY*)Y->X + m0 * Y->ldx, Y->ldx, m, Y->d, w.dp, w.Yp, w.yn, status);
+      return (int)RPC_OK;
+    });
     hipLaunchKernelGGL(k_cross_kernel, dim3((unsigned)((m + 63) / 64), (unsigned)((r + 63) / 64)),
                        dim3(256), 0, st, (const double*)w.Yp, (const double*)w.yn, m, w.dp,
                        (const double*)w.XS, (const double*)w.xsn, r, X->eps, w.K, m);
@@ -116,6 +126,8 @@ static int nystrom_any(const rpc_points* Y, const rpc_points* X, const int64_t* 
   if (!Y || !X || !Y->X || !X->X || !pivots || !k || !F || !c || !E || !Phi || !status)
     return RPC_EINVAL;
   if (Y->N < 1 || Y->d != X->d || Y->ldx < Y->d || X->ldx < X->d || !(X->eps > 0.0)) return RPC_EINVAL;
+  for (const rpc_points* P : {X, Y})
+    if (P->dtype != RPC_F32 && P->dtype != RPC_F64 && P->dtype != RPC_BF16) return RPC_EINVAL;
   if (r < 1 || r > X->N || nev < 1 || nev > r || ldf < (pivot_rows ? r : X->N) || ldphi < Y->N)
     return RPC_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);

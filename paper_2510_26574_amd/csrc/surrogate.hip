@@ -307,12 +307,20 @@ __global__ __launch_bounds__(256) void k_sur_wgrad(const __bf16* __restrict__ dY
 
 // Sum the split partials (fixed order) and apply AdamW to the entries the
 // phase trains; c1 = 1/(1 - beta1^t), c2 = 1/(1 - beta2^t).
+// tdev (optional): the step number is tdev[0] + 1 and c1, c2 follow from it
+// here (a captured epoch replays with the counter kept in device memory).
 __global__ void k_sur_adamw(Lay L, int phase, int S, const float* __restrict__ part,
                             float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
                             __bf16* __restrict__ wb, float* __restrict__ grad, double lr,
-                            double b1, double b2, double eps, double wd, double c1, double c2) {
+                            double b1, double b2, double eps, double wd, double c1, double c2,
+                            const int64_t* __restrict__ tdev) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= L.total) return;
+  if (tdev) {
+    const double t = (double)(tdev[0] + 1);
+    c1 = 1.0 / (1.0 - pow(b1, t));
+    c2 = 1.0 / (1.0 - pow(b2, t));
+  }
   const int cls = entry_class(L, i);
   const bool tr = (phase == 0 && cls == 1) || (phase == 1 && cls == 2);
   if (!tr) {
@@ -332,6 +340,8 @@ __global__ void k_sur_adamw(Lay L, int phase, int S, const float* __restrict__ p
   p[i] = (float)pn;
   wb[i] = (__bf16)(float)pn;
 }
+
+__global__ void k_sur_step_inc(int64_t* t) { t[0] += 1; }
 
 // loss = scale * sum(part[0..n)) in float64, one workgroup.
 __global__ __launch_bounds__(256) void k_sur_loss(const float* __restrict__ part, int n,
@@ -635,6 +645,14 @@ int surrogate_train_workspace_size(const sur_shape* shape, int64_t batch, int32_
   return RPC_OK;
 }
 
+static int train_step_impl(const sur_shape* shape, const sur_train_opts* o, const float* X,
+                           int64_t ldx, int64_t N, const double* mean, const double* rstd,
+                           const int64_t* idx, int64_t batch, const void* T, int32_t t_dtype,
+                           int64_t ldt, double tscale, float* params, float* adam_m,
+                           float* adam_v, uint16_t* wbf16, float* grad, double* loss,
+                           void* workspace, size_t workspace_bytes, int32_t* dev_status,
+                           rpc_stream_t stream, int64_t* tdev);
+
 int surrogate_train_step(const sur_shape* shape, const sur_train_opts* o, const float* X,
                          int64_t ldx, int64_t N, const double* mean, const double* rstd,
                          const int64_t* idx, int64_t batch, const void* T, int32_t t_dtype,
@@ -642,6 +660,18 @@ int surrogate_train_step(const sur_shape* shape, const sur_train_opts* o, const 
                          float* adam_v, uint16_t* wbf16, float* grad, double* loss,
                          void* workspace, size_t workspace_bytes, int32_t* dev_status,
                          rpc_stream_t stream) {
+  return train_step_impl(shape, o, X, ldx, N, mean, rstd, idx, batch, T, t_dtype, ldt, tscale,
+                         params, adam_m, adam_v, wbf16, grad, loss, workspace, workspace_bytes,
+                         dev_status, stream, nullptr);
+}
+
+static int train_step_impl(const sur_shape* shape, const sur_train_opts* o, const float* X,
+                           int64_t ldx, int64_t N, const double* mean, const double* rstd,
+                           const int64_t* idx, int64_t batch, const void* T, int32_t t_dtype,
+                           int64_t ldt, double tscale, float* params, float* adam_m,
+                           float* adam_v, uint16_t* wbf16, float* grad, double* loss,
+                           void* workspace, size_t workspace_bytes, int32_t* dev_status,
+                           rpc_stream_t stream, int64_t* tdev) {
   Lay L;
   if (!o || !make_layout(shape, L)) return RPC_EINVAL;
   const int S = norm_splits(o->splits);
@@ -701,7 +731,8 @@ int surrogate_train_step(const sur_shape* shape, const sur_train_opts* o, const 
   const double c1 = 1.0 / (1.0 - pow(o->beta1, t)), c2 = 1.0 / (1.0 - pow(o->beta2, t));
   hipLaunchKernelGGL(k_sur_adamw, dim3(nblk(L.total)), dim3(256), 0, st, L, ph, S,
                      (const float*)w.part, params, adam_m, adam_v, wb, grad, o->lr, o->beta1,
-                     o->beta2, o->eps, o->weight_decay, c1, c2);
+                     o->beta2, o->eps, o->weight_decay, c1, c2, (const int64_t*)tdev);
+  if (tdev) hipLaunchKernelGGL(k_sur_step_inc, dim3(1), dim3(1), 0, st, tdev);
   if (loss) {
     const double ls = ph == 0 ? 1.0 / ((double)B * L.nout) : 1.0 / (double)B;
     hipLaunchKernelGGL(k_sur_loss, dim3(1), dim3(256), 0, st, (const float*)w.lpart, w.nlp, ls,
@@ -731,6 +762,43 @@ int surrogate_train_epoch(const sur_shape* shape, const sur_train_opts* o, const
                                         dev_status, stream);
     if (rc != RPC_OK) return rc;
   }
+  return RPC_OK;
+}
+
+int surrogate_train_graph_create(const sur_shape* shape, const sur_train_opts* o, const float* X,
+                                 int64_t ldx, int64_t N, const double* mean, const double* rstd,
+                                 const int64_t* idx, int64_t n_idx, int64_t batch, const void* T,
+                                 int32_t t_dtype, int64_t ldt, double tscale, float* params,
+                                 float* adam_m, float* adam_v, uint16_t* wbf16, double* loss,
+                                 int64_t* step_counter, void* workspace, size_t workspace_bytes,
+                                 int32_t* dev_status, rpc_stream_t stream, rpc_graph* out) {
+  if (!out || !stream || !o || !idx || !step_counter || n_idx < 1 || batch < 1 || prof::enabled())
+    return RPC_EINVAL;
+  *out = nullptr;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  RPC_HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  sur_train_opts so = *o;
+  so.step = 1;  // checked only; the step number comes from step_counter
+  int rc = RPC_OK;
+  int64_t s = 0;
+  for (int64_t b0 = 0; b0 < n_idx && rc == RPC_OK; b0 += batch, ++s) {
+    const int64_t nb = n_idx - b0 < batch ? n_idx - b0 : batch;
+    rc = train_step_impl(shape, &so, X, ldx, N, mean, rstd, idx + b0, nb, T, t_dtype, ldt, tscale,
+                         params, adam_m, adam_v, wbf16, nullptr, loss ? loss + s : nullptr,
+                         workspace, workspace_bytes, dev_status, stream, step_counter);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &g);
+  if (rc != RPC_OK || e != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return rc != RPC_OK ? rc : RPC_EHIP;
+  }
+  hipGraphExec_t x = nullptr;
+  if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(g);
+    return RPC_EHIP;
+  }
+  *out = new rpc_graph_s{g, x};
   return RPC_OK;
 }
 
@@ -829,8 +897,9 @@ int surrogate_extend(const sur_shape* shape, const float* params, const uint16_t
                      rpc_stream_t stream) {
   Lay L;
   if (!make_layout(shape, L) || !Y || !X || !Y->X || !n_fallback || !Phi || Y->d != L.d ||
-      X->d != L.d || nev < L.nout || Y->N < 0 || ldphi < Y->N)
+      X->d != L.d || nev < L.nout || Y->N < 0 || ldphi < Y->N || Y->dtype != RPC_F32)
     return RPC_EINVAL;
+  const float* Yx = static_cast<const float*>(Y->X);
   const int64_t M = Y->N;
   *n_fallback = 0;
   if (M == 0) return RPC_OK;
@@ -841,7 +910,7 @@ int surrogate_extend(const sur_shape* shape, const float* params, const uint16_t
   if (!cur.ok) return RPC_EWORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   float* rs = res ? res : w.res;
-  rc = run_infer(L, params, reinterpret_cast<const __bf16*>(wbf16), Y->X, Y->ldx, M, mean, rstd,
+  rc = run_infer(L, params, reinterpret_cast<const __bf16*>(wbf16), Yx, Y->ldx, M, mean, rstd,
                  Phi, ldphi, rs, w.inf, dev_status, st);
   if (rc != RPC_OK) return rc;
   const int64_t nb = (M + 1023) / 1024;
@@ -858,10 +927,10 @@ int surrogate_extend(const sur_shape* shape, const float* params, const uint16_t
   *n_fallback = nf;
   for (int64_t f0 = 0; f0 < nf; f0 += FB_CHUNK) {
     const int64_t n = nf - f0 < FB_CHUNK ? nf - f0 : FB_CHUNK;
-    hipLaunchKernelGGL(k_gather_rows, dim3(nblk(n * L.d)), dim3(256), 0, st, Y->X, Y->ldx,
+    hipLaunchKernelGGL(k_gather_rows, dim3(nblk(n * L.d)), dim3(256), 0, st, Yx, Y->ldx,
                        (int64_t)L.d, (const int64_t*)(w.list + f0), n, w.Yf);
     RPC_LAUNCH_CHECK();
-    rpc_points Yc{n, (int64_t)L.d, (int64_t)L.d, w.Yf, Y->eps};
+    rpc_points Yc{n, (int64_t)L.d, (int64_t)L.d, w.Yf, Y->eps, RPC_F32};
     rc = nystrom_extend(&Yc, X, pivots, k, F, f_dtype, ldf, r, c, ext_E, nev, w.Pn, n, w.nws,
                         w.nws_bytes, dev_status, stream);
     if (rc != RPC_OK) return rc;

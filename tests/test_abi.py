@@ -65,6 +65,11 @@ def test_host_side_validation(lib):
         for k, v in kw.items():
             setattr(o, k, v)
         assert lib.rpchol_factor_workspace_size(ctypes.byref(pts), ctypes.byref(o), ctypes.byref(nb)) == rp.RPC_EINVAL, kw
+    p3 = rp.rpc_points(100, 3, 3, 0x1000, 1.0, 3)  # points dtype: f32, f64 or bf16 only
+    assert lib.rpchol_factor_workspace_size(ctypes.byref(p3), ctypes.byref(opts), ctypes.byref(nb)) == -1
+    for dt in (0, 1, 2):
+        p4 = rp.rpc_points(100, 3, 3, 0x1000, 1.0, dt)
+        assert lib.rpchol_factor_workspace_size(ctypes.byref(p4), ctypes.byref(opts), ctypes.byref(nb)) == 0
     p2 = rp.rpc_points(100, 3, 3, 0x1000, 0.0)  # eps <= 0
     assert lib.rpchol_factor_workspace_size(ctypes.byref(p2), ctypes.byref(opts), ctypes.byref(nb)) == rp.RPC_EINVAL
     eo = rp.rpc_eig_opts(200, 0, 0, 0, 0, 0, 0.0)  # nev > r

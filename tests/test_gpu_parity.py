@@ -634,3 +634,44 @@ def test_eig_cholqr2(gpu, r, b, nev, gamma, norm):
     Bp = F[:, :k] / (d if norm == "bistochastic" else np.sqrt(d))[:, None]
     Bp[np.arange(k), np.arange(k)] += gamma
     assert np.abs(Bp @ eig["E"].cpu().numpy()[:k] - U).max() < 1e-8
+
+
+@pytest.mark.parametrize("pdt", ["f64", "bf16"])
+def test_point_dtypes(gpu, pdt):
+    """Points stored as float64 (values float32 cannot hold) or bf16: the
+    float64 path sees the stored values exactly, so pivots, F, the degrees and
+    the eigenpairs match the oracle run on the same values, and the Nystrom
+    extension of new points of the same type matches the oracle's."""
+    torch, rp = gpu
+    X32 = torus_points(1500, seed=17)
+    if pdt == "f64":
+        Xh = X32.astype(np.float64) + np.random.default_rng(17).normal(scale=1e-6, size=X32.shape)
+        assert np.abs(Xh - Xh.astype(np.float32)).max() > 0
+        Xd = torch.from_numpy(Xh).cuda()
+    else:
+        Xd = torch.from_numpy(X32).cuda().to(torch.bfloat16)
+        Xh = Xd.double().cpu().numpy()
+    eps = median_sq_distance(Xh, seed=17)
+    r, b, nev = 64, 8, 12
+    u = uniform_stream(2 * b * (r // b), seed=17)
+    ref = oracle.arpc(Xh, eps, r=r, b=b, mode="sampled", uniforms=u)
+    out = rp.rpchol_factor(Xd, eps, r, b, uniforms=torch.from_numpy(u).cuda())
+    deg = rp.bistoch_degrees(out["F"], out["k"], status=out["status"])
+    eig = rp.bistoch_eig(out["F"], out["k"], deg["d"], deg["q"], nev, status=out["status"])
+    assert rp.status_sync(out["status"]) == 0
+    k = int(out["k"].item())
+    assert k == ref["k"] and list(out["pivots"][:k].cpu().numpy()) == list(ref["S"])
+    F = out["F"][:, :k].cpu().numpy()
+    assert np.abs(F - ref["F"]).max() < 1e-12 * np.abs(ref["F"]).max()
+    res = oracle.bistoch_eig(ref["F"], nev)
+    assert np.abs(eig["lam"].cpu().numpy() / res["lam"] - 1).max() < 1e-10
+    assert _angle(eig["U"].cpu().numpy(), res["U"]) < 1e-8
+    Y32 = torus_points(300, seed=18)
+    Yd = torch.from_numpy(Y32.astype(np.float64)).cuda() if pdt == "f64" else \
+        torch.from_numpy(Y32).cuda().to(torch.bfloat16)
+    Yh = Yd.double().cpu().numpy()
+    ext = rp.nystrom_extend(Yd, Xd, eps, out["pivots"], out["k"], out["F"], deg["c"], eig["E"])
+    assert rp.status_sync(ext["status"]) == 0
+    Phi_o = oracle.nystrom_extend(Yh, Xh, ref["S"], ref["F"], res["c"], res["E"], eps)
+    Phi = ext["Phi"].cpu().numpy()
+    assert np.abs(Phi - Phi_o).max() < 1e-9 * np.abs(Phi_o).max()

@@ -442,3 +442,39 @@ def test_surrogate_gain_at_matched_accuracy(gpu):
     print(f"cheapest decomposition at least as accurate as the network: rank {r_m} (error "
           f"{nys[r_m][0]:.4f} <= {e_net:.4f}); the network extends {gain:.2f}x faster")
     assert gain > 1.0
+
+
+def test_train_epochs_graph_equals_eager(gpu):
+    """Epochs replayed from one captured graph (the step number kept in device
+    memory, the permutation copied into the graph's index buffer between
+    replays) equal eager train_epoch calls bit for bit: parameters, moments
+    and every step's loss of every replay."""
+    torch, rp = gpu
+    a = _setup(gpu, N=1500, seed=21)
+    b = _setup(gpu, N=1500, seed=21)
+    rng = np.random.default_rng(4)
+    E, batch = 3, 256
+    perms = np.stack([rng.permutation(1500) for _ in range(E)]).astype(np.int64)
+    spe = -(-1500 // batch)
+    loss_g = torch.zeros(E * spe, dtype=torch.float64, device="cuda")
+    a["sur"].train_epochs(a["dev"]["X"], a["dev"]["mu"], a["dev"]["rs"], torch.from_numpy(perms).cuda(),
+                          a["dev"]["T"], batch, loss=loss_g)
+    loss_e = torch.zeros(E * spe, dtype=torch.float64, device="cuda")
+    for e in range(E):
+        b["sur"].train_epoch(b["dev"]["X"], b["dev"]["mu"], b["dev"]["rs"],
+                             torch.from_numpy(perms[e].copy()).cuda(), b["dev"]["T"], batch,
+                             loss=loss_e[e * spe:(e + 1) * spe])
+        torch.cuda.synchronize()
+    assert a["sur"].steps[0] == b["sur"].steps[0] == E * spe
+    assert torch.equal(a["sur"].params, b["sur"].params)
+    assert torch.equal(a["sur"].m, b["sur"].m) and torch.equal(a["sur"].v, b["sur"].v)
+    assert torch.equal(a["sur"].wbf16, b["sur"].wbf16)
+    assert torch.equal(loss_g, loss_e)
+    # a second call continues the bias correction from the device step counter
+    more = np.stack([rng.permutation(1500) for _ in range(2)]).astype(np.int64)
+    a["sur"].train_epochs(a["dev"]["X"], a["dev"]["mu"], a["dev"]["rs"], torch.from_numpy(more).cuda(),
+                          a["dev"]["T"], batch)
+    for e in range(2):
+        b["sur"].train_epoch(b["dev"]["X"], b["dev"]["mu"], b["dev"]["rs"],
+                             torch.from_numpy(more[e].copy()).cuda(), b["dev"]["T"], batch)
+    assert torch.equal(a["sur"].params, b["sur"].params)
