@@ -362,13 +362,16 @@ def low_memory_pipeline(rp, torch, Xd, eps, ud, w):
     Qa, _ = np.linalg.qr(res["U"].cpu().numpy())
     Qb, _ = np.linalg.qr(eig["U"].cpu().numpy())
     ang = float(np.linalg.norm(Qb - Qa @ (Qa.T @ Qb), 2))
-    nbytes = (fac["Fbuf"].numel() * 8 + fac["workspace"].numel() + res["workspace"].numel()
-              + (res["c"].numel() + res["d"].numel() + res["q"].numel()) * 8
-              + res["U"].numel() * 8)
+    vec_bytes = (res["c"].numel() + res["d"].numel() + res["q"].numel()) * 8 + res["U"].numel() * 8
+    nbytes = fac["Fbuf"].numel() * 8 + fac["workspace"].numel() + res["workspace"].numel() + vec_bytes
     full_F = ref["Fbuf"].numel() * 8
+    # the same plain float64 method with the full factor: factor, its
+    # workspace and the eigen workspace (the degree workspace is smaller)
+    full_total = full_F + ref["workspace"].numel() + eig["workspace"].numel() + vec_bytes
     del ref, deg, eig
     return {"ms": dt * 1e3, "k": k, "status": st, "status_full_replay": st_ref,
             "device_bytes": int(nbytes), "full_factor_bytes": int(full_F),
+            "full_form_device_bytes": int(full_total),
             "lam_rel_err_vs_plain_fp64_replay": float(np.abs(lam / lam_f - 1).max()),
             "principal_angle_vs_plain_fp64_replay_rad": ang}
 
@@ -621,6 +624,9 @@ def bench_paper(args, rp, torch):
     # float32 noise floor are rejected (tau = 1e-6 max diag K, diag K = 1)
     printed = one(c["eps"] * c["J"], ("f32", "f32", "f32"), c["tau"], c["gamma"])
     printed64 = one(c["eps"] * c["J"], ("f64", "f64", "f64"), 0.0, c["gamma"])
+    # the same float32 factor with its Grams and QR in float64: separates the
+    # factor's own error from the float32 Gram's
+    printed_g64 = one(c["eps"] * c["J"], ("f32", "f32", "f64"), c["tau"], c["gamma"])
     eps_only = one(c["eps"], ("f32", "f32", "f32"), c["tau"], c["gamma"])
     line = {
         "metric": "paper workload (vector-valued KS delay embedding): seconds and trace error",
@@ -629,6 +635,7 @@ def bench_paper(args, rp, torch):
         "config": {"workload": f"VSA KS N*M={N} d=J={d} r={r} b={b} nev={c['nev']} gamma={c['gamma']}"},
         "kernel_eps_times_J": printed,
         "kernel_eps_times_J_float64": printed64,
+        "kernel_eps_times_J_float64_gram": printed_g64,
         "kernel_eps": eps_only,
         "paper_trace_error_context": {"value": c["trace_err"], "hardware": "1x NVIDIA A100 40 GiB, fp32",
                                       "note": "the authors' trajectory, random draws and regularised QR"},
@@ -773,6 +780,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the measurements beside the timed step (factor forms, low-memory "
+                         "pipeline, eight-bandwidth group, parity): for profiler runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--form", default="headline", choices=["headline", "surrogate", "batched", "paper"],
@@ -830,15 +840,17 @@ def main():
         roof_p, per_kernel_p = roofline(w, X.shape[1], res_p, prof_p, args.steps, plain)
     log("[bench] kernel columns alone (unfused path)")
     kcols = kernel_columns(rp, torch, Xd, eps, ud, w, X.shape[1], args.steps)
-    log("[bench] kernel columns of eight bandwidths per X pass (group)")
-    kgroup = kernel_columns_group(rp, torch, Xd, eps, w, X.shape[1])
-    log("[bench] factorisation product forms")
-    forms = factor_forms(rp, torch, Xd, eps, ud, w)
-    log("[bench] low-memory pipeline (factor + Algorithm 1)")
-    lowmem = low_memory_pipeline(rp, torch, Xd, eps, ud, w)
-    log(f"[bench] low-memory pipeline {lowmem['ms']:.1f} ms")
-    log("[bench] parity check")
-    par = parity(rp, torch, Xd, eps, w, res_m)
+    kgroup = forms = lowmem = par = None
+    if not args.no_extras:
+        log("[bench] kernel columns of eight bandwidths per X pass (group)")
+        kgroup = kernel_columns_group(rp, torch, Xd, eps, w, X.shape[1])
+        log("[bench] factorisation product forms")
+        forms = factor_forms(rp, torch, Xd, eps, ud, w)
+        log("[bench] low-memory pipeline (factor + Algorithm 1)")
+        lowmem = low_memory_pipeline(rp, torch, Xd, eps, ud, w)
+        log(f"[bench] low-memory pipeline {lowmem['ms']:.1f} ms")
+        log("[bench] parity check")
+        par = parity(rp, torch, Xd, eps, w, res_m)
     cpu = None
     if not args.no_cpu:
         log("[bench] cpu oracle sample")

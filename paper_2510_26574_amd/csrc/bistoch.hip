@@ -1231,12 +1231,15 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   return RPC_OK;
 }
 
+// chunks of the partial column sums
+static int degree_chunks(int64_t N) { return (int)((N + COLCHUNK - 1) / COLCHUNK); }
+
 template <typename TF>
 static int run_degrees(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k, double* c,
                        double* dt, double* qt, void* ws, size_t ws_bytes, int32_t* status,
                        hipStream_t st) {
   WsCursor cur{(char*)ws, 0, ws_bytes, true};
-  const int nch = (int)((N + COLCHUNK - 1) / COLCHUNK);
+  const int nch = degree_chunks(N);
   double* part = cur.take<double>((size_t)nch * r);
   double* inv = cur.take<double>((size_t)N);
   double* wv = cur.take<double>((size_t)r);
@@ -1269,7 +1272,7 @@ static int run_degrees(const TF* F, int64_t N, int64_t ldf, int r, const int32_t
 static int run_degrees_lm(const LmRows& lm, int64_t N, int r, const int32_t* k, double* c,
                           double* dt, double* qt, double* part, double* inv, double* wv,
                           int32_t* status, hipStream_t st) {
-  const int nch = (int)((N + COLCHUNK - 1) / COLCHUNK);
+  const int nch = degree_chunks(N);
   const size_t sh = (size_t)r * sizeof(double);
   prof::begin(prof::DEGREES, st);
   for (int pass = 0; pass < 3; ++pass) {
@@ -1304,8 +1307,7 @@ static int run_degrees_lm(const LmRows& lm, int64_t N, int r, const int32_t* k, 
 
 static size_t degrees_ws(int64_t N, int r) {
   WsCursor c{nullptr, 0, 0, true};
-  const int nch = (int)((N + COLCHUNK - 1) / COLCHUNK);
-  c.take<double>((size_t)nch * r);
+  c.take<double>((size_t)degree_chunks(N) * r);
   c.take<double>((size_t)N);
   c.take<double>((size_t)r);
   return c.used;
