@@ -204,12 +204,13 @@ RPC_FACTOR_SPLIT_SOLVE = 8
 
 def rpchol_factor(X, eps, r, b, mode="sampled", uniforms=None, replay=None, gemm_dtype="f64",
                   factor_dtype="f64", tau=0.0, unfused=False, shared_x=False, low_memory=False,
-                  split_solve=False, status=None, stream=None):
+                  split_solve=False, status=None, stream=None, ldf=None):
     """Algorithm 2 on the Gaussian kernel of the rows of X (N x d float32, CUDA).
 
-    Returns dict: F (N x r view, column-major storage; with low_memory the
-    r x r factor rows F(S, :) of the pivots in pivot order), pivots (r int64),
-    rho (N float64), k (1 int32, device), status (1 int32, device).
+    Returns dict: F (N x r view, column-major storage with leading dimension
+    ldf, by default the row count rounded up to 8; with low_memory the r x r
+    factor rows F(S, :) of the pivots in pivot order), pivots (r int64), rho
+    (N float64), k (1 int32, device), status (1 int32, device).
     """
     torch = _torch()
     lib = load_library()
@@ -217,7 +218,7 @@ def rpchol_factor(X, eps, r, b, mode="sampled", uniforms=None, replay=None, gemm
     dev = X.device
     fdt = torch.float64 if factor_dtype == "f64" else torch.float32
     rows = r if low_memory else N
-    ldf = _ld(rows)
+    ldf = _ld(rows) if ldf is None else int(ldf)
     Fbuf = torch.empty((r, ldf), dtype=fdt, device=dev)
     piv = torch.empty(r, dtype=torch.int64, device=dev)
     rho = torch.empty(N, dtype=torch.float64, device=dev)

@@ -939,99 +939,100 @@ __global__ __launch_bounds__(SolveCfg::NT) void k_solve_downdate(const TF* __res
 // The same G = W L^{-T} (float64 MFMA), F(:, k + j) = G(:, j) and
 // rho -= rownorms(G)^2 as k_solve_downdate, organised for N >> 128: one
 // workgroup per CU stages L^{-1} (128 x 128, lower triangular, zero past nT)
-// in LDS once; then each wave walks 16-row blocks on its own (no workgroup
-// barrier after the staging, so the waves drift apart and one wave's loads
-// overlap another's MFMAs).  A block's W entries go straight from global
-// memory into the MFMA A operand (lane l: row l % 16, k-slot l / 16), in
-// chunks of four k-steps with the next chunk in flight; MFMA steps wholly
-// above the diagonal of L^{-1} and column tiles at or past nT are skipped.
-// A row's norm is summed over its 16 lanes by xor shuffles in a fixed order
-// (deterministic).
+// in LDS once; then each of its eight waves walks 16-row blocks on its own
+// (no workgroup barrier after the staging).  A wave holds two blocks of W in
+// registers: while it multiplies one, the whole next block (and its rho
+// entries) is in flight, so a CU keeps about 48 KB of loads outstanding.  A
+// block's W entries go straight from global memory into the MFMA A operand
+// (lane l: row slot l % 16, k-slot l / 16); MFMA steps wholly above the
+// diagonal of L^{-1} are skipped, and the loop is specialised for the number
+// of 16-column tiles nT spans (the loads and MFMAs of a block are static).
+//
+// Row slot s of the A operand carries block row 4 (s % 4) + s / 4.  The
+// accumulator element e of lane l is row slot l / 16 + 4 e, i.e. block row
+// 4 (l / 16) + e: each lane ends with four consecutive rows of one column
+// and writes them with one vector store.  A row's norm is summed over its 16
+// lanes by xor shuffles in a fixed order (deterministic).
 constexpr int SP_LDK = MAXB + 1;  // odd stride: a fragment's 16 rows on distinct banks
-constexpr int SP_NT = 1024;
-
+// threads per workgroup: eight waves, two per SIMD (twelve were no faster
+// for a float32 factor)
 template <typename TF>
-__global__ __launch_bounds__(SP_NT) void k_solve_persist(const TF* __restrict__ W, int64_t ldw,
-                                                         int64_t N, const double* __restrict__ Linv,
-                                                         const int32_t* kptr, const int32_t* nTptr,
-                                                         TF* __restrict__ F, int64_t ldf,
-                                                         double* __restrict__ rho) {
-  constexpr int NJ = MAXB / 16, CH = 4;
-  const int nt = *nTptr;
-  if (nt == 0) return;
-  const int k = *kptr;
-  __shared__ double Ls[MAXB * SP_LDK];
-  for (int e = threadIdx.x; e < MAXB * MAXB; e += SP_NT) Ls[(e / MAXB) * SP_LDK + e % MAXB] = Linv[e];
-  __syncthreads();
-  const int lane = threadIdx.x & 63, kq = lane >> 4;
-  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int nks = (nt + 3) / 4, nch = (nks + CH - 1) / CH;
-  // k-steps each column tile needs: L^{-1}(n, k) = 0 for k > n
-  int lim[NJ];
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int l = 16 * j >= nt ? 0 : 4 * (j + 1);
-    lim[j] = l < nks ? l : nks;
-  }
-  const int64_t step = 4 * ldw;
+constexpr int sp_threads() { return 512; }
+
+// The block loop for NTL column tiles of 16 (nT <= 16 NTL): 4 NTL k-steps,
+// those past nT multiplied by zero.
+template <typename TF, int NTL>
+__device__ __forceinline__ void solve_persist_loop(const TF* __restrict__ W, int64_t ldw, int64_t N,
+                                                   const double* Ls, int nt, int k,
+                                                   TF* __restrict__ F, int64_t ldf,
+                                                   double* __restrict__ rho, int64_t rb, int64_t nw) {
+  constexpr int NKS = 4 * NTL;
+  const int lane = threadIdx.x & 63, kq = lane >> 4, sl = lane & 15;
+  const int prow = 4 * (sl & 3) + (sl >> 2);  // block row of this lane's A row slot
+  // 16-byte stores of four rows need 16-byte aligned columns
+  constexpr int VEC = 16 / (int)sizeof(TF);
+  const bool vec_ok = (ldf % VEC) == 0 && (((uintptr_t)F) & 15) == 0;
   const int64_t nrb = (N + 15) / 16;
-  for (int64_t rb = (int64_t)blockIdx.x * (SP_NT / 64) + wave; rb < nrb;
-       rb += (int64_t)gridDim.x * (SP_NT / 64)) {
-    const int64_t m = rb * 16 + (lane & 15);
-    const bool rok = m < N;
-    // W holds MAXB columns: with the row clamped every address is valid
-    const TF* wp = W + (rok ? m : N - 1) + (int64_t)kq * ldw;
-    auto load = [&](TF (&buf)[CH], int ch) __attribute__((always_inline)) {
-      const TF* pc = wp + (int64_t)(ch * CH) * step;
+  const int64_t step = 4 * ldw;
+  const int lb0 = sl * SP_LDK + kq;
+
+  auto load = [&](TF (&buf)[NKS], double& rh, int64_t b) __attribute__((always_inline)) {
+    const int64_t m = b * 16 + prow;
+    const TF* wp = W + (m < N ? m : N - 1) + (int64_t)kq * ldw;
 #pragma unroll
-      for (int q = 0; q < CH; ++q) {
-        const TF v = pc[q * step];
-        buf[q] = (rok && 4 * (ch * CH + q) + kq < nt) ? v : (TF)0;
-      }
-    };
-    v4d acc[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
-    auto compute = [&](const TF (&buf)[CH], int ch) __attribute__((always_inline)) {
-      double av[CH];
-#pragma unroll
-      for (int q = 0; q < CH; ++q) av[q] = (double)buf[q];
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        if (ch * CH >= lim[j]) continue;
-        const double* lrow = Ls + (16 * j + (lane & 15)) * SP_LDK + kq;
-        double b[CH];
-#pragma unroll
-        for (int q = 0; q < CH; ++q) {
-          const int sq = ch * CH + q;
-          b[q] = sq < lim[j] ? lrow[4 * sq] : 0.0;  // past the tile's limit: zero step
-        }
-#pragma unroll
-        for (int q = 0; q < CH; ++q) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], b[q], acc[j], 0, 0, 0);
-      }
-    };
-    TF a0[CH], a1[CH];
-    load(a0, 0);
-    for (int ch = 0; ch < nch; ch += 2) {
-      if (ch + 1 < nch) load(a1, ch + 1);
-      compute(a0, ch);
-      if (ch + 1 >= nch) break;
-      if (ch + 2 < nch) load(a0, ch + 2);
-      compute(a1, ch + 1);
+    for (int sq = 0; sq < NKS; ++sq) {
+      buf[sq] = *wp;
+      wp += step;
     }
-    // F columns (element e of lane l: row l / 16 + 4 e, column 16 j + l % 16)
-    // and the squared row norms of G
+    const int64_t mr = b * 16 + 4 * kq + (sl & 3);
+    rh = rho[mr < N ? mr : N - 1];
+  };
+  auto block = [&](const TF (&buf)[NKS], double rh, int64_t b) __attribute__((always_inline)) {
+    v4d acc[NTL];
+#pragma unroll
+    for (int j = 0; j < NTL; ++j) acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+    // the L^{-1} fragments are the same for every block: an opaque offset
+    // keeps their LDS reads in the block instead of hoisted into registers
+    int lb = lb0;
+    asm volatile("" : "+v"(lb));
+#pragma unroll
+    for (int sq = 0; sq < NKS; ++sq) {
+      // only the last four k-steps can reach past nT (nT > 16 (NTL - 1))
+      const double av = (sq < NKS - 4 || 4 * sq + kq < nt) ? (double)buf[sq] : 0.0;
+      // tiles j >= sq / 4 meet k-step sq below or on the diagonal of L^{-1}
+#pragma unroll
+      for (int j = sq / 4; j < NTL; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Ls[lb + 16 * j * SP_LDK + 4 * sq], acc[j], 0, 0, 0);
+    }
+    const int64_t row0 = b * 16 + 4 * kq;
+    // whole blocks with aligned columns take vector stores (wave-uniform)
+    const bool full = vec_ok && b * 16 + 16 <= N;
     double s2[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int col = 16 * j + (lane & 15);
-      if (16 * j >= nt) break;
+    for (int j = 0; j < NTL; ++j) {
+      const int col = 16 * j + sl;
+      const bool cok = col < nt;
+      double g[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const double g = col < nt ? acc[j][e] : 0.0;
-        s2[e] += g * g;
-        const int64_t row = rb * 16 + kq + 4 * e;
-        if (col < nt && row < N) F[row + (int64_t)(k + col) * ldf] = (TF)g;
+        g[e] = cok ? acc[j][e] : 0.0;
+        s2[e] += g[e] * g[e];
+      }
+      TF* fp = F + row0 + (int64_t)(k + col) * ldf;
+      if (full) {
+        if (cok) {
+          if constexpr (sizeof(TF) == 4) {
+            *reinterpret_cast<float4*>(fp) =
+                make_float4((float)g[0], (float)g[1], (float)g[2], (float)g[3]);
+          } else {
+            *reinterpret_cast<v2d*>(fp) = v2d{g[0], g[1]};
+            *reinterpret_cast<v2d*>(fp + 2) = v2d{g[2], g[3]};
+          }
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (cok && row0 + e < N) fp[e] = (TF)g[e];
       }
     }
 #pragma unroll
@@ -1041,12 +1042,62 @@ __global__ __launch_bounds__(SP_NT) void k_solve_persist(const TF* __restrict__ 
       v += __shfl_xor(v, 2, 64);
       v += __shfl_xor(v, 4, 64);
       v += __shfl_xor(v, 8, 64);
-      const int64_t row = rb * 16 + kq + 4 * e;
-      if ((lane & 15) == 0 && row < N) {
-        const double r2 = rho[row] - v;
-        rho[row] = r2 > 0.0 ? r2 : 0.0;
-      }
+      s2[e] = v;
     }
+    // lane sl < 4 of each k-slot group updates block row 4 kq + sl
+    const int q = sl & 3;
+    const double v = q == 0 ? s2[0] : (q == 1 ? s2[1] : (q == 2 ? s2[2] : s2[3]));
+    const int64_t row = row0 + q;
+    if (sl < 4 && row < N) {
+      const double r2 = rh - v;
+      rho[row] = r2 > 0.0 ? r2 : 0.0;
+    }
+  };
+
+  // the loads are issued unconditionally (a wave's last prefetch re-reads
+  // its current block) so that the waits before each block are static
+  TF wa[NKS], wb[NKS];
+  double ra, rbv;
+  load(wa, ra, rb);
+  for (;;) {
+    const int64_t rb1 = rb + nw;
+    load(wb, rbv, rb1 < nrb ? rb1 : rb);
+    block(wa, ra, rb);
+    if (rb1 >= nrb) break;
+    const int64_t rb2 = rb1 + nw;
+    load(wa, ra, rb2 < nrb ? rb2 : rb1);
+    block(wb, rbv, rb1);
+    if (rb2 >= nrb) break;
+    rb = rb2;
+  }
+}
+
+template <typename TF>
+__global__ __launch_bounds__(sp_threads<TF>(), 1) void k_solve_persist(const TF* __restrict__ W, int64_t ldw,
+                                                            int64_t N, const double* __restrict__ Linv,
+                                                            const int32_t* kptr, const int32_t* nTptr,
+                                                            TF* __restrict__ F, int64_t ldf,
+                                                            double* __restrict__ rho) {
+  const int nt = *nTptr;
+  if (nt == 0) return;
+  const int k = *kptr;
+  __shared__ double Ls[MAXB * SP_LDK];
+  constexpr int NT = sp_threads<TF>();
+  for (int e = threadIdx.x; e < MAXB * MAXB; e += NT) Ls[(e / MAXB) * SP_LDK + e % MAXB] = Linv[e];
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t rb = (int64_t)blockIdx.x * (NT / 64) + wave;
+  if (rb >= (N + 15) / 16) return;
+  const int64_t nw = (int64_t)gridDim.x * (NT / 64);
+  switch ((nt + 15) / 16) {
+    case 1: solve_persist_loop<TF, 1>(W, ldw, N, Ls, nt, k, F, ldf, rho, rb, nw); break;
+    case 2: solve_persist_loop<TF, 2>(W, ldw, N, Ls, nt, k, F, ldf, rho, rb, nw); break;
+    case 3: solve_persist_loop<TF, 3>(W, ldw, N, Ls, nt, k, F, ldf, rho, rb, nw); break;
+    case 4: solve_persist_loop<TF, 4>(W, ldw, N, Ls, nt, k, F, ldf, rho, rb, nw); break;
+    case 5: solve_persist_loop<TF, 5>(W, ldw, N, Ls, nt, k, F, ldf, rho, rb, nw); break;
+    case 6: solve_persist_loop<TF, 6>(W, ldw, N, Ls, nt, k, F, ldf, rho, rb, nw); break;
+    case 7: solve_persist_loop<TF, 7>(W, ldw, N, Ls, nt, k, F, ldf, rho, rb, nw); break;
+    default: solve_persist_loop<TF, 8>(W, ldw, N, Ls, nt, k, F, ldf, rho, rb, nw); break;
   }
 }
 
@@ -1628,9 +1679,10 @@ static void phase_solve(FJob<T, TN, TF>& j, int i, hipStream_t st) {
   } else {
     const int64_t nrb = (N + 15) / 16;
     const int64_t cus = device_cus();
-    const int64_t need = (nrb + SP_NT / 64 - 1) / (SP_NT / 64);
+    constexpr int spw = sp_threads<TF>() / 64;
+    const int64_t need = (nrb + spw - 1) / spw;
     const unsigned grid = (unsigned)(need < cus ? need : cus);
-    hipLaunchKernelGGL((k_solve_persist<TF>), dim3(grid), dim3(SP_NT), 0, st,
+    hipLaunchKernelGGL((k_solve_persist<TF>), dim3(grid), dim3(sp_threads<TF>()), 0, st,
                        (const TF*)w.W, w.ldw, N, (const double*)w.Linv, (const int32_t*)j.k_out,
                        (const int32_t*)w.nT, j.F, j.ldf, j.rho);
     (void)smD;

@@ -123,6 +123,31 @@ def test_sampled_ragged_shapes(gpu):
     assert np.abs(F[:, :k] - ref["F"]).max() / np.abs(ref["F"]).max() < 1e-12
 
 
+@pytest.mark.parametrize("fdt,gdt", [("f64", "f64"), ("f32", "f32"), ("f32", "bf16")])
+def test_factor_leading_dimension_and_ragged_tail(gpu, fdt, gdt):
+    """F stored with two leading dimensions (the default 1344 and 1352, both
+    multiples of 8 as the ABI asks) at N = 1337, whose last 16-row block of
+    the solve is ragged (element stores) while the others take vector stores:
+    pivots, F and the residual diagonal are equal bit for bit."""
+    torch, rp = gpu
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((1337, 37)).astype(np.float32)
+    eps = median_sq_distance(X, seed=9)
+    r, b = 200, 64
+    u = torch.from_numpy(uniform_stream(2 * b * 4, seed=9)).cuda()
+    Xd = torch.from_numpy(X).cuda()
+    outs = [rp.rpchol_factor(Xd, eps, r, b, uniforms=u, gemm_dtype=gdt, factor_dtype=fdt, ldf=ld)
+            for ld in (None, 1352)]
+    assert outs[0]["ldf"] == 1344 and outs[1]["ldf"] == 1352
+    for o in outs:
+        assert rp.status_sync(o["status"]) == 0
+    k = int(outs[0]["k"].item())
+    assert k == int(outs[1]["k"].item()) and k > 100
+    assert torch.equal(outs[0]["pivots"], outs[1]["pivots"])
+    assert torch.equal(outs[0]["F"][:, :k], outs[1]["F"][:, :k])
+    assert torch.equal(outs[0]["rho"], outs[1]["rho"])
+
+
 @pytest.mark.parametrize("n,d,unfused", [(77, 1, False), (1337, 37, False), (1337, 37, True),
                                          (2051, 70, False), (300, 130, True)])
 def test_split16_ragged_shapes(gpu, n, d, unfused):
