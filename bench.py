@@ -643,7 +643,7 @@ def bench_paper(args, rp, torch):
     print(json.dumps(line), flush=True)
 
 
-BATCH = dict(nev=16, n_streams=8, reps=3, datasets=64)
+BATCH = dict(nev=16, n_streams=16, reps=3, datasets=64)
 
 
 def bench_batched(args, rp, torch):
@@ -699,7 +699,7 @@ def bench_batched(args, rp, torch):
     log("[batched] autotuning block sizes")
     cache_path = os.path.join(os.environ.get("TMPDIR", "/tmp"), "rpchol_autotune.json")
     bs, cache = autotune.tune(probs, make_job, cache_path=cache_path, reps=1)
-    ns = BATCH["n_streams"]
+    ns = args.streams
 
     def measure(jobs, tag):
         ws = rp.batched_workspace(jobs, ns)
@@ -791,6 +791,9 @@ def main():
     ap.add_argument("--gram", default="split16", choices=["f32", "split16"],
                     help="arithmetic of the two N-long Gram products in the mixed form")
     ap.add_argument("--datasets", type=int, default=BATCH["datasets"])
+    ap.add_argument("--streams", type=int, default=BATCH["n_streams"],
+                    help="batched form: streams in the pool (each maps to a hardware queue while "
+                         "GPU_MAX_HW_QUEUES allows; the batched form asks HIP for that many queues)")
     ap.add_argument("--sur-epochs", type=int, default=SUR["epochs"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -798,6 +801,11 @@ def main():
               "single MI355X; multi-GPU row sharding is a design note, not a measured path.",
               file=sys.stderr)
         sys.exit(2)
+    if args.form == "batched":
+        # small jobs are bound by the latency of one-workgroup stages: one
+        # hardware queue per pool stream lets them overlap (HIP reads this
+        # before its first call; a value set by the caller is kept)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(args.streams, 32)))
     import torch
 
     import paper_2510_26574_amd as rp

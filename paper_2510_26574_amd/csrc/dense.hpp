@@ -354,7 +354,8 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ A, i
   __shared__ double cs[JMAX / 2], sn[JMAX / 2];
   __shared__ int pa[JMAX / 2], pb[JMAX / 2];
   __shared__ double red[16];
-  __shared__ int done;
+  __shared__ double thr2;
+  __shared__ int done, ident[JMAX / 2];
   const int tid = threadIdx.x;
   const int n = p + (p & 1);  // even size; a padded row/column is decoupled (zero)
   for (int e = tid; e < n * n; e += 1024) {
@@ -394,6 +395,10 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ A, i
       double t = 0.0;
       for (int w = 0; w < 16; ++w) t += red[w];
       done = (offs <= tol * tol * t) ? 1 : 0;
+      // rotations of pairs with a_pq^2 below tol^2 t / (4 n^2) are skipped:
+      // all of them together hold less than a quarter of the mass the
+      // stopping test allows, so a sweep that skips every pair ends the loop
+      thr2 = tol * tol * t / (4.0 * (double)n * (double)n);
       if (sweep == max_sweeps && !done) set_status(status, RPC_ENOCONV);
     }
     __syncthreads();
@@ -412,7 +417,9 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ A, i
         const int P = x < y ? x : y, Q = x < y ? y : x;
         const double app = a[P + P * n], aqq = a[Q + Q * n], apq = a[P + Q * n];
         double c = 1.0, s = 0.0;
-        if (apq != 0.0 && fabs(apq) > 1e-300) {
+        const bool skip_pair = !(apq * apq > thr2);
+        ident[tid] = skip_pair;
+        if (!skip_pair && fabs(apq) > 1e-300) {
           const double tau = (aqq - app) / (2.0 * apq);
           const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = rsqrt(1.0 + t * t);
@@ -427,6 +434,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ A, i
       // A <- J^T A J on every 2 x 2 block (rows of pair u, columns of pair w)
       for (int e = tid; e < h * h; e += 1024) {
         const int u = e % h, w = e / h;
+        if (ident[u] & ident[w]) continue;  // both rotations are the identity
         const int P = pa[u], Q = pb[u], R = pa[w], S = pb[w];
         const double cu = cs[u], su = sn[u], cw = cs[w], sw = sn[w];
         const double aPR = a[P + R * n], aPS = a[P + S * n], aQR = a[Q + R * n], aQS = a[Q + S * n];
@@ -442,6 +450,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ A, i
       // V <- V J
       for (int e = tid; e < n * h; e += 1024) {
         const int i = e % n, u = e / n;
+        if (ident[u]) continue;
         const int P = pa[u], Q = pb[u];
         const double c = cs[u], s = sn[u];
         const double vp = v[i + P * n], vq = v[i + Q * n];
