@@ -383,8 +383,10 @@ int nystrom_extend_lowmem(const rpc_points* Y, const rpc_points* X, const int64_
  * bistoch_degrees, then bistoch_eig, exactly as the three calls made one
  * after the other) with its own output buffers, all device memory owned by
  * the caller.  Small problems cannot fill the chip one at a time, so
- * rpc_batched_run forks `stream` onto n_streams internal streams (created on
- * first use per device, default priority, kept until the process ends),
+ * rpc_batched_run forks `stream` onto n_streams (1..32) internal streams
+ * (created on first use per device, default priority, kept until the process
+ * ends; HIP maps them onto GPU_MAX_HW_QUEUES hardware queues, four unless the
+ * process sets that variable before HIP starts),
  * assigns the jobs longest-first (estimated N r (2 d + 3 r)) to the stream
  * with the least assigned work, and joins them back into `stream`.  Jobs on
  * one stream run in sequence and share one slice of the workspace.  Each

@@ -15,7 +15,7 @@
 
 namespace {
 
-constexpr int MAX_STREAMS = 16;
+constexpr int MAX_STREAMS = 32;
 
 struct DevicePool {
   int device;

@@ -136,7 +136,7 @@ def test_batched_rejects_bad_arguments(gpu):
     data = _datasets(torch)[:1]
     jobs = _jobs(torch, rp, data)
     with pytest.raises(rp.RpcError):
-        rp.batched_run(jobs, n_streams=17)
+        rp.batched_run(jobs, n_streams=33)
     ws = torch.empty(16, dtype=torch.uint8, device="cuda")
     with pytest.raises(rp.RpcError):
         rp.batched_run(jobs, n_streams=2, workspace=ws)
