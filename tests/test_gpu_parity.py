@@ -198,6 +198,48 @@ def test_sampled_large_rank_f64(gpu):
     assert err < bar
 
 
+@pytest.mark.parametrize("gdt,fdt,ftol", [("f64", "f64", 1e-12), ("f32", "f32", 5e-5), ("bf16", "f32", 1e-2),
+                                           ("split16", "f32", 2e-4)])
+def test_wide_points(gpu, gdt, fdt, ftol):
+    """Points of width d = 2050 (the padded width 2080 spans 65 k-stages of 32
+    and 33 of 64 with a ragged last stage, and the proposal block's joint
+    coordinate/column range runs over nine slices of 256): float64 pivots are
+    the oracle's and F within 1e-12; the reduced-precision forms replay the
+    oracle's pivots and hold F to their bars."""
+    rng = np.random.default_rng(61)
+    X = rng.standard_normal((600, 2050)).astype(np.float32)
+    eps = median_sq_distance(X, seed=61)
+    r, b = 96, 32
+    u = uniform_stream(2 * b * (r // b), seed=61)
+    ref = oracle.arpc(X, eps, r=r, b=b, mode="sampled", uniforms=u)
+    mode, kw = ("sampled", {"u": u}) if gdt == "f64" else ("replay", {"replay": ref["S"]})
+    out, k, F, piv, rho = _run_factor(gpu, X, eps, r, b, mode, gdt=gdt, fdt=fdt, **kw)
+    assert k == ref["k"] and list(piv[:k]) == list(ref["S"])
+    err = np.abs(F[:, :k] - ref["F"]).max() / np.abs(ref["F"]).max()
+    print(f"{gdt}: k = {k}, F error {err:.3g}")
+    assert err < ftol
+
+
+def test_full_budget_f64(gpu):
+    """The whole budget r = N (200 points in R^8, b = 40: five rounds whose
+    proposals run out of fresh points, so repeats and rejections spend part
+    of the budget): pivots and F are the oracle's, and the residual K - F F^T,
+    positive semidefinite, has no entry above its largest diagonal entry
+    (the returned rho)."""
+    rng = np.random.default_rng(62)
+    X = rng.standard_normal((200, 8)).astype(np.float32)
+    eps = median_sq_distance(X, seed=62)
+    r, b = 200, 40
+    u = uniform_stream(2 * b * (r // b), seed=62)
+    ref = oracle.arpc(X, eps, r=r, b=b, mode="sampled", uniforms=u)
+    out, k, F, piv, rho = _run_factor(gpu, X, eps, r, b, "sampled", u=u)
+    assert k == ref["k"] and k > 100 and list(piv[:k]) == list(ref["S"])
+    assert np.abs(F[:, :k] - ref["F"]).max() / np.abs(ref["F"]).max() < 1e-12
+    K = oracle.gaussian_kernel(X.astype(np.float64), X.astype(np.float64), eps)
+    Fk = F[:, :k]
+    assert np.abs(Fk @ Fk.T - K).max() <= rho.max() + 1e-12
+
+
 def test_repeated_proposals(gpu):
     """A block that proposes the same point several times (32 draws from 50
     points, 8 of them repeats in the first round): Algorithm 3 accepts a point
