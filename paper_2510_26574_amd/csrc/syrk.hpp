@@ -500,33 +500,37 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_split_partial(
       }
 }
 
-// Both Grams of one row chunk (nz = 2) from a single pass over its panels:
-// each workgroup loads the float32 panels of its tile once and stages the
-// split of s_0 A and of s_1 A, so the panel reads per MFMA are half those of
-// k_syrk_split_partial.  The two accumulator sets fit the register budget
-// because the runs are joined in float32 rather than float64: a float32 run
-// covers 256 rows (as above) and a float32 second-level sum joins the runs of
-// the chunk, at most PAIR_RUNS of them (the launcher takes this kernel only
-// for such chunks), before the float64 partial tile is written.  Stages are
-// 32 rows deep, which fits two stage buffers of the eight hi/lo operand tiles
-// in the 160 KB of LDS.  Four waves take each Gram, a 64 x 64 quarter of the
-// tile apiece: LDS bandwidth bounds this kernel, and a 64 x 64 wave tile reads
-// a third fewer fragment bytes per MFMA than the 64 x 32 one.
+// Both Grams of one row chunk (nz = 2) in one launch, each (chunk, tile) as
+// two adjacent four-wave workgroups on the same XCD, one per Gram, so the
+// second finds the panels the first fetched in L2.  The two accumulator sets
+// of a wave fit its register budget because the runs are joined in float32
+// rather than float64: a float32 run covers 256 rows (as above) and a float32
+// second-level sum joins the runs of the chunk, at most PAIR_RUNS of them
+// (the launcher takes this kernel only for such chunks), before the float64
+// partial tile is written.  Stages are 32 rows deep: two stage buffers of the
+// four hi/lo operand tiles take 80 KB of LDS, so two workgroups share a CU.
+// Each wave computes a 64 x 64 quarter of its Gram's tile: LDS bandwidth
+// bounds this kernel, and a 64 x 64 wave tile reads a third fewer fragment
+// bytes per MFMA than the 64 x 32 one.  One workgroup per Gram (rather than
+// eight waves taking both Grams from one staging) lets the two workgroups on a
+// CU drift out of phase, so one's split conversion and LDS writes overlap the
+// other's MFMAs; a workgroup's stage barrier holds only its own four waves.
 constexpr int PAIR_BK = 32;
 constexpr int PAIR_LDK = PAIR_BK + 8;  // 80-byte pitch: the 16 rows of a fragment read
                                        // fall on distinct groups of four banks
 constexpr int PAIR_RUNS = 64;          // most 256-row runs in one chunk
+constexpr int PAIR_NTH = 256;          // four waves, 2 x 2 quarters of the tile
 
-struct PairLoader {  // 128 columns x 32 rows of float32, two 4-row vectors per thread
+struct PairLoader {  // 128 columns x 32 rows of float32, four 4-row vectors per thread
   static constexpr int VPC = PAIR_BK / 4;
-  static constexpr int PER = TILE * VPC / NTH;
-  static_assert(NTH % VPC == 0, "every vector of a thread covers the same rows");
+  static constexpr int PER = TILE * VPC / PAIR_NTH;
+  static_assert(PAIR_NTH % VPC == 0, "every vector of a thread covers the same rows");
   v4f buf[PER];
   __device__ inline void load(const float* __restrict__ A, int64_t lda, int r, int c0,
                               int64_t n0, int64_t n1, int tid) {
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
-      const int vid = tid + p * NTH;
+      const int vid = tid + p * PAIR_NTH;
       const int col = vid / VPC;
       const int64_t n = n0 + (vid % VPC) * 4;
       const int gc = c0 + col;
@@ -544,10 +548,9 @@ struct PairLoader {  // 128 columns x 32 rows of float32, two 4-row vectors per 
                                const float (&ss)[4], int tid) const {
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
-      const int vid = tid + p * NTH;
+      const int vid = tid + p * PAIR_NTH;
       const int col = vid / VPC;
       const int kv = (vid % VPC) * 4;
-      // v = x s rounded to float32, split into fp16 hi and lo
       uint32_t hw[2], lw[2];
 #pragma unroll
       for (int e = 0; e < 4; e += 2)
@@ -571,38 +574,40 @@ __device__ inline void pair_row_scales(const float* __restrict__ s, int64_t n, i
   }
 }
 
-// grid.x = 8 * ceil(nch / 8) * n_upper: chunk ch's tiles on XCD ch % 8.
-// s0 and s1 are both required; scl as for k_syrk_split_partial with nz = 2.
-__global__ __launch_bounds__(NTH, 2) void k_syrk_split_pair_partial(
+// grid.x = 2 * 8 * ceil(nch / 8) * n_upper: slot pairs (2 t, 2 t + 1) on XCD
+// blockIdx % 8 are Grams 0 and 1 of chunk (t / n_upper) * 8 + XCD, tile
+// t % n_upper.  s0 and s1 are both required; scl as for k_syrk_split_partial
+// with nz = 2.
+__global__ __launch_bounds__(PAIR_NTH, 2) void k_syrk_split_pair_partial(
     const float* __restrict__ A, int64_t lda, int64_t N, int r, const float* __restrict__ s0,
     const float* __restrict__ s1, const float* __restrict__ scl, int64_t chunk, int nch,
     double* __restrict__ part0, double* __restrict__ part1, const int32_t* kptr) {
   constexpr int BK = PAIR_BK;
   constexpr int LDK = PAIR_LDK;
   constexpr int TS = TILE * LDK;
-  // [stage buffer][z][A hi, A lo, B hi, B lo]
-  __shared__ __attribute__((aligned(16))) _Float16 lds[2][2][4][TS];
+  // [stage buffer][A hi, A lo, B hi, B lo]
+  __shared__ __attribute__((aligned(16))) _Float16 lds[2][4][TS];
   const int nt = n_tiles(r);
   const int nu = n_upper(nt);
   const int xcd = blockIdx.x % 8;
   const int slot = blockIdx.x / 8;
-  const int ch = (slot / nu) * 8 + xcd;
+  const int z = slot & 1, pslot = slot >> 1;
+  const int ch = (pslot / nu) * 8 + xcd;
   if (ch >= nch) return;
-  const int tile = slot % nu;
+  const int tile = pslot % nu;
   int ti, tj;
   upper_decode(tile, nt, ti, tj);
   const int kk = kptr ? *kptr : r;
   if (tj * TILE >= kk) return;
   const bool diag = ti == tj;
-  const float scale[2] = {scl[ch], scl[nch + ch]};
-  double* out0 = part0 + ((int64_t)ch * nu + tile) * TILE * TILE;
-  double* out1 = part1 + ((int64_t)ch * nu + tile) * TILE * TILE;
+  const float scale = scl[z * nch + ch];
+  const float* sz = z ? s1 : s0;
+  double* o = (z ? part1 : part0) + ((int64_t)ch * nu + tile) * TILE * TILE;
   const int64_t n0 = (int64_t)ch * chunk;
   const int64_t n1 = n0 + chunk < N ? n0 + chunk : N;
 
-  // waves 0-3 compute G_0's tile, waves 4-7 G_1's, each a 64 x 64 quarter
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wz = wave >> 2, wm = wave & 1, wn = (wave >> 1) & 1;
+  const int wm = wave & 1, wn = wave >> 1;
   const int64_t nrow = (tid % PairLoader::VPC) * 4;  // this thread's rows within a stage
   constexpr int PM = 4, PN = 4;                     // 16 x 16 blocks per wave
   v4f acc[PM][PN], acc2[PM][PN];
@@ -615,38 +620,33 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_split_pair_partial(
         acc[i][j][e] = 0.0f;
         acc2[i][j][e] = 0.0f;
       }
-  // register ring of two stages, as in k_syrk_split_partial
-  PairLoader la0, lb0, la1, lb1;
-  float w0[2][4], w1[2][4];  // row scales: w[z][e] = s_z at the rows of ring set 0 / 1
-  auto stage = [&](const PairLoader& la, const PairLoader& lb, const float (&w)[2][4], int b)
-                   __attribute__((always_inline)) {
+  PairLoader la, lb;
+  float w[4];  // s_z at the staged rows
+  auto stage = [&](int b) __attribute__((always_inline)) {
+    float ss[4];
 #pragma unroll
-    for (int z = 0; z < 2; ++z) {
-      float ss[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) ss[e] = w[z][e] * scale[z];
-      la.store(lds[b][z][0], lds[b][z][1], ss, tid);
-      if (!diag) lb.store(lds[b][z][2], lds[b][z][3], ss, tid);
-    }
+    for (int e = 0; e < 4; ++e) ss[e] = w[e] * scale;
+    la.store(lds[b][0], lds[b][1], ss, tid);
+    if (!diag) lb.store(lds[b][2], lds[b][3], ss, tid);
   };
   auto compute = [&](int b) __attribute__((always_inline)) {
-    const _Float16* ah_s = lds[b][wz][0];
-    const _Float16* al_s = lds[b][wz][1];
-    const _Float16* bh_s = diag ? lds[b][wz][0] : lds[b][wz][2];
-    const _Float16* bl_s = diag ? lds[b][wz][1] : lds[b][wz][3];
+    const _Float16* ah_s = lds[b][0];
+    const _Float16* al_s = lds[b][1];
+    const _Float16* bh_s = diag ? lds[b][0] : lds[b][2];
+    const _Float16* bl_s = diag ? lds[b][1] : lds[b][3];
     // lane group lane / 16 takes k = 8 (lane / 16) .. + 7 of the 32-row stage
     v8h bh[PN], bl[PN];
 #pragma unroll
     for (int j = 0; j < PN; ++j) {
-      const int o = (wn * 64 + j * 16 + (lane & 15)) * LDK + 8 * (lane >> 4);
-      bh[j] = *reinterpret_cast<const v8h*>(bh_s + o);
-      bl[j] = *reinterpret_cast<const v8h*>(bl_s + o);
+      const int o2 = (wn * 64 + j * 16 + (lane & 15)) * LDK + 8 * (lane >> 4);
+      bh[j] = *reinterpret_cast<const v8h*>(bh_s + o2);
+      bl[j] = *reinterpret_cast<const v8h*>(bl_s + o2);
     }
 #pragma unroll
     for (int i = 0; i < PM; ++i) {
-      const int o = (wm * 64 + i * 16 + (lane & 15)) * LDK + 8 * (lane >> 4);
-      const v8h ah = *reinterpret_cast<const v8h*>(ah_s + o);
-      const v8h al = *reinterpret_cast<const v8h*>(al_s + o);
+      const int o2 = (wm * 64 + i * 16 + (lane & 15)) * LDK + 8 * (lane >> 4);
+      const v8h ah = *reinterpret_cast<const v8h*>(ah_s + o2);
+      const v8h al = *reinterpret_cast<const v8h*>(al_s + o2);
 #pragma unroll
       for (int j = 0; j < PN; ++j) {
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[j], acc[i][j], 0, 0, 0);
@@ -671,33 +671,29 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_split_pair_partial(
         }
   };
   const int nst = (int)((n1 - n0 + BK - 1) / BK);
-  auto fetch = [&](PairLoader& la, PairLoader& lb, float (&w)[2][4], int q)
-                   __attribute__((always_inline)) {
+  auto fetch = [&](int q) __attribute__((always_inline)) {
     const int64_t p0 = n0 + (int64_t)q * BK;
     la.load(A, lda, r, ti * TILE, p0, n1, tid);
     if (!diag) lb.load(A, lda, r, tj * TILE, p0, n1, tid);
-    pair_row_scales(s0, p0 + nrow, n1, w[0]);
-    pair_row_scales(s1, p0 + nrow, n1, w[1]);
+    pair_row_scales(sz, p0 + nrow, n1, w);
   };
-  fetch(la0, lb0, w0, 0);
-  if (nst > 1) fetch(la1, lb1, w1, 1);
-  stage(la0, lb0, w0, 0);
+  // one stage in registers: stage q + 1's panels are read during stage q's
+  // MFMAs and split into the other buffer after them
+  fetch(0);
+  stage(0);
+  if (nst > 1) fetch(1);
   __syncthreads();
-  for (int q = 0; q < nst; q += 2) {
-    if (q + 2 < nst) fetch(la0, lb0, w0, q + 2);
-    compute(0);
-    if (q + 1 < nst) stage(la1, lb1, w1, 1);
-    flush();
-    __syncthreads();
-    if (q + 1 >= nst) break;
-    if (q + 3 < nst) fetch(la1, lb1, w1, q + 3);
-    compute(1);
-    if (q + 2 < nst) stage(la0, lb0, w0, 0);
+  for (int q = 0; q < nst; ++q) {
+    const int b = q & 1;
+    compute(b);
+    if (q + 1 < nst) {
+      stage(b ^ 1);
+      if (q + 2 < nst) fetch(q + 2);
+    }
     flush();
     __syncthreads();
   }
-  const double unscale = 1.0 / ((double)scale[wz] * (double)scale[wz]);
-  double* o = wz ? out1 : out0;
+  const double unscale = 1.0 / ((double)scale * (double)scale);
 #pragma unroll
   for (int i = 0; i < PM; ++i)
 #pragma unroll
@@ -824,8 +820,8 @@ inline void gram2_partial_split(hipStream_t st, const float* A, int64_t lda, int
   const int groups = nz * nch;
   hipLaunchKernelGGL(k_split_scales, dim3(groups), dim3(256), 0, st, s0, s1, N, chunk, nch, scl);
   if (nz == 2 && s0 && s1 && chunk <= (int64_t)PAIR_RUNS * FLUSH_ROWS) {
-    const unsigned blocks = (unsigned)(8 * ((nch + 7) / 8) * nu);
-    hipLaunchKernelGGL(k_syrk_split_pair_partial, dim3(blocks), dim3(NTH), 0, st, A, lda, N, r,
+    const unsigned blocks = (unsigned)(2 * 8 * ((nch + 7) / 8) * nu);
+    hipLaunchKernelGGL(k_syrk_split_pair_partial, dim3(blocks), dim3(PAIR_NTH), 0, st, A, lda, N, r,
                        s0, s1, (const float*)scl, chunk, nch, part0, part1, kptr);
     return;
   }
