@@ -60,44 +60,10 @@ __global__ __launch_bounds__(256) void k_zero_upper(double* A, int64_t ld, int n
 }
 
 // ------------------------------------------------ one-workgroup Cholesky
-// In-place lower Cholesky of the n x n block `a` in LDS (column-major,
-// lda_s); only the lower triangle is read and written.  Right-looking with
-// deferred column scaling: step j subtracts a(i,j) a(c,j) / a(j,j) from the
-// trailing lower triangle (column j still unscaled), so each step needs one
-// barrier; the columns are scaled by 1/sqrt(pivot) once at the end.  `piv`
-// is LDS scratch of n doubles.  A pivot <= 0 sets RPC_EBREAKDOWN and is
-// replaced by 1 so the rest stays finite.
-__device__ inline void chol_block_lds(double* a, int n, int lda_s, double* piv, int32_t* status) {
-  const int nth = blockDim.x, tid = threadIdx.x;
-  const int rows = nth / 32, ty = tid / 32, tx = tid % 32;
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    double p = a[j + j * lda_s];
-    if (!(p > 0.0)) {
-      if (tid == 0) set_status(status, RPC_EBREAKDOWN);
-      p = 1.0;
-    }
-    if (tid == 0) piv[j] = p;
-    const double rp = 1.0 / p;
-    for (int i = j + 1 + ty; i < n; i += rows) {
-      const double aij = a[i + j * lda_s] * rp;
-      for (int c = j + 1 + tx; c <= i; c += 32) a[i + c * lda_s] -= aij * a[c + j * lda_s];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < n * n; e += nth) {
-    const int i = e % n, j = e / n;
-    if (i >= j) {
-      const double sp = sqrt(piv[j]);
-      a[i + j * lda_s] = (i == j) ? sp : a[i + j * lda_s] / sp;
-    }
-  }
-  __syncthreads();
-}
-
-// Same factorisation (L with the square roots applied, lower triangle of `a`)
-// for n <= 128 + 8, blocked by panels of 8 columns: wave 0 loads a panel
-// into registers (lane l holds panel rows j0 + l and j0 + l + 64), factors it
+// In-place lower Cholesky (L with the square roots applied, lower triangle of
+// `a` in LDS, column-major, lda_s) for n <= 128 + 8, blocked by panels of 8
+// columns: wave 0 loads a panel into registers (lane l holds panel rows
+// j0 + l and j0 + l + 64), factors it
 // right-looking with the pivot-row values broadcast by readlane, and writes
 // it back; then every thread applies the panel to the trailing lower
 // triangle.  Two workgroup barriers per panel.  A pivot <= 0 sets
@@ -181,24 +147,45 @@ __device__ inline int active_n(int n, const int32_t* kptr) {
 }
 
 // Factor the NB x NB diagonal block starting at (j0, j0) of A (n x n, ld);
-// only its part inside the active order.
-__global__ __launch_bounds__(256) void k_chol_diag(double* A, int64_t ld, int n, int j0,
-                                                   int32_t* status, const int32_t* kptr) {
-  constexpr int LDS = NB + 1;  // odd stride: column walks do not pile onto one bank
-  __shared__ double a[NB * LDS];
-  __shared__ double piv[NB];
+// only its part inside the active order.  One wave: lane i keeps row i of the
+// block in registers (rows and columns past the active order are those of
+// the identity); step j takes the pivot from lane j, scales column j, writes
+// it to LDS and every lane subtracts L(i, j) L(c, j) from its entries c > j.
+// The steps are unrolled, so the register indices are constants, and the
+// wave needs no barrier (its LDS accesses complete in order).  A pivot <= 0
+// sets RPC_EBREAKDOWN and is replaced by 1.
+static_assert(NB == 64, "one row of the diagonal block per lane");
+__global__ __launch_bounds__(64) void k_chol_diag(double* A, int64_t ld, int n, int j0,
+                                                  int32_t* status, const int32_t* kptr) {
+  __shared__ double col[NB];
   n = active_n(n, kptr);
   if (j0 >= n) return;
   const int nb = n - j0 < NB ? n - j0 : NB;
-  for (int e = threadIdx.x; e < nb * nb; e += 256) {
-    int i = e % nb, c = e / nb;
-    a[i + c * LDS] = A[(j0 + i) + (int64_t)(j0 + c) * ld];
+  const int i = threadIdx.x;
+  double r[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+    r[c] = (i < nb && c < nb) ? A[(j0 + i) + (int64_t)(j0 + c) * ld] : (i == c ? 1.0 : 0.0);
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    double d = bcast_lane(r[j], j);
+    bad |= !(d > 0.0);
+    d = d > 0.0 ? d : 1.0;
+    const double rs = rsqrt(d);
+    const double l = i == j ? d * rs : r[j] * rs;  // L(i, j) for i >= j
+    r[j] = l;
+    col[i] = l;
+    __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4));  // lgkmcnt(0): the write landed
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int c = j + 1; c < NB; ++c) r[c] -= l * col[c];
+    __builtin_amdgcn_wave_barrier();  // this step's reads come before the next step's write
   }
-  chol_panel_lds(a, nb, LDS, status);
-  for (int e = threadIdx.x; e < nb * nb; e += 256) {
-    int i = e % nb, c = e / nb;
-    A[(j0 + i) + (int64_t)(j0 + c) * ld] = i >= c ? a[i + c * LDS] : 0.0;
-  }
+  if (bad && i == 0) set_status(status, RPC_EBREAKDOWN);
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+    if (i < nb && c < nb) A[(j0 + i) + (int64_t)(j0 + c) * ld] = c <= i ? r[c] : 0.0;
 }
 
 // Panel: rows i >= j0 + NB of block column j0 solve x L_jj^T = a (forward
@@ -259,7 +246,7 @@ inline void cholesky(hipStream_t st, double* A, int64_t ld, int n, int32_t* stat
   if (kptr && skip)
     hipLaunchKernelGGL(k_chol_skips, dim3(1), dim3(256), 0, st, n, kptr, nblk, skip);
   for (int j0 = 0; j0 < n; j0 += NB) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, A, ld, n, j0, status, kptr);
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, st, A, ld, n, j0, status, kptr);
     const int rest = n - j0 - NB;
     if (rest > 0) {
       hipLaunchKernelGGL(k_chol_panel, dim3((rest + 255) / 256), dim3(256), 0, st, A, ld, n, j0,
