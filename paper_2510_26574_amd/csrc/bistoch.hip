@@ -526,13 +526,17 @@ __global__ __launch_bounds__(FormUCfg<T>::NT) void k_form_u(const TF* __restrict
 // writes its four consecutive rows of a column directly.
 typedef TileCfg<__bf16, 128, 128, 64, 2, 4> FormUSplitCfg;
 
+// With cpv/cpi non-null the kernel also writes, for each column, the largest
+// |U| over its 128 rows and that row (the lowest on ties) to
+// cpv/cpi[col * gridDim.x + blockIdx.x], the partials of the sign rule.
 template <typename TU>
 __global__ __launch_bounds__(512, 4) void k_form_u_split(const float* __restrict__ F, int64_t ldf,
                                                          int64_t N, int r, const float* __restrict__ Zt,
                                                          int nev, const float* __restrict__ zsc,
                                                          const double* __restrict__ dinv,
                                                          TU* __restrict__ U, int64_t ldu,
-                                                         const int32_t* kptr) {
+                                                         const int32_t* kptr, double* __restrict__ cpv,
+                                                         int64_t* __restrict__ cpi) {
   typedef FormUSplitCfg Cfg;
   extern __shared__ char smem_raw[];
   const int kk = *kptr;
@@ -549,6 +553,13 @@ __global__ __launch_bounds__(512, 4) void k_form_u_split(const float* __restrict
   const float un = 1.0f / (SchurSplit::SC * zs);  // both powers of two
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave % Cfg::WAVES_M, wn = wave / Cfg::WAVES_M;
+  double bv[Cfg::NI];
+  int64_t bi[Cfg::NI];
+#pragma unroll
+  for (int j = 0; j < Cfg::NI; ++j) {
+    bv[j] = -1.0;
+    bi[j] = -1;
+  }
 #pragma unroll
   for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
@@ -560,10 +571,60 @@ __global__ __launch_bounds__(512, 4) void k_form_u_split(const float* __restrict
       for (int e = 0; e < 4; ++e) {
         if (m + e < N) {
           const double v = (double)(acc.a[i][j][e] * un);
-          U[m + e + (int64_t)col * ldu] = (TU)(dinv ? v * dinv[m + e] : v);
+          const TU u = (TU)(dinv ? v * dinv[m + e] : v);
+          U[m + e + (int64_t)col * ldu] = u;
+          // rows visited in increasing order: a strict > keeps the lowest on ties
+          const double a = fabs(to_d(u));
+          if (a > bv[j]) {
+            bv[j] = a;
+            bi[j] = m + e;
+          }
         }
       }
     }
+  if (!cpv) return;
+  // combine the four row groups of a column (lanes l, l ^ 16, l ^ 32, l ^ 48),
+  // then the two waves that share the column slice, through LDS
+  double* sv = reinterpret_cast<double*>(smem_raw);
+  int64_t* sx = reinterpret_cast<int64_t*>(sv + Cfg::NT / 64 * Cfg::WTN);
+#pragma unroll
+  for (int j = 0; j < Cfg::NI; ++j) {
+#pragma unroll
+    for (int o = 16; o <= 32; o <<= 1) {
+      const double v2 = __shfl_xor(bv[j], o, 64);
+      const int64_t i2 = __shfl_xor(bi[j], o, 64);
+      if (i2 >= 0 && (bi[j] < 0 || v2 > bv[j] || (v2 == bv[j] && i2 < bi[j]))) {
+        bv[j] = v2;
+        bi[j] = i2;
+      }
+    }
+    if (lane < 16) {
+      sv[wave * Cfg::WTN + j * 16 + lane] = bv[j];
+      sx[wave * Cfg::WTN + j * 16 + lane] = bi[j];
+    }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < Cfg::BN) {
+    const int cwn = t / Cfg::WTN, cc = t % Cfg::WTN;
+    const int col = n0 + t;
+    double v = -1.0;
+    int64_t ix = -1;
+#pragma unroll
+    for (int h = 0; h < Cfg::WAVES_M; ++h) {
+      const int w2 = cwn * Cfg::WAVES_M + h;  // wave = wm + WAVES_M wn
+      const double v2 = sv[w2 * Cfg::WTN + cc];
+      const int64_t i2 = sx[w2 * Cfg::WTN + cc];
+      if (i2 >= 0 && (ix < 0 || v2 > v || (v2 == v && i2 < ix))) {
+        v = v2;
+        ix = i2;
+      }
+    }
+    if (col < nev) {
+      cpv[(int64_t)col * gridDim.x + blockIdx.x] = v;
+      cpi[(int64_t)col * gridDim.x + blockIdx.x] = ix;
+    }
+  }
 }
 
 // The regularised QR factors B' = D~^{-1} F + gamma E_k (E_k: ones at (i, i),
@@ -735,7 +796,8 @@ static size_t carve_eig(WsCursor& c, EigWs& w, int64_t N, int r, int nev, bool f
                         bool cholqr2, int64_t gram_rows = 0) {
   w.p = r <= dense::JMAX ? r : dense::JMAX;
   const int p = w.p;
-  const int nbu = (int)((N + 4095) / 4096);
+  // sign-rule partials: one per 4096 rows, or one per 128-row tile of the split U kernel
+  const int nbu = (int)((N + 127) / 128);
   w.sd = c.take<double>(N);
   w.sq = c.take<double>(N);
   w.ssd = c.take<double>(N);
@@ -1146,6 +1208,10 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   hipLaunchKernelGGL((k_cvt<TG>), dim3(nblk((int64_t)r * nev)), dim3(256), 0, st, (const double*)w.Z,
                      Zt, (int64_t)r * nev);
   bool split_u = false;
+  // the split U kernel also finds the column maxima of the sign rule when
+  // nothing changes U after it (no gamma rows, no constant column)
+  const bool fused_sign = o->gamma == 0.0 && !o->fix_const && !qr2 && !lm;
+  const unsigned nbt = (unsigned)((N + 127) / 128);
   if (qr2) {
     typedef FormUCfg<double> CfgQ;
     size_t smQ = TileSmem<CfgQ, false, true>::bytes;
@@ -1163,7 +1229,8 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
       const dim3 gs((unsigned)((N + 127) / 128), (unsigned)((nev + 127) / 128));
       hipLaunchKernelGGL((k_form_u_split<TU>), gs, dim3(512), SchurSplit::bytes / 2, st,
                          (const float*)F, ldf, N, r, (const float*)Zt, nev, (const float*)w.gsc,
-                         (const double*)w.sd, U, ldu, k);
+                         (const double*)w.sd, U, ldu, k, fused_sign ? w.pv : (double*)nullptr,
+                         fused_sign ? w.pi : (int64_t*)nullptr);
     }
   }
   if (lm) {
@@ -1204,9 +1271,13 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
   }
 
   // ---- column signs: largest-magnitude entry positive
-  const int nbu = (int)((N + 4095) / 4096);
-  hipLaunchKernelGGL((k_colmax_partial<TU>), dim3((unsigned)nbu, (unsigned)nev), dim3(256), 0, st,
-                     (const TU*)U, ldu, N, nev, w.pv, w.pi, nbu);
+  int nbu = (int)((N + 4095) / 4096);
+  if (split_u && fused_sign) {
+    nbu = (int)nbt;  // partials of the 128-row tiles, written by k_form_u_split
+  } else {
+    hipLaunchKernelGGL((k_colmax_partial<TU>), dim3((unsigned)nbu, (unsigned)nev), dim3(256), 0, st,
+                       (const TU*)U, ldu, N, nev, w.pv, w.pi, nbu);
+  }
   hipLaunchKernelGGL((k_colsign<TU>), dim3((unsigned)nev), dim3(256), 0, st, (const TU*)U, ldu,
                      (const double*)w.pv, (const int64_t*)w.pi, nbu, w.sgn);
   hipLaunchKernelGGL((k_apply_sign<TU>), dim3(nblk(N), (unsigned)nev), dim3(256), 0, st, U, ldu, N,

@@ -358,10 +358,15 @@ def test_eig_reduced_precision(gpu, gdt, fdt, gram, case, ltol, atol):
     lam = eig["lam"].cpu().numpy()
     m = _gap_index(res["lam_all"], nev)
     le = np.abs(lam / res["lam"] - 1).max()
-    ae = _angle(eig["U"].cpu().numpy()[:, :m], res["U"][:, :m])
+    U = eig["U"].cpu().numpy()
+    ae = _angle(U[:, :m], res["U"][:, :m])
     print(f"{gdt}/{gram}/{case}: eigenvalue error {le:.3g}, angle {ae:.3g}")
     assert le < ltol
     assert ae < atol
+    # the sign rule on the returned columns (the split form finds the column
+    # maxima inside its U kernel): the largest |U(:, j)|, lowest row on ties, is positive
+    top = np.argmax(np.abs(U), axis=0)
+    assert np.all(U[top, np.arange(U.shape[1])] > 0)
 
 
 @pytest.mark.parametrize("gram,ltol,atol", [("f32", 1e-6, 1e-4), ("split16", 4e-6, 4e-4)])
