@@ -794,7 +794,12 @@ struct EigWs {
 // rows of the low-memory form), which sizes the chunk partial buffers.
 static size_t carve_eig(WsCursor& c, EigWs& w, int64_t N, int r, int nev, bool fix_const,
                         bool cholqr2, int64_t gram_rows = 0) {
-  w.p = r <= dense::JMAX ? r : dense::JMAX;
+  // block of the subspace iteration (r > JMAX): twice the wanted eigenpairs,
+  // at least 64 and at most JMAX (the one-workgroup Rayleigh-Ritz limit)
+  int pb = 2 * nev;
+  pb = pb < 64 ? 64 : pb;
+  pb = pb > dense::JMAX ? dense::JMAX : pb;
+  w.p = r <= dense::JMAX ? r : pb;
   const int p = w.p;
   // sign-rule partials: one per 4096 rows, or one per 128-row tile of the split U kernel
   const int nbu = (int)((N + 127) / 128);
