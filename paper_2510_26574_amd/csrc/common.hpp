@@ -113,6 +113,25 @@ __device__ inline void split_pair_f16(float v0, float v1, uint32_t& hb, uint32_t
       : "+v"(lb) : "v"(v1), "v"(hb));
 }
 
+// ------------------------------------------------------------ LDS layout
+// Bank behaviour of the gfx950 LDS, as counted (SQ_LDS_BANK_CONFLICT):
+//   ds_read_b128:  64 banks of 4 bytes; a wave is served in four passes of 16
+//     lanes, a pass being the four-lane groups g = lane / 4 of one half-wave
+//     whose three low bits have equal parity (lanes 0-3, 12-15, 20-23, 24-27);
+//   ds_write_b128: 32 banks, 8 consecutive lanes per pass;
+//   ds_write_b64:  32 banks, 16 consecutive lanes per pass.
+// A 16 x 32 fp16/bf16 MFMA fragment (lane: row lane % 16, 16-byte k-chunk
+// lane / 16) read from rows padded to 144 bytes therefore takes two passes per
+// pass-group.  Rows of 128 bytes (eight chunks, no pad) whose chunk index is
+// XORed with lds_swz8(row) serve it in one, and keep conflict-free both the
+// row-major chunk writes (eight lanes on one row) and the writes of four lanes
+// per row at a fixed chunk group: the three bits of lds_swz8 over rows
+// 8 m .. 8 m + 7 are a permutation, rows 2 m and 2 m + 1 differ in bit 2, and
+// bit 3 of the row separates rows r and r + 8 of one pass.
+__device__ inline int lds_swz8(int row) {
+  return (((row & 1) << 2) | ((row >> 1) & 3)) ^ ((row & 8) >> 1);
+}
+
 // Broadcast lane `src` (wave-uniform) of a double held in a VGPR pair.
 __device__ inline double bcast_lane(double v, int src) {
   const unsigned long long u = __double_as_longlong(v);

@@ -26,12 +26,15 @@
 //     across the wave);
 //   B (FSa, k-contiguous rows): thread t holds row t / 4 at k groups t % 4
 //     and t % 4 + 4;
-// both land in LDS as [row][k] fp16 pairs (hi and lo arrays, 144-byte rows),
-// so every MFMA operand is one 16-byte read.
+// both land in LDS as [row][k] fp16 pairs (hi and lo arrays, 128-byte rows
+// with their 16-byte chunks permuted by lds_swz8 against bank conflicts), so
+// every MFMA operand is one 16-byte read.
 struct SchurSplit {
   static constexpr int BK = 64;
-  static constexpr int LDK = BK + 8;
+  static constexpr int LDK = BK;
   static constexpr int ELEMS = 128 * LDK;
+  // half offset of 16-byte chunk c (k = 8 c .. 8 c + 7) of a staged row
+  __device__ static inline int at(int row, int c) { return row * LDK + 8 * (c ^ lds_swz8(row)); }
   static constexpr size_t bytes = 2 * 4 * (size_t)ELEMS * sizeof(_Float16);
   static constexpr float SC = 4096.0f;  // 2^12 per operand
 };
@@ -127,7 +130,7 @@ struct SchurSplitPipe {
     for (int h = 0; h < 2; ++h) {
       v8h_t hi, lo;
       split8(a[h], hi, lo, asc);
-      const int o = arow * LDK + 8 * (ag + 4 * h);
+      const int o = SchurSplit::at(arow, ag + 4 * h);
       *reinterpret_cast<v8h_t*>(base + o) = hi;
       *reinterpret_cast<v8h_t*>(base + EL + o) = lo;
     }
@@ -135,7 +138,7 @@ struct SchurSplitPipe {
     for (int h = 0; h < 2; ++h) {
       v8h_t hi, lo;
       split8(b[h], hi, lo, bsc);
-      const int o = brow * LDK + 8 * (bg + 4 * h);
+      const int o = SchurSplit::at(brow, bg + 4 * h);
       *reinterpret_cast<v8h_t*>(base + 2 * EL + o) = hi;
       *reinterpret_cast<v8h_t*>(base + 3 * EL + o) = lo;
     }
@@ -153,13 +156,13 @@ struct SchurSplitPipe {
       v8h_t bh[Cfg::NI], bl[Cfg::NI];
 #pragma unroll
       for (int j = 0; j < Cfg::NI; ++j) {
-        const int o = (wn * Cfg::WTN + j * 16 + (lane & 15)) * LDK + kq + 8 * (lane >> 4);
+        const int o = SchurSplit::at(wn * Cfg::WTN + j * 16 + (lane & 15), kq / 8 + (lane >> 4));
         bh[j] = *reinterpret_cast<const v8h_t*>(base + 2 * EL + o);
         bl[j] = *reinterpret_cast<const v8h_t*>(base + 3 * EL + o);
       }
 #pragma unroll
       for (int i = 0; i < Cfg::MI; ++i) {
-        const int o = (wm * Cfg::WTM + i * 16 + (lane & 15)) * LDK + kq + 8 * (lane >> 4);
+        const int o = SchurSplit::at(wm * Cfg::WTM + i * 16 + (lane & 15), kq / 8 + (lane >> 4));
         const v8h_t ah = *reinterpret_cast<const v8h_t*>(base + o);
         const v8h_t al = *reinterpret_cast<const v8h_t*>(base + EL + o);
 #pragma unroll

@@ -508,7 +508,7 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_split_partial(
 // second-level sum joins the runs of the chunk, at most PAIR_RUNS of them
 // (the launcher takes this kernel only for such chunks), before the float64
 // partial tile is written.  Stages are 32 rows deep: two stage buffers of the
-// four hi/lo operand tiles take 80 KB of LDS, so two workgroups share a CU.
+// four hi/lo operand tiles take 64 KB of LDS, so two workgroups share a CU.
 // Each wave computes a 64 x 64 quarter of its Gram's tile: LDS bandwidth
 // bounds this kernel, and a 64 x 64 wave tile reads a third fewer fragment
 // bytes per MFMA than the 64 x 32 one.  One workgroup per Gram (rather than
@@ -516,10 +516,21 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_split_partial(
 // CU drift out of phase, so one's split conversion and LDS writes overlap the
 // other's MFMAs; a workgroup's stage barrier holds only its own four waves.
 constexpr int PAIR_BK = 32;
-constexpr int PAIR_LDK = PAIR_BK + 8;  // 80-byte pitch: the 16 rows of a fragment read
-                                       // fall on distinct groups of four banks
+constexpr int PAIR_LDK = PAIR_BK;  // 64-byte columns, 16-byte k-slots permuted per column
 constexpr int PAIR_RUNS = 64;          // most 256-row runs in one chunk
 constexpr int PAIR_NTH = 256;          // four waves, 2 x 2 quarters of the tile
+
+// Half offset of k-slot q (8 rows, 16 bytes) of staged column c.  A 16-byte
+// LDS read serves a wave in four passes of 16 lanes; the lanes of one pass are
+// the four-lane groups g = lane / 4 of one half-wave whose three low bits have
+// the same parity (counted on this chip: lanes 0-3, 12-15, 20-23 and 24-27
+// share a pass).  A fragment read (lane: column lane % 16, slot lane / 16)
+// then puts columns c and c + 4 of adjacent slots in one pass, and with 64-byte
+// columns those meet on the same banks; XORing the slot with 2 on every other
+// group of four columns moves them apart, so each pass covers all 64 banks.
+// The stage writes stay conflict-free: two adjacent columns are one 128-byte
+// row of the 32 banks an 8-byte write pass covers.
+__device__ inline int pair_at(int c, int q) { return c * PAIR_LDK + 8 * (q ^ (c & 4) >> 1); }
 
 struct PairLoader {  // 128 columns x 32 rows of float32, four 4-row vectors per thread
   static constexpr int VPC = PAIR_BK / 4;
@@ -550,13 +561,14 @@ struct PairLoader {  // 128 columns x 32 rows of float32, four 4-row vectors per
     for (int p = 0; p < PER; ++p) {
       const int vid = tid + p * PAIR_NTH;
       const int col = vid / VPC;
-      const int kv = (vid % VPC) * 4;
+      const int kv = vid % VPC;  // rows 4 kv .. 4 kv + 3: half kv & 1 of slot kv / 2
       uint32_t hw[2], lw[2];
 #pragma unroll
       for (int e = 0; e < 4; e += 2)
         split_pair_f16(buf[p][e] * ss[e], buf[p][e + 1] * ss[e + 1], hw[e >> 1], lw[e >> 1]);
-      *reinterpret_cast<uint2*>(hi + col * PAIR_LDK + kv) = make_uint2(hw[0], hw[1]);
-      *reinterpret_cast<uint2*>(lo + col * PAIR_LDK + kv) = make_uint2(lw[0], lw[1]);
+      const int o = pair_at(col, kv >> 1) + 4 * (kv & 1);
+      *reinterpret_cast<uint2*>(hi + o) = make_uint2(hw[0], hw[1]);
+      *reinterpret_cast<uint2*>(lo + o) = make_uint2(lw[0], lw[1]);
     }
   }
 };
@@ -638,13 +650,13 @@ __global__ __launch_bounds__(PAIR_NTH, 2) void k_syrk_split_pair_partial(
     v8h bh[PN], bl[PN];
 #pragma unroll
     for (int j = 0; j < PN; ++j) {
-      const int o2 = (wn * 64 + j * 16 + (lane & 15)) * LDK + 8 * (lane >> 4);
+      const int o2 = pair_at(wn * 64 + j * 16 + (lane & 15), lane >> 4);
       bh[j] = *reinterpret_cast<const v8h*>(bh_s + o2);
       bl[j] = *reinterpret_cast<const v8h*>(bl_s + o2);
     }
 #pragma unroll
     for (int i = 0; i < PM; ++i) {
-      const int o2 = (wm * 64 + i * 16 + (lane & 15)) * LDK + 8 * (lane >> 4);
+      const int o2 = pair_at(wm * 64 + i * 16 + (lane & 15), lane >> 4);
       const v8h ah = *reinterpret_cast<const v8h*>(ah_s + o2);
       const v8h al = *reinterpret_cast<const v8h*>(al_s + o2);
 #pragma unroll

@@ -48,13 +48,20 @@ struct LdsKC {
 //   k-contiguous operand   -> s[row * LDK + k],  LDK = BK + 16 bytes of pad
 //   row-contiguous operand -> s[k * LDR + row],  LDR = ROWS + 16 elements of pad
 // Both keep 16-byte aligned vector stores (the staged vectors run along the
-// contiguous index) and spread a fragment's 16 rows over distinct banks.
+// contiguous index).  A k-contiguous slice of a 2-byte type with 128-byte rows
+// (BK = 64, read as 16-byte MFMA fragments) is instead stored unpadded with
+// its 16-byte chunks permuted per row by lds_swz8, which keeps the fragment
+// reads free of bank conflicts (the padded rows cost two passes per read).
 template <typename T, int ROWS, int BK, bool KC>
 struct SliceLayout {
-  static constexpr int LDK = BK + 16 / (int)sizeof(T);
+  static constexpr bool SWZ = KC && sizeof(T) == 2 && BK * sizeof(T) == 128;
+  static constexpr int LDK = SWZ ? BK : BK + 16 / (int)sizeof(T);
   static constexpr int LDR = ROWS + 16;
   static constexpr int ELEMS = KC ? ROWS * LDK : BK * LDR;
-  __device__ static inline int at(int row, int k) { return KC ? row * LDK + k : k * LDR + row; }
+  __device__ static inline int at(int row, int k) {
+    if constexpr (SWZ) return row * LDK + ((((k >> 3) ^ lds_swz8(row)) << 3) | (k & 7));
+    return KC ? row * LDK + k : k * LDR + row;
+  }
 };
 
 template <class Cfg, bool KCA, bool KCB>
@@ -277,6 +284,8 @@ __device__ inline void for_each_acc(TileAcc<Cfg>& acc, Fn&& fn) {
 // [16 l, 16 l + 16) after the instruction's wave-uniform LDS base.  A padded
 // slice (SliceLayout) is therefore filled chunk by chunk, line by line; the
 // pad chunk at the end of each line is filled from the line's first chunk.
+// In a swizzled slice LDS chunk j of a line holds the line's global chunk
+// j ^ lds_swz8(line), which is what the lane of that chunk fetches.
 // No registers hold data in flight, so several stages can be outstanding at
 // once (the register-staged main loop above has one).
 #define RPC_GPTR(p) ((const void __attribute__((address_space(1)))*)(p))
@@ -326,7 +335,8 @@ struct DirectSlice {
   static constexpr int CPL = PITCH / E;                   // chunks per line, pad included
   static constexpr int DCPL = (KC ? BK : ROWS) / E;       // data chunks per line
   static constexpr int WINST = LINES * CPL / 64;          // wave instructions per slice
-  static_assert(PITCH % E == 0 && (LINES * CPL) % 64 == 0 && DCPL < CPL, "direct slice shape");
+  static_assert(PITCH % E == 0 && (LINES * CPL) % 64 == 0 && (L::SWZ ? DCPL == CPL : DCPL < CPL),
+                "direct slice shape");
   __device__ static inline int count(int wave) { return wave < WINST ? (WINST - wave + NW - 1) / NW : 0; }
   // rows r0 .. r0 + ROWS - 1 and k0 .. k0 + BK - 1 must be readable
   __device__ static inline void issue(T* slice, const T* p, int64_t ld, int64_t r0, int64_t k0,
@@ -335,7 +345,8 @@ struct DirectSlice {
       const int c = q * 64 + lane;
       const int line = c / CPL;
       int j = c % CPL;
-      if (j >= DCPL) j = 0;
+      if constexpr (L::SWZ) j ^= lds_swz8(line);
+      else if (j >= DCPL) j = 0;
       const T* g = KC ? p + (r0 + line) * ld + k0 + (int64_t)j * E
                       : p + (r0 + (int64_t)j * E) + (k0 + line) * ld;
       __builtin_amdgcn_global_load_lds(RPC_GPTR(g), RPC_LPTR(slice + q * 64 * E), 16, 0, 0);
