@@ -509,9 +509,8 @@ __global__ __launch_bounds__(NTH, 2) void k_syrk_split_partial(
 // (the launcher takes this kernel only for such chunks), before the float64
 // partial tile is written.  Stages are 32 rows deep: two stage buffers of the
 // four hi/lo operand tiles take 64 KB of LDS, so two workgroups share a CU.
-// Each wave computes a 64 x 64 quarter of its Gram's tile: LDS bandwidth
-// bounds this kernel, and a 64 x 64 wave tile reads a third fewer fragment
-// bytes per MFMA than the 64 x 32 one.  One workgroup per Gram (rather than
+// Each wave computes a 64 x 64 quarter of its Gram's tile, which reads a third
+// fewer fragment bytes per MFMA than a 64 x 32 one.  One workgroup per Gram (rather than
 // eight waves taking both Grams from one staging) lets the two workgroups on a
 // CU drift out of phase, so one's split conversion and LDS writes overlap the
 // other's MFMAs; a workgroup's stage barrier holds only its own four waves.
