@@ -1046,9 +1046,18 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
 
   // ---- Cholesky QR in Gram space: S G_B S = L' L'^T, R = L'^T S^{-1}
   dense::cholesky(st, w.Gs, r, r, status, k, w.cskip);
-  // M = R C R^T = L'^T (S^{-1} C S^{-1}) L'
-  dense::gemm64<false, true>(st, r, r, r, w.Cs, r, w.Gs, r, w.T1, r, 1.0, 0.0);
-  dense::gemm64<true, true>(st, r, r, r, w.Gs, r, w.T1, r, w.M, r, 1.0, 0.0);
+  // M = R C R^T = L'^T (S^{-1} C S^{-1}) L'.  The Gram partial buffers are
+  // free here; when they hold four r x r slices, each product is split over
+  // four k ranges (four times the workgroups of an r x r tile grid).
+  if (w.part_cap >= (size_t)4 * r * r) {
+    dense::gemm64_splitk<false, true>(st, r, r, r, w.Cs, r, w.Gs, r, w.T1, r, 1.0, 0.0, w.part,
+                                      nullptr, 4);
+    dense::gemm64_splitk<true, true>(st, r, r, r, w.Gs, r, w.T1, r, w.M, r, 1.0, 0.0, w.part,
+                                     nullptr, 4);
+  } else {
+    dense::gemm64<false, true>(st, r, r, r, w.Cs, r, w.Gs, r, w.T1, r, 1.0, 0.0);
+    dense::gemm64<true, true>(st, r, r, r, w.Gs, r, w.T1, r, w.M, r, 1.0, 0.0);
+  }
   RPC_LAUNCH_CHECK();
   if (qr2) {
     // Cholesky QR2: Q1 = B R1^{-1} formed explicitly (float64), its Gram

@@ -12,6 +12,7 @@ namespace {  // internal linkage: each translation unit owns its copy
 
 constexpr int JMAX = 96;  // largest matrix the one-workgroup Jacobi holds in LDS
 constexpr int NB = 64;    // block size of the blocked Cholesky / triangular solve
+constexpr int SPLITK_MAX = 16;  // most k slices of a split-K product
 
 // C(m, n) = alpha * sum_k A(m, k) B(n, k) + beta * C(m, n)
 //   A(m, k) = KCA ? A[m * lda + k] : A[m + k * lda]
@@ -296,7 +297,8 @@ __global__ __launch_bounds__(1024) void k_trsm_ut_diag(const double* L, int64_t 
 template <bool KCA, bool KCB>
 inline void gemm64_splitk(hipStream_t st, int64_t M, int64_t N, int64_t K, const double* A,
                           int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
-                          double alpha, double beta, double* part, const int32_t* skip = nullptr);
+                          double alpha, double beta, double* part, const int32_t* skip = nullptr,
+                          int max_splits = SPLITK_MAX);
 
 // Solve L^T X = B in place (L lower n x n column-major; X n x m column-major).
 // `part` (SPLITK_MAX * NB * m doubles, or null) lets the block updates split
@@ -697,17 +699,16 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const double* __restrict_
   *c = beta == 0.0 ? alpha * s : alpha * s + beta * *c;
 }
 
-constexpr int SPLITK_MAX = 16;
-
-// C = alpha A B^T + beta C with K sliced into up to SPLITK_MAX pieces of at
-// least 64; `part` holds SPLITK_MAX * M * N doubles.
+// C = alpha A B^T + beta C with K sliced into up to max_splits (<= SPLITK_MAX)
+// pieces of at least 64; `part` holds max_splits * M * N doubles.
 template <bool KCA, bool KCB>
 inline void gemm64_splitk(hipStream_t st, int64_t M, int64_t N, int64_t K, const double* A,
                           int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
-                          double alpha, double beta, double* part, const int32_t* skip) {
+                          double alpha, double beta, double* part, const int32_t* skip,
+                          int max_splits) {
   if (M <= 0 || N <= 0) return;
   int splits = (int)((K + 63) / 64);
-  if (splits > SPLITK_MAX) splits = SPLITK_MAX;
+  if (splits > max_splits) splits = max_splits;
   if (splits < 2) {
     gemm64<KCA, KCB>(st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, skip);
     return;
