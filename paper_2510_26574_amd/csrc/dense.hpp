@@ -14,6 +14,26 @@ constexpr int JMAX = 96;  // largest matrix the one-workgroup Jacobi holds in LD
 constexpr int NB = 64;    // block size of the blocked Cholesky / triangular solve
 constexpr int SPLITK_MAX = 16;  // most k slices of a split-K product
 
+// Visits e = t, t + step, ... below n * n with (i, c) = (e mod n, e / n):
+// the same elements in the same order as a loop over e, but with one integer
+// division per call instead of two per element (a division by a run-time
+// value costs some thirty instructions).
+template <typename Fn>
+__device__ inline void for_nn(int t, int step, int n, Fn&& fn) {
+  if (n <= 0) return;
+  const int di = step % n, dc = step / n;
+  int i = t % n, c = t / n;
+  for (int e = t; e < n * n; e += step) {
+    fn(i, c);
+    i += di;
+    c += dc;
+    if (i >= n) {
+      i -= n;
+      ++c;
+    }
+  }
+}
+
 // C(m, n) = alpha * sum_k A(m, k) B(n, k) + beta * C(m, n)
 //   A(m, k) = KCA ? A[m * lda + k] : A[m + k * lda]
 //   B(n, k) = KCB ? B[n * ldb + k] : B[n + k * ldb]
@@ -198,10 +218,9 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* A, int64_t ld, int n
   n = active_n(n, kptr);
   if (j0 >= n) return;
   const int nb = n - j0 < NB ? n - j0 : NB;
-  for (int e = threadIdx.x; e < nb * nb; e += 256) {
-    int i = e % nb, c = e / nb;
+  for_nn((int)threadIdx.x, 256, nb, [&](int i, int c) {
     L[i + c * NB] = A[(j0 + i) + (int64_t)(j0 + c) * ld];
-  }
+  });
   if ((int)threadIdx.x < nb) {
     const int c = threadIdx.x;
     rdg[c] = 1.0 / A[(j0 + c) + (int64_t)(j0 + c) * ld];
@@ -273,10 +292,9 @@ __global__ __launch_bounds__(1024) void k_trsm_ut_diag(const double* L, int64_t 
   constexpr int LDS = NB + 1;  // lanes reading row ii of the block walk distinct banks
   __shared__ double Ls[NB * LDS];
   __shared__ double rd[NB];
-  for (int e = threadIdx.x; e < nb * nb; e += 1024) {
-    int i = e % nb, c = e / nb;
+  for_nn((int)threadIdx.x, 1024, nb, [&](int i, int c) {
     Ls[i + c * LDS] = L[(i0 + i) + (int64_t)(i0 + c) * ld];
-  }
+  });
   __syncthreads();
   if (threadIdx.x < nb) rd[threadIdx.x] = 1.0 / Ls[threadIdx.x + threadIdx.x * LDS];
   __syncthreads();
@@ -347,23 +365,40 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ A, i
   __shared__ int done, ident[JMAX / 2];
   const int tid = threadIdx.x;
   const int n = p + (p & 1);  // even size; a padded row/column is decoupled (zero)
-  for (int e = tid; e < n * n; e += 1024) {
-    int i = e % n, c = e / n;
+  for_nn(tid, 1024, n, [&](int i, int c) {
     double x = (i < p && c < p) ? 0.5 * (A[i + c * lda] + A[c + i * lda]) : 0.0;
     a[i + c * n] = x;
     v[i + c * n] = i == c ? 1.0 : 0.0;
-  }
+  });
   __syncthreads();
   const int h = n / 2;
+  // Each thread's 2 x 2 blocks (pairs u, w) and V entries (row i, pair u) are
+  // the same in every step: their indices are taken once here, since an
+  // integer division by the run-time h or n costs some thirty instructions
+  // and the step loop would otherwise repeat eight of them per thread.
+  constexpr int AMAX = ((JMAX / 2) * (JMAX / 2) + 1023) / 1024;
+  constexpr int VMAX = (JMAX * (JMAX / 2) + 1023) / 1024;
+  int au[AMAX], aw[AMAX], vi[VMAX], vu[VMAX];
+#pragma unroll
+  for (int q = 0; q < AMAX; ++q) {
+    const int e = tid + q * 1024;
+    au[q] = e < h * h ? e % h : -1;
+    aw[q] = e < h * h ? e / h : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < VMAX; ++q) {
+    const int e = tid + q * 1024;
+    vi[q] = e < n * h ? e % n : 0;
+    vu[q] = e < n * h ? e / n : -1;
+  }
   for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
     // convergence: off-diagonal Frobenius mass vs total
     double off = 0.0, tot = 0.0;
-    for (int e = tid; e < n * n; e += 1024) {
-      int i = e % n, c = e / n;
+    for_nn(tid, 1024, n, [&](int i, int c) {
       double x = a[i + c * n];
       tot += x * x;
       if (i != c) off += x * x;
-    }
+    });
     off = wave_sum(off);
     tot = wave_sum(tot);
     if ((tid & 63) == 0) {
@@ -392,16 +427,19 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ A, i
     }
     __syncthreads();
     if (done || sweep == max_sweeps) break;
+    // round-robin pairing: player n-1 fixed, the others rotate; for thread
+    // t > 0, x = (step + t) mod (n - 1) and y = (step - t) mod (n - 1), kept
+    // by increments
+    int rx = tid, ry = n - 1 - tid;
     for (int step = 0; step < n - 1; ++step) {
       if (tid < h) {
-        // round-robin pairing: player n-1 fixed, the others rotate
         int x, y;
         if (tid == 0) {
           x = n - 1;
           y = step;
         } else {
-          x = (step + tid) % (n - 1);
-          y = (step - tid + (n - 1)) % (n - 1);
+          x = rx;
+          y = ry;
         }
         const int P = x < y ? x : y, Q = x < y ? y : x;
         const double app = a[P + P * n], aqq = a[Q + Q * n], apq = a[P + Q * n];
@@ -420,9 +458,13 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ A, i
         pb[tid] = Q;
       }
       __syncthreads();
+      rx = rx + 1 == n - 1 ? 0 : rx + 1;
+      ry = ry + 1 == n - 1 ? 0 : ry + 1;
       // A <- J^T A J on every 2 x 2 block (rows of pair u, columns of pair w)
-      for (int e = tid; e < h * h; e += 1024) {
-        const int u = e % h, w = e / h;
+#pragma unroll
+      for (int q = 0; q < AMAX; ++q) {
+        const int u = au[q], w = aw[q];
+        if (u < 0) continue;
         if (ident[u] & ident[w]) continue;  // both rotations are the identity
         const int P = pa[u], Q = pb[u], R = pa[w], S = pb[w];
         const double cu = cs[u], su = sn[u], cw = cs[w], sw = sn[w];
@@ -437,8 +479,10 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ A, i
         a[Q + S * n] = su * bPS + cu * bQS;
       }
       // V <- V J
-      for (int e = tid; e < n * h; e += 1024) {
-        const int i = e % n, u = e / n;
+#pragma unroll
+      for (int q = 0; q < VMAX; ++q) {
+        const int i = vi[q], u = vu[q];
+        if (u < 0) continue;
         if (ident[u]) continue;
         const int P = pa[u], Q = pb[u];
         const double c = cs[u], s = sn[u];
@@ -465,10 +509,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ A, i
   }
   __syncthreads();
   if (tid < p) evals[tid] = a[order[tid] + order[tid] * n];
-  for (int e = tid; e < p * p; e += 1024) {
-    int i = e % p, c = e / p;
-    W[i + c * ldw] = v[i + order[c] * n];
-  }
+  for_nn(tid, 1024, p, [&](int i, int c) { W[i + c * ldw] = v[i + order[c] * n]; });
 }
 
 // v from another lane of the same DPP row (CTRL: a DPP control code with
@@ -530,16 +571,12 @@ __global__ __launch_bounds__(1024) void k_chol_small(const double* __restrict__ 
     sc[tid] = (equil && g > 0.0) ? 1.0 / sqrt(g) : 1.0;
   }
   __syncthreads();
-  for (int e = tid; e < p * p; e += 1024) {
-    const int i = e % p, c = e / p;
-    a[i + c * LDS] = G[i + c * ldg] * sc[i] * sc[c];
-  }
+  for_nn(tid, 1024, p, [&](int i, int c) { a[i + c * LDS] = G[i + c * ldg] * sc[i] * sc[c]; });
   chol_panel_lds(a, p, LDS, status);  // lower L, R = L^T S^{-1}
   if (!inverse) {
-    for (int e = tid; e < p * p; e += 1024) {
-      const int i = e % p, c = e / p;
+    for_nn(tid, 1024, p, [&](int i, int c) {
       R[i + c * ldr] = (i <= c) ? a[c + i * LDS] / sc[c] : 0.0;
-    }
+    });
     return;
   }
   // X = L^{-1}, one column j per group of 8 lanes, right-looking: lane sub
@@ -578,10 +615,9 @@ __global__ __launch_bounds__(1024) void k_chol_small(const double* __restrict__ 
     }
   }
   __syncthreads();
-  for (int e = tid; e < p * p; e += 1024) {
-    const int i = e % p, c = e / p;
+  for_nn(tid, 1024, p, [&](int i, int c) {
     R[i + c * ldr] = (i <= c) ? sc[i] * xi[c + i * LDS] : 0.0;  // (S X^T)(i, c) = s_i X(c, i)
-  }
+  });
 }
 
 // Q = Y R^{-1} for p == P (R upper P x P, Y r x P, column-major): each
@@ -641,10 +677,7 @@ __global__ __launch_bounds__(64) void k_trsm_rows(const double* __restrict__ Y, 
   __shared__ double Rs[JMAX * JMAX];
   __shared__ double q[64 * LDS];
   const int t = threadIdx.x;
-  for (int e = t; e < p * p; e += 64) {
-    const int i = e % p, c = e / p;
-    Rs[i + c * p] = R[i + c * ldr];
-  }
+  for_nn(t, 64, p, [&](int i, int c) { Rs[i + c * p] = R[i + c * ldr]; });
   const int row = blockIdx.x * 64 + t;
   for (int j = 0; j < p; ++j) q[t * LDS + j] = row < rows ? Y[row + (int64_t)j * ldy] : 0.0;
   __syncthreads();
