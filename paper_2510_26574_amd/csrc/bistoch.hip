@@ -525,19 +525,22 @@ __global__ __launch_bounds__(FormUCfg<T>::NT) void k_form_u(const TF* __restrict
 // magnitude below 2^14.  Single LDS buffer, two workgroups per CU; each lane
 // writes its four consecutive rows of a column directly.
 typedef TileCfg<__bf16, 128, 128, 64, 2, 4> FormUSplitCfg;
+// nev <= 64: four waves on 128 x 64 tiles, 48 KB of LDS, three workgroups per
+// CU (half again the operand bytes in flight per CU of the eight-wave form)
+typedef TileCfg<__bf16, 128, 64, 64, 2, 2> FormUSplitCfg64;
 
 // With cpv/cpi non-null the kernel also writes, for each column, the largest
 // |U| over its 128 rows and that row (the lowest on ties) to
 // cpv/cpi[col * gridDim.x + blockIdx.x], the partials of the sign rule.
-template <typename TU>
-__global__ __launch_bounds__(512, 4) void k_form_u_split(const float* __restrict__ F, int64_t ldf,
+template <typename TU, class Cfg>
+__global__ __launch_bounds__(Cfg::NT, Cfg::NT == 512 ? 4 : 3) void k_form_u_split(
+    const float* __restrict__ F, int64_t ldf,
                                                          int64_t N, int r, const float* __restrict__ Zt,
                                                          int nev, const float* __restrict__ zsc,
                                                          const double* __restrict__ dinv,
                                                          TU* __restrict__ U, int64_t ldu,
                                                          const int32_t* kptr, double* __restrict__ cpv,
                                                          int64_t* __restrict__ cpi) {
-  typedef FormUSplitCfg Cfg;
   extern __shared__ char smem_raw[];
   const int kk = *kptr;
   const int64_t m0 = (int64_t)blockIdx.x * Cfg::BM;
@@ -1240,11 +1243,18 @@ static int run_eig(const TF* F, int64_t N, int64_t ldf, int r, const int32_t* k,
       split_u = true;
       hipLaunchKernelGGL(k_pow2_scale, dim3(1), dim3(1024), 0, st, (const float*)Zt,
                          (int64_t)r * nev, w.gsc);
-      const dim3 gs((unsigned)((N + 127) / 128), (unsigned)((nev + 127) / 128));
-      hipLaunchKernelGGL((k_form_u_split<TU>), gs, dim3(512), SchurSplit::bytes / 2, st,
-                         (const float*)F, ldf, N, r, (const float*)Zt, nev, (const float*)w.gsc,
-                         (const double*)w.sd, U, ldu, k, fused_sign ? w.pv : (double*)nullptr,
-                         fused_sign ? w.pi : (int64_t*)nullptr);
+      auto launch_u = [&](auto cfg) {
+        typedef decltype(cfg) Cfg;
+        const dim3 gs((unsigned)((N + 127) / 128), (unsigned)((nev + Cfg::BN - 1) / Cfg::BN));
+        hipLaunchKernelGGL((k_form_u_split<TU, Cfg>), gs, dim3(Cfg::NT),
+                           SchurSplitPipe<Cfg>::single_bytes, st, (const float*)F, ldf, N, r,
+                           (const float*)Zt, nev, (const float*)w.gsc, (const double*)w.sd, U, ldu, k,
+                           fused_sign ? w.pv : (double*)nullptr, fused_sign ? w.pi : (int64_t*)nullptr);
+      };
+      if (nev <= 64)
+        launch_u(FormUSplitCfg64{});
+      else
+        launch_u(FormUSplitCfg{});
     }
   }
   if (lm) {

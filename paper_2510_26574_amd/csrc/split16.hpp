@@ -59,10 +59,20 @@ __device__ inline void split8(const float (&x)[8], v8h_t& hi, v8h_t& lo,
 // A_ROWS: A is k-contiguous too (A[m * ldf + l], the points of a distance
 // product), loaded like B: thread t holds row t / 4 at k groups t % 4 and
 // t % 4 + 4.
+// Two shapes: eight waves on a 128 x 128 tile, or (A column-major only) four
+// waves on 128 x 64, where a thread holds row t % 128 of A at k groups t / 128
+// + 2 h (h < 4); B always takes four threads per row.
 template <class Cfg, bool A_ROWS = false>
 struct SchurSplitPipe {
-  static_assert(Cfg::NT == 512 && Cfg::BM == 128 && Cfg::BN == 128, "eight waves, 128 x 128");
-  static constexpr int BK = SchurSplit::BK, LDK = SchurSplit::LDK, EL = SchurSplit::ELEMS;
+  static_assert(Cfg::BM == 128 && ((Cfg::NT == 512 && Cfg::BN == 128) ||
+                                   (Cfg::NT == 256 && Cfg::BN == 64 && !A_ROWS)),
+                "eight waves on 128 x 128, or four on 128 x 64");
+  static constexpr int BK = SchurSplit::BK, LDK = SchurSplit::LDK;
+  static constexpr int ELA = 128 * LDK, ELB = Cfg::BN * LDK;  // halfs per hi or lo slice
+  static constexpr int GA = A_ROWS ? 2 : 8 * 128 / Cfg::NT;  // A k-groups per thread
+  static constexpr int GS = A_ROWS ? 4 : Cfg::NT / 128;      // and their stride
+  static constexpr int STAGE = 2 * ELA + 2 * ELB;             // halfs per LDS buffer
+  static constexpr size_t single_bytes = (size_t)STAGE * sizeof(_Float16);
   const float* __restrict__ F;
   int64_t ldf, N;
   const float* __restrict__ FSa;
@@ -70,7 +80,7 @@ struct SchurSplitPipe {
   int64_t m0;
   float bsc = SchurSplit::SC;  // power-of-two scale of the B operand
   float asc = SchurSplit::SC;  // and of the A operand
-  float a0[2][8], b0[2][8], a1[2][8], b1[2][8];
+  float a0[GA][8], b0[2][8], a1[GA][8], b1[2][8];
 
   // rows [row of this thread] of a k-contiguous operand (stride ld, `rows`
   // rows), 8 consecutive k at k groups g and g + 4 of the stage at kb
@@ -95,7 +105,7 @@ struct SchurSplitPipe {
     }
   }
 
-  __device__ inline void load_a(float (&a)[2][8], int kb) const {
+  __device__ inline void load_a(float (&a)[GA][8], int kb) const {
     const int tid = threadIdx.x;
     if constexpr (A_ROWS) {
       load_rows(a, F, ldf, m0 + (tid >> 2), N, kb, tid & 3);
@@ -103,8 +113,8 @@ struct SchurSplitPipe {
       const int arow = tid & 127, ag = tid >> 7;
       const int64_t am = m0 + arow;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int k0 = kb + 8 * (ag + 4 * h);
+      for (int h = 0; h < GA; ++h) {
+        const int k0 = kb + 8 * (ag + GS * h);
 #pragma unroll
         for (int e = 0; e < 8; ++e)
           a[h][e] = (am < N && k0 + e < k) ? F[am + (int64_t)(k0 + e) * ldf] : 0.0f;
@@ -115,32 +125,32 @@ struct SchurSplitPipe {
     const int tid = threadIdx.x;
     load_rows(b, FSa, r, tid >> 2, nt, kb, tid & 3);
   }
-  __device__ inline void load(float (&a)[2][8], float (&b)[2][8], int kb) const {
+  __device__ inline void load(float (&a)[GA][8], float (&b)[2][8], int kb) const {
     load_a(a, kb);
     load_b(b, kb);
   }
 
-  __device__ inline void store(const float (&a)[2][8], const float (&b)[2][8], _Float16* sm,
+  __device__ inline void store(const float (&a)[GA][8], const float (&b)[2][8], _Float16* sm,
                                int buf) const {
     const int tid = threadIdx.x;
     const int arow = A_ROWS ? tid >> 2 : tid & 127, ag = A_ROWS ? tid & 3 : tid >> 7;
     const int brow = tid >> 2, bg = tid & 3;
-    _Float16* base = sm + (size_t)buf * 4 * EL;
+    _Float16* base = sm + (size_t)buf * STAGE;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < GA; ++h) {
       v8h_t hi, lo;
       split8(a[h], hi, lo, asc);
-      const int o = SchurSplit::at(arow, ag + 4 * h);
+      const int o = SchurSplit::at(arow, ag + GS * h);
       *reinterpret_cast<v8h_t*>(base + o) = hi;
-      *reinterpret_cast<v8h_t*>(base + EL + o) = lo;
+      *reinterpret_cast<v8h_t*>(base + ELA + o) = lo;
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       v8h_t hi, lo;
       split8(b[h], hi, lo, bsc);
       const int o = SchurSplit::at(brow, bg + 4 * h);
-      *reinterpret_cast<v8h_t*>(base + 2 * EL + o) = hi;
-      *reinterpret_cast<v8h_t*>(base + 3 * EL + o) = lo;
+      *reinterpret_cast<v8h_t*>(base + 2 * ELA + o) = hi;
+      *reinterpret_cast<v8h_t*>(base + 2 * ELA + ELB + o) = lo;
     }
   }
 
@@ -148,7 +158,7 @@ struct SchurSplitPipe {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave % Cfg::WAVES_M, wn = wave / Cfg::WAVES_M;
     if (wn * Cfg::WTN >= nt) return;  // this wave's columns are all beyond the block
-    const _Float16* base = sm + (size_t)buf * 4 * EL;
+    const _Float16* base = sm + (size_t)buf * STAGE;
 #pragma unroll
     for (int kq = 0; kq < BK; kq += 32) {
       // B fragments for the whole k-step, A fragments one row block at a time
@@ -157,14 +167,14 @@ struct SchurSplitPipe {
 #pragma unroll
       for (int j = 0; j < Cfg::NI; ++j) {
         const int o = SchurSplit::at(wn * Cfg::WTN + j * 16 + (lane & 15), kq / 8 + (lane >> 4));
-        bh[j] = *reinterpret_cast<const v8h_t*>(base + 2 * EL + o);
-        bl[j] = *reinterpret_cast<const v8h_t*>(base + 3 * EL + o);
+        bh[j] = *reinterpret_cast<const v8h_t*>(base + 2 * ELA + o);
+        bl[j] = *reinterpret_cast<const v8h_t*>(base + 2 * ELA + ELB + o);
       }
 #pragma unroll
       for (int i = 0; i < Cfg::MI; ++i) {
         const int o = SchurSplit::at(wm * Cfg::WTM + i * 16 + (lane & 15), kq / 8 + (lane >> 4));
         const v8h_t ah = *reinterpret_cast<const v8h_t*>(base + o);
-        const v8h_t al = *reinterpret_cast<const v8h_t*>(base + EL + o);
+        const v8h_t al = *reinterpret_cast<const v8h_t*>(base + ELA + o);
 #pragma unroll
         for (int j = 0; j < Cfg::NI; ++j) {
           acc.a[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[j], acc.a[i][j], 0, 0, 0);
