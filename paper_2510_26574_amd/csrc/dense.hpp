@@ -86,8 +86,8 @@ __global__ __launch_bounds__(256) void k_zero_upper(double* A, int64_t ld, int n
 // columns: wave 0 loads a panel into registers (lane l holds panel rows
 // j0 + l and j0 + l + 64), factors it
 // right-looking with the pivot-row values broadcast by readlane, and writes
-// it back; then every thread applies the panel to the trailing lower
-// triangle.  Two workgroup barriers per panel.  A pivot <= 0 sets
+// it back; then every wave applies the panel to tiles of the trailing lower
+// triangle on the float64 MFMA.  Two workgroup barriers per panel.  A pivot <= 0 sets
 // RPC_EBREAKDOWN and is replaced by 1.
 __device__ inline void chol_panel_lds(double* a, int n, int lda_s, int32_t* status) {
   constexpr int W = 8;
@@ -141,18 +141,31 @@ __device__ inline void chol_panel_lds(double* a, int n, int lda_s, int32_t* stat
       }
     }
     __syncthreads();
-    // trailing lower triangle: columns c >= j0 + jw, rows i >= c
+    // trailing lower triangle (columns c >= j0 + jw, rows i >= c) -= P P^T,
+    // P the panel's rows below it: 16 x 16 tiles of the lower triangle on the
+    // float64 MFMA (two k-steps of four panel columns), one tile per wave at a
+    // time; element e of lane l is row l / 16 + 4 e, column l % 16 of a tile
     const int t0 = j0 + jw;
-    const int rows = nth / 32, ty = tid / 32, tx = tid % 32;
-    for (int ii = t0 + ty; ii < n; ii += rows) {
-      double li[W];
+    if (t0 < n) {
+      const int nt16 = (n - t0 + 15) / 16, ntile = nt16 * (nt16 + 1) / 2;
+      for (int tt = wave; tt < ntile; tt += nth / 64) {
+        int bi = 0;
+        while ((bi + 1) * (bi + 2) / 2 <= tt) ++bi;
+        const int bj = tt - bi * (bi + 1) / 2;
+        const int ra = t0 + 16 * bi + (lane & 15), cb = t0 + 16 * bj + (lane & 15);
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int q = 0; q < W; ++q) li[q] = q < jw ? a[ii + (j0 + q) * lda_s] : 0.0;
-      for (int ci = t0 + tx; ci <= ii; ci += 32) {
-        double t = 0.0;
+        for (int s4 = 0; s4 < W / 4; ++s4) {
+          const int q = 4 * s4 + (lane >> 4);
+          const double av = (ra < n && q < jw) ? a[ra + (j0 + q) * lda_s] : 0.0;
+          const double bv = (cb < n && q < jw) ? a[cb + (j0 + q) * lda_s] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
 #pragma unroll
-        for (int q = 0; q < W; ++q) t += li[q] * a[ci + (j0 + q) * lda_s];
-        a[ii + ci * lda_s] -= t;
+        for (int e = 0; e < 4; ++e) {
+          const int row = t0 + 16 * bi + (lane >> 4) + 4 * e;
+          if (row < n && cb < n && row >= cb) a[row + cb * lda_s] -= acc[e];
+        }
       }
     }
     __syncthreads();
