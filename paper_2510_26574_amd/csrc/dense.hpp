@@ -525,43 +525,6 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ A, i
   for_nn(tid, 1024, p, [&](int i, int c) { W[i + c * ldw] = v[i + order[c] * n]; });
 }
 
-// v from another lane of the same DPP row (CTRL: a DPP control code with
-// every lane's source inside its row), as two 32-bit moves.
-template <int CTRL>
-__device__ inline double dpp_f64(double v) {
-  const unsigned long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffull), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-
-// v of lane S of this lane's aligned group of 8: lane S & 3 of each quad by a
-// quad permutation, then the other quad's copy by the half-row mirror.
-template <int S>
-__device__ inline double bcast8(double v) {
-  constexpr int K = S & 3;
-  const double v1 = dpp_f64<K | (K << 2) | (K << 4) | (K << 6)>(v);
-  const double v2 = dpp_f64<0x141>(v1);
-  return ((int)(threadIdx.x & 7) >> 2) == (S >> 2) ? v1 : v2;
-}
-
-// One step i = 8 m + S of the right-looking solve in k_chol_small's inverse.
-template <int S>
-__device__ inline void step8(double (&xr)[JMAX / 8], int m, int sub, int p, int j,
-                             const double* __restrict__ a, const double* __restrict__ rdg) {
-  constexpr int LDS = JMAX + 1;
-  const int i = 8 * m + S;
-  const double xv = bcast8<S>(xr[m] * rdg[i]);
-  if (sub == S) xr[m] = xv;
-#pragma unroll
-  for (int m2 = 0; m2 < JMAX / 8; ++m2) {
-    if (m2 < m) continue;
-    const int r = sub + 8 * m2;
-    const double l = a[r + i * LDS];  // r, i < JMAX: inside the array
-    xr[m2] = (r > i && r < p) ? xr[m2] - l * xv : xr[m2];
-  }
-}
-
 // One-workgroup Cholesky G = R^T R of a p x p SPD matrix (p <= JMAX); writes
 // R (upper, column-major, ldr; zero below the diagonal).  With `equil` the
 // factorisation runs on the equilibrated S G S, s_i = 1/sqrt(G_ii), and
@@ -592,42 +555,62 @@ __global__ __launch_bounds__(1024) void k_chol_small(const double* __restrict__ 
     });
     return;
   }
-  // X = L^{-1}, one column j per group of 8 lanes, right-looking: lane sub
-  // keeps rows r = sub + 8 m of x in registers; step i (unrolled, so i is a
-  // constant) takes x_i = b_i / L(i, i) in its owner lane, broadcasts it to
-  // the group (two DPP moves) and subtracts L(r, i) x_i from the rows r > i.
-  // The steps are straight-line code and their L loads do not depend on
-  // earlier steps, so only the broadcast and one fma per step are serial.
-  // Steps i < j see x_i = 0.  Then R^{-1} = S L^{-T} = S X^T.
-  __shared__ double rdg[JMAX];
-  if (tid < p) rdg[tid] = 1.0 / a[tid + tid * LDS];
-  __syncthreads();
-  constexpr int MR = JMAX / 8;
-  const int g = tid >> 3, sub = tid & 7;
-  if (g < p) {
-    const int j = g;
-    double xr[MR];
+  // X = L^{-1} by 16 x 16 blocks (p padded to a multiple of 16 with the
+  // identity).  First each diagonal block X_bb = L_bb^{-1}, one wave per block
+  // and one column per lane (forward substitution); then block row b after
+  // block row (one barrier each): X_bc = -X_bb sum_{c <= d < b} L_bd X_dc for
+  // c < b, one wave per block, as float64 MFMA products (16 x 16 x 4 steps).
+  // The accumulator of the sum is, element s of lane l, the B operand of the
+  // product with X_bb at k-step s, so it needs no trip through LDS.  Then
+  // R^{-1} = S L^{-T} = S X^T.
+  {
+    const int lane = tid & 63, wave = tid >> 6;
+    const int nb = (p + 15) / 16;
+    // the identity in the padding, so that every read below is unconditional
+    for_nn(tid, 1024, 16 * nb, [&](int i, int c) {
+      if (i >= p || c >= p) a[i + c * LDS] = i == c ? 1.0 : 0.0;
+    });
+    __syncthreads();
+    auto L_at = [&](int r, int c) -> double { return a[r + c * LDS]; };
+    if (wave < nb && lane < 16) {
+      const int b0 = 16 * wave, c = lane;  // column c of X_bb
+      double x[16];
 #pragma unroll
-    for (int m = 0; m < MR; ++m) xr[m] = (sub + 8 * m == j) ? 1.0 : 0.0;
+      for (int i = 0; i < 16; ++i) {
+        double s0 = i == c ? 1.0 : 0.0;
 #pragma unroll
-    for (int m = 0; m < MR; ++m) {
-      // steps i >= p (possible for p < JMAX) only touch rows >= p, never stored
-      step8<0>(xr, m, sub, p, j, a, rdg);
-      step8<1>(xr, m, sub, p, j, a, rdg);
-      step8<2>(xr, m, sub, p, j, a, rdg);
-      step8<3>(xr, m, sub, p, j, a, rdg);
-      step8<4>(xr, m, sub, p, j, a, rdg);
-      step8<5>(xr, m, sub, p, j, a, rdg);
-      step8<6>(xr, m, sub, p, j, a, rdg);
-      step8<7>(xr, m, sub, p, j, a, rdg);
+        for (int l = 0; l < i; ++l) s0 -= L_at(b0 + i, b0 + l) * x[l];
+        x[i] = s0 / L_at(b0 + i, b0 + i);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) xi[(b0 + i) + (b0 + c) * LDS] = x[i];  // zero above the diagonal
     }
+    __syncthreads();
+    for (int b = 1; b < nb; ++b) {
+      if (wave < b) {
+        const int cb = wave;  // block column
+        const int m = lane & 15, kq = lane >> 4;
+        v4d t = {0.0, 0.0, 0.0, 0.0};
+        for (int d = cb; d < b; ++d) {
 #pragma unroll
-    for (int m = 0; m < MR; ++m) {
-      const int r = sub + 8 * m;
-      if (r < p) xi[r + j * LDS] = xr[m];
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const double av = L_at(16 * b + m, 16 * d + 4 * s4 + kq);
+            const double bv = xi[(16 * d + 4 * s4 + kq) + (16 * cb + m) * LDS];
+            t = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, t, 0, 0, 0);
+          }
+        }
+        v4d xb = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const double av = xi[(16 * b + m) + (16 * b + 4 * s4 + kq) * LDS];
+          xb = __builtin_amdgcn_mfma_f64_16x16x4f64(av, t[s4], xb, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xi[(16 * b + kq + 4 * e) + (16 * cb + m) * LDS] = -xb[e];
+      }
+      __syncthreads();
     }
   }
-  __syncthreads();
   for_nn(tid, 1024, p, [&](int i, int c) {
     R[i + c * ldr] = (i <= c) ? sc[i] * xi[c + i * LDS] : 0.0;  // (S X^T)(i, c) = s_i X(c, i)
   });
