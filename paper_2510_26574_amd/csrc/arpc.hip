@@ -469,19 +469,26 @@ static void launch_pivot_block(const T* XS, int64_t dp, const TF* FS, int r, int
 // Column i is not read again after its step, so its division by
 // sqrt(H(i,i)) (which makes it a Cholesky column) is deferred.  Outputs: the
 // accepted pivots (appended to `pivots`), the Cholesky factor L of the
-// accepted block (row-major MAXB x MAXB, zero-padded), and the accepted rows
-// XSa / nsa / FSa for the column kernels.
+// accepted block (row-major MAXB x MAXB, zero-padded), and the block positions
+// (acc) and norms (nsa) of the accepted proposals; k_copy_accepted then
+// gathers their point and factor rows over many workgroups.
 __device__ inline int tri(int a, int c) { return a * (a + 1) / 2 + c; }
+
+// v from lane l of the wave (l uniform)
+__device__ inline double rdlane(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 template <typename T, typename TN, typename TF>
 __global__ __launch_bounds__(1024) void k_accept_reject(
     const double* __restrict__ Hg, int bi, const int64_t* __restrict__ prop,
-    const double* __restrict__ z, double tau, int mode, const T* __restrict__ XS, int64_t dp,
-    const TN* __restrict__ ns, const TF* __restrict__ FS, int r, int32_t* kptr,
-    const int32_t* kfptr, int32_t* nTptr, const int32_t* stop, int64_t* __restrict__ pivots,
-    double* __restrict__ Lc,
-    int64_t* __restrict__ Si, T* __restrict__ XSa, TN* __restrict__ nsa, TF* __restrict__ FSa,
-    int32_t* status) {
+    const double* __restrict__ z, double tau, int mode, const TN* __restrict__ ns,
+    int32_t* kptr, int32_t* nTptr, const int32_t* stop, int64_t* __restrict__ pivots,
+    double* __restrict__ Lc, int64_t* __restrict__ Si, int32_t* __restrict__ acc,
+    TN* __restrict__ nsa, int32_t* status) {
   constexpr int PK = MAXB * (MAXB + 1) / 2;
   __shared__ double H[PK];
   __shared__ int accl[MAXB];
@@ -496,8 +503,7 @@ __global__ __launch_bounds__(1024) void k_accept_reject(
     if (tid == 0) *nTptr = 0;
     return;
   }
-  const int k = *kptr;    // accepted pivots so far (position in `pivots`)
-  const int kf = *kfptr;  // leading columns of the proposal rows FS to carry into FSa
+  const int k = *kptr;  // accepted pivots so far (position in `pivots`)
   for (int a = wave; a < bi; a += 16)
     for (int c = lane; c <= a; c += 64) H[tri(a, c)] = Hg[a * MAXB + c];
   if (tid < bi) {
@@ -516,64 +522,141 @@ __global__ __launch_bounds__(1024) void k_accept_reject(
     first[tid] = f;
   }
   __syncthreads();
-  // Every thread takes each decision itself from the same values, so a step
-  // needs one barrier if it accepts (after its elimination) and none if it
-  // rejects (H is then unchanged).  A proposal repeats an accepted one iff a
-  // proposal of the block with the same point was accepted before it: each
-  // thread keeps the accepted points as a bit mask over first[] in registers.
-  static_assert(MAXB <= 128, "two 64-bit masks");
+  // Panels of PW steps.  The first wave holds the panel's columns for rows
+  // i0 .. bi-1 in registers (lane l: rows i0 + l and i0 + l + 64) and runs
+  // its steps alone, reading pivot-row entries across lanes, so a step costs
+  // no barrier.  Every lane takes each decision from the same values; repeated
+  // points are tracked as a bit mask over first[].  The panel's eliminated
+  // columns (raw in R, scaled by 1 / H(i,i) in Q) then update the trailing
+  // triangle in step order with the same multiply-adds as one step at a time,
+  // so the result does not depend on the panel width.
+  static_assert(MAXB <= 128, "two rows per lane, two 64-bit masks");
+  constexpr int PW = 8;
+  __shared__ double Qp[MAXB * PW], Rp[MAXB * PW];
+  __shared__ int pmask_s[2], na_s;  // pmask_s by panel parity: a panel with no
+  // accepted step skips the trailing barrier, so the next panel must not
+  // overwrite the mask the other waves may still be reading
   unsigned long long taken[2] = {0ull, 0ull};
   int na = 0;
-  for (int i = 0; i < bi; ++i) {
-    const double hii = H[tri(i, i)];
-    const int fi = first[i];
-    const bool dup = (taken[fi >> 6] >> (fi & 63)) & 1ull;
-    bool ok;
-    if (mode == RPC_REPLAY) {
-      ok = hii > tau && !dup;
-      if (!ok && tid == 0) set_status(status, RPC_EBREAKDOWN);
-    } else if (mode == RPC_GREEDY) {
-      ok = hii > tau;  // b = 1: z * H(0,0) < H(0,0) holds for every z in [0, 1)
-    } else {
-      ok = !dup && hii > tau && zs[i] * rho_loc[i] < hii;
-    }
-    if (!ok) continue;
-    if (tid == 0) {
-      dinv[na] = 1.0 / sqrt(hii);
-      accl[na] = i;
-    }
-    taken[fi >> 6] |= 1ull << (fi & 63);
-    ++na;
-    // lower trailing triangle, 32 row groups x 32 column lanes
-    const double rh = 1.0 / hii;
-    const int ty = tid >> 5, tx = tid & 31;
-    for (int a = i + 1 + ty; a < bi; a += 32) {
-      const double hai = H[tri(a, i)] * rh;
-      const int ra = tri(a, 0);
-      for (int c = i + 1 + tx; c <= a; c += 32) H[ra + c] -= hai * H[tri(c, i)];
+  if (tid == 0) na_s = 0;  // read after the closing barrier
+  for (int i0 = 0; i0 < bi; i0 += PW) {
+    if (wave == 0) {
+      const int ra0 = i0 + lane, ra1 = i0 + lane + 64;
+      double x0[PW], x1[PW], rh[PW];
+#pragma unroll
+      for (int c = 0; c < PW; ++c) {
+        const int cg = i0 + c;
+        const bool v0 = ra0 < bi && cg <= ra0, v1 = ra1 < bi && cg <= ra1;
+        const double h0 = H[v0 ? tri(ra0, cg) : 0], h1 = H[v1 ? tri(ra1, cg) : 0];
+        x0[c] = v0 ? h0 : 0.0;
+        x1[c] = v1 ? h1 : 0.0;
+      }
+      int pm = 0;
+#pragma unroll
+      for (int j = 0; j < PW; ++j) {
+        const int i = i0 + j;
+        rh[j] = 0.0;
+        if (i >= bi) continue;
+        const double hii = rdlane(x0[j], j);
+        const int fi = first[i];
+        const bool dup = (taken[fi >> 6] >> (fi & 63)) & 1ull;
+        bool ok;
+        if (mode == RPC_REPLAY) {
+          ok = hii > tau && !dup;
+          if (!ok && lane == 0) set_status(status, RPC_EBREAKDOWN);
+        } else if (mode == RPC_GREEDY) {
+          ok = hii > tau;  // b = 1: z * H(0,0) < H(0,0) holds for every z in [0, 1)
+        } else {
+          ok = !dup && hii > tau && zs[i] * rho_loc[i] < hii;
+        }
+        if (!ok) continue;
+        if (lane == 0) {
+          dinv[na] = 1.0 / sqrt(hii);
+          accl[na] = i;
+        }
+        taken[fi >> 6] |= 1ull << (fi & 63);
+        ++na;
+        pm |= 1 << j;
+        rh[j] = 1.0 / hii;
+        const double hai0 = x0[j] * rh[j], hai1 = x1[j] * rh[j];
+#pragma unroll
+        for (int c = j + 1; c < PW; ++c) {
+          const double hci = rdlane(x0[j], c);
+          x0[c] -= hai0 * hci;
+          x1[c] -= hai1 * hci;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < PW; ++c) {
+        const int cg = i0 + c;
+        if (ra0 < bi && cg <= ra0) H[tri(ra0, cg)] = x0[c];
+        if (ra1 < bi && cg <= ra1) H[tri(ra1, cg)] = x1[c];
+        if (ra0 < bi) {
+          Rp[ra0 * PW + c] = x0[c];
+          Qp[ra0 * PW + c] = x0[c] * rh[c];
+        }
+        if (ra1 < bi) {
+          Rp[ra1 * PW + c] = x1[c];
+          Qp[ra1 * PW + c] = x1[c] * rh[c];
+        }
+      }
+      if (lane == 0) {
+        pmask_s[(i0 / PW) & 1] = pm;
+        na_s = na;
+      }
     }
     __syncthreads();
+    const int t0 = i0 + PW, pm = pmask_s[(i0 / PW) & 1];
+    if (t0 < bi && pm != 0) {
+      // lower trailing triangle, 32 row groups x 32 column lanes
+      const int ty = tid >> 5, tx = tid & 31;
+      for (int a = t0 + ty; a < bi; a += 32) {
+        double q[PW];
+#pragma unroll
+        for (int j = 0; j < PW; ++j) q[j] = Qp[a * PW + j];
+        const int ra = tri(a, 0);
+        for (int c = t0 + tx; c <= a; c += 32) {
+          double h = H[ra + c];
+#pragma unroll
+          for (int j = 0; j < PW; ++j)
+            if ((pm >> j) & 1) h -= q[j] * Rp[c * PW + j];
+          H[ra + c] = h;
+        }
+      }
+      __syncthreads();
+    }
   }
   __syncthreads();
-  const int nt = na;
+  const int nt = na_s;
   // compact L(x, y) = H(accl[x], accl[y]) dinv[y] (x >= y), row-major MAXB x MAXB
   for (int x = wave; x < MAXB; x += 16) {
     const int ax = x < nt ? accl[x] : 0;
     for (int y = lane; y < MAXB; y += 64)
       Lc[x * MAXB + y] = (x < nt && y <= x) ? H[tri(ax, accl[y])] * dinv[y] : 0.0;
   }
-  // accepted rows for the column kernels: wave w copies rows w, w + 16, ...
-  for (int a = wave; a < nt; a += 16) {
-    const int64_t src = accl[a];
-    for (int64_t c = lane; c < dp; c += 64) XSa[a * dp + c] = XS[src * dp + c];
-    for (int l = lane; l < kf; l += 64) FSa[(int64_t)a * r + l] = FS[src * r + l];
-  }
   if (tid < nt) {
+    acc[tid] = accl[tid];
     nsa[tid] = ns[accl[tid]];
     Si[tid] = prop[accl[tid]];
     pivots[k + tid] = prop[accl[tid]];
   }
   if (tid == 0) *nTptr = nt;
+}
+
+// Accepted rows for the column kernels: workgroup a copies the point row and
+// the leading kf factor entries of the a-th accepted proposal (a < nT).
+template <typename T, typename TF>
+__global__ __launch_bounds__(256) void k_copy_accepted(const int32_t* __restrict__ acc,
+                                                       const int32_t* nTptr, const int32_t* kfptr,
+                                                       const T* __restrict__ XS, int64_t dp,
+                                                       const TF* __restrict__ FS, int r,
+                                                       T* __restrict__ XSa, TF* __restrict__ FSa) {
+  const int a = blockIdx.x;
+  if (a >= *nTptr) return;
+  const int64_t src = acc[a];
+  const int kf = *kfptr;
+  for (int64_t c = threadIdx.x; c < dp; c += 256) XSa[a * dp + c] = XS[src * dp + c];
+  for (int l = threadIdx.x; l < kf; l += 256) FSa[(int64_t)a * r + l] = FS[src * r + l];
 }
 
 // L^{-1} of the accepted block, one workgroup per column c: four waves stage
@@ -1424,6 +1507,7 @@ struct FactorWs {
   _Float16* Ll;
   float* lsc;
   int64_t* Si;
+  int32_t* acc;  // block positions of the accepted proposals
   void* XSa;
   void* nsa;
   void* FSa;
@@ -1468,6 +1552,7 @@ static void carve_job(WsCursor& c, FactorWs& w, int64_t N, int64_t d, int r) {
   w.Ll = c.take<_Float16>((size_t)MAXB * MAXB);
   w.lsc = c.take<float>(1);
   w.Si = c.take<int64_t>(MAXB);
+  w.acc = c.take<int32_t>(MAXB);
   w.XSa = c.take<T>((size_t)MAXB * w.dp);
   w.nsa = c.take<TN>(MAXB);
   w.FSa = c.take<TF>((size_t)MAXB * r);
@@ -1566,9 +1651,11 @@ static void phase_select(FJob<T, TN, TF>& j, int i, hipStream_t st) {
   launch_pivot_block<T, TF>((const T*)w.XS, dp, (const TF*)w.FS, r, bi, j.k_out, w.stop, j.X.eps,
                             w.pd2, w.pff, w.H, st);
   hipLaunchKernelGGL((k_accept_reject<T, TN, TF>), dim3(1), dim3(1024), 0, st, w.H, bi, w.prop, z,
-                     o->tau, o->mode, (const T*)w.XS, dp, (const TN*)w.ns, (const TF*)w.FS, r,
-                     j.k_out, (const int32_t*)j.k_out, w.nT, w.stop, j.pivots, w.Lc, w.Si,
-                     (T*)w.XSa, (TN*)w.nsa, (TF*)w.FSa, j.status);
+                     o->tau, o->mode, (const TN*)w.ns, j.k_out, w.nT, w.stop, j.pivots, w.Lc,
+                     w.Si, w.acc, (TN*)w.nsa, j.status);
+  hipLaunchKernelGGL((k_copy_accepted<T, TF>), dim3(MAXB), dim3(256), 0, st, (const int32_t*)w.acc,
+                     (const int32_t*)w.nT, (const int32_t*)j.k_out, (const T*)w.XS, dp,
+                     (const TF*)w.FS, r, (T*)w.XSa, (TF*)w.FSa);
   hipLaunchKernelGGL(k_tri_inv, dim3(MAXB), dim3(256), 0, st, (const double*)w.Lc, w.nT, w.Linv);
   prof::end(prof::ACCEPT, st);
 }
@@ -1948,9 +2035,12 @@ static int run_factor_lowmem(const rpc_points* X, const rpc_factor_opts* o, doub
                                   (const int32_t*)(l.pads + i), w.stop, X->eps, w.pd2, w.pff, w.H,
                                   st);
     hipLaunchKernelGGL((k_accept_reject<T, TN, double>), dim3(1), dim3(1024), 0, st, w.H, bi,
-                       w.prop, z, o->tau, o->mode, (const T*)w.XS, dp, (const TN*)w.ns,
-                       (const double*)w.FS, R, k_out, (const int32_t*)(l.pads + i), w.nT, w.stop,
-                       pivots, w.Lc, w.Si, (T*)w.XSa, (TN*)w.nsa, (double*)w.FSa, status);
+                       w.prop, z, o->tau, o->mode, (const TN*)w.ns, k_out, w.nT, w.stop, pivots,
+                       w.Lc, w.Si, w.acc, (TN*)w.nsa, status);
+    hipLaunchKernelGGL((k_copy_accepted<T, double>), dim3(MAXB), dim3(256), 0, st,
+                       (const int32_t*)w.acc, (const int32_t*)w.nT,
+                       (const int32_t*)(l.pads + i), (const T*)w.XS, dp, (const double*)w.FS, R,
+                       (T*)w.XSa, (double*)w.FSa);
     hipLaunchKernelGGL(k_lm_zero_rows, dim3((unsigned)((MAXB * R + 255) / 256)), dim3(256), 0, st,
                        (double*)w.FSa, R, (const int32_t*)w.nT);
     hipLaunchKernelGGL(k_tri_inv, dim3(MAXB), dim3(256), 0, st, (const double*)w.Lc, w.nT, w.Linv);
