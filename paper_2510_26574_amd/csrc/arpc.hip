@@ -532,7 +532,7 @@ __global__ __launch_bounds__(1024) void k_accept_reject(
   // so the result does not depend on the panel width.
   static_assert(MAXB <= 128, "two rows per lane, two 64-bit masks");
   constexpr int PW = 8;
-  __shared__ double Qp[MAXB * PW], Rp[MAXB * PW];
+  __shared__ double Qp[PW * MAXB], Rp[PW * MAXB];  // column j of the panel at j * MAXB
   __shared__ int pmask_s[2], na_s;  // pmask_s by panel parity: a panel with no
   // accepted step skips the trailing barrier, so the next panel must not
   // overwrite the mask the other waves may still be reading
@@ -592,12 +592,12 @@ __global__ __launch_bounds__(1024) void k_accept_reject(
         if (ra0 < bi && cg <= ra0) H[tri(ra0, cg)] = x0[c];
         if (ra1 < bi && cg <= ra1) H[tri(ra1, cg)] = x1[c];
         if (ra0 < bi) {
-          Rp[ra0 * PW + c] = x0[c];
-          Qp[ra0 * PW + c] = x0[c] * rh[c];
+          Rp[c * MAXB + ra0] = x0[c];
+          Qp[c * MAXB + ra0] = x0[c] * rh[c];
         }
         if (ra1 < bi) {
-          Rp[ra1 * PW + c] = x1[c];
-          Qp[ra1 * PW + c] = x1[c] * rh[c];
+          Rp[c * MAXB + ra1] = x1[c];
+          Qp[c * MAXB + ra1] = x1[c] * rh[c];
         }
       }
       if (lane == 0) {
@@ -613,13 +613,13 @@ __global__ __launch_bounds__(1024) void k_accept_reject(
       for (int a = t0 + ty; a < bi; a += 32) {
         double q[PW];
 #pragma unroll
-        for (int j = 0; j < PW; ++j) q[j] = Qp[a * PW + j];
+        for (int j = 0; j < PW; ++j) q[j] = Qp[j * MAXB + a];
         const int ra = tri(a, 0);
         for (int c = t0 + tx; c <= a; c += 32) {
           double h = H[ra + c];
 #pragma unroll
           for (int j = 0; j < PW; ++j)
-            if ((pm >> j) & 1) h -= q[j] * Rp[c * PW + j];
+            if ((pm >> j) & 1) h -= q[j] * Rp[j * MAXB + c];
           H[ra + c] = h;
         }
       }
